@@ -1,0 +1,141 @@
+"""Seeded block-loss patterns and the per-block descriptors handed to FSE.
+
+A lost block ``B`` is a ``bh x bw`` rectangle at ``(y0, x0)`` of frame
+``frame``; its extrapolation area is ``B`` grown by ``border`` pixels on every
+side (Section II, Fig. 1 of the paper: loss area B, support area A, together
+the area L of size M x N). Each descriptor also carries the transform size
+``fft`` and the iteration count ``iters`` used for that block.
+
+The availability mask is ``uint8`` with 1 = received and 0 = lost.
+Loss-pattern random numbers come from ``default_rng(seed + 10**6)`` so that
+the image and its loss pattern can share one seed without sharing a stream.
+"""
+from dataclasses import dataclass
+import math
+
+import numpy as np
+
+#: Memory layout of one block descriptor, identical to ``fse_block_t`` in
+#: ``include/fse.h`` (24 bytes, naturally aligned).
+BLOCK_DTYPE = np.dtype([("frame", "<i4"), ("y0", "<i4"), ("x0", "<i4"),
+                        ("bh", "<i2"), ("bw", "<i2"), ("border", "<i2"),
+                        ("fft", "<i2"), ("iters", "<i4")])
+assert BLOCK_DTYPE.itemsize == 24
+
+FFT_SIZES = (32, 64, 128)
+LOSS_SEED_OFFSET = 10 ** 6
+
+
+@dataclass(frozen=True)
+class Block:
+    frame: int
+    y0: int
+    x0: int
+    bh: int
+    bw: int
+    border: int
+    fft: int
+    iters: int
+
+    @property
+    def M(self):
+        return self.bh + 2 * self.border
+
+    @property
+    def N(self):
+        return self.bw + 2 * self.border
+
+
+def blocks_to_array(blocks):
+    """List of :class:`Block` -> structured array of ``BLOCK_DTYPE``."""
+    arr = np.zeros(len(blocks), dtype=BLOCK_DTYPE)
+    for i, b in enumerate(blocks):
+        arr[i] = (b.frame, b.y0, b.x0, b.bh, b.bw, b.border, b.fft, b.iters)
+    return arr
+
+
+def array_to_blocks(arr):
+    return [Block(*(int(v) for v in rec)) for rec in arr]
+
+
+def fft_size_for_area(M, N):
+    """Smallest F in {32, 64, 128} with F >= ceil(4*max(M,N)/3).
+
+    The paper pads a 48x48 area to a 64x64 transform (Section IV); this rule
+    keeps that ratio for other area sizes."""
+    need = math.ceil(4 * max(M, N) / 3)
+    for F in FFT_SIZES:
+        if F >= need:
+            return F
+    raise ValueError(f"area {M}x{N} needs a transform larger than {FFT_SIZES[-1]}")
+
+
+def isolated_grid_losses(height, width, bs, border, fft, iters, frame=0):
+    """Every other ``bs x bs`` block in both directions, starting at block
+    index (1, 1): each lost block has all 8 neighbours intact."""
+    blocks = []
+    for by in range(1, height // bs, 2):
+        for bx in range(1, width // bs, 2):
+            blocks.append(Block(frame, by * bs, bx * bs, bs, bs, border, fft, iters))
+    return blocks
+
+
+def random_grid_losses(height, width, bs, frac, seed, border, fft, iters, frame=0):
+    """Exactly ``round(frac * cells)`` cells of the ``bs`` grid, no two of
+    them 8-neighbours, drawn by seeded rejection sampling."""
+    rng = np.random.default_rng(seed + LOSS_SEED_OFFSET)
+    gh, gw = height // bs, width // bs
+    want = int(round(frac * gh * gw))
+    taken = np.zeros((gh + 2, gw + 2), dtype=bool)  # one-cell guard ring
+    chosen = []
+    for cell in rng.permutation(gh * gw):
+        cy, cx = divmod(int(cell), gw)
+        if taken[cy:cy + 3, cx:cx + 3].any():
+            continue
+        taken[cy + 1, cx + 1] = True
+        chosen.append((cy, cx))
+        if len(chosen) == want:
+            break
+    if len(chosen) != want:
+        raise RuntimeError(f"could only place {len(chosen)} of {want} non-adjacent blocks")
+    chosen.sort()
+    return [Block(frame, cy * bs, cx * bs, bs, bs, border, fft, iters) for cy, cx in chosen]
+
+
+def mixed_size_losses(height, width, seed, frame=0, sizes=(4, 8, 16, 32), per_size=305,
+                      border_range=(8, 16), iter_choices=(50, 100, 200, 500)):
+    """``per_size`` square blocks of each size at uniform positions, no two
+    blocks overlapping or closer than 1 pixel; border ~ U{border_range},
+    transform size by :func:`fft_size_for_area`, iterations drawn from
+    ``iter_choices``. Larger blocks are placed first."""
+    rng = np.random.default_rng(seed + LOSS_SEED_OFFSET)
+    occ = np.zeros((height, width), dtype=bool)
+    blocks = []
+    for bs in sorted(sizes, reverse=True):
+        placed = 0
+        tries = 0
+        while placed < per_size:
+            tries += 1
+            if tries > 10000 * per_size:
+                raise RuntimeError("could not place blocks")
+            y0 = int(rng.integers(0, height - bs + 1))
+            x0 = int(rng.integers(0, width - bs + 1))
+            ya, yb = max(y0 - 1, 0), min(y0 + bs + 1, height)
+            xa, xb = max(x0 - 1, 0), min(x0 + bs + 1, width)
+            if occ[ya:yb, xa:xb].any():
+                continue
+            occ[y0:y0 + bs, x0:x0 + bs] = True
+            border = int(rng.integers(border_range[0], border_range[1] + 1))
+            iters = int(iter_choices[int(rng.integers(0, len(iter_choices)))])
+            M = bs + 2 * border
+            blocks.append(Block(frame, y0, x0, bs, bs, border, fft_size_for_area(M, M), iters))
+            placed += 1
+    return blocks
+
+
+def availability_mask(shape, blocks):
+    """``uint8`` mask of shape ``(frames, H, W)``: 0 inside every block, else 1."""
+    avail = np.ones(shape, dtype=np.uint8)
+    for b in blocks:
+        avail[b.frame, b.y0:b.y0 + b.bh, b.x0:b.x0 + b.bw] = 0
+    return avail

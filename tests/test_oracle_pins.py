@@ -1,0 +1,334 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by the
+mathematics, independent of the oracle's own code paths.
+
+Each test names the passage it pins. A plausible slip in the oracle (wrong
+sign in the twiddles, a transposed operand, a dropped weight, a wrong
+denominator, a wrong update sign, an off-centre window) fails at least one.
+"""
+import cmath
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import alg1, cfse
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rng(seed=0):
+    return np.random.default_rng(seed)
+
+
+def _brute_dft(x, F):
+    """Double sum over the area of x[m,n]*exp(-j2pi(km+ln)/F), plain loops."""
+    M, N = x.shape
+    X = np.zeros((F, F), dtype=complex)
+    for k in range(F):
+        for l in range(F):
+            acc = 0j
+            for m in range(M):
+                for n in range(N):
+                    acc += complex(x[m, n]) * cmath.exp(-2j * math.pi * (k * m + l * n) / F)
+            X[k, l] = acc
+    return X
+
+
+# --------------------------------------------------------------- eq. (7)
+
+@pytest.mark.parametrize("F,M,N", [(4, 3, 2), (4, 4, 4), (8, 5, 7), (8, 8, 8)])
+def test_projection_is_dft_bruteforce(F, M, N):
+    """eq. (7): the projection onto phi* is the unnormalised DFT; the
+    separable oracle projection equals the brute-force double sum and
+    numpy's FFT of the zero-padded area."""
+    rng = _rng(F * 100 + M * 10 + N)
+    x = rng.normal(size=(M, N)) + 1j * rng.normal(size=(M, N))
+    got = cfse.project(x, cfse.analysis_matrix(F, M), cfse.analysis_matrix(F, N))
+    brute = _brute_dft(x, F)
+    pad = np.zeros((F, F), dtype=complex)
+    pad[:M, :N] = x
+    np.testing.assert_allclose(got, brute, atol=1e-12)
+    np.testing.assert_allclose(got, np.fft.fft2(pad), atol=1e-12)
+
+
+def test_parseval():
+    """Energy of the area equals the spectrum energy divided by F^2."""
+    rng = _rng(3)
+    F, M, N = 16, 11, 13
+    x = rng.normal(size=(M, N))
+    X = cfse.project(x, cfse.analysis_matrix(F, M), cfse.analysis_matrix(F, N))
+    assert abs(np.sum(np.abs(x) ** 2) - np.sum(np.abs(X) ** 2) / F ** 2) < 1e-10 * np.sum(x ** 2)
+
+
+def test_basis_products():
+    """eqs. (5), (6): phi_a phi_b = phi_(a+b), phi_a phi_b* = phi_(a-b), mod F."""
+    F, M, N = 8, 5, 6
+    a, b = (3, 5), (6, 7)
+    pa = cfse.basis(F, M, N, *a)
+    pb = cfse.basis(F, M, N, *b)
+    np.testing.assert_allclose(pa * pb, cfse.basis(F, M, N, (a[0] + b[0]) % F, (a[1] + b[1]) % F), atol=1e-14)
+    np.testing.assert_allclose(pa * np.conj(pb), cfse.basis(F, M, N, (a[0] - b[0]) % F, (a[1] - b[1]) % F), atol=1e-14)
+    # eq. (1): explicit exponential
+    m, n = 4, 5
+    assert abs(pa[m, n] - cmath.exp(2j * math.pi * (a[0] * m + a[1] * n) / F)) < 1e-14
+
+
+def test_orthogonality_full_grid():
+    """eq. (16): on the full F x F grid distinct basis functions are
+    orthogonal and each has energy F*F."""
+    F = 8
+    for (u, v), (k, l) in [((1, 2), (1, 2)), ((1, 2), (3, 2)), ((0, 0), (7, 7))]:
+        s = np.sum(cfse.basis(F, F, F, u, v) * np.conj(cfse.basis(F, F, F, k, l)))
+        assert abs(s - (F * F if (u, v) == (k, l) else 0)) < 1e-12
+
+
+# --------------------------------------------------------------- eq. (3)
+
+def test_window_closed_form():
+    """eq. (3): the four centre pixels of an even-sized area sit sqrt(0.5)
+    from the centre, the corner sqrt(2)*(M-1)/2; odd sizes have weight 1
+    at the centre."""
+    rho = 0.8
+    w = cfse.window(48, 48, rho)
+    for m, n in [(23, 23), (23, 24), (24, 23), (24, 24)]:
+        assert w[m, n] == pytest.approx(rho ** math.sqrt(0.5), rel=1e-15)
+    assert w[0, 0] == pytest.approx(rho ** (math.sqrt(2) * 23.5), rel=1e-14)
+    assert w[47, 0] == pytest.approx(w[0, 0], rel=1e-15)
+    w2 = cfse.window(5, 7, rho)
+    assert w2[2, 3] == 1.0
+    assert w2[0, 3] == pytest.approx(rho ** 2, rel=1e-15)
+    assert w2[2, 0] == pytest.approx(rho ** 3, rel=1e-15)
+
+
+def test_weighting_masks_loss_and_frame_edge():
+    """eq. (3) and the block geometry: w = 0 on B, on lost pixels of other
+    blocks and outside the frame."""
+    frames = np.full((1, 40, 40), 100, dtype=np.uint8)
+    avail = np.ones_like(frames)
+    avail[0, 10:12, 28:30] = 0      # pixels of another lost block inside the area
+    blk = dict(frame=0, y0=4, x0=32, bh=4, bw=4, border=6, fft=32, iters=1)
+    s, A, B = cfse.area_of_block(frames, avail, blk)   # area rows -2..13, cols 26..41
+    assert s.shape == (16, 16)
+    assert B.sum() == 16 and not (A & B).any()
+    assert not A[:, 14:].any()                # x >= 40 lies outside the frame
+    assert not A[0:2, :].any()                # y < 0 lies outside the frame
+    assert not A[12:14, 2:4].any()            # the other block's lost pixels
+    assert A.sum() == 16 * 16 - 16 - 2 * 16 - 2 * 14 + 0 - 4
+    w = cfse.weighting(16, 16, 0.8, A)
+    assert (w[~A] == 0).all() and (w[A] > 0).all()
+
+
+# --------------------------------------------------------------- iteration algebra
+
+def _patch(seed=0, M=12, N=12, hole=4, F=16):
+    rng = _rng(seed)
+    y, x = np.mgrid[0:M, 0:N]
+    s = 100 + 30 * np.sin(2 * np.pi * x / 7.3 + 1) + 20 * np.cos(2 * np.pi * y / 5.1) + rng.normal(0, 2, (M, N))
+    A = np.ones((M, N), dtype=bool)
+    b0 = (M - hole) // 2
+    A[b0:b0 + hole, b0:b0 + hole] = False
+    w = cfse.weighting(M, N, 0.8, A)
+    return s, w, F
+
+
+@pytest.mark.parametrize("gamma", [0.2, 0.5, 1.0])
+def test_energy_identity_and_monotone(gamma):
+    """Weighted least squares along one basis function (eqs. (9), (13),
+    (17)) lowers the weighted residual energy sum(w|r|^2) by exactly
+    gamma*(2-gamma)*|R_w[u,v]|^2/W0 with W0 = sum(w) and R_w[u,v] =
+    W0*c/gamma; hence it never increases for 0 < gamma <= 1."""
+    s, w, F = _patch()
+    res = cfse.cfse(s, w, F, gamma, 60)
+    W0 = w.sum()
+    E = np.array(res["energy"])
+    for nu, c in enumerate(res["chat"]):
+        R = W0 * c / gamma
+        expect = E[nu] - gamma * (2 - gamma) * abs(R) ** 2 / W0
+        assert abs(E[nu + 1] - expect) <= 1e-10 * E[0]
+    assert np.all(np.diff(E) <= 1e-12 * E[0])
+
+
+def test_selection_is_bruteforce_least_squares():
+    """eq. (10): the selected basis function gives the largest drop of the
+    weighted residual energy when fitted alone by weighted least squares;
+    eq. (13): the coefficient is gamma times that fit. Checked with an
+    independent dense least-squares solve per candidate."""
+    s, w, F = _patch(seed=5, M=6, N=6, hole=2, F=8)
+    gamma = 0.7
+    res = cfse.cfse(s, w, F, gamma, 6)
+    M, N = s.shape
+    sw = np.sqrt(w).ravel()
+    r = s.astype(complex)
+    for nu in range(6):
+        drops = np.zeros(F * F)
+        fits = np.zeros(F * F, dtype=complex)
+        for idx in range(F * F):
+            k, l = divmod(idx, F)
+            phi = np.array([[cmath.exp(2j * math.pi * (k * m + l * n) / F) for n in range(N)] for m in range(M)])
+            A = (sw * phi.ravel())[:, None]
+            b = sw * r.ravel()
+            c, *_ = np.linalg.lstsq(A, b, rcond=None)
+            fits[idx] = c[0]
+            drops[idx] = np.sum(np.abs(b) ** 2) - np.sum(np.abs(b - A[:, 0] * c[0]) ** 2)
+        best = np.flatnonzero(drops >= drops.max() * (1 - 1e-9))
+        assert res["seq"][nu] == best[0]
+        assert abs(res["chat"][nu] - gamma * fits[best[0]]) < 1e-9 * abs(fits[best[0]])
+        k, l = divmod(best[0], F)
+        phi = np.array([[cmath.exp(2j * math.pi * (k * m + l * n) / F) for n in range(N)] for m in range(M)])
+        r = r - gamma * fits[best[0]] * phi
+
+
+def test_worked_example_f2_golden():
+    """Hand-derived 2x2 example (tests/golden/f2_worked_example.txt)."""
+    rows, G, E = [], None, None
+    with open(os.path.join(GOLDEN, "f2_worked_example.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            f = line.split()
+            if f[0] == "G":
+                G = Fraction(int(f[1]), int(f[2]))
+            elif f[0] == "E":
+                E = (Fraction(int(f[1]), int(f[2])), Fraction(int(f[3]), int(f[4])))
+            else:
+                rows.append((int(f[1]), int(f[2]), Fraction(int(f[3]), int(f[4]))))
+    for rho in (0.8, 0.3, 1.0):
+        s = np.array([[4.0, 2.0], [1.0, 77.0]])      # s(1,1) is lost: any value
+        A = np.array([[True, True], [True, False]])
+        w = cfse.weighting(2, 2, rho, A)
+        omega = rho ** math.sqrt(0.5)
+        res = cfse.cfse(s, w, 2, 0.5, 3)
+        for (k, l, c), idx, got in zip(rows, res["seq"], res["chat"]):
+            assert idx == k * 2 + l
+            assert abs(got - float(c)) < 1e-13
+        assert abs(res["g"][1, 1] - float(G)) < 1e-13
+        assert abs(res["energy"][0] - float(E[0]) * omega) < 1e-12
+        assert abs(res["energy"][1] - float(E[1]) * omega) < 1e-12
+
+
+# --------------------------------------------------------------- special cases
+
+@pytest.mark.parametrize("k0,l0", [(3, 5), (0, 0), (8, 1)])
+def test_single_basis_function(k0, l0):
+    """A complex input equal to a*phi_(k0,l0) on the area: every iteration
+    selects (k0,l0) (the shifted window spectrum is smaller than W0 off DC),
+    the accumulated coefficient after nu iterations is a*(1-(1-gamma)^nu),
+    and gamma = 1 recovers the signal exactly in one iteration, B included."""
+    F, M, N = 16, 12, 12
+    a = 37.5 - 12.25j
+    A = np.ones((M, N), dtype=bool)
+    A[4:8, 4:8] = False
+    w = cfse.weighting(M, N, 0.8, A)
+    s = a * cfse.basis(F, M, N, k0, l0)
+    for gamma in (0.3, 0.5):
+        res = cfse.cfse(s, w, F, gamma, 10)
+        assert all(i == k0 * F + l0 for i in res["seq"])
+        acc = np.cumsum(res["chat"])
+        for nu in range(10):
+            assert abs(acc[nu] - a * (1 - (1 - gamma) ** (nu + 1))) < 1e-12 * abs(a)
+    res = cfse.cfse(s, w, F, 1.0, 1)
+    np.testing.assert_allclose(res["g"], s, atol=1e-12 * abs(a))
+
+
+def test_real_cosine_picks_lower_conjugate():
+    """A real cosine has two conjugate projections of equal size; the tie
+    goes to the lower linear index, and the second pick is its partner."""
+    F, M, N = 16, 12, 12
+    A = np.ones((M, N), dtype=bool)
+    A[4:8, 4:8] = False
+    w = cfse.weighting(M, N, 0.8, A)
+    k0, l0 = 13, 2                       # partner (3, 14) has the lower index
+    s = 50.0 * cfse.basis(F, M, N, k0, l0).real
+    res = cfse.cfse(s, w, F, 0.5, 2)
+    lo = min(k0 * F + l0, ((-k0) % F) * F + (-l0) % F)
+    hi = max(k0 * F + l0, ((-k0) % F) * F + (-l0) % F)
+    assert res["seq"][0] == lo
+    assert res["gap"][0] < 1e-12
+
+
+def test_placement_covariance():
+    """Moving the area by (a, b) inside the transform grid multiplies every
+    projection by the unit phase exp(-j2pi(ka+lb)/F): same selections, same
+    model on the area, coefficients rotated by that phase."""
+    s, w, F = _patch(seed=2)
+    base = cfse.cfse(s, w, F, 0.5, 25)
+    a, b = 3, 2
+    moved = cfse.cfse(s, w, F, 0.5, 25, offset=(a, b))
+    assert moved["seq"] == base["seq"]
+    for idx, c0, c1 in zip(base["seq"], base["chat"], moved["chat"]):
+        u, v = divmod(idx, F)
+        assert abs(c1 - c0 * cmath.exp(-2j * math.pi * (u * a + v * b) / F)) < 1e-10 * abs(c0)
+    np.testing.assert_allclose(moved["g"], base["g"], atol=1e-9)
+
+
+def test_homogeneity():
+    """Scaling the signal scales every coefficient and keeps the selections."""
+    s, w, F = _patch(seed=4)
+    base = cfse.cfse(s, w, F, 0.5, 20)
+    scaled = cfse.cfse(-2.5 * s, w, F, 0.5, 20)
+    assert scaled["seq"] == base["seq"]
+    np.testing.assert_allclose(scaled["chat"], -2.5 * np.array(base["chat"]), rtol=1e-11)
+
+
+def test_degenerate_cases():
+    """gamma = 0 and I = 0 leave the model at zero; rho = 1 makes w the
+    indicator of A; an empty support is an error."""
+    s, w, F = _patch(seed=6)
+    res = cfse.cfse(s, w, F, 0.0, 5)
+    assert np.all(np.array(res["chat"]) == 0) and np.all(res["g"] == 0)
+    res = cfse.cfse(s, w, F, 0.5, 0)
+    assert res["seq"] == [] and np.all(res["g"] == 0)
+    A = w > 0
+    assert np.array_equal(cfse.weighting(*A.shape, 1.0, A), A.astype(float))
+    with pytest.raises(ValueError):
+        cfse.cfse(s, np.zeros_like(w), F, 0.5, 1)
+
+
+def test_window_spectrum_properties():
+    """W = DFT(w) (eq. (11)): W[0,0] = sum(w) is the denominator of eq. (9),
+    and W[-k,-l] = conj(W[k,l]) for real w."""
+    s, w, F = _patch(seed=7)
+    M, N = w.shape
+    Wf = cfse.project(w, cfse.analysis_matrix(F, M), cfse.analysis_matrix(F, N))
+    assert abs(Wf[0, 0] - w.sum()) < 1e-12 * w.sum()
+    idx = (-np.arange(F)) % F
+    np.testing.assert_allclose(Wf[np.ix_(idx, idx)], np.conj(Wf), atol=1e-11)
+
+
+def test_independence_from_outside_area():
+    """A block's result depends only on its own area: changing pixels outside
+    it, or lost pixels inside it, changes nothing."""
+    from synth import workloads
+    wl = workloads.isolated_256()
+    blk = wl.blocks[27]
+    base = cfse.extrapolate_block(wl.frames, wl.avail, blk, 0.8, 0.5, iters=30)
+    frames = wl.frames.copy()
+    frames[0, :int(blk["y0"]) - 17, :] = 7                 # outside the area
+    frames[wl.avail == 0] = 255                             # every lost pixel
+    other = cfse.extrapolate_block(frames, wl.avail, blk, 0.8, 0.5, iters=30)
+    assert other["seq"] == base["seq"]
+    np.testing.assert_array_equal(other["values"], base["values"])
+
+
+# --------------------------------------------------------------- eq. (18)
+
+def test_frequency_domain_update_matches_projection():
+    """eq. (18) is eq. (17) followed by eq. (7): Algorithm 1 in the Fourier
+    domain, forced along the oracle's selections, reproduces the oracle's
+    coefficients and model (FP64, relative 1e-10)."""
+    from synth import workloads
+    wl = workloads.isolated_256()
+    for bi in (0, 9, 36, 63):
+        blk = wl.blocks[bi]
+        s, A, B = cfse.area_of_block(wl.frames, wl.avail, blk)
+        w = cfse.weighting(*s.shape, 0.8, A)
+        res = cfse.cfse(s, w, 64, 0.5, 100)
+        seq, chat, g = alg1.cfse_fft(s, w, 64, 0.5, 100, forced=res["seq"])
+        d = np.array(chat) - np.array(res["chat"])
+        assert np.linalg.norm(d) <= 1e-10 * np.linalg.norm(res["chat"])
+        np.testing.assert_allclose(g, res["g"], atol=1e-9)
+        # free-running: the same tie rule gives the same selections
+        seq_free, _, _ = alg1.cfse_fft(s, w, 64, 0.5, 100)
+        assert seq_free == res["seq"]
