@@ -1,0 +1,157 @@
+/*
+ * fse.h - C ABI of the MI355X (gfx950) complex-valued Frequency Selective
+ * Extrapolation library (libfse.so).
+ *
+ * The library conceals lost rectangular blocks of 8-bit frames. For every
+ * lost block B it cuts the extrapolation area L = A u B (B grown by `border`
+ * pixels on each side; Seiler & Kaup, Section II and Fig. 1), weights the
+ * received pixels with the isotropic window of eq. (3), and runs the
+ * frequency-domain cFSE iteration of Section III / Algorithm 1:
+ *   R_w = DFT(s*w), W = DFT(w)                          (eq. (11))
+ *   repeat I times:
+ *     (u,v) = argmax |R_w[k,l]|^2, lowest k*F+l on ties  (eq. (12))
+ *     c = gamma * R_w[u,v] / W[0,0]                      (eq. (13))
+ *     G[u,v] += F*F*c                                     (eq. (15))
+ *     R_w[k,l] -= c * W[(k-u) mod F, (l-v) mod F]  all k,l (eq. (18))
+ *   g = IDFT(G); B <- Re{g}                               (Algorithm 1)
+ * on an F x F zero-padded transform grid (F in {32, 64, 128}; the paper uses
+ * a 48x48 area in a 64x64 transform, Section IV).
+ *
+ * Conventions used by every entry point:
+ *  - Pointers prefixed d_ are device memory on the current HIP device and
+ *    are owned by the caller; h_ pointers are host memory owned by the
+ *    caller. The library never frees caller memory.
+ *  - Frames are row-major uint8 [n_frames][H][pitch]; the availability mask
+ *    has the same layout (nonzero = received, 0 = lost). The output is
+ *    float32 [n_frames][H][out_pitch]; only pixels of the blocks' B regions
+ *    are written, everything else is left untouched.
+ *  - Inside the area, pixels outside the frame, lost pixels (mask 0) and B
+ *    itself carry zero weight; blocks are therefore independent.
+ *  - Errors found on the host are returned before anything is launched.
+ *    Launch-time HIP errors return FSE_ERR_HIP. Per-block conditions are
+ *    written to d_status once the stream reaches them.
+ *  - Entry points are thread-safe for distinct handles. One batch handle
+ *    must not run on two streams at once (its work queue is shared).
+ */
+#ifndef FSE_H_
+#define FSE_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FSE_OK = 0,
+  FSE_ERR_INVALID_ARG = -1,  /* null pointer, bad size, bad parameter        */
+  FSE_ERR_UNSUPPORTED = -2,  /* F not in {32,64,128}, area larger than F ... */
+  FSE_ERR_OOM = -3,          /* device or host allocation failed             */
+  FSE_ERR_HIP = -4,          /* a HIP runtime call failed                    */
+  FSE_ERR_OVERLAP = -5       /* two blocks' loss areas B overlap             */
+} fse_status_t;
+
+/* Per-block result codes written to d_status[i] for block i. */
+enum {
+  FSE_BLOCK_OK = 0,
+  FSE_BLOCK_EMPTY_SUPPORT = 1, /* W[0,0] == 0: no received pixel; B untouched */
+  FSE_BLOCK_NONFINITE = 2      /* a coefficient was not finite; B untouched   */
+};
+
+/* One lost block: B is the bh x bw rectangle with top-left (y0, x0) in frame
+ * `frame`; its area extends `border` pixels beyond B on every side, so the
+ * area is M x N = (bh + 2*border) x (bw + 2*border) and must fit the
+ * transform: M <= fft and N <= fft. `iters` is the iteration count I.
+ * 24 bytes, natural alignment. */
+typedef struct {
+  int32_t frame;
+  int32_t y0, x0;
+  int16_t bh, bw;
+  int16_t border;
+  int16_t fft;
+  int32_t iters;
+} fse_block_t;
+
+/* Plan parameters shared by every block run with the plan. */
+typedef struct {
+  float rho;          /* window decay rho in (0, 1], eq. (3)                  */
+  float gamma;        /* orthogonality deficiency compensation, [0, 1], eq. (13) */
+  int32_t max_iters;  /* largest per-block iteration count accepted (<= 4096) */
+  uint32_t flags;     /* reserved, must be 0                                  */
+} fse_plan_desc_t;
+
+/* One record per block and iteration when tracing: selected bin (u, v),
+ * coefficient c of eq. (13) and |R_w[u,v]|^2 as seen by the argmax. */
+typedef struct {
+  uint16_t u, v;
+  float c_re, c_im;
+  float r2;
+} fse_trace_t;
+
+typedef struct fse_plan_s* fse_plan_t;
+typedef struct fse_batch_s* fse_batch_t;
+
+/* Create a plan: validates the descriptor and builds the window table
+ * rho^(distance) (eq. (3)) and the DFT twiddle tables in FP64 on the host,
+ * rounded to FP32. Host-only: no device memory is touched until the first
+ * batch is created. Returns FSE_ERR_INVALID_ARG for rho outside (0,1], gamma
+ * outside [0,1], max_iters outside [0,4096], nonzero flags or null pointers. */
+fse_status_t fse_plan_create(const fse_plan_desc_t* desc, fse_plan_t* out_plan);
+
+/* Destroy a plan and the device tables it uploaded. Batches created from it
+ * must be destroyed first. Null is ignored. */
+void fse_plan_destroy(fse_plan_t plan);
+
+/* Host-only check of a block list against frames of n_frames x H x W:
+ * fft in {32,64,128}; bh, bw >= 1; border >= 0; M, N <= fft; 0 <= iters <=
+ * max_iters; frame in range; B inside the frame; no two B overlapping.
+ * Returns FSE_OK, FSE_ERR_UNSUPPORTED, FSE_ERR_OVERLAP or
+ * FSE_ERR_INVALID_ARG. *bad_index (if not null) receives the first offending
+ * block index, or -1. */
+fse_status_t fse_validate_blocks(fse_plan_t plan, const fse_block_t* h_blocks, int32_t n_blocks,
+                                 int32_t n_frames, int32_t H, int32_t W, int32_t* bad_index);
+
+/* Prepare a batch: validates h_blocks (as fse_validate_blocks), groups the
+ * blocks by transform size, orders each group longest-first by F*F*I,
+ * uploads descriptors, the schedule and the plan tables to the current
+ * device and allocates the work-queue counters. Synchronous. After this
+ * call h_blocks may be freed. */
+fse_status_t fse_batch_create(fse_plan_t plan, const fse_block_t* h_blocks, int32_t n_blocks,
+                              int32_t n_frames, int32_t H, int32_t W, fse_batch_t* out_batch);
+
+/* Release a batch's device memory. Synchronises the device. Null is ignored. */
+void fse_batch_destroy(fse_batch_t batch);
+
+/* Largest iteration count among the batch's blocks (the trace stride). */
+int32_t fse_batch_max_iters(fse_batch_t batch);
+
+/* Run cFSE on every block of the batch: kernel launches only, on `stream`
+ * (a hipStream_t; null = default stream), asynchronous, no allocation and no
+ * host-device copies, so the call may be captured into a HIP graph.
+ *   d_image, d_avail : uint8 [n_frames][H][pitch] (pitch >= W, in bytes)
+ *   d_out            : float32 [n_frames][H][out_pitch]; B pixels written
+ *   d_status         : int32 [n_blocks], FSE_BLOCK_* per block (required)
+ *   d_trace          : null, or fse_trace_t [n_blocks][fse_batch_max_iters]
+ *                      receiving every block's selections in order
+ * Block i of the list given to fse_batch_create writes d_status[i] and
+ * trace row i. Results do not depend on the other blocks of the batch. */
+fse_status_t fse_extrapolate_batch(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail,
+                                   int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
+                                   fse_trace_t* d_trace, void* stream);
+
+/* Launch configuration chosen for transform size F (32, 64 or 128): threads
+ * per workgroup, workgroups resident per CU, persistent grid size and the
+ * dynamic LDS bytes per workgroup. Valid after fse_batch_create; returns
+ * FSE_ERR_INVALID_ARG if the batch has no block of that size. */
+fse_status_t fse_batch_launch_info(fse_batch_t batch, int32_t F, int32_t* threads, int32_t* wg_per_cu,
+                                   int32_t* grid, int32_t* lds_bytes);
+
+/* Static description of the most recent error on this thread (never null). */
+const char* fse_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSE_H_ */

@@ -1,0 +1,58 @@
+"""ctypes declarations of the C ABI in include/fse.h."""
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfse.so")
+
+
+class fse_block_t(C.Structure):
+    _fields_ = [("frame", C.c_int32), ("y0", C.c_int32), ("x0", C.c_int32),
+                ("bh", C.c_int16), ("bw", C.c_int16), ("border", C.c_int16),
+                ("fft", C.c_int16), ("iters", C.c_int32)]
+
+
+class fse_plan_desc_t(C.Structure):
+    _fields_ = [("rho", C.c_float), ("gamma", C.c_float), ("max_iters", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+class fse_trace_t(C.Structure):
+    _fields_ = [("u", C.c_uint16), ("v", C.c_uint16), ("c_re", C.c_float),
+                ("c_im", C.c_float), ("r2", C.c_float)]
+
+
+P = C.c_void_p
+I32 = C.c_int32
+I64 = C.c_int64
+PI32 = C.POINTER(C.c_int32)
+
+# name -> (restype, argtypes); every function declared in include/fse.h
+SIGNATURES = {
+    "fse_plan_create": (I32, [C.POINTER(fse_plan_desc_t), C.POINTER(P)]),
+    "fse_plan_destroy": (None, [P]),
+    "fse_validate_blocks": (I32, [P, P, I32, I32, I32, I32, PI32]),
+    "fse_batch_create": (I32, [P, P, I32, I32, I32, I32, C.POINTER(P)]),
+    "fse_batch_destroy": (None, [P]),
+    "fse_batch_max_iters": (I32, [P]),
+    "fse_extrapolate_batch": (I32, [P, P, P, I64, P, I64, P, P, P]),
+    "fse_batch_launch_info": (I32, [P, I32, PI32, PI32, PI32, PI32]),
+    "fse_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libfse.so (built in-tree by paper_2204_14193_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2204_14193_amd.build` (there is no CPU fallback)")
+        h = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(h, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = h
+    return _lib

@@ -1,0 +1,338 @@
+// Host side of the C ABI declared in include/fse.h: parameter checks, the
+// FP64 window and twiddle tables, block validation and scheduling, device
+// memory of a batch, and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "fse.h"
+#include "fse_internal.h"
+
+namespace {
+
+thread_local const char* g_error = "no error";
+
+fse_status_t fail(fse_status_t code, const char* msg) {
+  g_error = msg;
+  return code;
+}
+
+constexpr int kSizes[3] = {128, 64, 32};  // class order: longest blocks first
+
+int class_of(int F) {
+  for (int c = 0; c < 3; ++c)
+    if (kSizes[c] == F) return c;
+  return -1;
+}
+
+struct DeviceTables {
+  float* wtab = nullptr;          // kWinStride^2 floats
+  float2* twid[3] = {nullptr, nullptr, nullptr};
+};
+
+}  // namespace
+
+struct fse_plan_s {
+  float rho = 0.f, gamma = 0.f;
+  int32_t max_iters = 0;
+  std::vector<float> wtab;                 // host copy, FP64-computed
+  std::vector<float2> twid[3];             // per class
+  std::mutex mu;
+  std::map<int, DeviceTables> dev;         // uploaded tables per device
+};
+
+struct fse_batch_s {
+  fse_plan_t plan = nullptr;
+  int device = 0;
+  int32_t n = 0, n_frames = 0, H = 0, W = 0;
+  int32_t max_iters = 0;
+  fse_block_t* d_blocks = nullptr;
+  int32_t* d_orig = nullptr;
+  int32_t* d_queue = nullptr;              // 3 classes x 32 ints (own cache lines)
+  const DeviceTables* tables = nullptr;
+  struct Cls {
+    const fse::Variant* v = nullptr;
+    int32_t offset = 0, count = 0, iters_cap = 0;
+    int32_t grid = 0, wg_per_cu = 0;
+    size_t lds = 0;
+  } cls[3];
+};
+
+extern "C" const char* fse_last_error(void) { return g_error; }
+
+extern "C" fse_status_t fse_plan_create(const fse_plan_desc_t* desc, fse_plan_t* out_plan) {
+  if (!desc || !out_plan) return fail(FSE_ERR_INVALID_ARG, "null argument");
+  *out_plan = nullptr;
+  if (!(desc->rho > 0.f && desc->rho <= 1.f)) return fail(FSE_ERR_INVALID_ARG, "rho must lie in (0, 1]");
+  if (!(desc->gamma >= 0.f && desc->gamma <= 1.f)) return fail(FSE_ERR_INVALID_ARG, "gamma must lie in [0, 1]");
+  if (desc->max_iters < 0 || desc->max_iters > fse::kMaxIters)
+    return fail(FSE_ERR_INVALID_ARG, "max_iters must lie in [0, 4096]");
+  if (desc->flags != 0) return fail(FSE_ERR_INVALID_ARG, "flags must be 0");
+  fse_plan_s* p = new (std::nothrow) fse_plan_s;
+  if (!p) return fail(FSE_ERR_OOM, "host allocation failed");
+  p->rho = desc->rho;
+  p->gamma = desc->gamma;
+  p->max_iters = desc->max_iters;
+  // eq. (3): rho^distance, distance = sqrt(a^2 + b^2) / 2 for doubled offsets
+  const int S = fse::kWinStride;
+  p->wtab.resize((size_t)S * S);
+  const double rho = (double)desc->rho;
+  for (int a = 0; a < S; ++a)
+    for (int b = 0; b < S; ++b)
+      p->wtab[(size_t)a * S + b] = (float)std::pow(rho, 0.5 * std::sqrt((double)a * a + (double)b * b));
+  for (int c = 0; c < 3; ++c) {
+    const int F = kSizes[c];
+    p->twid[c].resize(F);
+    for (int q = 0; q < F; ++q) {
+      const double ang = -2.0 * M_PI * (double)q / (double)F;
+      p->twid[c][q] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    // exact values at the quarter points keep real-input symmetry exact
+    p->twid[c][0] = make_float2(1.f, 0.f);
+    p->twid[c][F / 4] = make_float2(0.f, -1.f);
+    p->twid[c][F / 2] = make_float2(-1.f, 0.f);
+    p->twid[c][3 * F / 4] = make_float2(0.f, 1.f);
+  }
+  *out_plan = p;
+  return FSE_OK;
+}
+
+extern "C" void fse_plan_destroy(fse_plan_t plan) {
+  if (!plan) return;
+  if (!plan->dev.empty()) {  // a plan that never reached a GPU makes no HIP call
+    int cur = 0;
+    const bool have = hipGetDevice(&cur) == hipSuccess;
+    for (auto& kv : plan->dev) {
+      if (hipSetDevice(kv.first) != hipSuccess) continue;
+      (void)hipFree(kv.second.wtab);
+      for (auto* t : kv.second.twid) (void)hipFree(t);
+    }
+    if (have) (void)hipSetDevice(cur);
+  }
+  delete plan;
+}
+
+extern "C" fse_status_t fse_validate_blocks(fse_plan_t plan, const fse_block_t* h_blocks, int32_t n_blocks,
+                                            int32_t n_frames, int32_t H, int32_t W, int32_t* bad_index) {
+  if (bad_index) *bad_index = -1;
+  if (!plan) return fail(FSE_ERR_INVALID_ARG, "null plan");
+  if (n_blocks < 0 || (n_blocks > 0 && !h_blocks)) return fail(FSE_ERR_INVALID_ARG, "bad block list");
+  if (n_frames <= 0 || H <= 0 || W <= 0) return fail(FSE_ERR_INVALID_ARG, "frame dimensions must be positive");
+  for (int32_t i = 0; i < n_blocks; ++i) {
+    const fse_block_t& b = h_blocks[i];
+    if (bad_index) *bad_index = i;
+    if (class_of(b.fft) < 0) return fail(FSE_ERR_UNSUPPORTED, "fft must be 32, 64 or 128");
+    if (b.bh < 1 || b.bw < 1 || b.border < 0) return fail(FSE_ERR_INVALID_ARG, "block size must be >= 1, border >= 0");
+    if (b.bh + 2 * b.border > b.fft || b.bw + 2 * b.border > b.fft)
+      return fail(FSE_ERR_UNSUPPORTED, "area larger than the transform");
+    if (b.iters < 0 || b.iters > plan->max_iters) return fail(FSE_ERR_INVALID_ARG, "iters outside [0, max_iters]");
+    if (b.frame < 0 || b.frame >= n_frames) return fail(FSE_ERR_INVALID_ARG, "frame index out of range");
+    if (b.y0 < 0 || b.x0 < 0 || (int64_t)b.y0 + b.bh > H || (int64_t)b.x0 + b.bw > W)
+      return fail(FSE_ERR_INVALID_ARG, "lost block outside the frame");
+  }
+  // overlap of loss areas: one bit per pixel
+  const size_t npix = (size_t)n_frames * H * W;
+  std::vector<uint64_t> bits((npix + 63) / 64, 0);
+  for (int32_t i = 0; i < n_blocks; ++i) {
+    const fse_block_t& b = h_blocks[i];
+    for (int y = b.y0; y < b.y0 + b.bh; ++y) {
+      for (int x = b.x0; x < b.x0 + b.bw; ++x) {
+        const size_t p = ((size_t)b.frame * H + y) * W + x;
+        const uint64_t m = 1ull << (p & 63);
+        if (bits[p >> 6] & m) {
+          if (bad_index) *bad_index = i;
+          return fail(FSE_ERR_OVERLAP, "loss areas of two blocks overlap");
+        }
+        bits[p >> 6] |= m;
+      }
+    }
+  }
+  if (bad_index) *bad_index = -1;
+  return FSE_OK;
+}
+
+namespace {
+
+fse_status_t upload_tables(fse_plan_t plan, int device, const DeviceTables** out) {
+  std::lock_guard<std::mutex> lock(plan->mu);
+  auto it = plan->dev.find(device);
+  if (it != plan->dev.end()) {
+    *out = &it->second;
+    return FSE_OK;
+  }
+  DeviceTables t;
+  const size_t wbytes = plan->wtab.size() * sizeof(float);
+  if (hipMalloc(&t.wtab, wbytes) != hipSuccess) return fail(FSE_ERR_OOM, "hipMalloc failed (window table)");
+  if (hipMemcpy(t.wtab, plan->wtab.data(), wbytes, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(FSE_ERR_HIP, "hipMemcpy failed (window table)");
+  for (int c = 0; c < 3; ++c) {
+    const size_t b = plan->twid[c].size() * sizeof(float2);
+    if (hipMalloc(&t.twid[c], b) != hipSuccess) return fail(FSE_ERR_OOM, "hipMalloc failed (twiddles)");
+    if (hipMemcpy(t.twid[c], plan->twid[c].data(), b, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(FSE_ERR_HIP, "hipMemcpy failed (twiddles)");
+  }
+  auto res = plan->dev.emplace(device, t);
+  *out = &res.first->second;
+  return FSE_OK;
+}
+
+void free_batch(fse_batch_s* b) {
+  (void)hipFree(b->d_blocks);
+  (void)hipFree(b->d_orig);
+  (void)hipFree(b->d_queue);
+  delete b;
+}
+
+}  // namespace
+
+extern "C" fse_status_t fse_batch_create(fse_plan_t plan, const fse_block_t* h_blocks, int32_t n_blocks,
+                                         int32_t n_frames, int32_t H, int32_t W, fse_batch_t* out_batch) {
+  if (!out_batch) return fail(FSE_ERR_INVALID_ARG, "null argument");
+  *out_batch = nullptr;
+  fse_status_t st = fse_validate_blocks(plan, h_blocks, n_blocks, n_frames, H, W, nullptr);
+  if (st != FSE_OK) return st;
+  fse_batch_s* b = new (std::nothrow) fse_batch_s;
+  if (!b) return fail(FSE_ERR_OOM, "host allocation failed");
+  b->plan = plan;
+  b->n = n_blocks;
+  b->n_frames = n_frames;
+  b->H = H;
+  b->W = W;
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    delete b;
+    return fail(FSE_ERR_HIP, "hipGetDevice failed");
+  }
+  // group by transform size (largest first), longest-running block first
+  std::vector<int32_t> order(n_blocks);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    const int cx = class_of(h_blocks[x].fft), cy = class_of(h_blocks[y].fft);
+    if (cx != cy) return cx < cy;
+    return h_blocks[x].iters > h_blocks[y].iters;
+  });
+  std::vector<fse_block_t> sorted(n_blocks);
+  for (int32_t i = 0; i < n_blocks; ++i) {
+    sorted[i] = h_blocks[order[i]];
+    b->max_iters = std::max(b->max_iters, (int32_t)h_blocks[order[i]].iters);
+    fse_batch_s::Cls& c = b->cls[class_of(sorted[i].fft)];
+    if (c.count == 0) c.offset = i;
+    c.count++;
+    c.iters_cap = std::max(c.iters_cap, (int32_t)sorted[i].iters);
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) {
+    delete b;
+    return fail(FSE_ERR_HIP, "hipGetDeviceProperties failed");
+  }
+  for (int ci = 0; ci < 3; ++ci) {
+    fse_batch_s::Cls& c = b->cls[ci];
+    if (c.count == 0) continue;
+    c.v = fse::variant_for(kSizes[ci]);
+    if (!c.v) {
+      delete b;
+      return fail(FSE_ERR_UNSUPPORTED, "no kernel for this transform size");
+    }
+    c.lds = fse::lds_bytes(*c.v, c.iters_cap);
+    if (hipFuncSetAttribute(c.v->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds) != hipSuccess) {
+      delete b;
+      return fail(FSE_ERR_HIP, "hipFuncSetAttribute failed (LDS size)");
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c.v->fn, c.v->threads, c.lds) != hipSuccess ||
+        per_cu < 1) {
+      delete b;
+      return fail(FSE_ERR_UNSUPPORTED, "kernel does not fit on a compute unit (iteration count too large)");
+    }
+    c.wg_per_cu = per_cu;
+    c.grid = std::min<int64_t>(c.count, (int64_t)per_cu * prop.multiProcessorCount);
+  }
+  st = upload_tables(plan, b->device, &b->tables);
+  if (st != FSE_OK) {
+    delete b;
+    return st;
+  }
+  const size_t nb = (size_t)std::max(n_blocks, 1);
+  if (hipMalloc(&b->d_blocks, nb * sizeof(fse_block_t)) != hipSuccess ||
+      hipMalloc(&b->d_orig, nb * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&b->d_queue, 3 * 32 * sizeof(int32_t)) != hipSuccess) {
+    free_batch(b);
+    return fail(FSE_ERR_OOM, "hipMalloc failed (batch)");
+  }
+  if ((n_blocks > 0 &&
+       (hipMemcpy(b->d_blocks, sorted.data(), n_blocks * sizeof(fse_block_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_orig, order.data(), n_blocks * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)) ||
+      hipMemset(b->d_queue, 0, 3 * 32 * sizeof(int32_t)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    free_batch(b);
+    return fail(FSE_ERR_HIP, "upload of the batch failed");
+  }
+  *out_batch = b;
+  return FSE_OK;
+}
+
+extern "C" void fse_batch_destroy(fse_batch_t batch) {
+  if (!batch) return;
+  (void)hipDeviceSynchronize();
+  free_batch(batch);
+}
+
+extern "C" int32_t fse_batch_max_iters(fse_batch_t batch) { return batch ? batch->max_iters : 0; }
+
+extern "C" fse_status_t fse_batch_launch_info(fse_batch_t batch, int32_t F, int32_t* threads, int32_t* wg_per_cu,
+                                              int32_t* grid, int32_t* lds_bytes) {
+  if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
+  const int ci = class_of(F);
+  if (ci < 0 || batch->cls[ci].count == 0) return fail(FSE_ERR_INVALID_ARG, "no block of this transform size");
+  const fse_batch_s::Cls& c = batch->cls[ci];
+  if (threads) *threads = c.v->threads;
+  if (wg_per_cu) *wg_per_cu = c.wg_per_cu;
+  if (grid) *grid = c.grid;
+  if (lds_bytes) *lds_bytes = (int32_t)c.lds;
+  return FSE_OK;
+}
+
+extern "C" fse_status_t fse_extrapolate_batch(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail,
+                                              int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
+                                              fse_trace_t* d_trace, void* stream) {
+  if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
+  if (batch->n == 0) return FSE_OK;
+  if (!d_image || !d_avail || !d_out || !d_status) return fail(FSE_ERR_INVALID_ARG, "null device pointer");
+  if (pitch < batch->W || out_pitch < batch->W) return fail(FSE_ERR_INVALID_ARG, "pitch smaller than the width");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != batch->device)
+    return fail(FSE_ERR_INVALID_ARG, "batch was created on another device");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (int ci = 0; ci < 3; ++ci) {
+    const fse_batch_s::Cls& c = batch->cls[ci];
+    if (c.count == 0) continue;
+    fse::ClassArgs a;
+    a.img = d_image;
+    a.avail = d_avail;
+    a.pitch = pitch;
+    a.out = d_out;
+    a.out_pitch = out_pitch;
+    a.H = batch->H;
+    a.W = batch->W;
+    a.blocks = batch->d_blocks + c.offset;
+    a.orig = batch->d_orig + c.offset;
+    a.n = c.count;
+    a.iters_cap = c.iters_cap;
+    a.status = d_status;
+    a.trace = d_trace;
+    a.trace_stride = batch->max_iters;
+    a.wtab = batch->tables->wtab;
+    a.twid = batch->tables->twid[ci];
+    a.gamma = batch->plan->gamma;
+    a.queue = batch->d_queue + 32 * ci;
+    if (fse::launch_class(*c.v, a, c.grid, c.lds, s) != hipSuccess)
+      return fail(FSE_ERR_HIP, "kernel launch failed");
+  }
+  return FSE_OK;
+}

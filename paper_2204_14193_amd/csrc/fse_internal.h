@@ -1,0 +1,57 @@
+// Internal interface between the host API (fse_api.cpp) and the device code
+// (fse_kernels.hip). Not installed; not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fse.h"
+
+namespace fse {
+
+// Window table: wtab[a * kWinStride + b] = rho^(sqrt(a*a + b*b) / 2) for
+// a = |2m - (M-1)|, b = |2n - (N-1)|, i.e. rho^distance-to-area-centre
+// (eq. (3)) indexed by doubled integer offsets; a, b < kWinStride.
+constexpr int kWinStride = 128;
+constexpr int kMaxIters = 4096;
+
+// Arguments of one launch over the blocks of a single transform size.
+struct ClassArgs {
+  const uint8_t* img;      // [n_frames][H][pitch]
+  const uint8_t* avail;    // [n_frames][H][pitch]
+  int64_t pitch;
+  float* out;              // [n_frames][H][out_pitch]
+  int64_t out_pitch;
+  int32_t H, W;
+  const fse_block_t* blocks;  // this class's blocks, longest first
+  const int32_t* orig;        // index of each block in the caller's list
+  int32_t n;                  // number of blocks in the class
+  int32_t iters_cap;          // largest iteration count in the class
+  int32_t* status;            // [caller's n_blocks]
+  fse_trace_t* trace;         // null or [caller's n_blocks][trace_stride]
+  int32_t trace_stride;
+  const float* wtab;          // window table (see kWinStride)
+  const float2* twid;         // F entries: exp(-j 2 pi q / F)
+  float gamma;
+  int32_t* queue;             // [2]: next block, finished workgroups
+};
+
+// One compiled kernel variant for transform size F.
+struct Variant {
+  int F;
+  int threads;         // workgroup size
+  bool dup;            // window spectrum stored twice (rows 0..2F-1)
+  const void* fn;      // kernel symbol
+};
+
+// Kernel variant used for transform size F (32, 64, 128), or null.
+const Variant* variant_for(int F);
+
+// Dynamic LDS bytes a variant needs for a class whose largest iteration
+// count is iters_cap.
+size_t lds_bytes(const Variant& v, int iters_cap);
+
+// Launch one class; grid = number of persistent workgroups.
+hipError_t launch_class(const Variant& v, const ClassArgs& a, int grid, size_t lds, hipStream_t s);
+
+}  // namespace fse

@@ -1,0 +1,450 @@
+// Persistent complex-valued FSE kernels for gfx950 (CDNA4, wave64).
+//
+// One workgroup conceals one lost block at a time and pulls the next block
+// from a work queue until the class is exhausted. Per block:
+//   1. gather the M x N area from HBM, weight it with the window of eq. (3)
+//      on the support area A (zero on B, on lost pixels and off-frame);
+//   2. one complex F x F FFT of z = s*w + j*alpha*w in LDS (eq. (11)), split
+//      by conjugate symmetry into R_w = DFT(s*w) and W = DFT(w);
+//   3. I iterations of Algorithm 1: argmax of |R_w|^2 (eq. (12), lowest
+//      linear index k*F+l on ties), c = gamma*R_w[u,v]/W[0,0] (eq. (13)),
+//      append (u,v,c) to the model (eq. (15)), R_w -= c*W shifted by (u,v)
+//      over all bins (eq. (18)) fused with the next argmax;
+//   4. the model is evaluated on B only, Re{sum c*phi_(u,v)} (the inverse
+//      transform of G restricted to B), and written to HBM.
+//
+// Data placement: R_w lives in VGPRs (BPL bins per lane, bin j*NT + tid);
+// W lives in LDS, stored twice (rows 0..2F-1) when it fits so that the
+// cyclic row shift k-u becomes a compile-time offset; the wave argmax is a
+// DPP reduction, the cross-wave step one LDS exchange and one barrier.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fse_internal.h"
+
+namespace fse {
+namespace {
+
+// Scale of the window in the packed transform z = s*w + j*alpha*w: balances
+// the two real signals (s in [0,255]) so the conjugate-symmetric split keeps
+// W accurate; a power of two, so the scaling is exact.
+constexpr float kAlpha = 128.0f;
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_max(float x) {
+  const int moved = __builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), CTRL, ROW_MASK, 0xf, false);
+  return fmaxf(x, __int_as_float(moved));
+}
+
+// Maximum over the 64 lanes of a wave, returned as a wave-uniform value.
+__device__ __forceinline__ float wave_max(float x) {
+  x = dpp_max<0xb1, 0xf>(x);   // quad_perm [1,0,3,2]
+  x = dpp_max<0x4e, 0xf>(x);   // quad_perm [2,3,0,1]
+  x = dpp_max<0x141, 0xf>(x);  // row_half_mirror
+  x = dpp_max<0x140, 0xf>(x);  // row_mirror: every lane holds its row maximum
+  x = dpp_max<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x = dpp_max<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+__device__ __forceinline__ float readlane_f(float x, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+
+// ------------------------------------------------------------------ FFT
+// Forward DFT (exp(-j...)) of every row, then every column, of the F x F
+// buffer Z, as Stockham passes of radix 4 (plus one radix-2 pass when log2 F
+// is odd). Each pass loads its butterflies into registers, waits, and writes
+// the results back into the same buffer, so one F x F buffer suffices.
+
+template <int R>
+__device__ __forceinline__ void dft_small(float2 (&a)[R]) {
+  if constexpr (R == 2) {
+    const float2 t = a[0];
+    a[0] = cadd(t, a[1]);
+    a[1] = csub(t, a[1]);
+  } else {
+    const float2 t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+    const float2 t2 = cadd(a[1], a[3]), t3 = csub(a[1], a[3]);
+    a[0] = cadd(t0, t2);
+    a[2] = csub(t0, t2);
+    a[1] = make_float2(t1.x + t3.y, t1.y - t3.x);  // t1 - j*t3
+    a[3] = make_float2(t1.x - t3.y, t1.y + t3.x);  // t1 + j*t3
+  }
+}
+
+template <int F, int NT, int R, int NS, bool COLS>
+__device__ __forceinline__ void fft_pass(float2* Z, const float2* tw, int t) {
+  constexpr int L = F / R;           // butterflies per line
+  constexpr int PER = F * F / R / NT;  // butterflies per thread
+  static_assert(PER * R * NT == F * F, "pass does not tile the grid");
+  float2 v[PER][R];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int b = t + i * NT;
+    const int line = COLS ? (b % F) : (b / L);
+    const int j = COLS ? (b / F) : (b % L);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int e = j + r * L;
+      v[i][r] = COLS ? Z[e * F + line] : Z[line * F + e];
+    }
+    if constexpr (NS > 1) {
+      const int k = j % NS;
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[(r * k * (F / (NS * R))) & (F - 1)]);
+    }
+    dft_small<R>(v[i]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int b = t + i * NT;
+    const int line = COLS ? (b % F) : (b / L);
+    const int j = COLS ? (b / F) : (b % L);
+    const int o = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int e = o + r * NS;
+      if (COLS) Z[e * F + line] = v[i][r]; else Z[line * F + e] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int F, int NT, bool COLS>
+__device__ __forceinline__ void fft_lines(float2* Z, const float2* tw, int t) {
+  fft_pass<F, NT, 4, 1, COLS>(Z, tw, t);
+  fft_pass<F, NT, 4, 4, COLS>(Z, tw, t);
+  if constexpr (F == 32) {
+    fft_pass<F, NT, 2, 16, COLS>(Z, tw, t);
+  } else if constexpr (F == 64) {
+    fft_pass<F, NT, 4, 16, COLS>(Z, tw, t);
+  } else {
+    static_assert(F == 128, "unsupported transform size");
+    fft_pass<F, NT, 4, 16, COLS>(Z, tw, t);
+    fft_pass<F, NT, 2, 64, COLS>(Z, tw, t);
+  }
+}
+
+// ------------------------------------------------------------------ kernel
+
+template <int F, int NT, bool DUP>
+struct Shape {
+  static constexpr int BPL = F * F / NT;      // bins per lane
+  static constexpr int NW = NT / 64;          // waves per workgroup
+  static constexpr int ROWS = NT / F;         // rows covered by one bin slab
+  static constexpr int WROWS = DUP ? 2 * F : F;
+  static_assert(NT % F == 0 && NT % 64 == 0 && BPL * NT == F * F, "bad tiling");
+};
+
+// LDS carve-up of one workgroup (dynamic shared memory).
+struct Lds {
+  float2* Wd;      // WROWS x F: FFT buffer, then the window spectrum W
+  float2* tw;      // F twiddles exp(-j 2 pi q / F)
+  int4* red;       // 2 x NW cross-wave argmax slots (|R|^2 bits, index, re, im)
+  int* misc;       // [0]: block index popped from the queue
+  int* cl_idx;     // selections of the current block
+  float2* cl_c;    // coefficients of the current block
+};
+
+// Conceal one block with every lane of the workgroup. All values that steer
+// control flow (block geometry, W0, the selected bin) are wave-uniform, so
+// every branch below is taken by all lanes together. Returns FSE_BLOCK_*.
+template <int F, int NT, bool DUP>
+__device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, const Lds& s, const int t,
+                                             int& parity) {
+  using S = Shape<F, NT, DUP>;
+  constexpr int BPL = S::BPL, NW = S::NW, ROWS = S::ROWS;
+  const int lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int kt = t / F;  // row of this thread's first bin
+  const int lt = t % F;  // column of all of this thread's bins
+  float2* const Wd = s.Wd;
+
+  const fse_block_t bd = a.blocks[bi];
+  const int orig = a.orig[bi];
+  const int bh = bd.bh, bw = bd.bw, bo = bd.border;
+  const int M = bh + 2 * bo, N = bw + 2 * bo;
+  const int ya = bd.y0 - bo, xa = bd.x0 - bo;
+  const int I = bd.iters;
+  const int64_t fofs = (int64_t)bd.frame * a.H;
+  const uint8_t* img = a.img + fofs * a.pitch;
+  const uint8_t* av = a.avail + fofs * a.pitch;
+
+  // 1. gather and weight (eq. (3)); z = s*w + j*alpha*w on the F x F grid
+  for (int e = t; e < F * F; e += NT) {
+    const int m = e / F, n = e % F;
+    float2 z = make_float2(0.f, 0.f);
+    if (m < M && n < N) {
+      const int y = ya + m, x = xa + n;
+      const bool inB = (m >= bo) && (m < bo + bh) && (n >= bo) && (n < bo + bw);
+      if (!inB && y >= 0 && y < a.H && x >= 0 && x < a.W) {
+        const int64_t p = (int64_t)y * a.pitch + x;
+        if (av[p] != 0) {
+          const int da = abs(2 * m - (M - 1)), db = abs(2 * n - (N - 1));
+          const float w = a.wtab[da * kWinStride + db];
+          z = make_float2((float)img[p] * w, kAlpha * w);
+        }
+      }
+    }
+    Wd[e] = z;
+  }
+  __syncthreads();
+
+  // 2. forward transform (eq. (7) on the F x F grid)
+  fft_lines<F, NT, false>(Wd, s.tw, t);
+  fft_lines<F, NT, true>(Wd, s.tw, t);
+
+  // split Z = R_w + j*alpha*W by conjugate symmetry; R_w goes to VGPRs
+  float2 Rr[BPL];
+  float2 Wv[BPL];
+#pragma unroll
+  for (int j = 0; j < BPL; ++j) {
+    const int k = j * ROWS + kt, l = lt;
+    const float2 zk = Wd[k * F + l];
+    const float2 zn = Wd[((F - k) & (F - 1)) * F + ((F - l) & (F - 1))];
+    Rr[j] = make_float2((zk.x + zn.x) * 0.5f, (zk.y - zn.y) * 0.5f);
+    Wv[j] = make_float2((zk.y + zn.y) * (0.5f / kAlpha), (zn.x - zk.x) * (0.5f / kAlpha));
+  }
+  const float W0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(Wd[0].y))) * (1.0f / kAlpha);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < BPL; ++j) {
+    const int k = j * ROWS + kt;
+    Wd[k * F + lt] = Wv[j];
+    if constexpr (DUP) Wd[(k + F) * F + lt] = Wv[j];
+  }
+  __syncthreads();
+
+  if (!(W0 > 0.f)) return FSE_BLOCK_EMPTY_SUPPORT;  // no received pixel in the area
+  const float gW = a.gamma * (1.0f / W0);
+
+  // 3. iterations
+  float mg[BPL];
+#pragma unroll
+  for (int j = 0; j < BPL; ++j) mg[j] = fmaf(Rr[j].y, Rr[j].y, Rr[j].x * Rr[j].x);
+
+  int sel = 0;
+  float sre = 0.f, sim = 0.f, smag = 0.f;
+  // argmax of mg over the workgroup, lowest linear index j*NT + t on ties
+  auto select = [&]() {
+    float lm = mg[0];
+#pragma unroll
+    for (int j = 1; j < BPL; ++j) lm = fmaxf(lm, mg[j]);
+    const float wm = wave_max(lm);
+    int wj = 0, wl = 0;
+    float re = readlane_f(Rr[0].x, 0), im = readlane_f(Rr[0].y, 0);
+#pragma unroll
+    for (int j = 0; j < BPL; ++j) {
+      const unsigned long long msk = __ballot(mg[j] == wm);
+      if (msk) {
+        wl = __builtin_ctzll(msk);
+        wj = j;
+        re = readlane_f(Rr[j].x, wl);
+        im = readlane_f(Rr[j].y, wl);
+        break;
+      }
+    }
+    const int widx = wj * NT + wave * 64 + wl;
+    if constexpr (NW == 1) {
+      sel = widx; sre = re; sim = im; smag = wm;
+    } else {
+      int4* slot = s.red + parity * NW;
+      slot[wave] = make_int4(__float_as_int(wm), widx, __float_as_int(re), __float_as_int(im));  // uniform
+      __syncthreads();
+      // Every lane reads the same slots; the comparison runs on wave-uniform
+      // integers (|R|^2 >= 0, so its bit pattern orders like the value) and
+      // every field is selected explicitly.
+      const int4 s0 = slot[0];
+      unsigned bm = (unsigned)__builtin_amdgcn_readfirstlane(s0.x);
+      int bidx = __builtin_amdgcn_readfirstlane(s0.y);
+      int bre = __builtin_amdgcn_readfirstlane(s0.z);
+      int bim = __builtin_amdgcn_readfirstlane(s0.w);
+#pragma unroll
+      for (int w = 1; w < NW; ++w) {
+        const int4 o = slot[w];
+        const unsigned om = (unsigned)__builtin_amdgcn_readfirstlane(o.x);
+        const int oidx = __builtin_amdgcn_readfirstlane(o.y);
+        const int ore = __builtin_amdgcn_readfirstlane(o.z);
+        const int oim = __builtin_amdgcn_readfirstlane(o.w);
+        const bool take = (om > bm) || (om == bm && oidx < bidx);
+        bm = take ? om : bm;
+        bidx = take ? oidx : bidx;
+        bre = take ? ore : bre;
+        bim = take ? oim : bim;
+      }
+      parity ^= 1;
+      sel = bidx;
+      smag = __uint_as_float(bm);
+      sre = __int_as_float(bre);
+      sim = __int_as_float(bim);
+    }
+  };
+  select();
+
+  bool finite = true;
+  for (int it = 0; it < I; ++it) {
+    const float cre = gW * sre, cim = gW * sim;          // eq. (13)
+    finite = finite && isfinite(cre) && isfinite(cim);
+    // All lanes of wave 0 store the same uniform values: no lane-divergent
+    // region inside the loops (see the persistent loop below).
+    if (wave == 0) {
+      s.cl_idx[it] = sel;                                 // eq. (15): G[u,v] += F*F*c
+      s.cl_c[it] = make_float2(cre, cim);
+      if (a.trace) {
+        fse_trace_t rec;
+        rec.u = (uint16_t)(sel / F);
+        rec.v = (uint16_t)(sel % F);
+        rec.c_re = cre;
+        rec.c_im = cim;
+        rec.r2 = smag;
+        a.trace[(int64_t)orig * a.trace_stride + it] = rec;
+      }
+    }
+    if (it + 1 == I) break;
+    const int u = sel / F, v = sel % F;
+    const int col = (lt - v) & (F - 1);
+    // eq. (18): R_w[k,l] -= c * W[k-u, l-v], fused with |R_w|^2
+    if constexpr (DUP) {
+      const float2* wp = Wd + (kt - u + F) * F + col;
+#pragma unroll
+      for (int j = 0; j < BPL; ++j) {
+        const float2 w = wp[j * NT];
+        float2 r = Rr[j];
+        r.x = fmaf(-cre, w.x, r.x);
+        r.x = fmaf(cim, w.y, r.x);
+        r.y = fmaf(-cre, w.y, r.y);
+        r.y = fmaf(-cim, w.x, r.y);
+        Rr[j] = r;
+        mg[j] = fmaf(r.y, r.y, r.x * r.x);
+      }
+    } else {
+      static_assert(DUP || F >= 64, "single-copy layout needs wave-uniform rows");
+      const int k0 = __builtin_amdgcn_readfirstlane(kt);
+#pragma unroll
+      for (int j = 0; j < BPL; ++j) {
+        const int row = (j * ROWS + k0 - u) & (F - 1);
+        const float2 w = Wd[row * F + col];
+        float2 r = Rr[j];
+        r.x = fmaf(-cre, w.x, r.x);
+        r.x = fmaf(cim, w.y, r.x);
+        r.y = fmaf(-cre, w.y, r.y);
+        r.y = fmaf(-cim, w.x, r.y);
+        Rr[j] = r;
+        mg[j] = fmaf(r.y, r.y, r.x * r.x);
+      }
+    }
+    select();
+  }
+  __syncthreads();
+  if (!finite) return FSE_BLOCK_NONFINITE;
+
+  // 4. model on B: Re{ sum_nu c_nu exp(j 2 pi (u m + v n) / F) }
+  for (int p = t; p < bh * bw; p += NT) {
+    const int i = p / bw, jj = p % bw;
+    const int m = bo + i, n = bo + jj;
+    float acc = 0.f;
+    for (int it = 0; it < I; ++it) {
+      const int sidx = s.cl_idx[it];
+      const int q = ((sidx / F) * m + (sidx % F) * n) & (F - 1);
+      const float2 e = s.tw[q];  // exp(-j theta): Re{c e^{j theta}} = c.x e.x + c.y e.y
+      const float2 c = s.cl_c[it];
+      acc = fmaf(c.x, e.x, acc);
+      acc = fmaf(c.y, e.y, acc);
+    }
+    a.out[(fofs + bd.y0 + i) * a.out_pitch + bd.x0 + jj] = acc;
+  }
+  return FSE_BLOCK_OK;
+}
+
+template <int F, int NT, bool DUP>
+__global__ __launch_bounds__(NT) void fse_persistent(ClassArgs a) {
+  using S = Shape<F, NT, DUP>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  Lds s;
+  s.Wd = reinterpret_cast<float2*>(smem);
+  s.tw = s.Wd + S::WROWS * F;
+  s.red = reinterpret_cast<int4*>(s.tw + F);
+  s.misc = reinterpret_cast<int*>(s.red + 2 * S::NW);
+  s.cl_idx = s.misc + 4;
+  s.cl_c = reinterpret_cast<float2*>(s.cl_idx + ((a.iters_cap + 1) & ~1));
+
+  const int t = threadIdx.x;
+  for (int i = t; i < F; i += NT) s.tw[i] = a.twid[i];
+  int parity = 0;
+
+  // Persistent loop, one block per pass. The loop body contains no
+  // lane-divergent region: the queue is popped by the whole first wave with
+  // one lane adding 1 and the others 0, the result is made uniform with
+  // readfirstlane, and bookkeeping stores are done by every lane of wave 0
+  // with the same value. (A thread-0-only pop followed by a barrier is not
+  // safe in a single-wave workgroup: without a real barrier the compiler may
+  // let the other lanes run ahead into the next pass.)
+  const int lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  for (;;) {
+    int bi;
+    if constexpr (S::NW == 1) {
+      bi = __builtin_amdgcn_readfirstlane(atomicAdd(&a.queue[0], lane == 0 ? 1 : 0));
+    } else {
+      if (wave == 0) s.misc[0] = __builtin_amdgcn_readfirstlane(atomicAdd(&a.queue[0], lane == 0 ? 1 : 0));
+      __syncthreads();
+      bi = __builtin_amdgcn_readfirstlane(s.misc[0]);
+      __syncthreads();
+    }
+    if (bi >= a.n) break;
+    const int code = conceal_block<F, NT, DUP>(a, bi, s, t, parity);
+    if (wave == 0) a.status[a.orig[bi]] = code;
+  }
+
+  // the last workgroup to leave re-arms the queue for the next launch
+  if (wave == 0) {
+    __threadfence();
+    const int done = __builtin_amdgcn_readfirstlane(atomicAdd(&a.queue[1], lane == 0 ? 1 : 0));
+    if (done == (int)gridDim.x - 1 && lane == 0) {
+      atomicExch(&a.queue[0], 0);
+      atomicExch(&a.queue[1], 0);
+    }
+  }
+}
+
+template <int F, int NT, bool DUP>
+constexpr Variant make_variant() {
+  return Variant{F, NT, DUP, reinterpret_cast<const void*>(&fse_persistent<F, NT, DUP>)};
+}
+
+const Variant kVariants[] = {
+    make_variant<32, 64, true>(),
+    make_variant<64, 256, true>(),
+    make_variant<128, 1024, false>(),
+};
+
+}  // namespace
+
+const Variant* variant_for(int F) {
+  for (const Variant& v : kVariants)
+    if (v.F == F) return &v;
+  return nullptr;
+}
+
+size_t lds_bytes(const Variant& v, int iters_cap) {
+  const size_t F = (size_t)v.F;
+  const size_t rows = v.dup ? 2 * F : F;
+  const size_t nw = (size_t)v.threads / 64;
+  const size_t cap = (size_t)((iters_cap + 1) & ~1);
+  return rows * F * 8 + F * 8 + 2 * nw * 16 + 16 + cap * 4 + cap * 8;
+}
+
+hipError_t launch_class(const Variant& v, const ClassArgs& a, int grid, size_t lds, hipStream_t s) {
+  void* args[] = {const_cast<ClassArgs*>(&a)};
+  return hipLaunchKernel(v.fn, dim3(grid), dim3(v.threads), args, lds, s);
+}
+
+}  // namespace fse

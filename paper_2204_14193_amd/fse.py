@@ -1,0 +1,165 @@
+"""Python binding of libfse (argument marshalling only).
+
+Device memory and streams come from PyTorch; every step of the
+extrapolation runs in the library's HIP kernels.
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+
+BLOCK_OK, BLOCK_EMPTY_SUPPORT, BLOCK_NONFINITE = 0, 1, 2
+
+BLOCK_DTYPE = np.dtype([("frame", "<i4"), ("y0", "<i4"), ("x0", "<i4"),
+                        ("bh", "<i2"), ("bw", "<i2"), ("border", "<i2"),
+                        ("fft", "<i2"), ("iters", "<i4")])
+TRACE_DTYPE = np.dtype([("u", "<u2"), ("v", "<u2"), ("c_re", "<f4"),
+                        ("c_im", "<f4"), ("r2", "<f4")])
+assert BLOCK_DTYPE.itemsize == C.sizeof(_lib.fse_block_t) == 24
+assert TRACE_DTYPE.itemsize == C.sizeof(_lib.fse_trace_t) == 16
+
+_STATUS = {0: "FSE_OK", -1: "FSE_ERR_INVALID_ARG", -2: "FSE_ERR_UNSUPPORTED",
+           -3: "FSE_ERR_OOM", -4: "FSE_ERR_HIP", -5: "FSE_ERR_OVERLAP"}
+
+
+class FseError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = _lib.lib().fse_last_error().decode()
+        super().__init__(f"{where}: {_STATUS.get(code, code)}: {msg}")
+
+
+def _check(code, where):
+    if code != 0:
+        raise FseError(code, where)
+
+
+def _blocks_array(blocks):
+    arr = np.ascontiguousarray(blocks)
+    if arr.dtype != BLOCK_DTYPE:
+        arr = arr.astype(BLOCK_DTYPE)
+    return arr
+
+
+class Plan:
+    """fse_plan_t: window decay rho, compensation gamma, iteration limit."""
+
+    def __init__(self, rho=0.8, gamma=0.5, max_iters=4096):
+        L = _lib.lib()
+        desc = _lib.fse_plan_desc_t(float(rho), float(gamma), int(max_iters), 0)
+        h = C.c_void_p()
+        _check(L.fse_plan_create(C.byref(desc), C.byref(h)), "fse_plan_create")
+        self._h = h
+        self.rho, self.gamma, self.max_iters = float(rho), float(gamma), int(max_iters)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def validate(self, blocks, n_frames, H, W):
+        """Host-only check of a block list; returns (status, bad_index)."""
+        arr = _blocks_array(blocks)
+        bad = C.c_int32(-1)
+        st = _lib.lib().fse_validate_blocks(self._h, arr.ctypes.data_as(C.c_void_p), len(arr),
+                                            int(n_frames), int(H), int(W), C.byref(bad))
+        return st, bad.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib().fse_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """fse_batch_t: a validated, scheduled block list resident on the GPU."""
+
+    def __init__(self, plan, blocks, n_frames, H, W):
+        arr = _blocks_array(blocks)
+        h = C.c_void_p()
+        _check(_lib.lib().fse_batch_create(plan.handle, arr.ctypes.data_as(C.c_void_p), len(arr),
+                                           int(n_frames), int(H), int(W), C.byref(h)),
+               "fse_batch_create")
+        self._h = h
+        self.plan = plan
+        self.n = len(arr)
+        self.shape = (int(n_frames), int(H), int(W))
+        self.max_iters = _lib.lib().fse_batch_max_iters(h)
+
+    def launch_info(self, F):
+        t, w, g, l = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(_lib.lib().fse_batch_launch_info(self._h, int(F), C.byref(t), C.byref(w),
+                                                C.byref(g), C.byref(l)), "fse_batch_launch_info")
+        return dict(threads=t.value, wg_per_cu=w.value, grid=g.value, lds_bytes=l.value)
+
+    def run(self, image, avail, out, status, trace=None, stream=None):
+        """Launch on torch CUDA tensors: image/avail uint8 [F,H,W] (rows may
+        be padded: pitch = stride(1)), out float32 [F,H,W], status int32
+        [n], trace None or uint8 [n, max_iters*16]. Asynchronous."""
+        import torch
+        nf, H, W = self.shape
+        for name, t, dt in (("image", image, torch.uint8), ("avail", avail, torch.uint8),
+                            ("out", out, torch.float32)):
+            if not t.is_cuda or t.dtype != dt or tuple(t.shape) != (nf, H, W) or t.stride(2) != 1 \
+                    or t.stride(0) != t.stride(1) * H:
+                raise ValueError(f"{name} must be a CUDA {dt} tensor of shape {(nf, H, W)} with dense frames")
+        if image.stride(1) != avail.stride(1):
+            raise ValueError("image and avail must share a pitch")
+        if not status.is_cuda or status.dtype != torch.int32 or status.numel() < self.n:
+            raise ValueError("status must be a CUDA int32 tensor with one entry per block")
+        tptr = None
+        if trace is not None:
+            if not trace.is_cuda or trace.numel() * trace.element_size() < self.n * self.max_iters * 16:
+                raise ValueError("trace buffer too small")
+            tptr = C.c_void_p(trace.data_ptr())
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(_lib.lib().fse_extrapolate_batch(
+            self._h, C.c_void_p(image.data_ptr()), C.c_void_p(avail.data_ptr()), image.stride(1),
+            C.c_void_p(out.data_ptr()), out.stride(1), C.c_void_p(status.data_ptr()), tptr,
+            C.c_void_p(s.cuda_stream)), "fse_extrapolate_batch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib().fse_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def extrapolate_batch(image, avail, blocks, rho=0.8, gamma=0.5, trace=False, out=None):
+    """Conceal ``blocks`` in frames ``image`` (uint8 CUDA tensor [F,H,W] or
+    [H,W]) with availability ``avail``. Returns (out float32, status int32
+    numpy, trace numpy of TRACE_DTYPE [n, max_iters] or None). ``out``
+    defaults to the distorted frames as float32."""
+    import torch
+    if image.dim() == 2:
+        image, avail = image[None], avail[None]
+    arr = _blocks_array(blocks)
+    nf, H, W = image.shape
+    plan = Plan(rho, gamma, max(4096, int(arr["iters"].max()) if len(arr) else 0))
+    batch = Batch(plan, arr, nf, H, W)
+    if out is None:
+        out = (image * (avail != 0)).to(torch.float32)
+    status = torch.full((max(len(arr), 1),), -1, dtype=torch.int32, device=image.device)
+    tbuf = None
+    if trace and batch.max_iters > 0:
+        tbuf = torch.zeros((len(arr), batch.max_iters * 16), dtype=torch.uint8, device=image.device)
+    batch.run(image, avail, out, status, tbuf)
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()[:len(arr)]
+    tr = None
+    if tbuf is not None:
+        tr = tbuf.cpu().numpy().view(TRACE_DTYPE).reshape(len(arr), batch.max_iters)
+    batch.close()
+    plan.close()
+    return out, st, tr

@@ -1,0 +1,90 @@
+"""GPU-versus-oracle comparison (test helper; imports the oracle, never the
+other way round).
+
+Replay protocol for one block, given the GPU's trace of selections and
+coefficients:
+1. the FP64 oracle is run forced along the GPU's selections; at every
+   iteration the GPU's bin must be the oracle's own free choice, or lie within
+   a relative 1e-6 of the largest |R_w| (a near tie that FP32 may break
+   either way);
+2. the accumulated coefficients per distinct bin must agree: for every bin
+   |c_gpu - c_orc| <= 1e-4 * max|c_orc|, and ||dc||_2 <= 1e-4 * ||c_orc||_2;
+3. frame PSNR over the lost pixels, GPU output vs the free-running oracle's
+   output, each against the undistorted frame, must differ by <= 0.01 dB.
+"""
+import numpy as np
+
+from oracle import cfse, metrics
+
+GAP_TOL = 1e-6
+COEF_TOL = 1e-4
+PSNR_TOL = 0.01
+
+
+def gpu_sequence(trace_row, F, I):
+    rec = trace_row[:I]
+    seq = rec["u"].astype(np.int64) * F + rec["v"].astype(np.int64)
+    c = rec["c_re"].astype(np.float64) + 1j * rec["c_im"].astype(np.float64)
+    return seq, c
+
+
+def accumulate(seq, c):
+    acc = {}
+    for s, v in zip(seq, c):
+        acc[int(s)] = acc.get(int(s), 0) + v
+    return acc
+
+
+def replay_block(frames, avail, blk, rho, gamma, trace_row):
+    """Returns a dict of per-block parity figures (raises nothing)."""
+    F, I = int(blk["fft"]), int(blk["iters"])
+    seq, c = gpu_sequence(trace_row, F, I)
+    res = cfse.extrapolate_block(frames, avail, blk, rho, gamma, forced=seq)
+    short = np.array(res["short"]) if I else np.zeros(0)
+    free = np.array(res["free"]) if I else np.zeros(0, dtype=int)
+    diverged = free != seq
+    bad_gap = diverged & (short >= GAP_TOL)
+    ag = accumulate(seq, c)
+    ao = accumulate(seq, np.array(res["chat"]))
+    keys = sorted(ao)
+    vo = np.array([ao[k] for k in keys])
+    vg = np.array([ag.get(k, 0) for k in keys])
+    scale = np.abs(vo).max() if len(vo) else 0.0
+    d = np.abs(vg - vo)
+    return dict(
+        ties=int(diverged.sum()), gap_violations=int(bad_gap.sum()),
+        max_short=float(short[diverged].max()) if diverged.any() else 0.0,
+        coef_max=float(d.max() / scale) if scale > 0 else 0.0,
+        coef_l2=float(np.linalg.norm(vg - vo) / np.linalg.norm(vo)) if scale > 0 else 0.0,
+        values=res["values"])
+
+
+def check_blocks(frames, avail, blocks, rho, gamma, trace, out_gpu, idx=None):
+    """Replay every block in ``idx`` (default all); assert the per-block bars
+    and return the per-block figures."""
+    idx = range(len(blocks)) if idx is None else idx
+    rows = []
+    for i in idx:
+        blk = blocks[i]
+        r = replay_block(frames, avail, blk, rho, gamma, trace[i])
+        f, y0, x0 = int(blk["frame"]), int(blk["y0"]), int(blk["x0"])
+        g = out_gpu[f, y0:y0 + int(blk["bh"]), x0:x0 + int(blk["bw"])].astype(np.float64)
+        r["pix_maxabs"] = float(np.abs(g - r["values"]).max())
+        r["index"] = int(i)
+        rows.append(r)
+        assert r["gap_violations"] == 0, (i, r)
+        assert r["coef_max"] <= COEF_TOL and r["coef_l2"] <= COEF_TOL, (i, r)
+    return rows
+
+
+def psnr_delta(frames, avail, blocks, rho, gamma, out_gpu, processes=1):
+    """|PSNR(GPU) - PSNR(free-running oracle)| over the lost pixels of the
+    given blocks (other lost pixels are ignored), plus both PSNRs."""
+    ref = cfse.extrapolate_frames(frames, avail, blocks, rho, gamma, processes=processes)
+    mask = np.ones_like(avail)
+    for b in blocks:
+        mask[int(b["frame"]), int(b["y0"]):int(b["y0"]) + int(b["bh"]),
+             int(b["x0"]):int(b["x0"]) + int(b["bw"])] = 0
+    p_gpu = metrics.psnr_lost(frames, out_gpu, mask)
+    p_orc = metrics.psnr_lost(frames, ref, mask)
+    return abs(p_gpu - p_orc), p_gpu, p_orc, metrics.psnr_between(out_gpu, ref, mask)

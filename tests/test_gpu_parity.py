@@ -1,0 +1,132 @@
+"""GPU parity: libfse (FP32, HIP) against the FP64 oracle, through the C ABI.
+
+Each test prints the case it runs before touching the GPU.
+"""
+import numpy as np
+import pytest
+
+from synth import losses, workloads
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(wl, trace=True, rho=None, gamma=None):
+    import torch
+    import paper_2204_14193_amd as fse
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(wl.distorted).to(dev)
+    av = torch.from_numpy(wl.avail).to(dev)
+    out, status, tr = fse.extrapolate_batch(img, av, wl.blocks, wl.rho if rho is None else rho,
+                                            wl.gamma if gamma is None else gamma, trace=trace)
+    return out.cpu().numpy(), status, tr
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def test_isolated_256_full_parity():
+    """64 isolated 16x16 losses in a 256x256 frame, F=64, I=100: every block
+    replayed against the oracle; frame PSNR within 0.01 dB."""
+    wl = workloads.isolated_256()
+    _say(f"case isolated-256: {len(wl.blocks)} blocks F=64 I=100")
+    out, st, tr = _run(wl)
+    assert (st == 0).all()
+    rows = parity.check_blocks(wl.frames, wl.avail, wl.blocks, wl.rho, wl.gamma, tr, out)
+    d, pg, po, pb = parity.psnr_delta(wl.frames, wl.avail, wl.blocks, wl.rho, wl.gamma, out)
+    _say(f"ties={sum(r['ties'] for r in rows)} coef_max={max(r['coef_max'] for r in rows):.2e} "
+         f"pix={max(r['pix_maxabs'] for r in rows):.2e} psnr gpu={pg:.4f} oracle={po:.4f} between={pb:.1f}")
+    assert d <= parity.PSNR_TOL
+    # pixels outside every B are untouched
+    lost = wl.avail == 0
+    assert np.array_equal(out[~lost], wl.distorted[~lost].astype(np.float32))
+
+
+def test_random_1080p_8x8_subset_parity():
+    """1080p, 3240 non-adjacent 8x8 losses (40x40 areas), F=64, I=200: the
+    whole frame runs in one launch; a seeded sample of 96 blocks is replayed."""
+    wl = workloads.random_1080p_8x8()
+    _say(f"case random-1080p-8x8: {len(wl.blocks)} blocks F=64 I=200")
+    out, st, tr = _run(wl)
+    assert (st == 0).all()
+    idx = np.random.default_rng(7).choice(len(wl.blocks), 96, replace=False)
+    parity.check_blocks(wl.frames, wl.avail, wl.blocks, wl.rho, wl.gamma, tr, out, idx)
+    sub = wl.blocks[np.sort(idx)]
+    d, pg, po, _ = parity.psnr_delta(wl.frames, wl.avail, sub, wl.rho, wl.gamma, out)
+    _say(f"sample psnr gpu={pg:.4f} oracle={po:.4f}")
+    assert d <= parity.PSNR_TOL
+
+
+def test_random_1080p_16x16_sampled_parity_8_frames():
+    """Eight 1080p frames, 804 16x16 losses each (6432 blocks, F=64, I=100),
+    in the launch configuration of the benchmark; 48 sampled blocks replayed,
+    all blocks checked for status and finite, bounded output."""
+    wl = workloads.random_1080p_16x16(seeds=tuple(range(99, 107)))
+    _say(f"case random-1080p-16x16 x8: {len(wl.blocks)} blocks F=64 I=100")
+    out, st, tr = _run(wl, trace=True)
+    assert (st == 0).all()
+    lost = wl.avail == 0
+    assert np.isfinite(out[lost]).all() and np.abs(out[lost]).max() < 1e4
+    idx = np.random.default_rng(11).choice(len(wl.blocks), 48, replace=False)
+    parity.check_blocks(wl.frames, wl.avail, wl.blocks, wl.rho, wl.gamma, tr, out, idx)
+
+
+def _ragged_workload():
+    """Small frames with ragged geometry: non-square blocks, odd sizes, areas
+    crossing every frame edge, all three transform sizes, I in {0, 1, 2, 37}."""
+    frames = np.stack([__import__("synth").synthetic_image(96, 130, 31),
+                       __import__("synth").synthetic_image(96, 130, 32)])
+    B = losses.Block
+    blocks = [
+        B(0, 0, 0, 5, 11, 7, 32, 37),        # top-left corner, 19x25 area
+        B(0, 90, 120, 6, 10, 9, 32, 2),      # bottom-right corner
+        B(0, 40, 60, 16, 16, 16, 64, 37),    # interior, paper geometry
+        B(1, 3, 100, 13, 7, 16, 64, 1),      # top edge, 45x39 area
+        B(1, 50, 0, 32, 30, 16, 128, 37),    # left edge, 64x62 area in F=128
+        B(1, 60, 70, 9, 9, 0, 32, 37),       # no border: empty support
+        B(0, 20, 30, 4, 4, 8, 32, 0),        # zero iterations
+    ]
+    arr = losses.blocks_to_array(blocks)
+    avail = losses.availability_mask(frames.shape, blocks)
+    return workloads.Workload("ragged", frames, avail, arr, 0.8, 0.5)
+
+
+def test_ragged_edges_and_degenerate_blocks():
+    wl = _ragged_workload()
+    _say(f"case ragged: {len(wl.blocks)} blocks F=32/64/128")
+    out, st, tr = _run(wl)
+    assert st.tolist() == [0, 0, 0, 0, 0, 1, 0]
+    # empty support: B untouched (stays the distorted value 0)
+    b = wl.blocks[5]
+    assert (out[1, 60:69, 70:79] == 0).all()
+    # zero iterations: model is zero on B
+    assert (out[0, 20:24, 30:34] == 0).all()
+    idx = [0, 1, 2, 3, 4]
+    parity.check_blocks(wl.frames, wl.avail, wl.blocks, wl.rho, wl.gamma, tr, out, idx)
+
+
+def test_gamma_zero_gives_zero_model():
+    wl = workloads.subset(workloads.isolated_256(iters=20), np.arange(8))
+    _say("case gamma=0")
+    out, st, _ = _run(wl, trace=False, gamma=0.0)
+    assert (st == 0).all()
+    for b in wl.blocks:
+        assert (out[0, b["y0"]:b["y0"] + 16, b["x0"]:b["x0"] + 16] == 0).all()
+
+
+def test_batch_invariance_and_determinism():
+    """A block's output and selections do not depend on its batch companions
+    or on the run: alone, in a batch, and twice in a row give identical bits."""
+    wl = workloads.isolated_256(iters=60)
+    _say("case batch invariance")
+    out_all, _, tr_all = _run(wl)
+    out_again, _, tr_again = _run(wl)
+    assert np.array_equal(out_all, out_again) and np.array_equal(tr_all, tr_again)
+    for i in (0, 17, 63):
+        sub = workloads.subset(wl, [i])
+        out1, _, tr1 = _run(sub)
+        b = wl.blocks[i]
+        sl = (0, slice(b["y0"], b["y0"] + 16), slice(b["x0"], b["x0"] + 16))
+        assert np.array_equal(out1[sl], out_all[sl])
+        assert np.array_equal(tr1[0], tr_all[i])
