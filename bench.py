@@ -103,6 +103,9 @@ def main():
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the (untimed) autotuner")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="also run 3 plain device copies of this many bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -121,8 +124,9 @@ def main():
     status = torch.zeros(n, dtype=torch.int32, device=dev)
     plan = fse.Plan(wl.rho, wl.gamma, args.iters)
     batch = fse.Batch(plan, wl.blocks, *wl.frames.shape)
-    info = batch.launch_info(64)
     stream = torch.cuda.current_stream()
+    tuning = batch.autotune(img, av, out, status, reps=2) if not args.no_tune else []
+    info = batch.launch_info(64)
 
     for _ in range(args.warmup):
         batch.run(img, av, out, status)
@@ -158,13 +162,22 @@ def main():
                                f"gamma 0.5, {I} iterations, plain FSE",
                    "blocks": n, "fft": F, "iters": I, "rho": wl.rho, "gamma": wl.gamma},
         "mpixel_per_s": lost_px / (ms_per_step * 1e-3) / 1e6,
-        "launch": dict(info, kernel="fse_persistent<64,256,dup>", avg_ms=launch_ms),
+        "launch": dict(info, kernel=f"fse_persistent<64,{info['threads']},{'dup' if info['dup'] else 'single'}>",
+                       avg_ms=launch_ms, autotune_us={f"{t}{'d' if d else 's'}": round(us, 1)
+                                                      for _, t, d, us in tuning}),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(n)},
         "lds_roofline": {"achieved": lds_bytes / (launch_ms * 1e-3) / 1e12, "peak": NOMINAL_LDS_TBPS,
                          "unit": "TB/s", "frac": lds_bytes / (launch_ms * 1e-3) / 1e12 / NOMINAL_LDS_TBPS,
                          "note": "algorithmic 24 B/bin/iteration against the nominal LDS bandwidth"},
     }
+    if args.copy_bytes > 0:
+        src = torch.randint(0, 255, (args.copy_bytes,), dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        rec["copy_calibration_bytes"] = args.copy_bytes
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, n))
     batch.close()

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -51,7 +52,7 @@ struct fse_plan_s {
 
 struct fse_batch_s {
   fse_plan_t plan = nullptr;
-  int device = 0;
+  int device = 0, cus = 0;
   int32_t n = 0, n_frames = 0, H = 0, W = 0;
   int32_t max_iters = 0;
   fse_block_t* d_blocks = nullptr;
@@ -184,6 +185,22 @@ fse_status_t upload_tables(fse_plan_t plan, int device, const DeviceTables** out
   return FSE_OK;
 }
 
+// Select variant v for class c: LDS size, resident workgroups per CU and
+// the persistent grid (one wave of workgroups, never more than the blocks).
+fse_status_t configure(fse_batch_s* b, fse_batch_s::Cls& c, const fse::Variant* v) {
+  const size_t lds = fse::lds_bytes(*v, c.iters_cap);
+  if (hipFuncSetAttribute(v->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return fail(FSE_ERR_HIP, "hipFuncSetAttribute failed (LDS size)");
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, v->fn, v->threads, lds) != hipSuccess || per_cu < 1)
+    return fail(FSE_ERR_UNSUPPORTED, "kernel does not fit on a compute unit (iteration count too large)");
+  c.v = v;
+  c.lds = lds;
+  c.wg_per_cu = per_cu;
+  c.grid = (int32_t)std::min<int64_t>(c.count, (int64_t)per_cu * b->cus);
+  return FSE_OK;
+}
+
 void free_batch(fse_batch_s* b) {
   (void)hipFree(b->d_blocks);
   (void)hipFree(b->d_orig);
@@ -232,27 +249,16 @@ extern "C" fse_status_t fse_batch_create(fse_plan_t plan, const fse_block_t* h_b
     delete b;
     return fail(FSE_ERR_HIP, "hipGetDeviceProperties failed");
   }
+  b->cus = prop.multiProcessorCount;
   for (int ci = 0; ci < 3; ++ci) {
     fse_batch_s::Cls& c = b->cls[ci];
     if (c.count == 0) continue;
-    c.v = fse::variant_for(kSizes[ci]);
-    if (!c.v) {
+    const fse::Variant* v = fse::variant_for(kSizes[ci]);
+    st = v ? configure(b, c, v) : fail(FSE_ERR_UNSUPPORTED, "no kernel for this transform size");
+    if (st != FSE_OK) {
       delete b;
-      return fail(FSE_ERR_UNSUPPORTED, "no kernel for this transform size");
+      return st;
     }
-    c.lds = fse::lds_bytes(*c.v, c.iters_cap);
-    if (hipFuncSetAttribute(c.v->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds) != hipSuccess) {
-      delete b;
-      return fail(FSE_ERR_HIP, "hipFuncSetAttribute failed (LDS size)");
-    }
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c.v->fn, c.v->threads, c.lds) != hipSuccess ||
-        per_cu < 1) {
-      delete b;
-      return fail(FSE_ERR_UNSUPPORTED, "kernel does not fit on a compute unit (iteration count too large)");
-    }
-    c.wg_per_cu = per_cu;
-    c.grid = std::min<int64_t>(c.count, (int64_t)per_cu * prop.multiProcessorCount);
   }
   st = upload_tables(plan, b->device, &b->tables);
   if (st != FSE_OK) {
@@ -285,18 +291,23 @@ extern "C" void fse_batch_destroy(fse_batch_t batch) {
 
 extern "C" int32_t fse_batch_max_iters(fse_batch_t batch) { return batch ? batch->max_iters : 0; }
 
-extern "C" fse_status_t fse_batch_launch_info(fse_batch_t batch, int32_t F, int32_t* threads, int32_t* wg_per_cu,
-                                              int32_t* grid, int32_t* lds_bytes) {
+extern "C" fse_status_t fse_batch_launch_info(fse_batch_t batch, int32_t F, int32_t* threads, int32_t* dup,
+                                              int32_t* wg_per_cu, int32_t* grid, int32_t* lds_bytes) {
   if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
   const int ci = class_of(F);
   if (ci < 0 || batch->cls[ci].count == 0) return fail(FSE_ERR_INVALID_ARG, "no block of this transform size");
   const fse_batch_s::Cls& c = batch->cls[ci];
   if (threads) *threads = c.v->threads;
+  if (dup) *dup = c.v->dup ? 1 : 0;
   if (wg_per_cu) *wg_per_cu = c.wg_per_cu;
   if (grid) *grid = c.grid;
   if (lds_bytes) *lds_bytes = (int32_t)c.lds;
   return FSE_OK;
 }
+
+static fse_status_t launch_one(fse_batch_t batch, int ci, const uint8_t* d_image, const uint8_t* d_avail,
+                               int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
+                               fse_trace_t* d_trace, hipStream_t s);
 
 extern "C" fse_status_t fse_extrapolate_batch(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail,
                                               int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
@@ -310,8 +321,18 @@ extern "C" fse_status_t fse_extrapolate_batch(fse_batch_t batch, const uint8_t* 
     return fail(FSE_ERR_INVALID_ARG, "batch was created on another device");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   for (int ci = 0; ci < 3; ++ci) {
+    if (batch->cls[ci].count == 0) continue;
+    fse_status_t st = launch_one(batch, ci, d_image, d_avail, pitch, d_out, out_pitch, d_status, d_trace, s);
+    if (st != FSE_OK) return st;
+  }
+  return FSE_OK;
+}
+
+static fse_status_t launch_one(fse_batch_t batch, int ci, const uint8_t* d_image, const uint8_t* d_avail,
+                               int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
+                               fse_trace_t* d_trace, hipStream_t s) {
+  {
     const fse_batch_s::Cls& c = batch->cls[ci];
-    if (c.count == 0) continue;
     fse::ClassArgs a;
     a.img = d_image;
     a.avail = d_avail;
@@ -335,4 +356,67 @@ extern "C" fse_status_t fse_extrapolate_batch(fse_batch_t batch, const uint8_t* 
       return fail(FSE_ERR_HIP, "kernel launch failed");
   }
   return FSE_OK;
+}
+
+extern "C" fse_status_t fse_batch_set_variant(fse_batch_t batch, int32_t F, int32_t threads, int32_t dup) {
+  if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
+  const int ci = class_of(F);
+  if (ci < 0 || batch->cls[ci].count == 0) return fail(FSE_ERR_INVALID_ARG, "no block of this transform size");
+  const fse::Variant* vs[16];
+  const int nv = std::min(fse::variants_for(F, vs, 16), 16);
+  for (int i = 0; i < nv; ++i)
+    if (vs[i]->threads == threads && vs[i]->dup == (dup != 0)) return configure(batch, batch->cls[ci], vs[i]);
+  return fail(FSE_ERR_UNSUPPORTED, "no compiled kernel with this workgroup shape");
+}
+
+extern "C" fse_status_t fse_batch_autotune(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail,
+                                           int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
+                                           int32_t reps, void* stream, char* report, size_t report_len) {
+  if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
+  if (reps < 1) return fail(FSE_ERR_INVALID_ARG, "reps must be >= 1");
+  if (report && report_len) report[0] = 0;
+  size_t used = 0;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(FSE_ERR_HIP, "hipEventCreate failed");
+  fse_status_t st = FSE_OK;
+  for (int ci = 0; ci < 3 && st == FSE_OK; ++ci) {
+    fse_batch_s::Cls& c = batch->cls[ci];
+    if (c.count == 0) continue;
+    const fse::Variant* vs[16];
+    const int nv = std::min(fse::variants_for(kSizes[ci], vs, 16), 16);
+    const fse::Variant* best = nullptr;
+    float best_ms = 0.f;
+    for (int i = 0; i < nv && st == FSE_OK; ++i) {
+      if (configure(batch, c, vs[i]) != FSE_OK) continue;  // does not fit: skip
+      st = launch_one(batch, ci, d_image, d_avail, pitch, d_out, out_pitch, d_status, nullptr, s);  // warm-up
+      if (st != FSE_OK) break;
+      if (hipEventRecord(e0, s) != hipSuccess) { st = fail(FSE_ERR_HIP, "hipEventRecord failed"); break; }
+      for (int r = 0; r < reps && st == FSE_OK; ++r)
+        st = launch_one(batch, ci, d_image, d_avail, pitch, d_out, out_pitch, d_status, nullptr, s);
+      if (st != FSE_OK) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = fail(FSE_ERR_HIP, "event timing failed");
+        break;
+      }
+      ms /= (float)reps;
+      if (report && used + 64 < report_len)
+        used += (size_t)snprintf(report + used, report_len - used, "%d %d %d %.3f\n", vs[i]->F, vs[i]->threads,
+                                 vs[i]->dup ? 1 : 0, 1000.0 * ms);
+      if (!best || ms < best_ms) {
+        best = vs[i];
+        best_ms = ms;
+      }
+    }
+    if (st == FSE_OK) {
+      if (!best) st = fail(FSE_ERR_UNSUPPORTED, "no variant fits");
+      else st = configure(batch, c, best);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
 }

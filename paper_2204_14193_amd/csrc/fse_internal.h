@@ -44,8 +44,11 @@ struct Variant {
   const void* fn;      // kernel symbol
 };
 
-// Kernel variant used for transform size F (32, 64, 128), or null.
+// Default kernel variant for transform size F (32, 64, 128), or null.
 const Variant* variant_for(int F);
+
+// All compiled variants for F; returns their number, fills up to cap.
+int variants_for(int F, const Variant** out, int cap);
 
 // Dynamic LDS bytes a variant needs for a class whose largest iteration
 // count is iters_cap.

@@ -36,21 +36,25 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 
+template <int N>
+using fvec = float __attribute__((ext_vector_type(N)));
+
 template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_max(float x) {
-  const int moved = __builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), CTRL, ROW_MASK, 0xf, false);
-  return fmaxf(x, __int_as_float(moved));
+__device__ __forceinline__ unsigned dpp_umax(unsigned x) {
+  const unsigned moved = (unsigned)__builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, ROW_MASK, 0xf, false);
+  return max(x, moved);
 }
 
-// Maximum over the 64 lanes of a wave, returned as a wave-uniform value.
-__device__ __forceinline__ float wave_max(float x) {
-  x = dpp_max<0xb1, 0xf>(x);   // quad_perm [1,0,3,2]
-  x = dpp_max<0x4e, 0xf>(x);   // quad_perm [2,3,0,1]
-  x = dpp_max<0x141, 0xf>(x);  // row_half_mirror
-  x = dpp_max<0x140, 0xf>(x);  // row_mirror: every lane holds its row maximum
-  x = dpp_max<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
-  x = dpp_max<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+// Maximum over the 64 lanes of a wave of non-negative floats given as bit
+// patterns (which order like the values), returned wave-uniform.
+__device__ __forceinline__ unsigned wave_max_bits(unsigned x) {
+  x = dpp_umax<0xb1, 0xf>(x);   // quad_perm [1,0,3,2]
+  x = dpp_umax<0x4e, 0xf>(x);   // quad_perm [2,3,0,1]
+  x = dpp_umax<0x141, 0xf>(x);  // row_half_mirror
+  x = dpp_umax<0x140, 0xf>(x);  // row_mirror: every lane holds its row maximum
+  x = dpp_umax<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x = dpp_umax<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+  return (unsigned)__builtin_amdgcn_readlane((int)x, 63);
 }
 
 __device__ __forceinline__ float readlane_f(float x, int lane) {
@@ -202,66 +206,76 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
   fft_lines<F, NT, false>(Wd, s.tw, t);
   fft_lines<F, NT, true>(Wd, s.tw, t);
 
-  // split Z = R_w + j*alpha*W by conjugate symmetry; R_w goes to VGPRs
-  float2 Rr[BPL];
-  float2 Wv[BPL];
+  // split Z = R_w + j*alpha*W by conjugate symmetry; R_w goes to VGPRs.
+  // With the doubled layout W is written straight into rows F..2F-1, which
+  // the split does not read, and copied down after the barrier; the single
+  // layout has to hold W in registers until every thread has read Z.
+  fvec<BPL> Rx, Ry;
+  float2 Wv[DUP ? 1 : BPL];
 #pragma unroll
   for (int j = 0; j < BPL; ++j) {
     const int k = j * ROWS + kt, l = lt;
     const float2 zk = Wd[k * F + l];
     const float2 zn = Wd[((F - k) & (F - 1)) * F + ((F - l) & (F - 1))];
-    Rr[j] = make_float2((zk.x + zn.x) * 0.5f, (zk.y - zn.y) * 0.5f);
-    Wv[j] = make_float2((zk.y + zn.y) * (0.5f / kAlpha), (zn.x - zk.x) * (0.5f / kAlpha));
+    Rx[j] = (zk.x + zn.x) * 0.5f;
+    Ry[j] = (zk.y - zn.y) * 0.5f;
+    const float2 w = make_float2((zk.y + zn.y) * (0.5f / kAlpha), (zn.x - zk.x) * (0.5f / kAlpha));
+    if constexpr (DUP) Wd[(k + F) * F + l] = w; else Wv[j] = w;
   }
   const float W0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(Wd[0].y))) * (1.0f / kAlpha);
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < BPL; ++j) {
     const int k = j * ROWS + kt;
-    Wd[k * F + lt] = Wv[j];
-    if constexpr (DUP) Wd[(k + F) * F + lt] = Wv[j];
+    if constexpr (DUP) Wd[k * F + lt] = Wd[(k + F) * F + lt]; else Wd[k * F + lt] = Wv[j];
   }
   __syncthreads();
 
   if (!(W0 > 0.f)) return FSE_BLOCK_EMPTY_SUPPORT;  // no received pixel in the area
   const float gW = a.gamma * (1.0f / W0);
 
-  // 3. iterations
-  float mg[BPL];
+  // 3. iterations. |R_w|^2 is kept as its bit pattern: for values >= 0 the
+  // unsigned order of the bits is the order of the values, so the argmax
+  // runs on integer max/compare (a NaN sorts above every finite value and
+  // is then reported as a non-finite coefficient).
+  unsigned mb[BPL];
 #pragma unroll
-  for (int j = 0; j < BPL; ++j) mg[j] = fmaf(Rr[j].y, Rr[j].y, Rr[j].x * Rr[j].x);
+  for (int j = 0; j < BPL; ++j) mb[j] = __float_as_uint(fmaf(Ry[j], Ry[j], Rx[j] * Rx[j]));
 
   int sel = 0;
   float sre = 0.f, sim = 0.f, smag = 0.f;
-  // argmax of mg over the workgroup, lowest linear index j*NT + t on ties
+  // Argmax over the workgroup, lowest linear index j*NT + t on ties:
+  // per-lane maximum, wave maximum by DPP, then one ballot per bin slot j;
+  // the lowest slot with a hit and the lowest lane in it are found with
+  // scalar selects (no branches), and R at that bin is read with a
+  // wave-uniform register index.
   auto select = [&]() {
-    float lm = mg[0];
+    unsigned lm = mb[0];
 #pragma unroll
-    for (int j = 1; j < BPL; ++j) lm = fmaxf(lm, mg[j]);
-    const float wm = wave_max(lm);
-    int wj = 0, wl = 0;
-    float re = readlane_f(Rr[0].x, 0), im = readlane_f(Rr[0].y, 0);
+    for (int j = 1; j < BPL; ++j) lm = max(lm, mb[j]);
+    const unsigned wm = wave_max_bits(lm);
+    int wj = BPL - 1;
+    unsigned long long wmask = __ballot(mb[BPL - 1] == wm);
 #pragma unroll
-    for (int j = 0; j < BPL; ++j) {
-      const unsigned long long msk = __ballot(mg[j] == wm);
-      if (msk) {
-        wl = __builtin_ctzll(msk);
-        wj = j;
-        re = readlane_f(Rr[j].x, wl);
-        im = readlane_f(Rr[j].y, wl);
-        break;
-      }
+    for (int j = BPL - 2; j >= 0; --j) {
+      const unsigned long long m = __ballot(mb[j] == wm);
+      const bool hit = m != 0;
+      wj = hit ? j : wj;
+      wmask = hit ? m : wmask;
     }
+    wj = __builtin_amdgcn_readfirstlane(wj);
+    const int wl = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(wmask));
+    const float re = readlane_f(Rx[wj], wl);
+    const float im = readlane_f(Ry[wj], wl);
     const int widx = wj * NT + wave * 64 + wl;
     if constexpr (NW == 1) {
-      sel = widx; sre = re; sim = im; smag = wm;
+      sel = widx; sre = re; sim = im; smag = __uint_as_float(wm);
     } else {
       int4* slot = s.red + parity * NW;
-      slot[wave] = make_int4(__float_as_int(wm), widx, __float_as_int(re), __float_as_int(im));  // uniform
+      slot[wave] = make_int4((int)wm, widx, __float_as_int(re), __float_as_int(im));  // uniform
       __syncthreads();
       // Every lane reads the same slots; the comparison runs on wave-uniform
-      // integers (|R|^2 >= 0, so its bit pattern orders like the value) and
-      // every field is selected explicitly.
+      // integers and every field is selected explicitly.
       const int4 s0 = slot[0];
       unsigned bm = (unsigned)__builtin_amdgcn_readfirstlane(s0.x);
       int bidx = __builtin_amdgcn_readfirstlane(s0.y);
@@ -312,34 +326,24 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
     const int u = sel / F, v = sel % F;
     const int col = (lt - v) & (F - 1);
     // eq. (18): R_w[k,l] -= c * W[k-u, l-v], fused with |R_w|^2
-    if constexpr (DUP) {
-      const float2* wp = Wd + (kt - u + F) * F + col;
 #pragma unroll
-      for (int j = 0; j < BPL; ++j) {
-        const float2 w = wp[j * NT];
-        float2 r = Rr[j];
-        r.x = fmaf(-cre, w.x, r.x);
-        r.x = fmaf(cim, w.y, r.x);
-        r.y = fmaf(-cre, w.y, r.y);
-        r.y = fmaf(-cim, w.x, r.y);
-        Rr[j] = r;
-        mg[j] = fmaf(r.y, r.y, r.x * r.x);
+    for (int j = 0; j < BPL; ++j) {
+      float2 w;
+      if constexpr (DUP) {
+        w = Wd[(kt - u + F) * F + col + j * NT];
+      } else {
+        static_assert(DUP || F >= 64, "single-copy layout needs wave-uniform rows");
+        const int row = (j * ROWS + __builtin_amdgcn_readfirstlane(kt) - u) & (F - 1);
+        w = Wd[row * F + col];
       }
-    } else {
-      static_assert(DUP || F >= 64, "single-copy layout needs wave-uniform rows");
-      const int k0 = __builtin_amdgcn_readfirstlane(kt);
-#pragma unroll
-      for (int j = 0; j < BPL; ++j) {
-        const int row = (j * ROWS + k0 - u) & (F - 1);
-        const float2 w = Wd[row * F + col];
-        float2 r = Rr[j];
-        r.x = fmaf(-cre, w.x, r.x);
-        r.x = fmaf(cim, w.y, r.x);
-        r.y = fmaf(-cre, w.y, r.y);
-        r.y = fmaf(-cim, w.x, r.y);
-        Rr[j] = r;
-        mg[j] = fmaf(r.y, r.y, r.x * r.x);
-      }
+      float rx = Rx[j], ry = Ry[j];
+      rx = fmaf(-cre, w.x, rx);
+      rx = fmaf(cim, w.y, rx);
+      ry = fmaf(-cre, w.y, ry);
+      ry = fmaf(-cim, w.x, ry);
+      Rx[j] = rx;
+      Ry[j] = ry;
+      mb[j] = __float_as_uint(fmaf(ry, ry, rx * rx));
     }
     select();
   }
@@ -400,7 +404,13 @@ __global__ __launch_bounds__(NT) void fse_persistent(ClassArgs a) {
       __syncthreads();
     }
     if (bi >= a.n) break;
-    const int code = conceal_block<F, NT, DUP>(a, bi, s, t, parity);
+    // An opaque copy of the thread index keeps the compiler from hoisting
+    // every index-derived LDS address out of this loop, where they would
+    // stay live in VGPRs for the whole kernel; recomputing them per block
+    // costs a few instructions.
+    int tb = t;
+    asm volatile("" : "+v"(tb));
+    const int code = conceal_block<F, NT, DUP>(a, bi, s, tb, parity);
     if (wave == 0) a.status[a.orig[bi]] = code;
   }
 
@@ -420,10 +430,18 @@ constexpr Variant make_variant() {
   return Variant{F, NT, DUP, reinterpret_cast<const void*>(&fse_persistent<F, NT, DUP>)};
 }
 
+// Workgroup shapes compiled for each transform size. The first entry of
+// each size is the default; the autotuner may pick another per batch.
 const Variant kVariants[] = {
     make_variant<32, 64, true>(),
+    make_variant<32, 128, true>(),
+    make_variant<32, 256, true>(),
     make_variant<64, 256, true>(),
+    make_variant<64, 512, true>(),
+    make_variant<64, 256, false>(),
+    make_variant<64, 512, false>(),
     make_variant<128, 1024, false>(),
+    make_variant<128, 512, false>(),
 };
 
 }  // namespace
@@ -432,6 +450,16 @@ const Variant* variant_for(int F) {
   for (const Variant& v : kVariants)
     if (v.F == F) return &v;
   return nullptr;
+}
+
+int variants_for(int F, const Variant** out, int cap) {
+  int n = 0;
+  for (const Variant& v : kVariants)
+    if (v.F == F) {
+      if (n < cap) out[n] = &v;
+      ++n;
+    }
+  return n;
 }
 
 size_t lds_bytes(const Variant& v, int iters_cap) {

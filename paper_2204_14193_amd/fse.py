@@ -93,15 +93,33 @@ class Batch:
         self.max_iters = _lib.lib().fse_batch_max_iters(h)
 
     def launch_info(self, F):
-        t, w, g, l = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
-        _check(_lib.lib().fse_batch_launch_info(self._h, int(F), C.byref(t), C.byref(w),
+        t, d, w, g, l = (C.c_int32() for _ in range(5))
+        _check(_lib.lib().fse_batch_launch_info(self._h, int(F), C.byref(t), C.byref(d), C.byref(w),
                                                 C.byref(g), C.byref(l)), "fse_batch_launch_info")
-        return dict(threads=t.value, wg_per_cu=w.value, grid=g.value, lds_bytes=l.value)
+        return dict(threads=t.value, dup=bool(d.value), wg_per_cu=w.value, grid=g.value, lds_bytes=l.value)
 
-    def run(self, image, avail, out, status, trace=None, stream=None):
-        """Launch on torch CUDA tensors: image/avail uint8 [F,H,W] (rows may
-        be padded: pitch = stride(1)), out float32 [F,H,W], status int32
-        [n], trace None or uint8 [n, max_iters*16]. Asynchronous."""
+    def set_variant(self, F, threads, dup):
+        _check(_lib.lib().fse_batch_set_variant(self._h, int(F), int(threads), int(bool(dup))),
+               "fse_batch_set_variant")
+
+    def autotune(self, image, avail, out, status, reps=3, stream=None):
+        """Time every compiled workgroup shape on these inputs and keep the
+        fastest per transform size; returns [(F, threads, dup, us), ...]."""
+        import torch
+        self._check_tensors(image, avail, out, status)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        buf = C.create_string_buffer(4096)
+        _check(_lib.lib().fse_batch_autotune(
+            self._h, C.c_void_p(image.data_ptr()), C.c_void_p(avail.data_ptr()), image.stride(1),
+            C.c_void_p(out.data_ptr()), out.stride(1), C.c_void_p(status.data_ptr()), int(reps),
+            C.c_void_p(s.cuda_stream), buf, len(buf)), "fse_batch_autotune")
+        rows = []
+        for line in buf.value.decode().splitlines():
+            f, t, d, us = line.split()
+            rows.append((int(f), int(t), bool(int(d)), float(us)))
+        return rows
+
+    def _check_tensors(self, image, avail, out, status):
         import torch
         nf, H, W = self.shape
         for name, t, dt in (("image", image, torch.uint8), ("avail", avail, torch.uint8),
@@ -113,6 +131,13 @@ class Batch:
             raise ValueError("image and avail must share a pitch")
         if not status.is_cuda or status.dtype != torch.int32 or status.numel() < self.n:
             raise ValueError("status must be a CUDA int32 tensor with one entry per block")
+
+    def run(self, image, avail, out, status, trace=None, stream=None):
+        """Launch on torch CUDA tensors: image/avail uint8 [F,H,W] (rows may
+        be padded: pitch = stride(1)), out float32 [F,H,W], status int32
+        [n], trace None or uint8 [n, max_iters*16]. Asynchronous."""
+        import torch
+        self._check_tensors(image, avail, out, status)
         tptr = None
         if trace is not None:
             if not trace.is_cuda or trace.numel() * trace.element_size() < self.n * self.max_iters * 16:

@@ -130,3 +130,67 @@ def test_batch_invariance_and_determinism():
         sl = (0, slice(b["y0"], b["y0"] + 16), slice(b["x0"], b["x0"] + 16))
         assert np.array_equal(out1[sl], out_all[sl])
         assert np.array_equal(tr1[0], tr_all[i])
+
+
+def _run_batch(wl, variants=None, trace=True):
+    """Run through the Batch API with optional forced variants {F: (threads, dup)}."""
+    import torch
+    import paper_2204_14193_amd as fse
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(wl.distorted).to(dev)
+    av = torch.from_numpy(wl.avail).to(dev)
+    plan = fse.Plan(wl.rho, wl.gamma, int(wl.blocks["iters"].max()))
+    batch = fse.Batch(plan, wl.blocks, *wl.frames.shape)
+    for F, (nt, dup) in (variants or {}).items():
+        batch.set_variant(F, nt, dup)
+    out = (img * (av != 0)).to(torch.float32)
+    status = torch.full((len(wl.blocks),), -1, dtype=torch.int32, device=dev)
+    tb = torch.zeros((len(wl.blocks), batch.max_iters * 16), dtype=torch.uint8, device=dev) if trace else None
+    batch.run(img, av, out, status, tb)
+    torch.cuda.synchronize()
+    res = (out.cpu().numpy(), status.cpu().numpy(), None if tb is None else tb.cpu().numpy())
+    batch.close()
+    plan.close()
+    return res
+
+
+@pytest.mark.parametrize("F,shapes", [
+    (64, [(256, True), (512, True), (256, False), (512, False)]),
+    (32, [(64, True), (128, True), (256, True)]),
+    (128, [(1024, False), (512, False)]),
+])
+def test_every_variant_is_bit_identical(F, shapes):
+    """Each compiled workgroup shape computes identical bits (same per-bin
+    arithmetic, exact argmax), so the autotuner may pick any of them."""
+    wl = _ragged_workload() if F != 64 else workloads.isolated_256(iters=50)
+    _say(f"case variants F={F}: {shapes}")
+    ref = _run_batch(wl, {F: shapes[0]})
+    for shp in shapes[1:]:
+        got = _run_batch(wl, {F: shp})
+        assert np.array_equal(got[1], ref[1]), shp
+        assert np.array_equal(got[0], ref[0]), shp
+        assert np.array_equal(got[2], ref[2]), shp
+
+
+def test_autotune_picks_a_variant_and_keeps_results():
+    import torch
+    import paper_2204_14193_amd as fse
+    wl = workloads.isolated_256(iters=50)
+    _say("case autotune")
+    ref = _run_batch(wl)
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(wl.distorted).to(dev)
+    av = torch.from_numpy(wl.avail).to(dev)
+    plan = fse.Plan(wl.rho, wl.gamma, 50)
+    batch = fse.Batch(plan, wl.blocks, *wl.frames.shape)
+    out = (img * (av != 0)).to(torch.float32)
+    status = torch.zeros(len(wl.blocks), dtype=torch.int32, device=dev)
+    rows = batch.autotune(img, av, out, status, reps=2)
+    assert {r[0] for r in rows} == {64} and len(rows) >= 2
+    best = min(rows, key=lambda r: r[3])
+    info = batch.launch_info(64)
+    assert (info["threads"], info["dup"]) == (best[1], best[2])
+    out.copy_((img * (av != 0)).to(torch.float32))
+    batch.run(img, av, out, status)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), ref[0])
