@@ -162,9 +162,8 @@ def main():
                                f"gamma 0.5, {I} iterations, plain FSE",
                    "blocks": n, "fft": F, "iters": I, "rho": wl.rho, "gamma": wl.gamma},
         "mpixel_per_s": lost_px / (ms_per_step * 1e-3) / 1e6,
-        "launch": dict(info, kernel=f"fse_persistent<64,{info['threads']},{'dup' if info['dup'] else 'single'}>",
-                       avg_ms=launch_ms, autotune_us={f"{t}{'d' if d else 's'}": round(us, 1)
-                                                      for _, t, d, us in tuning}),
+        "launch": dict(info, kernel=f"fse_persistent<64,{info['threads']}>", avg_ms=launch_ms,
+                       autotune_us={str(t): round(us, 1) for _, t, us in tuning}),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(n)},
         "lds_roofline": {"achieved": lds_bytes / (launch_ms * 1e-3) / 1e12, "peak": NOMINAL_LDS_TBPS,

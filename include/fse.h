@@ -141,28 +141,28 @@ fse_status_t fse_extrapolate_batch(fse_batch_t batch, const uint8_t* d_image, co
                                    fse_trace_t* d_trace, void* stream);
 
 /* Launch configuration chosen for transform size F (32, 64 or 128): threads
- * per workgroup, whether W is stored twice (dup), workgroups resident per
- * CU, persistent grid size and dynamic LDS bytes per workgroup. Any output
- * pointer may be null. Returns FSE_ERR_INVALID_ARG if the batch has no
- * block of that size. */
-fse_status_t fse_batch_launch_info(fse_batch_t batch, int32_t F, int32_t* threads, int32_t* dup,
-                                   int32_t* wg_per_cu, int32_t* grid, int32_t* lds_bytes);
+ * per workgroup, workgroups resident per CU, persistent grid size and
+ * dynamic LDS bytes per workgroup. Any output pointer may be null. Returns
+ * FSE_ERR_INVALID_ARG if the batch has no block of that size. */
+fse_status_t fse_batch_launch_info(fse_batch_t batch, int32_t F, int32_t* threads, int32_t* wg_per_cu,
+                                   int32_t* grid, int32_t* lds_bytes);
 
 /* Run the blocks of transform size F with the compiled kernel variant that
- * has `threads` threads per workgroup and stores W once (dup = 0) or twice
- * (dup = 1). Every variant computes bit-identical results; they differ in
- * speed only. Returns FSE_ERR_UNSUPPORTED if no such variant is compiled or
- * it does not fit a compute unit, FSE_ERR_INVALID_ARG if the batch has no
- * block of that size. Host-side; affects later fse_extrapolate_batch calls. */
-fse_status_t fse_batch_set_variant(fse_batch_t batch, int32_t F, int32_t threads, int32_t dup);
+ * has `threads` threads per workgroup (F=32: 64, 128, 256; F=64: 128, 256,
+ * 512; F=128: 512, 1024). Every variant computes bit-identical results;
+ * they differ in speed only. Returns FSE_ERR_UNSUPPORTED if no such variant
+ * is compiled or it does not fit a compute unit, FSE_ERR_INVALID_ARG if the
+ * batch has no block of that size. Host-side; affects later
+ * fse_extrapolate_batch calls. */
+fse_status_t fse_batch_set_variant(fse_batch_t batch, int32_t F, int32_t threads);
 
 /* Autotuner: for every transform size present in the batch, launch every
  * compiled variant once untimed and `reps` times timed (HIP events on
  * `stream`) on the given inputs, and keep the fastest. Synchronous.
  * Arguments as for fse_extrapolate_batch (d_out and d_status receive the
  * results of the last launch). If `report` is not null, up to report_len
- * bytes of text are written to it, one line "F threads dup microseconds"
- * per variant timed. */
+ * bytes of text are written to it, one line "F threads microseconds" per
+ * variant timed. */
 fse_status_t fse_batch_autotune(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail, int64_t pitch,
                                 float* d_out, int64_t out_pitch, int32_t* d_status, int32_t reps, void* stream,
                                 char* report, size_t report_len);

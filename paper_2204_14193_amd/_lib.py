@@ -35,8 +35,8 @@ SIGNATURES = {
     "fse_batch_destroy": (None, [P]),
     "fse_batch_max_iters": (I32, [P]),
     "fse_extrapolate_batch": (I32, [P, P, P, I64, P, I64, P, P, P]),
-    "fse_batch_launch_info": (I32, [P, I32, PI32, PI32, PI32, PI32, PI32]),
-    "fse_batch_set_variant": (I32, [P, I32, I32, I32]),
+    "fse_batch_launch_info": (I32, [P, I32, PI32, PI32, PI32, PI32]),
+    "fse_batch_set_variant": (I32, [P, I32, I32]),
     "fse_batch_autotune": (I32, [P, P, P, I64, P, I64, P, I32, P, C.c_char_p, C.c_size_t]),
     "fse_last_error": (C.c_char_p, []),
 }

@@ -291,14 +291,13 @@ extern "C" void fse_batch_destroy(fse_batch_t batch) {
 
 extern "C" int32_t fse_batch_max_iters(fse_batch_t batch) { return batch ? batch->max_iters : 0; }
 
-extern "C" fse_status_t fse_batch_launch_info(fse_batch_t batch, int32_t F, int32_t* threads, int32_t* dup,
-                                              int32_t* wg_per_cu, int32_t* grid, int32_t* lds_bytes) {
+extern "C" fse_status_t fse_batch_launch_info(fse_batch_t batch, int32_t F, int32_t* threads, int32_t* wg_per_cu,
+                                              int32_t* grid, int32_t* lds_bytes) {
   if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
   const int ci = class_of(F);
   if (ci < 0 || batch->cls[ci].count == 0) return fail(FSE_ERR_INVALID_ARG, "no block of this transform size");
   const fse_batch_s::Cls& c = batch->cls[ci];
   if (threads) *threads = c.v->threads;
-  if (dup) *dup = c.v->dup ? 1 : 0;
   if (wg_per_cu) *wg_per_cu = c.wg_per_cu;
   if (grid) *grid = c.grid;
   if (lds_bytes) *lds_bytes = (int32_t)c.lds;
@@ -358,14 +357,14 @@ static fse_status_t launch_one(fse_batch_t batch, int ci, const uint8_t* d_image
   return FSE_OK;
 }
 
-extern "C" fse_status_t fse_batch_set_variant(fse_batch_t batch, int32_t F, int32_t threads, int32_t dup) {
+extern "C" fse_status_t fse_batch_set_variant(fse_batch_t batch, int32_t F, int32_t threads) {
   if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
   const int ci = class_of(F);
   if (ci < 0 || batch->cls[ci].count == 0) return fail(FSE_ERR_INVALID_ARG, "no block of this transform size");
   const fse::Variant* vs[16];
   const int nv = std::min(fse::variants_for(F, vs, 16), 16);
   for (int i = 0; i < nv; ++i)
-    if (vs[i]->threads == threads && vs[i]->dup == (dup != 0)) return configure(batch, batch->cls[ci], vs[i]);
+    if (vs[i]->threads == threads) return configure(batch, batch->cls[ci], vs[i]);
   return fail(FSE_ERR_UNSUPPORTED, "no compiled kernel with this workgroup shape");
 }
 
@@ -404,8 +403,8 @@ extern "C" fse_status_t fse_batch_autotune(fse_batch_t batch, const uint8_t* d_i
       }
       ms /= (float)reps;
       if (report && used + 64 < report_len)
-        used += (size_t)snprintf(report + used, report_len - used, "%d %d %d %.3f\n", vs[i]->F, vs[i]->threads,
-                                 vs[i]->dup ? 1 : 0, 1000.0 * ms);
+        used += (size_t)snprintf(report + used, report_len - used, "%d %d %.3f\n", vs[i]->F, vs[i]->threads,
+                                 1000.0 * ms);
       if (!best || ms < best_ms) {
         best = vs[i];
         best_ms = ms;

@@ -40,7 +40,6 @@ struct ClassArgs {
 struct Variant {
   int F;
   int threads;         // workgroup size
-  bool dup;            // window spectrum stored twice (rows 0..2F-1)
   const void* fn;      // kernel symbol
 };
 

@@ -13,10 +13,14 @@
 //   4. the model is evaluated on B only, Re{sum c*phi_(u,v)} (the inverse
 //      transform of G restricted to B), and written to HBM.
 //
-// Data placement: R_w lives in VGPRs (BPL bins per lane, bin j*NT + tid);
-// W lives in LDS, stored twice (rows 0..2F-1) when it fits so that the
-// cyclic row shift k-u becomes a compile-time offset; the wave argmax is a
-// DPP reduction, the cross-wave step one LDS exchange and one barrier.
+// Data placement: R_w lives in VGPRs. Wave w of the workgroup owns the RPW
+// consecutive spectrum rows [w*RPW, (w+1)*RPW); its slot j holds the 64
+// consecutive bins w*RPW*F + 64*j + lane. W lives in LDS as its F rows plus
+// copies of its first RPW-1 rows, so the rows a wave reads for a shift
+// (k-u) mod F are always consecutive and every load of the update uses a
+// compile-time offset from one per-iteration base address. The argmax is a
+// DPP reduction inside the wave and one LDS exchange and barrier across
+// waves.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -39,22 +43,57 @@ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(
 template <int N>
 using fvec = float __attribute__((ext_vector_type(N)));
 
+// DPP row operations of gfx9 used below.
+constexpr int kQuadXor1 = 0xb1;      // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4e;      // quad_perm [2,3,0,1]
+constexpr int kRowHalfMirror = 0x141;
+constexpr int kRowMirror = 0x140;
+constexpr int kRowBcast15 = 0x142;
+constexpr int kRowBcast31 = 0x143;
+
+// Lanes that receive no value keep the identity (0 for max, ~0 for min),
+// so the move folds into the max/min instruction.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ unsigned dpp_umax(unsigned x) {
-  const unsigned moved = (unsigned)__builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, ROW_MASK, 0xf, false);
-  return max(x, moved);
+  return max(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, false));
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ unsigned dpp_umin(unsigned x) {
+  return min(x, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)x, CTRL, ROW_MASK, 0xf, false));
 }
 
 // Maximum over the 64 lanes of a wave of non-negative floats given as bit
 // patterns (which order like the values), returned wave-uniform.
 __device__ __forceinline__ unsigned wave_max_bits(unsigned x) {
-  x = dpp_umax<0xb1, 0xf>(x);   // quad_perm [1,0,3,2]
-  x = dpp_umax<0x4e, 0xf>(x);   // quad_perm [2,3,0,1]
-  x = dpp_umax<0x141, 0xf>(x);  // row_half_mirror
-  x = dpp_umax<0x140, 0xf>(x);  // row_mirror: every lane holds its row maximum
-  x = dpp_umax<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
-  x = dpp_umax<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+  x = dpp_umax<kQuadXor1, 0xf>(x);
+  x = dpp_umax<kQuadXor2, 0xf>(x);
+  x = dpp_umax<kRowHalfMirror, 0xf>(x);
+  x = dpp_umax<kRowMirror, 0xf>(x);  // every lane holds its row maximum
+  x = dpp_umax<kRowBcast15, 0xa>(x);  // into rows 1 and 3
+  x = dpp_umax<kRowBcast31, 0xc>(x);  // into rows 2 and 3
   return (unsigned)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+__device__ __forceinline__ unsigned wave_min_u32(unsigned x) {
+  x = dpp_umin<kQuadXor1, 0xf>(x);
+  x = dpp_umin<kQuadXor2, 0xf>(x);
+  x = dpp_umin<kRowHalfMirror, 0xf>(x);
+  x = dpp_umin<kRowMirror, 0xf>(x);
+  x = dpp_umin<kRowBcast15, 0xa>(x);
+  x = dpp_umin<kRowBcast31, 0xc>(x);
+  return (unsigned)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// One step of a 64-bit maximum across lanes (key = hi:lo), all rows active.
+template <int CTRL>
+__device__ __forceinline__ void dpp_max64(unsigned& hi, unsigned& lo) {
+  const unsigned ohi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)hi, CTRL, 0xf, 0xf, false);
+  const unsigned olo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)lo, CTRL, 0xf, 0xf, false);
+  const unsigned long long a = ((unsigned long long)hi << 32) | lo;
+  const unsigned long long b = ((unsigned long long)ohi << 32) | olo;
+  const bool take = b > a;
+  hi = take ? ohi : hi;
+  lo = take ? olo : lo;
 }
 
 __device__ __forceinline__ float readlane_f(float x, int lane) {
@@ -139,13 +178,16 @@ __device__ __forceinline__ void fft_lines(float2* Z, const float2* tw, int t) {
 
 // ------------------------------------------------------------------ kernel
 
-template <int F, int NT, bool DUP>
+template <int F, int NT>
 struct Shape {
-  static constexpr int BPL = F * F / NT;      // bins per lane
   static constexpr int NW = NT / 64;          // waves per workgroup
-  static constexpr int ROWS = NT / F;         // rows covered by one bin slab
-  static constexpr int WROWS = DUP ? 2 * F : F;
-  static_assert(NT % F == 0 && NT % 64 == 0 && BPL * NT == F * F, "bad tiling");
+  static constexpr int BPL = F * F / NT;      // bins per lane
+  static constexpr int RPW = F / NW;          // spectrum rows owned by one wave
+  static constexpr int WROWS = F + RPW - 1;   // W rows in LDS: F plus RPW-1 wrapped copies
+  static constexpr int PH = F > 64 ? F / 64 : 1;  // column phases of a lane
+  static_assert(NT % 64 == 0 && NW <= 16 && F % NW == 0 && BPL * NT == F * F && BPL * 64 == RPW * F,
+                "bad tiling");
+  static_assert(F <= 64 || (F % 64 == 0 && BPL % PH == 0), "bad tiling");
 };
 
 // LDS carve-up of one workgroup (dynamic shared memory).
@@ -153,23 +195,22 @@ struct Lds {
   float2* Wd;      // WROWS x F: FFT buffer, then the window spectrum W
   float2* tw;      // F twiddles exp(-j 2 pi q / F)
   int4* red;       // 2 x NW cross-wave argmax slots (|R|^2 bits, index, re, im)
-  int* misc;       // [0]: block index popped from the queue
   int* cl_idx;     // selections of the current block
   float2* cl_c;    // coefficients of the current block
+  int* misc;       // [0]: block index popped from the queue
 };
 
 // Conceal one block with every lane of the workgroup. All values that steer
 // control flow (block geometry, W0, the selected bin) are wave-uniform, so
 // every branch below is taken by all lanes together. Returns FSE_BLOCK_*.
-template <int F, int NT, bool DUP>
+template <int F, int NT>
 __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, const Lds& s, const int t,
                                              int& parity) {
-  using S = Shape<F, NT, DUP>;
-  constexpr int BPL = S::BPL, NW = S::NW, ROWS = S::ROWS;
+  using S = Shape<F, NT>;
+  constexpr int BPL = S::BPL, NW = S::NW, RPW = S::RPW, PH = S::PH;
   const int lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
-  const int kt = t / F;  // row of this thread's first bin
-  const int lt = t % F;  // column of all of this thread's bins
+  const int wbase = wave * RPW * F;  // linear index of this wave's first bin
   float2* const Wd = s.Wd;
 
   const fse_block_t bd = a.blocks[bi];
@@ -206,28 +247,28 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
   fft_lines<F, NT, false>(Wd, s.tw, t);
   fft_lines<F, NT, true>(Wd, s.tw, t);
 
-  // split Z = R_w + j*alpha*W by conjugate symmetry; R_w goes to VGPRs.
-  // With the doubled layout W is written straight into rows F..2F-1, which
-  // the split does not read, and copied down after the barrier; the single
-  // layout has to hold W in registers until every thread has read Z.
+  // split Z = R_w + j*alpha*W by conjugate symmetry; R_w goes to VGPRs, W
+  // is held until every thread has read Z, then written over it (rows
+  // 0..RPW-2 also into their wrapped copies F..F+RPW-2).
   fvec<BPL> Rx, Ry;
-  float2 Wv[DUP ? 1 : BPL];
+  float2 Wv[BPL];
 #pragma unroll
   for (int j = 0; j < BPL; ++j) {
-    const int k = j * ROWS + kt, l = lt;
+    const int idx = wbase + j * 64 + lane;
+    const int k = idx / F, l = idx % F;
     const float2 zk = Wd[k * F + l];
     const float2 zn = Wd[((F - k) & (F - 1)) * F + ((F - l) & (F - 1))];
     Rx[j] = (zk.x + zn.x) * 0.5f;
     Ry[j] = (zk.y - zn.y) * 0.5f;
-    const float2 w = make_float2((zk.y + zn.y) * (0.5f / kAlpha), (zn.x - zk.x) * (0.5f / kAlpha));
-    if constexpr (DUP) Wd[(k + F) * F + l] = w; else Wv[j] = w;
+    Wv[j] = make_float2((zk.y + zn.y) * (0.5f / kAlpha), (zn.x - zk.x) * (0.5f / kAlpha));
   }
   const float W0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(Wd[0].y))) * (1.0f / kAlpha);
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < BPL; ++j) {
-    const int k = j * ROWS + kt;
-    if constexpr (DUP) Wd[k * F + lt] = Wd[(k + F) * F + lt]; else Wd[k * F + lt] = Wv[j];
+    const int idx = wbase + j * 64 + lane;
+    Wd[idx] = Wv[j];
+    if (idx < (RPW - 1) * F) Wd[idx + F * F] = Wv[j];
   }
   __syncthreads();
 
@@ -244,61 +285,56 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
 
   int sel = 0;
   float sre = 0.f, sim = 0.f, smag = 0.f;
-  // Argmax over the workgroup, lowest linear index j*NT + t on ties:
-  // per-lane maximum, wave maximum by DPP, then one ballot per bin slot j;
-  // the lowest slot with a hit and the lowest lane in it are found with
-  // scalar selects (no branches), and R at that bin is read with a
-  // wave-uniform register index.
+  // Argmax over the workgroup, lowest linear index on ties. In a wave the
+  // linear index grows with (slot j, lane), so the wave's winner is the
+  // lowest slot, then the lowest lane, holding the wave maximum.
   auto select = [&]() {
     unsigned lm = mb[0];
 #pragma unroll
     for (int j = 1; j < BPL; ++j) lm = max(lm, mb[j]);
     const unsigned wm = wave_max_bits(lm);
-    int wj = BPL - 1;
-    unsigned long long wmask = __ballot(mb[BPL - 1] == wm);
+    const unsigned long long cand = __ballot(lm == wm);
+    int wj = 0, wl;
+    if (__builtin_popcountll(cand) == 1) {
+      // usual case: one lane holds the maximum; find its slot on the scalar unit
+      wl = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(cand));
 #pragma unroll
-    for (int j = BPL - 2; j >= 0; --j) {
-      const unsigned long long m = __ballot(mb[j] == wm);
-      const bool hit = m != 0;
-      wj = hit ? j : wj;
-      wmask = hit ? m : wmask;
+      for (int j = BPL - 1; j >= 0; --j)
+        wj = ((unsigned)__builtin_amdgcn_readlane((int)mb[j], wl) == wm) ? j : wj;
+    } else {
+      // several lanes hold it (exact ties, e.g. conjugate bins): take the
+      // lowest (slot, lane) key over the wave
+      int bj = BPL;
+#pragma unroll
+      for (int j = BPL - 1; j >= 0; --j) bj = (mb[j] == wm) ? j : bj;
+      const unsigned key = wave_min_u32((unsigned)(bj * 64 + lane));
+      wj = (int)(key >> 6);
+      wl = (int)(key & 63);
     }
     wj = __builtin_amdgcn_readfirstlane(wj);
-    const int wl = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(wmask));
     const float re = readlane_f(Rx[wj], wl);
     const float im = readlane_f(Ry[wj], wl);
-    const int widx = wj * NT + wave * 64 + wl;
+    const int widx = wbase + wj * 64 + wl;
     if constexpr (NW == 1) {
       sel = widx; sre = re; sim = im; smag = __uint_as_float(wm);
     } else {
       int4* slot = s.red + parity * NW;
       slot[wave] = make_int4((int)wm, widx, __float_as_int(re), __float_as_int(im));  // uniform
       __syncthreads();
-      // Every lane reads the same slots; the comparison runs on wave-uniform
-      // integers and every field is selected explicitly.
-      const int4 s0 = slot[0];
-      unsigned bm = (unsigned)__builtin_amdgcn_readfirstlane(s0.x);
-      int bidx = __builtin_amdgcn_readfirstlane(s0.y);
-      int bre = __builtin_amdgcn_readfirstlane(s0.z);
-      int bim = __builtin_amdgcn_readfirstlane(s0.w);
-#pragma unroll
-      for (int w = 1; w < NW; ++w) {
-        const int4 o = slot[w];
-        const unsigned om = (unsigned)__builtin_amdgcn_readfirstlane(o.x);
-        const int oidx = __builtin_amdgcn_readfirstlane(o.y);
-        const int ore = __builtin_amdgcn_readfirstlane(o.z);
-        const int oim = __builtin_amdgcn_readfirstlane(o.w);
-        const bool take = (om > bm) || (om == bm && oidx < bidx);
-        bm = take ? om : bm;
-        bidx = take ? oidx : bidx;
-        bre = take ? ore : bre;
-        bim = take ? oim : bim;
-      }
+      // lane i < NW holds wave i's candidate; key = (|R|^2 bits, ~index) so
+      // the largest key is the largest value with the lowest index
+      const int4 o = slot[lane & (NW - 1)];
+      unsigned hi = (unsigned)o.x, lo = ~(unsigned)o.y;
+      if constexpr (NW >= 2) dpp_max64<kQuadXor1>(hi, lo);
+      if constexpr (NW >= 4) dpp_max64<kQuadXor2>(hi, lo);
+      if constexpr (NW >= 8) dpp_max64<kRowHalfMirror>(hi, lo);
+      if constexpr (NW >= 16) dpp_max64<kRowMirror>(hi, lo);
+      sel = (int)~(unsigned)__builtin_amdgcn_readfirstlane((int)lo);
+      smag = __uint_as_float((unsigned)__builtin_amdgcn_readfirstlane((int)hi));
+      const int4 win = slot[sel / (RPW * F)];
+      sre = __int_as_float(__builtin_amdgcn_readfirstlane(win.z));
+      sim = __int_as_float(__builtin_amdgcn_readfirstlane(win.w));
       parity ^= 1;
-      sel = bidx;
-      smag = __uint_as_float(bm);
-      sre = __int_as_float(bre);
-      sim = __int_as_float(bim);
     }
   };
   select();
@@ -324,18 +360,20 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
     }
     if (it + 1 == I) break;
     const int u = sel / F, v = sel % F;
-    const int col = (lt - v) & (F - 1);
-    // eq. (18): R_w[k,l] -= c * W[k-u, l-v], fused with |R_w|^2
+    // eq. (18): R_w[k,l] -= c * W[k-u, l-v] over the wave's bins, fused with
+    // |R_w|^2. Row (k-u) mod F of the wave's first bin is r0; the rows of its
+    // later bins follow consecutively (wrapped copies cover the overflow).
+    const int r0 = (wave * RPW - u) & (F - 1);
+    int wb[PH];
+#pragma unroll
+    for (int p = 0; p < PH; ++p) {
+      const int lr = F <= 64 ? lane / F : 0;
+      const int lc = F <= 64 ? lane % F : p * 64 + lane;
+      wb[p] = (r0 + lr) * F + ((lc - v) & (F - 1));
+    }
 #pragma unroll
     for (int j = 0; j < BPL; ++j) {
-      float2 w;
-      if constexpr (DUP) {
-        w = Wd[(kt - u + F) * F + col + j * NT];
-      } else {
-        static_assert(DUP || F >= 64, "single-copy layout needs wave-uniform rows");
-        const int row = (j * ROWS + __builtin_amdgcn_readfirstlane(kt) - u) & (F - 1);
-        w = Wd[row * F + col];
-      }
+      const float2 w = Wd[wb[j % PH] + (j / PH) * 64 * PH];
       float rx = Rx[j], ry = Ry[j];
       rx = fmaf(-cre, w.x, rx);
       rx = fmaf(cim, w.y, rx);
@@ -368,17 +406,17 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
   return FSE_BLOCK_OK;
 }
 
-template <int F, int NT, bool DUP>
+template <int F, int NT>
 __global__ __launch_bounds__(NT) void fse_persistent(ClassArgs a) {
-  using S = Shape<F, NT, DUP>;
+  using S = Shape<F, NT>;
   extern __shared__ __align__(16) unsigned char smem[];
   Lds s;
   s.Wd = reinterpret_cast<float2*>(smem);
   s.tw = s.Wd + S::WROWS * F;
   s.red = reinterpret_cast<int4*>(s.tw + F);
-  s.misc = reinterpret_cast<int*>(s.red + 2 * S::NW);
-  s.cl_idx = s.misc + 4;
-  s.cl_c = reinterpret_cast<float2*>(s.cl_idx + ((a.iters_cap + 1) & ~1));
+  s.cl_c = reinterpret_cast<float2*>(s.red + 2 * S::NW);
+  s.cl_idx = reinterpret_cast<int*>(s.cl_c + a.iters_cap);
+  s.misc = s.cl_idx + a.iters_cap;
 
   const int t = threadIdx.x;
   for (int i = t; i < F; i += NT) s.tw[i] = a.twid[i];
@@ -410,7 +448,7 @@ __global__ __launch_bounds__(NT) void fse_persistent(ClassArgs a) {
     // costs a few instructions.
     int tb = t;
     asm volatile("" : "+v"(tb));
-    const int code = conceal_block<F, NT, DUP>(a, bi, s, tb, parity);
+    const int code = conceal_block<F, NT>(a, bi, s, tb, parity);
     if (wave == 0) a.status[a.orig[bi]] = code;
   }
 
@@ -425,23 +463,17 @@ __global__ __launch_bounds__(NT) void fse_persistent(ClassArgs a) {
   }
 }
 
-template <int F, int NT, bool DUP>
+template <int F, int NT>
 constexpr Variant make_variant() {
-  return Variant{F, NT, DUP, reinterpret_cast<const void*>(&fse_persistent<F, NT, DUP>)};
+  return Variant{F, NT, reinterpret_cast<const void*>(&fse_persistent<F, NT>)};
 }
 
 // Workgroup shapes compiled for each transform size. The first entry of
 // each size is the default; the autotuner may pick another per batch.
 const Variant kVariants[] = {
-    make_variant<32, 64, true>(),
-    make_variant<32, 128, true>(),
-    make_variant<32, 256, true>(),
-    make_variant<64, 256, true>(),
-    make_variant<64, 512, true>(),
-    make_variant<64, 256, false>(),
-    make_variant<64, 512, false>(),
-    make_variant<128, 1024, false>(),
-    make_variant<128, 512, false>(),
+    make_variant<32, 64>(),  make_variant<32, 128>(), make_variant<32, 256>(),
+    make_variant<64, 256>(), make_variant<64, 128>(), make_variant<64, 512>(),
+    make_variant<128, 1024>(), make_variant<128, 512>(),
 };
 
 }  // namespace
@@ -464,10 +496,10 @@ int variants_for(int F, const Variant** out, int cap) {
 
 size_t lds_bytes(const Variant& v, int iters_cap) {
   const size_t F = (size_t)v.F;
-  const size_t rows = v.dup ? 2 * F : F;
   const size_t nw = (size_t)v.threads / 64;
-  const size_t cap = (size_t)((iters_cap + 1) & ~1);
-  return rows * F * 8 + F * 8 + 2 * nw * 16 + 16 + cap * 4 + cap * 8;
+  const size_t rows = F + F / nw - 1;
+  const size_t cap = (size_t)iters_cap;
+  return rows * F * 8 + F * 8 + 2 * nw * 16 + cap * 8 + cap * 4 + 16;
 }
 
 hipError_t launch_class(const Variant& v, const ClassArgs& a, int grid, size_t lds, hipStream_t s) {

@@ -93,18 +93,17 @@ class Batch:
         self.max_iters = _lib.lib().fse_batch_max_iters(h)
 
     def launch_info(self, F):
-        t, d, w, g, l = (C.c_int32() for _ in range(5))
-        _check(_lib.lib().fse_batch_launch_info(self._h, int(F), C.byref(t), C.byref(d), C.byref(w),
+        t, w, g, l = (C.c_int32() for _ in range(4))
+        _check(_lib.lib().fse_batch_launch_info(self._h, int(F), C.byref(t), C.byref(w),
                                                 C.byref(g), C.byref(l)), "fse_batch_launch_info")
-        return dict(threads=t.value, dup=bool(d.value), wg_per_cu=w.value, grid=g.value, lds_bytes=l.value)
+        return dict(threads=t.value, wg_per_cu=w.value, grid=g.value, lds_bytes=l.value)
 
-    def set_variant(self, F, threads, dup):
-        _check(_lib.lib().fse_batch_set_variant(self._h, int(F), int(threads), int(bool(dup))),
-               "fse_batch_set_variant")
+    def set_variant(self, F, threads):
+        _check(_lib.lib().fse_batch_set_variant(self._h, int(F), int(threads)), "fse_batch_set_variant")
 
     def autotune(self, image, avail, out, status, reps=3, stream=None):
         """Time every compiled workgroup shape on these inputs and keep the
-        fastest per transform size; returns [(F, threads, dup, us), ...]."""
+        fastest per transform size; returns [(F, threads, us), ...]."""
         import torch
         self._check_tensors(image, avail, out, status)
         s = stream if stream is not None else torch.cuda.current_stream()
@@ -115,8 +114,8 @@ class Batch:
             C.c_void_p(s.cuda_stream), buf, len(buf)), "fse_batch_autotune")
         rows = []
         for line in buf.value.decode().splitlines():
-            f, t, d, us = line.split()
-            rows.append((int(f), int(t), bool(int(d)), float(us)))
+            f, t, us = line.split()
+            rows.append((int(f), int(t), float(us)))
         return rows
 
     def _check_tensors(self, image, avail, out, status):

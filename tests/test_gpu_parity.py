@@ -133,7 +133,7 @@ def test_batch_invariance_and_determinism():
 
 
 def _run_batch(wl, variants=None, trace=True):
-    """Run through the Batch API with optional forced variants {F: (threads, dup)}."""
+    """Run through the Batch API with optional forced variants {F: threads}."""
     import torch
     import paper_2204_14193_amd as fse
     dev = torch.device("cuda:0")
@@ -141,8 +141,8 @@ def _run_batch(wl, variants=None, trace=True):
     av = torch.from_numpy(wl.avail).to(dev)
     plan = fse.Plan(wl.rho, wl.gamma, int(wl.blocks["iters"].max()))
     batch = fse.Batch(plan, wl.blocks, *wl.frames.shape)
-    for F, (nt, dup) in (variants or {}).items():
-        batch.set_variant(F, nt, dup)
+    for F, nt in (variants or {}).items():
+        batch.set_variant(F, nt)
     out = (img * (av != 0)).to(torch.float32)
     status = torch.full((len(wl.blocks),), -1, dtype=torch.int32, device=dev)
     tb = torch.zeros((len(wl.blocks), batch.max_iters * 16), dtype=torch.uint8, device=dev) if trace else None
@@ -154,11 +154,7 @@ def _run_batch(wl, variants=None, trace=True):
     return res
 
 
-@pytest.mark.parametrize("F,shapes", [
-    (64, [(256, True), (512, True), (256, False), (512, False)]),
-    (32, [(64, True), (128, True), (256, True)]),
-    (128, [(1024, False), (512, False)]),
-])
+@pytest.mark.parametrize("F,shapes", [(64, [256, 128, 512]), (32, [64, 128, 256]), (128, [1024, 512])])
 def test_every_variant_is_bit_identical(F, shapes):
     """Each compiled workgroup shape computes identical bits (same per-bin
     arithmetic, exact argmax), so the autotuner may pick any of them."""
@@ -187,9 +183,9 @@ def test_autotune_picks_a_variant_and_keeps_results():
     status = torch.zeros(len(wl.blocks), dtype=torch.int32, device=dev)
     rows = batch.autotune(img, av, out, status, reps=2)
     assert {r[0] for r in rows} == {64} and len(rows) >= 2
-    best = min(rows, key=lambda r: r[3])
+    best = min(rows, key=lambda r: r[2])
     info = batch.launch_info(64)
-    assert (info["threads"], info["dup"]) == (best[1], best[2])
+    assert info["threads"] == best[1]
     out.copy_((img * (av != 0)).to(torch.float32))
     batch.run(img, av, out, status)
     torch.cuda.synchronize()
