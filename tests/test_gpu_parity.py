@@ -190,3 +190,75 @@ def test_autotune_picks_a_variant_and_keeps_results():
     batch.run(img, av, out, status)
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), ref[0])
+
+
+def _mixed_4k(n_frames=2):
+    return workloads.mixed_4k(seeds=tuple(range(2, 2 + n_frames)))
+
+
+def test_mixed_4k_uneven_batch_parity():
+    """Two 3840x2160 frames with 305 losses each of 4, 8, 16 and 32 pixels
+    (borders 8..16, F in {32, 64, 128}, I in {50, 100, 200, 500}) in one
+    call; a stratified seeded sample (3 blocks per loss size and transform
+    size) replayed against the oracle, with per-stratum FP32 error printed."""
+    wl = _mixed_4k()
+    _say(f"case mixed-4k x2: {len(wl.blocks)} blocks, F classes {sorted(set(wl.blocks['fft'].tolist()))}")
+    out, st, tr = _run(wl)
+    assert (st == 0).all()
+    lost = wl.avail == 0
+    assert np.isfinite(out[lost]).all()
+    rng = np.random.default_rng(3)
+    idx = []
+    for bs in (4, 8, 16, 32):
+        for F in (32, 64, 128):
+            cand = np.flatnonzero((wl.blocks["bh"] == bs) & (wl.blocks["fft"] == F))
+            if len(cand):
+                # prefer short runs for the oracle's sake, but include one long one
+                cand = cand[np.argsort(wl.blocks["iters"][cand], kind="stable")]
+                pick = list(rng.choice(cand[:max(3, len(cand) // 2)], min(2, len(cand)), replace=False))
+                pick.append(cand[-1])
+                idx += [int(i) for i in pick]
+    rows = parity.check_blocks(wl.frames, wl.avail, wl.blocks, wl.rho, wl.gamma, tr, out, idx)
+    for r in rows:
+        b = wl.blocks[r["index"]]
+        _say(f"  size {b['bh']:2d} F={b['fft']:3d} I={b['iters']:3d}: coef_max={r['coef_max']:.2e} "
+             f"coef_l2={r['coef_l2']:.2e} pix_maxabs={r['pix_maxabs']:.2e} ties={r['ties']}")
+
+
+def test_graph_capture_replays_match_eager():
+    """The launch is capture-safe: replaying a captured call several times,
+    with eager work in between, reproduces the eager result bit for bit."""
+    import torch
+    import paper_2204_14193_amd as fse
+    wl = _mixed_4k(1)
+    _say(f"case graph capture: {len(wl.blocks)} blocks")
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(wl.distorted).to(dev)
+    av = torch.from_numpy(wl.avail).to(dev)
+    plan = fse.Plan(wl.rho, wl.gamma, 500)
+    batch = fse.Batch(plan, wl.blocks, *wl.frames.shape)
+    base = (img * (av != 0)).to(torch.float32)
+    out = base.clone()
+    status = torch.zeros(len(wl.blocks), dtype=torch.int32, device=dev)
+    batch.run(img, av, out, status)
+    torch.cuda.synchronize()
+    eager = out.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    out.copy_(base)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        batch.run(img, av, out, status, stream=s)
+    for rep in range(3):
+        out.copy_(base)
+        status.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert (status == 0).all(), rep
+        assert torch.equal(out, eager), rep
+        _ = (img.float() * 2).sum().item()          # unrelated eager work between replays
+    del g
+    batch.close()
+    plan.close()
