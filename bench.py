@@ -36,7 +36,7 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(n_blocks):
+def measured_traffic(n_blocks, workload):
     """HBM bytes per launch from committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     counts, scaled by the copy-kernel calibration; None when the counters
     were taken on another version of the kernel."""
@@ -45,7 +45,7 @@ def measured_traffic(n_blocks):
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != kernel_source_hash() or t.get("blocks") != n_blocks:
+    if t.get("kernel_sha") != kernel_source_hash() or t.get("blocks") != n_blocks or t.get("workload") != workload:
         return None
     return float(t["bytes_per_launch"])
 
@@ -91,7 +91,7 @@ def cpu_baseline(wl, n_sample, seed=5):
         pass
     return {"value": n_sample / dt, "unit": "blocks/s", "cores": cores, "kind": "oracle",
             "sample": f"{n_sample} seeded blocks of the same workload (FP64 direct projection, "
-                      f"{int(wl.blocks[0]['iters'])} iterations each), {dt:.1f} s wall on {cpu}"}
+                      f"{int(wl.blocks[idx[0]]['iters'])} iterations each), {dt:.1f} s wall on {cpu}"}
 
 
 def main():
@@ -101,7 +101,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--frames", type=int, default=8)
     ap.add_argument("--iters", type=int, default=100)
-    ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--workload", default="random-1080p-16x16",
+                    choices=["random-1080p-16x16", "random-1080p-8x8", "mixed-4k"],
+                    help="the metric's workload (default) or one of the other configurations")
+    ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the (untimed) autotuner")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -115,18 +118,30 @@ def main():
     import paper_2204_14193_amd as fse
     from synth import workloads
 
-    wl = workloads.random_1080p_16x16(seeds=tuple(range(99, 99 + args.frames)), iters=args.iters)
+    if args.workload == "random-1080p-16x16":
+        wl = workloads.random_1080p_16x16(seeds=tuple(range(99, 99 + args.frames)), iters=args.iters)
+        desc = (f"{args.frames}x 1920x1080 synthetic frames, 804 isolated 16x16 losses per frame (10%), "
+                f"border 16 (48x48 area), 64x64 transform, rho 0.8, gamma 0.5, {args.iters} iterations, plain FSE")
+    elif args.workload == "random-1080p-8x8":
+        wl = workloads.random_1080p_8x8(iters=200)
+        desc = ("1920x1080 synthetic frame, 3240 isolated 8x8 losses (10%), border 16 (40x40 area), "
+                "64x64 transform, rho 0.8, gamma 0.5, 200 iterations, plain FSE")
+    else:
+        wl = workloads.mixed_4k(seeds=tuple(range(2, 2 + args.frames)))
+        desc = (f"{args.frames}x 3840x2160 synthetic frames, 305 losses each of 4, 8, 16, 32 px per frame (5%), "
+                "border 8-16, transform 32/64/128, 50-500 iterations, plain FSE")
     n = len(wl.blocks)
     dev = torch.device("cuda:0")
     img = torch.from_numpy(wl.distorted).to(dev)
     av = torch.from_numpy(wl.avail).to(dev)
     out = img.to(torch.float32)
     status = torch.zeros(n, dtype=torch.int32, device=dev)
-    plan = fse.Plan(wl.rho, wl.gamma, args.iters)
+    plan = fse.Plan(wl.rho, wl.gamma, int(wl.blocks["iters"].max()))
     batch = fse.Batch(plan, wl.blocks, *wl.frames.shape)
     stream = torch.cuda.current_stream()
     tuning = batch.autotune(img, av, out, status, reps=2) if not args.no_tune else []
-    info = batch.launch_info(64)
+    classes = sorted(set(int(f) for f in wl.blocks["fft"]))
+    info = {F: batch.launch_info(F) for F in classes}
 
     for _ in range(args.warmup):
         batch.run(img, av, out, status)
@@ -146,26 +161,26 @@ def main():
     launch_ms = float(np.mean([s.elapsed_time(e) for s, e in ev]))
     ms_per_step = wall * 1e3 / args.steps
 
-    F, I = 64, args.iters
     blocks_per_s = n / (ms_per_step * 1e-3)
     lost_px = int(wl.blocks["bh"].astype(np.int64) @ wl.blocks["bw"].astype(np.int64))
-    flop = FLOP_PER_BIN_ITER * F * F * I * n
+    bin_iters = int(np.sum(wl.blocks["fft"].astype(np.int64) ** 2 * wl.blocks["iters"].astype(np.int64)))
+    flop = FLOP_PER_BIN_ITER * bin_iters
     achieved = flop / (launch_ms * 1e-3) / 1e12
-    lds_bytes = LDS_BYTES_PER_BIN_ITER * F * F * I * n
+    lds_bytes = LDS_BYTES_PER_BIN_ITER * bin_iters
     rec = {
         "metric": METRIC, "value": blocks_per_s, "unit": "blocks/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.frames}x 1920x1080 synthetic frames, 804 isolated 16x16 losses "
-                               f"per frame (10%), border 16 (48x48 area), 64x64 transform, rho 0.8, "
-                               f"gamma 0.5, {I} iterations, plain FSE",
-                   "blocks": n, "fft": F, "iters": I, "rho": wl.rho, "gamma": wl.gamma},
+        "config": {"workload": desc, "name": args.workload, "blocks": n,
+                   "fft": classes[0] if len(classes) == 1 else classes,
+                   "iters": int(wl.blocks["iters"][0]) if len(set(wl.blocks["iters"].tolist())) == 1 else "mixed",
+                   "rho": wl.rho, "gamma": wl.gamma},
         "mpixel_per_s": lost_px / (ms_per_step * 1e-3) / 1e6,
-        "launch": dict(info, kernel=f"fse_persistent<64,{info['threads']}>", avg_ms=launch_ms,
-                       autotune_us={str(t): round(us, 1) for _, t, us in tuning}),
+        "launch": {"kernels": {f"fse_persistent<{F},{info[F]['threads']}>": info[F] for F in classes},
+                   "avg_ms": launch_ms, "autotune_us": {f"{F}/{t}": round(us, 1) for F, t, us in tuning}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(n)},
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(n, args.workload)},
         "lds_roofline": {"achieved": lds_bytes / (launch_ms * 1e-3) / 1e12, "peak": NOMINAL_LDS_TBPS,
                          "unit": "TB/s", "frac": lds_bytes / (launch_ms * 1e-3) / 1e12 / NOMINAL_LDS_TBPS,
                          "note": "algorithmic 24 B/bin/iteration against the nominal LDS bandwidth"},

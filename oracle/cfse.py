@@ -221,6 +221,15 @@ def extrapolate_block(frames, avail, blk, rho, gamma, forced=None, init=None, ca
 _SHARED = {}
 
 
+def _one_blas_thread():
+    """Worker processes use one BLAS thread each (the matrices are small)."""
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
+
+
 def _block_worker(i):
     frames, avail, blocks, rho, gamma = _SHARED["job"]
     res = extrapolate_block(frames, avail, blocks[i], rho, gamma)
@@ -236,7 +245,7 @@ def extrapolate_frames(frames, avail, blocks, rho, gamma, processes=1):
     try:
         if processes > 1:
             import multiprocessing as mp
-            with mp.get_context("fork").Pool(processes) as pool:
+            with mp.get_context("fork").Pool(processes, initializer=_one_blas_thread) as pool:
                 vals = pool.map(_block_worker, range(len(blocks)),
                                 chunksize=max(1, len(blocks) // (4 * processes)))
         else:
