@@ -167,6 +167,91 @@ fse_status_t fse_batch_autotune(fse_batch_t batch, const uint8_t* d_image, const
                                 float* d_out, int64_t out_pitch, int32_t* d_status, int32_t reps, void* stream,
                                 char* report, size_t report_len);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start. Not part of the paper's method: a small network reads
+ * each 48x48 area and scores every bin of the 64x64 transform; the K best
+ * bins become a candidate set. FSE iterations restricted to the candidates
+ * (argmax and update over those bins only, eqs. (12), (13), (18)) produce
+ * the first coefficients, which are then applied to the whole spectrum
+ * (eq. (18) once per distinct bin), and the usual FSE iterations over all
+ * bins continue from there. Plain FSE is the fallback.
+ *
+ * Network: input [B][48][48][2] BF16 (channel 0: (s - mean over A)/64 on
+ * the support area A, channel 1: indicator of A); four 3x3 stride-2
+ * convolutions with bias and ReLU, 2->32->32->32->32 channels
+ * (48->24->12->6->3 pixels); a dense head from the 288 features to 4096
+ * logits (bin k*64+l). BF16 weights and activations, FP32 accumulation.
+ * Parameters are one flat FP32 vector (fse_cnn_num_params elements, in the
+ * order conv1..conv4 weight [32][3][3][Cin] and bias [32], head weight
+ * [4096][288] and bias [4096]).
+ * ---------------------------------------------------------------------- */
+typedef struct fse_cnn_s* fse_cnn_t;
+
+/* Number of parameters of the network (1212096). */
+int64_t fse_cnn_num_params(void);
+
+/* Create the network on the current device for batches of up to max_batch
+ * samples: FP32 master parameters (He-uniform weights drawn from `seed`,
+ * zero biases), their BF16 working copy and the Adam state. Training
+ * buffers are allocated by the first forward that keeps activations. */
+fse_status_t fse_cnn_create(int32_t max_batch, uint64_t seed, fse_cnn_t* out);
+void fse_cnn_destroy(fse_cnn_t net);
+
+/* Host copies of the FP32 master parameters: set (also refreshes the BF16
+ * copy) and get; get may also fetch the accumulated gradient (h_grads not
+ * null). Synchronous. */
+fse_status_t fse_cnn_set_params(fse_cnn_t net, const float* h_params);
+fse_status_t fse_cnn_get_params(fse_cnn_t net, float* h_params, float* h_grads);
+
+/* Network inputs for every block of a batch whose areas are all 48x48:
+ * d_x [n_blocks][48][48][2] BF16, row i for block i of the caller's list.
+ * Returns FSE_ERR_UNSUPPORTED for other area sizes. Asynchronous. */
+fse_status_t fse_cnn_patches(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail, int64_t pitch,
+                             uint16_t* d_x, void* stream);
+
+/* Forward pass: d_logits [B][4096] FP32. keep_activations != 0 stores what
+ * fse_cnn_backward needs. Asynchronous. */
+fse_status_t fse_cnn_forward(fse_cnn_t net, const uint16_t* d_x, int32_t B, float* d_logits,
+                             int32_t keep_activations, void* stream);
+
+/* Loss and gradient of the last forward (same d_x and B, activations kept):
+ * binary cross-entropy of d_logits against the target bits
+ * d_target_bits [B][128] (bit l%32 of word l/32 = bin l selected), positives
+ * weighted by pos_weight, averaged over B*4096 terms; adds the loss to
+ * *d_loss and writes the gradient into the network's gradient buffer
+ * (cleared by fse_cnn_adam). B must be a multiple of 16. Asynchronous. */
+fse_status_t fse_cnn_backward(fse_cnn_t net, const uint16_t* d_x, const float* d_logits,
+                              const uint32_t* d_target_bits, int32_t B, float pos_weight, float* d_loss,
+                              void* stream);
+
+/* One Adam step on the FP32 master parameters with bias correction, then
+ * the BF16 copy is refreshed and the gradient cleared. Asynchronous. */
+fse_status_t fse_cnn_adam(fse_cnn_t net, float lr, float beta1, float beta2, float eps, void* stream);
+
+/* Candidate sets: for each of B rows of d_logits [B][4096], the K bins with
+ * the largest logits (ties to the lower bin), written in ascending bin order
+ * to d_cand [B][K]; d_flags[b] = 1 if row b holds a NaN (the block then
+ * falls back to plain FSE), else 0. Asynchronous. */
+fse_status_t fse_cnn_topk(const float* d_logits, int32_t B, int32_t K, int16_t* d_cand, int32_t* d_flags,
+                          void* stream);
+
+/* Warm-started cFSE for a batch whose blocks all use F = 64. For block i
+ * with d_flags[i] == 0: restricted_iters iterations over the kc candidates
+ * d_cand[i][0..kc) (ascending bins; kc in {128, 256, 512}), their distinct
+ * coefficients applied to the whole spectrum, then the block's `iters` full
+ * iterations. A block with d_flags[i] != 0 runs fallback_iters plain
+ * iterations instead. Output, status and threading as
+ * fse_extrapolate_batch; d_trace (optional) rows have
+ * fse_warm_trace_stride(...) entries: the restricted selections first. */
+fse_status_t fse_warm_extrapolate_batch(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail,
+                                        int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
+                                        fse_trace_t* d_trace, const int16_t* d_cand, const int32_t* d_flags,
+                                        int32_t kc, int32_t restricted_iters, int32_t fallback_iters,
+                                        void* stream);
+
+/* restricted_iters + max(largest block iteration count, fallback_iters). */
+int32_t fse_warm_trace_stride(fse_batch_t batch, int32_t restricted_iters, int32_t fallback_iters);
+
 /* Static description of the most recent error on this thread (never null). */
 const char* fse_last_error(void);
 

@@ -39,6 +39,18 @@ SIGNATURES = {
     "fse_batch_set_variant": (I32, [P, I32, I32]),
     "fse_batch_autotune": (I32, [P, P, P, I64, P, I64, P, I32, P, C.c_char_p, C.c_size_t]),
     "fse_last_error": (C.c_char_p, []),
+    "fse_cnn_num_params": (I64, []),
+    "fse_cnn_create": (I32, [I32, C.c_uint64, C.POINTER(P)]),
+    "fse_cnn_destroy": (None, [P]),
+    "fse_cnn_set_params": (I32, [P, P]),
+    "fse_cnn_get_params": (I32, [P, P, P]),
+    "fse_cnn_patches": (I32, [P, P, P, I64, P, P]),
+    "fse_cnn_forward": (I32, [P, P, I32, P, I32, P]),
+    "fse_cnn_backward": (I32, [P, P, P, P, I32, C.c_float, P, P]),
+    "fse_cnn_adam": (I32, [P, C.c_float, C.c_float, C.c_float, C.c_float, P]),
+    "fse_cnn_topk": (I32, [P, I32, I32, P, P, P]),
+    "fse_warm_extrapolate_batch": (I32, [P, P, P, I64, P, I64, P, P, P, P, I32, I32, I32, P]),
+    "fse_warm_trace_stride": (I32, [P, I32, I32]),
 }
 
 _lib = None

@@ -1,0 +1,578 @@
+// Warm-start network kernels for gfx950: BF16 storage, FP32 accumulation.
+//
+// Dense contractions (the four convolutions and the head, forward and
+// backward) run on v_mfma_f32_32x32x16_bf16. Its operand layout: lane l
+// supplies 8 consecutive K elements k = 8*(l/32)+i of row l%32 of A (M x K)
+// and of column l%32 of B (K x N); accumulator i of lane l holds
+// D[8*(i/4) + 4*(l/32) + i%4][l%32].
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "cnn_internal.h"
+#include "fse.h"
+
+namespace fse {
+namespace cnn {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// FP32 -> BF16, round to nearest even (NaN stays NaN).
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ f32x16 mfma(uint4 a, uint4 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                 0, 0, 0);
+}
+
+__device__ __forceinline__ int drow(int i, int lane) { return 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3); }
+
+// ------------------------------------------------------------------ patches
+// Network input of one 48x48 area: channel 0 = (s - mean_A(s)) / 64 on the
+// support area A, channel 1 = indicator of A; both 0 elsewhere.
+__global__ __launch_bounds__(256) void k_patches(const uint8_t* img, const uint8_t* avail, int64_t pitch, int H,
+                                                 int W, const fse_block_t* blocks, const int32_t* orig, int n,
+                                                 uint16_t* x) {
+  __shared__ float red_s[256];
+  __shared__ float red_c[256];
+  const int b = blockIdx.x;
+  if (b >= n) return;
+  const int t = threadIdx.x;
+  const fse_block_t bd = blocks[b];
+  const int bo = bd.border;
+  const int ya = bd.y0 - bo, xa = bd.x0 - bo;
+  const uint8_t* im = img + (int64_t)bd.frame * H * pitch;
+  const uint8_t* av = avail + (int64_t)bd.frame * H * pitch;
+  float sum = 0.f, cnt = 0.f;
+  float sv[9];
+  bool ia[9];
+#pragma unroll
+  for (int r = 0; r < 9; ++r) {
+    const int e = t + 256 * r;
+    const int m = e / kIn, c = e % kIn;
+    const int y = ya + m, xx = xa + c;
+    const bool inB = m >= bo && m < bo + bd.bh && c >= bo && c < bo + bd.bw;
+    bool a = false;
+    float s = 0.f;
+    if (!inB && y >= 0 && y < H && xx >= 0 && xx < W) {
+      const int64_t p = (int64_t)y * pitch + xx;
+      a = av[p] != 0;
+      s = (float)im[p];
+    }
+    ia[r] = a;
+    sv[r] = s;
+    sum += a ? s : 0.f;
+    cnt += a ? 1.f : 0.f;
+  }
+  red_s[t] = sum;
+  red_c[t] = cnt;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      red_s[t] += red_s[t + w];
+      red_c[t] += red_c[t + w];
+    }
+    __syncthreads();
+  }
+  const float mu = red_c[0] > 0.f ? red_s[0] / red_c[0] : 0.f;
+  uint32_t* out = reinterpret_cast<uint32_t*>(x + (int64_t)orig[b] * kPatchElems);
+#pragma unroll
+  for (int r = 0; r < 9; ++r) {
+    const int e = t + 256 * r;
+    const uint32_t v = ia[r] ? ((uint32_t)f2bf((sv[r] - mu) * (1.0f / 64.0f)) | (0x3f80u << 16)) : 0u;
+    out[e] = v;
+  }
+}
+
+// ------------------------------------------------------------------ forward
+// One 3x3 stride-2 convolution with bias and ReLU, activations in LDS
+// (NHWC, BF16), as an implicit GEMM: rows = output pixels, columns = the 32
+// output channels, depth = (tap, input channel).
+template <int CIN, int HIN>
+__device__ __forceinline__ void conv_layer(const uint16_t* in, uint16_t* out, const uint16_t* w,
+                                           const uint16_t* bias, int t) {
+  constexpr int HO = HIN / 2, P = HO * HO, K = 9 * CIN, KP = (K + 15) / 16 * 16;
+  constexpr int MT = (P + 31) / 32;
+  const int lane = t & 63, wave = t >> 6;
+  const int n = lane & 31;
+  const int kh = 8 * (lane >> 5);
+  const float bn = bf2f(bias[n]);
+  for (int tile = wave; tile < MT; tile += 4) {
+    const int m = tile * 32 + (lane & 31);
+    const int oy = m / HO, ox = m % HO;
+    const bool mv = m < P;
+    f32x16 acc = {};
+#pragma unroll
+    for (int ks = 0; ks < KP / 16; ++ks) {
+      const int k0 = ks * 16 + kh;
+      uint4 av = {0u, 0u, 0u, 0u}, bv = {0u, 0u, 0u, 0u};
+      if constexpr (CIN == kCh) {
+        const int tap = k0 >> 5, c0 = k0 & 31;
+        const int iy = 2 * oy - 1 + tap / 3, ix = 2 * ox - 1 + tap % 3;
+        if (mv && iy >= 0 && iy < HIN && ix >= 0 && ix < HIN)
+          av = *reinterpret_cast<const uint4*>(in + (iy * HIN + ix) * CIN + c0);
+        bv = *reinterpret_cast<const uint4*>(w + n * K + k0);
+      } else {
+        uint32_t a4[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int k = k0 + 2 * q;
+          if (k < K) {
+            const int tap = k / CIN;
+            const int iy = 2 * oy - 1 + tap / 3, ix = 2 * ox - 1 + tap % 3;
+            if (mv && iy >= 0 && iy < HIN && ix >= 0 && ix < HIN)
+              a4[q] = *reinterpret_cast<const uint32_t*>(in + (iy * HIN + ix) * CIN);
+          }
+        }
+        av = make_uint4(a4[0], a4[1], a4[2], a4[3]);
+        uint32_t b4[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int k = k0 + 2 * q;
+          const uint32_t lo = k < K ? w[n * K + k] : 0u;
+          const uint32_t hi = k + 1 < K ? w[n * K + k + 1] : 0u;
+          b4[q] = lo | (hi << 16);
+        }
+        bv = make_uint4(b4[0], b4[1], b4[2], b4[3]);
+      }
+      acc = mfma(av, bv, acc);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int p = tile * 32 + drow(i, lane);
+      if (p < P) out[p * kCh + n] = f2bf(fmaxf(acc[i] + bn, 0.f));
+    }
+  }
+}
+
+// The whole convolution stack for one sample per workgroup, activations in
+// LDS; writes the 288 features and, for training, every activation.
+__global__ __launch_bounds__(256) void k_forward(const uint16_t* x, int B, const uint16_t* prm, uint16_t* feats,
+                                                 uint16_t* acts) {
+  __shared__ __align__(16) uint16_t a0[kPatchElems];
+  __shared__ __align__(16) uint16_t a1[24 * 24 * kCh];
+  __shared__ __align__(16) uint16_t a2[12 * 12 * kCh];
+  __shared__ __align__(16) uint16_t a3[6 * 6 * kCh];
+  __shared__ __align__(16) uint16_t a4[3 * 3 * kCh];
+  const int b = blockIdx.x;
+  if (b >= B) return;
+  const int t = threadIdx.x;
+  const uint4* src = reinterpret_cast<const uint4*>(x + (int64_t)b * kPatchElems);
+  for (int i = t; i < kPatchElems / 8; i += 256) reinterpret_cast<uint4*>(a0)[i] = src[i];
+  __syncthreads();
+  conv_layer<2, 48>(a0, a1, prm + kOffW[0], prm + kOffB[0], t);
+  __syncthreads();
+  conv_layer<kCh, 24>(a1, a2, prm + kOffW[1], prm + kOffB[1], t);
+  __syncthreads();
+  conv_layer<kCh, 12>(a2, a3, prm + kOffW[2], prm + kOffB[2], t);
+  __syncthreads();
+  conv_layer<kCh, 6>(a3, a4, prm + kOffW[3], prm + kOffB[3], t);
+  __syncthreads();
+  for (int i = t; i < kFeat; i += 256) feats[(int64_t)b * kFeat + i] = a4[i];
+  if (acts) {
+    uint16_t* dst = acts + (int64_t)b * kActElems;
+    for (int i = t; i < 18432 / 8; i += 256)
+      reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(a1)[i];
+    for (int i = t; i < 4608 / 8; i += 256)
+      reinterpret_cast<uint4*>(dst + kActOff[1])[i] = reinterpret_cast<const uint4*>(a2)[i];
+    for (int i = t; i < 1152 / 8; i += 256)
+      reinterpret_cast<uint4*>(dst + kActOff[2])[i] = reinterpret_cast<const uint4*>(a3)[i];
+    for (int i = t; i < kFeat; i += 256) dst[kActOff[3] + i] = a4[i];
+  }
+}
+
+// ------------------------------------------------------------------ GEMM
+// C = A * B^T: each wave computes one 32x32 tile, a workgroup 64x64.
+__global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* A, int lda, const uint16_t* Bm, int ldb, float* C,
+                                                 int ldc, const uint16_t* bias, int M, int N, int K) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int tm = blockIdx.x * 64 + (wave & 1) * 32;
+  const int tn = blockIdx.y * 64 + (wave >> 1) * 32;
+  if (tm >= M || tn >= N) return;
+  const int m = tm + (lane & 31), n = tn + (lane & 31);
+  const int kh = 8 * (lane >> 5);
+  const uint16_t* pa = A + (int64_t)m * lda + kh;
+  const uint16_t* pb = Bm + (int64_t)n * ldb + kh;
+  const bool ma = m < M, nb = n < N;
+  f32x16 acc = {};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const uint4 av = ma ? *reinterpret_cast<const uint4*>(pa + k0) : make_uint4(0u, 0u, 0u, 0u);
+    const uint4 bv = nb ? *reinterpret_cast<const uint4*>(pb + k0) : make_uint4(0u, 0u, 0u, 0u);
+    acc = mfma(av, bv, acc);
+  }
+  const int col = tn + (lane & 31);
+  if (col >= N) return;
+  const float bb = bias ? bf2f(bias[col]) : 0.f;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int row = tm + drow(i, lane);
+    if (row < M) C[(int64_t)row * ldc + col] = acc[i] + bb;
+  }
+}
+
+// ------------------------------------------------------------------ helpers
+__global__ __launch_bounds__(256) void k_transpose_u16(const uint16_t* in, int rows, int cols, int ld_in,
+                                                       uint16_t* out, int ld_out) {
+  __shared__ uint16_t tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int y = by + r, x = bx + tx;
+    if (y < rows && x < cols) tile[r][tx] = in[(int64_t)y * ld_in + x];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int y = bx + r, x = by + tx;  // out row = in column
+    if (y < cols && x < rows) out[(int64_t)y * ld_out + x] = tile[tx][r];
+  }
+}
+
+__global__ void k_f32_to_bf16(const float* in, int64_t n, uint16_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = f2bf(in[i]);
+}
+
+// col[(b*P + p)][k] = input of layer `layer` under tap k of output pixel p.
+template <int CIN, int HIN>
+__global__ void k_im2col(const uint16_t* act, int B, int64_t act_stride, uint16_t* col) {
+  constexpr int HO = HIN / 2, P = HO * HO, K = 9 * CIN, KP = (K + 15) / 16 * 16;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)B * P * KP) return;
+  const int k = (int)(i % KP);
+  const int64_t r = i / KP;
+  const int p = (int)(r % P);
+  const int b = (int)(r / P);
+  uint16_t v = 0;
+  if (k < K) {
+    const int tap = k / CIN, c = k % CIN;
+    const int iy = 2 * (p / HO) - 1 + tap / 3, ix = 2 * (p % HO) - 1 + tap % 3;
+    if (iy >= 0 && iy < HIN && ix >= 0 && ix < HIN) v = act[b * act_stride + (iy * HIN + ix) * CIN + c];
+  }
+  col[i] = v;
+}
+
+// dact[b][q][c] = sum of dcol[b*P + p][tap*CIN + c] over the (p, tap) that
+// read input pixel q (the adjoint of k_im2col, a gather, no atomics).
+template <int CIN, int HIN>
+__global__ void k_col2im(const float* dcol, int B, float* dact) {
+  constexpr int HO = HIN / 2, P = HO * HO, K = 9 * CIN, KP = (K + 15) / 16 * 16;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)B * HIN * HIN * CIN) return;
+  const int c = (int)(i % CIN);
+  const int64_t r = i / CIN;
+  const int q = (int)(r % (HIN * HIN));
+  const int b = (int)(r / (HIN * HIN));
+  const int iy = q / HIN, ix = q % HIN;
+  float acc = 0.f;
+#pragma unroll
+  for (int ky = 0; ky < 3; ++ky) {
+    const int ty = iy + 1 - ky;
+    if (ty < 0 || (ty & 1) || (ty >> 1) >= HO) continue;
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx) {
+      const int tx = ix + 1 - kx;
+      if (tx < 0 || (tx & 1) || (tx >> 1) >= HO) continue;
+      const int p = (ty >> 1) * HO + (tx >> 1);
+      acc += dcol[((int64_t)b * P + p) * KP + (ky * 3 + kx) * CIN + c];
+    }
+  }
+  dact[i] = acc;
+}
+
+// dz = dact where the layer's (saved, per-sample strided) ReLU output is > 0.
+__global__ void k_relu_mask(const float* dact, const uint16_t* act, int per_sample, int64_t act_stride, int64_t n,
+                            float* dz, uint16_t* dzb) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint16_t a = act[(i / per_sample) * act_stride + (i % per_sample)];
+  const float v = (a != 0 && !(a & 0x8000)) ? dact[i] : 0.f;
+  dz[i] = v;
+  dzb[i] = f2bf(v);
+}
+
+// out[c] += sum over rows of in[row][c]; workgroups take row chunks.
+__global__ __launch_bounds__(256) void k_colsum_add(const float* in, int rows, int cols, float* out) {
+  __shared__ float part[256];
+  const int t = threadIdx.x;
+  const int groups = 256 / cols > 0 ? 256 / cols : 1;
+  const int c = t % cols, g = t / cols;
+  const int col_block = cols > 256 ? blockIdx.y * 256 : 0;
+  float acc = 0.f;
+  if (cols <= 256) {
+    if (g < groups)
+      for (int r = blockIdx.x * groups + g; r < rows; r += gridDim.x * groups) acc += in[(int64_t)r * cols + c];
+    part[t] = acc;
+    __syncthreads();
+    if (g == 0) {
+      for (int j = 1; j < groups; ++j) acc += part[t + j * cols];
+      atomicAdd(&out[c], acc);
+    }
+  } else {
+    const int cc = col_block + t;
+    if (cc < cols) {
+      for (int r = blockIdx.x; r < rows; r += gridDim.x) acc += in[(int64_t)r * cols + cc];
+      atomicAdd(&out[cc], acc);
+    }
+  }
+}
+
+// Binary cross-entropy with logits, positives weighted, mean over B*4096:
+// writes the gradient and adds the batch loss to *loss.
+__global__ __launch_bounds__(256) void k_bce(const float* logits, const uint32_t* bits, int B, float pw,
+                                             float* dlogits, float* loss) {
+  __shared__ float red[256];
+  const int b = blockIdx.x;
+  if (b >= B) return;
+  const int t = threadIdx.x;
+  const float scale = 1.0f / ((float)B * (float)kBins);
+  float acc = 0.f;
+  for (int j = t; j < kBins; j += 256) {
+    const float z = logits[(int64_t)b * kBins + j];
+    const float y = (bits[(int64_t)b * (kBins / 32) + (j >> 5)] >> (j & 31)) & 1u ? 1.f : 0.f;
+    const float sp_pos = fmaxf(z, 0.f) + log1pf(expf(-fabsf(z)));   // softplus(z)  = -log(1 - s)
+    const float sp_neg = sp_pos - z;                                 // softplus(-z) = -log s
+    acc += pw * y * sp_neg + (1.f - y) * sp_pos;
+    const float s = 1.f / (1.f + expf(-z));
+    dlogits[(int64_t)b * kBins + j] = (pw * y * (s - 1.f) + (1.f - y) * s) * scale;
+  }
+  red[t] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  if (t == 0) atomicAdd(loss, red[0] * scale);
+}
+
+// Adam on FP32 master weights; refreshes the BF16 working copy and clears
+// the gradient for the next step.
+__global__ void k_adam(float* master, float* grad, float* m, float* v, uint16_t* work, int64_t n, float lr,
+                       float b1, float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float g = grad[i];
+  const float mi = b1 * m[i] + (1.f - b1) * g;
+  const float vi = b2 * v[i] + (1.f - b2) * g * g;
+  m[i] = mi;
+  v[i] = vi;
+  const float w = master[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+  master[i] = w;
+  work[i] = f2bf(w);
+  grad[i] = 0.f;
+}
+
+// ------------------------------------------------------------------ top-K
+// Per sample, the K bins with the largest logits (ties: lower bin first),
+// written in ascending bin order; flags[b] = 1 if a logit is NaN.
+__device__ __forceinline__ uint32_t order_key(float v) {
+  uint32_t u = __float_as_uint(v);
+  if (u == 0x80000000u) u = 0u;  // -0 ties with +0
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__global__ __launch_bounds__(256) void k_topk(const float* logits, int B, int K, int16_t* cand, int32_t* flags) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t scan[256];
+  __shared__ uint32_t sh[4];
+  const int b = blockIdx.x;
+  if (b >= B) return;
+  const int t = threadIdx.x;
+  uint32_t key[16];
+  bool nan = false;
+  const float4* src = reinterpret_cast<const float4*>(logits + (int64_t)b * kBins + 16 * t);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float4 v = src[q];
+    const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      nan = nan || (vv[r] != vv[r]);
+      key[4 * q + r] = order_key(vv[r]);
+    }
+  }
+  if (t == 0) sh[3] = 0;
+  __syncthreads();
+  if (nan) atomicOr(&sh[3], 1u);
+  // radix select of the K-th largest key, 8 bits at a time from the top
+  uint32_t prefix = 0, mask = 0, remaining = (uint32_t)K;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    hist[t] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if ((key[j] & mask) == prefix) atomicAdd(&hist[(key[j] >> shift) & 255u], 1u);
+    __syncthreads();
+    if (t == 0) {
+      uint32_t above = 0;
+      int d = 255;
+      for (; d > 0; --d) {
+        if (above + hist[d] >= remaining) break;
+        above += hist[d];
+      }
+      sh[0] = prefix | ((uint32_t)d << shift);
+      sh[1] = remaining - above;
+    }
+    __syncthreads();
+    prefix = sh[0];
+    remaining = sh[1];
+    mask |= 255u << shift;
+    __syncthreads();
+  }
+  const uint32_t T = prefix;   // the K-th largest key; `remaining` keys equal to T are taken
+  uint32_t gt = 0, eq = 0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    gt += key[j] > T;
+    eq += key[j] == T;
+  }
+  // exclusive scan of eq (to rank ties by bin) then of the selected counts
+  scan[t] = eq;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const uint32_t v = t >= o ? scan[t - o] : 0u;
+    __syncthreads();
+    scan[t] += v;
+    __syncthreads();
+  }
+  const uint32_t eq_before = scan[t] - eq;
+  const uint32_t eq_take = eq_before >= remaining ? 0u : min(eq, remaining - eq_before);
+  const uint32_t mine = gt + eq_take;
+  __syncthreads();
+  scan[t] = mine;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const uint32_t v = t >= o ? scan[t - o] : 0u;
+    __syncthreads();
+    scan[t] += v;
+    __syncthreads();
+  }
+  uint32_t pos = scan[t] - mine;
+  uint32_t eq_seen = 0;
+  int16_t* out = cand + (int64_t)b * K;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    bool take = key[j] > T;
+    if (key[j] == T) {
+      take = eq_seen < eq_take;
+      ++eq_seen;
+    }
+    if (take && pos < (uint32_t)K) out[pos++] = (int16_t)(16 * t + j);
+  }
+  if (t == 0) flags[b] = sh[3] ? 1 : 0;
+}
+
+}  // namespace
+
+hipError_t patches(const uint8_t* img, const uint8_t* avail, int64_t pitch, int32_t H, int32_t W, const void* blocks,
+                   const int32_t* orig, int32_t n, uint16_t* x, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_patches, dim3(n), dim3(256), 0, s, img, avail, pitch, H, W,
+                     reinterpret_cast<const fse_block_t*>(blocks), orig, n, x);
+  return hipGetLastError();
+}
+
+hipError_t forward(const uint16_t* x, int32_t B, const uint16_t* prm, uint16_t* feats, uint16_t* acts,
+                   hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_forward, dim3(B), dim3(256), 0, s, x, B, prm, feats, acts);
+  return hipGetLastError();
+}
+
+hipError_t gemm_nt(const uint16_t* A, int lda, const uint16_t* B, int ldb, float* C, int ldc,
+                   const uint16_t* bias_bf16, int M, int N, int K, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gemm_nt, dim3((M + 63) / 64, (N + 63) / 64), dim3(256), 0, s, A, lda, B, ldb, C, ldc,
+                     bias_bf16, M, N, K);
+  return hipGetLastError();
+}
+
+hipError_t transpose_u16(const uint16_t* in, int rows, int cols, int ld_in, uint16_t* out, int ld_out,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_transpose_u16, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(256), 0, s, in, rows, cols,
+                     ld_in, out, ld_out);
+  return hipGetLastError();
+}
+
+hipError_t f32_to_bf16(const float* in, int64_t n, uint16_t* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_f32_to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, n, out);
+  return hipGetLastError();
+}
+
+hipError_t im2col(const uint16_t* act, int32_t B, int layer, uint16_t* col, hipStream_t s) {
+  const int HO = kHin[layer] / 2;
+  const int64_t n = (int64_t)B * HO * HO * kKpad[layer];
+  const dim3 g((unsigned)((n + 255) / 256)), blk(256);
+  // layer 0 reads the network input, the others the saved activations
+  const int64_t st = layer == 0 ? kPatchElems : kActElems;
+  switch (layer) {
+    case 0: hipLaunchKernelGGL((k_im2col<2, 48>), g, blk, 0, s, act, B, st, col); break;
+    case 1: hipLaunchKernelGGL((k_im2col<kCh, 24>), g, blk, 0, s, act, B, st, col); break;
+    case 2: hipLaunchKernelGGL((k_im2col<kCh, 12>), g, blk, 0, s, act, B, st, col); break;
+    default: hipLaunchKernelGGL((k_im2col<kCh, 6>), g, blk, 0, s, act, B, st, col); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t col2im(const float* dcol, int32_t B, int layer, float* dact, hipStream_t s) {
+  const int64_t n = (int64_t)B * kHin[layer] * kHin[layer] * kCin[layer];
+  const dim3 g((unsigned)((n + 255) / 256)), blk(256);
+  switch (layer) {
+    case 1: hipLaunchKernelGGL((k_col2im<kCh, 24>), g, blk, 0, s, dcol, B, dact); break;
+    case 2: hipLaunchKernelGGL((k_col2im<kCh, 12>), g, blk, 0, s, dcol, B, dact); break;
+    case 3: hipLaunchKernelGGL((k_col2im<kCh, 6>), g, blk, 0, s, dcol, B, dact); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t relu_mask(const float* dact, const uint16_t* act, int per_sample, int64_t act_stride, int64_t n,
+                     float* dz, uint16_t* dz_bf16, hipStream_t s) {
+  hipLaunchKernelGGL(k_relu_mask, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dact, act, per_sample,
+                     act_stride, n, dz, dz_bf16);
+  return hipGetLastError();
+}
+
+hipError_t colsum_add(const float* in, int rows, int cols, float* out, hipStream_t s) {
+  if (cols <= 256) {
+    const int groups = 256 / cols;
+    const int grid = std::min(1024, (rows + groups * 64 - 1) / (groups * 64) + 1);
+    hipLaunchKernelGGL(k_colsum_add, dim3(grid), dim3(256), 0, s, in, rows, cols, out);
+  } else {
+    hipLaunchKernelGGL(k_colsum_add, dim3(std::min(rows, 64), (cols + 255) / 256), dim3(256), 0, s, in, rows, cols,
+                       out);
+  }
+  return hipGetLastError();
+}
+
+hipError_t bce(const float* logits, const uint32_t* target_bits, int32_t B, float pos_weight, float* dlogits,
+               float* loss, hipStream_t s) {
+  hipLaunchKernelGGL(k_bce, dim3(B), dim3(256), 0, s, logits, target_bits, B, pos_weight, dlogits, loss);
+  return hipGetLastError();
+}
+
+hipError_t adam(float* master, float* grad, float* m, float* v, uint16_t* work, int64_t n, float lr, float b1,
+                float b2, float eps, float c1, float c2, hipStream_t s) {
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, master, grad, m, v, work, n, lr,
+                     b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t topk(const float* logits, int32_t B, int32_t K, int16_t* cand, int32_t* flags, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_topk, dim3(B), dim3(256), 0, s, logits, B, K, cand, flags);
+  return hipGetLastError();
+}
+
+}  // namespace cnn
+}  // namespace fse

@@ -14,6 +14,7 @@
 #include <numeric>
 #include <vector>
 
+#include "cnn_internal.h"
 #include "fse.h"
 #include "fse_internal.h"
 
@@ -25,6 +26,12 @@ fse_status_t fail(fse_status_t code, const char* msg) {
   g_error = msg;
   return code;
 }
+
+}  // namespace
+
+void fse::set_error(const char* msg) { g_error = msg; }
+
+namespace {
 
 constexpr int kSizes[3] = {128, 64, 32};  // class order: longest blocks first
 
@@ -65,6 +72,9 @@ struct fse_batch_s {
     int32_t grid = 0, wg_per_cu = 0;
     size_t lds = 0;
   } cls[3];
+  Cls warm;                                // warm-started launch of the F = 64 class
+  int32_t warm_kc = 0, warm_ir = -1, warm_fb = -1;
+  bool all_48 = false;                     // every area is 48 x 48 (network input size)
 };
 
 extern "C" const char* fse_last_error(void) { return g_error; }
@@ -235,6 +245,9 @@ extern "C" fse_status_t fse_batch_create(fse_plan_t plan, const fse_block_t* h_b
     if (cx != cy) return cx < cy;
     return h_blocks[x].iters > h_blocks[y].iters;
   });
+  b->all_48 = true;
+  for (int32_t i = 0; i < n_blocks; ++i)
+    b->all_48 = b->all_48 && h_blocks[i].bh + 2 * h_blocks[i].border == 48 && h_blocks[i].bw + 2 * h_blocks[i].border == 48;
   std::vector<fse_block_t> sorted(n_blocks);
   for (int32_t i = 0; i < n_blocks; ++i) {
     sorted[i] = h_blocks[order[i]];
@@ -306,7 +319,8 @@ extern "C" fse_status_t fse_batch_launch_info(fse_batch_t batch, int32_t F, int3
 
 static fse_status_t launch_one(fse_batch_t batch, int ci, const uint8_t* d_image, const uint8_t* d_avail,
                                int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
-                               fse_trace_t* d_trace, hipStream_t s);
+                               fse_trace_t* d_trace, hipStream_t s, const int16_t* cand = nullptr,
+                               const int32_t* flags = nullptr);
 
 extern "C" fse_status_t fse_extrapolate_batch(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail,
                                               int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
@@ -329,9 +343,10 @@ extern "C" fse_status_t fse_extrapolate_batch(fse_batch_t batch, const uint8_t* 
 
 static fse_status_t launch_one(fse_batch_t batch, int ci, const uint8_t* d_image, const uint8_t* d_avail,
                                int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
-                               fse_trace_t* d_trace, hipStream_t s) {
+                               fse_trace_t* d_trace, hipStream_t s, const int16_t* cand, const int32_t* flags) {
   {
-    const fse_batch_s::Cls& c = batch->cls[ci];
+    const bool warm = cand != nullptr;
+    const fse_batch_s::Cls& c = warm ? batch->warm : batch->cls[ci];
     fse::ClassArgs a;
     a.img = d_image;
     a.avail = d_avail;
@@ -351,6 +366,14 @@ static fse_status_t launch_one(fse_batch_t batch, int ci, const uint8_t* d_image
     a.twid = batch->tables->twid[ci];
     a.gamma = batch->plan->gamma;
     a.queue = batch->d_queue + 32 * ci;
+    a.cand = cand;
+    a.flags = flags;
+    a.ir = warm ? batch->warm_ir : 0;
+    a.fb_iters = warm ? batch->warm_fb : 0;
+    if (warm) {
+      a.iters_cap = c.iters_cap;
+      a.trace_stride = batch->warm_ir + std::max(batch->max_iters, batch->warm_fb);
+    }
     if (fse::launch_class(*c.v, a, c.grid, c.lds, s) != hipSuccess)
       return fail(FSE_ERR_HIP, "kernel launch failed");
   }
@@ -418,4 +441,53 @@ extern "C" fse_status_t fse_batch_autotune(fse_batch_t batch, const uint8_t* d_i
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return st;
+}
+
+extern "C" fse_status_t fse_cnn_patches(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail,
+                                        int64_t pitch, uint16_t* d_x, void* stream) {
+  if (!batch || !d_image || !d_avail || !d_x) return fail(FSE_ERR_INVALID_ARG, "null argument");
+  if (!batch->all_48) return fail(FSE_ERR_UNSUPPORTED, "network inputs need 48x48 areas");
+  if (pitch < batch->W) return fail(FSE_ERR_INVALID_ARG, "pitch smaller than the width");
+  if (fse::cnn::patches(d_image, d_avail, pitch, batch->H, batch->W, batch->d_blocks, batch->d_orig, batch->n, d_x,
+                        reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+    return fail(FSE_ERR_HIP, "kernel launch failed");
+  return FSE_OK;
+}
+
+extern "C" int32_t fse_warm_trace_stride(fse_batch_t batch, int32_t restricted_iters, int32_t fallback_iters) {
+  return batch ? restricted_iters + std::max(batch->max_iters, fallback_iters) : 0;
+}
+
+extern "C" fse_status_t fse_warm_extrapolate_batch(fse_batch_t batch, const uint8_t* d_image,
+                                                   const uint8_t* d_avail, int64_t pitch, float* d_out,
+                                                   int64_t out_pitch, int32_t* d_status, fse_trace_t* d_trace,
+                                                   const int16_t* d_cand, const int32_t* d_flags, int32_t kc,
+                                                   int32_t restricted_iters, int32_t fallback_iters, void* stream) {
+  if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
+  if (batch->n == 0) return FSE_OK;
+  if (!d_image || !d_avail || !d_out || !d_status || !d_cand || !d_flags)
+    return fail(FSE_ERR_INVALID_ARG, "null device pointer");
+  if (pitch < batch->W || out_pitch < batch->W) return fail(FSE_ERR_INVALID_ARG, "pitch smaller than the width");
+  const int ci = class_of(64);
+  if (batch->cls[ci].count != batch->n) return fail(FSE_ERR_UNSUPPORTED, "the warm start needs F = 64 blocks only");
+  if (restricted_iters < 0 || fallback_iters < 0 ||
+      restricted_iters + std::max(batch->max_iters, fallback_iters) > batch->plan->max_iters)
+    return fail(FSE_ERR_INVALID_ARG, "iteration counts outside the plan's limit");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != batch->device)
+    return fail(FSE_ERR_INVALID_ARG, "batch was created on another device");
+  if (kc != batch->warm_kc || restricted_iters != batch->warm_ir || fallback_iters != batch->warm_fb) {
+    const fse::Variant* v = fse::warm_variant_for(64, kc);
+    if (!v) return fail(FSE_ERR_UNSUPPORTED, "no warm-start kernel for this candidate count");
+    fse_batch_s::Cls c = batch->cls[ci];
+    c.iters_cap = restricted_iters + std::max(c.iters_cap, fallback_iters);
+    fse_status_t st = configure(batch, c, v);
+    if (st != FSE_OK) return st;
+    batch->warm = c;
+    batch->warm_kc = kc;
+    batch->warm_ir = restricted_iters;
+    batch->warm_fb = fallback_iters;
+  }
+  return launch_one(batch, ci, d_image, d_avail, pitch, d_out, out_pitch, d_status, d_trace,
+                    reinterpret_cast<hipStream_t>(stream), d_cand, d_flags);
 }

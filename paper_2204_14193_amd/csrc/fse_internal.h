@@ -34,24 +34,36 @@ struct ClassArgs {
   const float2* twid;         // F entries: exp(-j 2 pi q / F)
   float gamma;
   int32_t* queue;             // [2]: next block, finished workgroups
+  // warm-started form only
+  const int16_t* cand;        // [caller's n_blocks][kc] candidate bins, ascending
+  const int32_t* flags;       // [caller's n_blocks]: nonzero = run plain FSE
+  int32_t ir;                 // restricted iterations
+  int32_t fb_iters;           // full iterations of a block that falls back
 };
 
 // One compiled kernel variant for transform size F.
 struct Variant {
   int F;
   int threads;         // workgroup size
+  int kc;              // candidates per block (warm-started form), 0 = plain
   const void* fn;      // kernel symbol
 };
 
 // Default kernel variant for transform size F (32, 64, 128), or null.
 const Variant* variant_for(int F);
 
-// All compiled variants for F; returns their number, fills up to cap.
+// Warm-started variant for F with kc candidates per block, or null.
+const Variant* warm_variant_for(int F, int kc);
+
+// All compiled plain variants for F; returns their number, fills up to cap.
 int variants_for(int F, const Variant** out, int cap);
 
 // Dynamic LDS bytes a variant needs for a class whose largest iteration
 // count is iters_cap.
 size_t lds_bytes(const Variant& v, int iters_cap);
+
+// Record the message returned by fse_last_error() on this thread.
+void set_error(const char* msg);
 
 // Launch one class; grid = number of persistent workgroups.
 hipError_t launch_class(const Variant& v, const ClassArgs& a, int grid, size_t lds, hipStream_t s);

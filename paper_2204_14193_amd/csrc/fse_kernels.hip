@@ -197,17 +197,23 @@ struct Lds {
   int4* red;       // 2 x NW cross-wave argmax slots (|R|^2 bits, index, re, im)
   int* cl_idx;     // selections of the current block
   float2* cl_c;    // coefficients of the current block
-  int* misc;       // [0]: block index popped from the queue
+  int* misc;       // [0]: block index popped from the queue, [1]: warm list length
+  int* wl_idx;     // warm start: distinct bins chosen in the restricted phase
+  float2* wl_c;    // warm start: their accumulated coefficients
 };
 
 // Conceal one block with every lane of the workgroup. All values that steer
 // control flow (block geometry, W0, the selected bin) are wave-uniform, so
 // every branch below is taken by all lanes together. Returns FSE_BLOCK_*.
-template <int F, int NT>
+// KC > 0 compiles the warm-started form: KC candidate bins per block (from
+// the network), KC/64 per lane of wave 0.
+template <int F, int NT, int KC>
 __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, const Lds& s, const int t,
                                              int& parity) {
   using S = Shape<F, NT>;
   constexpr int BPL = S::BPL, NW = S::NW, RPW = S::RPW, PH = S::PH;
+  constexpr int CPL = KC > 0 ? KC / 64 : 1;  // candidates per lane of wave 0
+  static_assert(KC % 64 == 0 && KC <= 1024, "candidate count must be a multiple of 64");
   const int lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int wbase = wave * RPW * F;  // linear index of this wave's first bin
@@ -247,6 +253,27 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
   fft_lines<F, NT, false>(Wd, s.tw, t);
   fft_lines<F, NT, true>(Wd, s.tw, t);
 
+  // Warm start: wave 0 takes R_w at its candidate bins straight from the
+  // transform (same arithmetic as the split below, so the values are the
+  // bits the split produces for those bins). A block whose network output
+  // was unusable (flag set) runs plain FSE with the fallback count.
+  const bool warm = KC > 0 && __builtin_amdgcn_readfirstlane(a.flags[orig]) == 0;
+  const int I_full = KC > 0 && !warm ? a.fb_iters : I;
+  float cRx[CPL], cRy[CPL];
+  int cIdx[CPL];
+  if (KC > 0 && warm && wave == 0) {
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+      const int ci = a.cand[(int64_t)orig * KC + j * 64 + lane];
+      const int k = ci / F, l = ci % F;
+      const float2 zk = Wd[k * F + l];
+      const float2 zn = Wd[((F - k) & (F - 1)) * F + ((F - l) & (F - 1))];
+      cIdx[j] = ci;
+      cRx[j] = (zk.x + zn.x) * 0.5f;
+      cRy[j] = (zk.y - zn.y) * 0.5f;
+    }
+  }
+
   // split Z = R_w + j*alpha*W by conjugate symmetry; R_w goes to VGPRs, W
   // is held until every thread has read Z, then written over it (rows
   // 0..RPW-2 also into their wrapped copies F..F+RPW-2).
@@ -282,6 +309,123 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
   unsigned mb[BPL];
 #pragma unroll
   for (int j = 0; j < BPL; ++j) mb[j] = __float_as_uint(fmaf(Ry[j], Ry[j], Rx[j] * Rx[j]));
+
+  int tbase = 0;  // trace position of the first full iteration
+  if constexpr (KC > 0) {
+    if (warm) {
+      // Restricted phase (wave 0): FSE iterations whose argmax and update run
+      // over the candidate bins only; the candidates are in ascending bin
+      // order, so the lowest slot on ties is the lowest bin.
+      if (wave == 0) {
+        float cCx[CPL], cCy[CPL];
+        unsigned cm[CPL];
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+          cCx[j] = 0.f;
+          cCy[j] = 0.f;
+          cm[j] = __float_as_uint(fmaf(cRy[j], cRy[j], cRx[j] * cRx[j]));
+        }
+        for (int it = 0; it < a.ir; ++it) {
+          unsigned lm = cm[0];
+#pragma unroll
+          for (int j = 1; j < CPL; ++j) lm = max(lm, cm[j]);
+          const unsigned wm = wave_max_bits(lm);
+          int bj = CPL;
+#pragma unroll
+          for (int j = CPL - 1; j >= 0; --j) bj = (cm[j] == wm) ? j : bj;
+          const unsigned key = wave_min_u32((unsigned)(bj * 64 + lane));
+          const int wj = __builtin_amdgcn_readfirstlane((int)(key >> 6));
+          const int wl = __builtin_amdgcn_readfirstlane((int)(key & 63));
+          int bin = 0;
+          float re = 0.f, im = 0.f;
+#pragma unroll
+          for (int j = 0; j < CPL; ++j) {
+            if (j == wj) {
+              bin = __builtin_amdgcn_readlane(cIdx[j], wl);
+              re = readlane_f(cRx[j], wl);
+              im = readlane_f(cRy[j], wl);
+            }
+          }
+          const float cre = gW * re, cim = gW * im;      // eq. (13)
+          s.cl_idx[it] = bin;                             // uniform stores
+          s.cl_c[it] = make_float2(cre, cim);
+          if (a.trace) {
+            fse_trace_t rec;
+            rec.u = (uint16_t)(bin / F);
+            rec.v = (uint16_t)(bin % F);
+            rec.c_re = cre;
+            rec.c_im = cim;
+            rec.r2 = __uint_as_float(wm);
+            a.trace[(int64_t)orig * a.trace_stride + it] = rec;
+          }
+          const int u = bin / F, v = bin % F;
+#pragma unroll
+          for (int j = 0; j < CPL; ++j) {
+            const bool hit = (j == wj) && (lane == wl);
+            cCx[j] += hit ? cre : 0.f;
+            cCy[j] += hit ? cim : 0.f;
+            const int k = cIdx[j] / F, l = cIdx[j] % F;
+            const float2 w = Wd[((k - u) & (F - 1)) * F + ((l - v) & (F - 1))];
+            float rx = cRx[j], ry = cRy[j];
+            rx = fmaf(-cre, w.x, rx);
+            rx = fmaf(cim, w.y, rx);
+            ry = fmaf(-cre, w.y, ry);
+            ry = fmaf(-cim, w.x, ry);
+            cRx[j] = rx;
+            cRy[j] = ry;
+            cm[j] = __float_as_uint(fmaf(ry, ry, rx * rx));
+          }
+        }
+        // compact the candidates that received a coefficient
+        int base = 0;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+          const bool nz = cCx[j] != 0.f || cCy[j] != 0.f;
+          const unsigned long long m = __ballot(nz);
+          const int pos = base + __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+          if (nz) {
+            s.wl_idx[pos] = cIdx[j];
+            s.wl_c[pos] = make_float2(cCx[j], cCy[j]);
+          }
+          base += __builtin_popcountll(m);
+        }
+        s.misc[1] = base;  // uniform store
+      }
+      __syncthreads();
+      // Apply the restricted model to the whole spectrum (eq. (18) once per
+      // distinct bin with its accumulated coefficient).
+      const int nw = __builtin_amdgcn_readfirstlane(s.misc[1]);
+      for (int q = 0; q < nw; ++q) {
+        const int bin = __builtin_amdgcn_readfirstlane(s.wl_idx[q]);
+        const float2 c = s.wl_c[q];
+        const float cre = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(c.x)));
+        const float cim = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(c.y)));
+        const int u = bin / F, v = bin % F;
+        const int r0 = (wave * RPW - u) & (F - 1);
+        int wb[PH];
+#pragma unroll
+        for (int p = 0; p < PH; ++p) {
+          const int lr = F <= 64 ? lane / F : 0;
+          const int lc = F <= 64 ? lane % F : p * 64 + lane;
+          wb[p] = (r0 + lr) * F + ((lc - v) & (F - 1));
+        }
+#pragma unroll
+        for (int j = 0; j < BPL; ++j) {
+          const float2 w = Wd[wb[j % PH] + (j / PH) * 64 * PH];
+          float rx = Rx[j], ry = Ry[j];
+          rx = fmaf(-cre, w.x, rx);
+          rx = fmaf(cim, w.y, rx);
+          ry = fmaf(-cre, w.y, ry);
+          ry = fmaf(-cim, w.x, ry);
+          Rx[j] = rx;
+          Ry[j] = ry;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < BPL; ++j) mb[j] = __float_as_uint(fmaf(Ry[j], Ry[j], Rx[j] * Rx[j]));
+      tbase = a.ir;
+    }
+  }
 
   int sel = 0;
   float sre = 0.f, sim = 0.f, smag = 0.f;
@@ -340,14 +484,14 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
   select();
 
   bool finite = true;
-  for (int it = 0; it < I; ++it) {
+  for (int it = 0; it < I_full; ++it) {
     const float cre = gW * sre, cim = gW * sim;          // eq. (13)
     finite = finite && isfinite(cre) && isfinite(cim);
     // All lanes of wave 0 store the same uniform values: no lane-divergent
     // region inside the loops (see the persistent loop below).
     if (wave == 0) {
-      s.cl_idx[it] = sel;                                 // eq. (15): G[u,v] += F*F*c
-      s.cl_c[it] = make_float2(cre, cim);
+      s.cl_idx[tbase + it] = sel;                         // eq. (15): G[u,v] += F*F*c
+      s.cl_c[tbase + it] = make_float2(cre, cim);
       if (a.trace) {
         fse_trace_t rec;
         rec.u = (uint16_t)(sel / F);
@@ -355,10 +499,10 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
         rec.c_re = cre;
         rec.c_im = cim;
         rec.r2 = smag;
-        a.trace[(int64_t)orig * a.trace_stride + it] = rec;
+        a.trace[(int64_t)orig * a.trace_stride + tbase + it] = rec;
       }
     }
-    if (it + 1 == I) break;
+    if (it + 1 == I_full) break;
     const int u = sel / F, v = sel % F;
     // eq. (18): R_w[k,l] -= c * W[k-u, l-v] over the wave's bins, fused with
     // |R_w|^2. Row (k-u) mod F of the wave's first bin is r0; the rows of its
@@ -386,14 +530,22 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
     select();
   }
   __syncthreads();
+  if (KC > 0 && warm) {
+    // the restricted phase's coefficients must be finite as well
+    for (int it = 0; it < a.ir; ++it) {
+      const float2 c = s.cl_c[it];
+      finite = finite && isfinite(c.x) && isfinite(c.y);
+    }
+  }
   if (!finite) return FSE_BLOCK_NONFINITE;
 
   // 4. model on B: Re{ sum_nu c_nu exp(j 2 pi (u m + v n) / F) }
+  const int n_coef = tbase + I_full;
   for (int p = t; p < bh * bw; p += NT) {
     const int i = p / bw, jj = p % bw;
     const int m = bo + i, n = bo + jj;
     float acc = 0.f;
-    for (int it = 0; it < I; ++it) {
+    for (int it = 0; it < n_coef; ++it) {
       const int sidx = s.cl_idx[it];
       const int q = ((sidx / F) * m + (sidx % F) * n) & (F - 1);
       const float2 e = s.tw[q];  // exp(-j theta): Re{c e^{j theta}} = c.x e.x + c.y e.y
@@ -406,7 +558,7 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
   return FSE_BLOCK_OK;
 }
 
-template <int F, int NT>
+template <int F, int NT, int KC>
 __global__ __launch_bounds__(NT) void fse_persistent(ClassArgs a) {
   using S = Shape<F, NT>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -415,8 +567,10 @@ __global__ __launch_bounds__(NT) void fse_persistent(ClassArgs a) {
   s.tw = s.Wd + S::WROWS * F;
   s.red = reinterpret_cast<int4*>(s.tw + F);
   s.cl_c = reinterpret_cast<float2*>(s.red + 2 * S::NW);
-  s.cl_idx = reinterpret_cast<int*>(s.cl_c + a.iters_cap);
-  s.misc = s.cl_idx + a.iters_cap;
+  s.wl_c = s.cl_c + a.iters_cap;
+  s.cl_idx = reinterpret_cast<int*>(s.wl_c + KC);
+  s.wl_idx = s.cl_idx + a.iters_cap;
+  s.misc = s.wl_idx + KC;
 
   const int t = threadIdx.x;
   for (int i = t; i < F; i += NT) s.tw[i] = a.twid[i];
@@ -448,7 +602,7 @@ __global__ __launch_bounds__(NT) void fse_persistent(ClassArgs a) {
     // costs a few instructions.
     int tb = t;
     asm volatile("" : "+v"(tb));
-    const int code = conceal_block<F, NT>(a, bi, s, tb, parity);
+    const int code = conceal_block<F, NT, KC>(a, bi, s, tb, parity);
     if (wave == 0) a.status[a.orig[bi]] = code;
   }
 
@@ -463,31 +617,39 @@ __global__ __launch_bounds__(NT) void fse_persistent(ClassArgs a) {
   }
 }
 
-template <int F, int NT>
+template <int F, int NT, int KC = 0>
 constexpr Variant make_variant() {
-  return Variant{F, NT, reinterpret_cast<const void*>(&fse_persistent<F, NT>)};
+  return Variant{F, NT, KC, reinterpret_cast<const void*>(&fse_persistent<F, NT, KC>)};
 }
 
 // Workgroup shapes compiled for each transform size. The first entry of
-// each size is the default; the autotuner may pick another per batch.
+// each size is the default; the autotuner may pick another per batch. The
+// entries with KC > 0 are the warm-started forms.
 const Variant kVariants[] = {
     make_variant<32, 64>(),  make_variant<32, 128>(), make_variant<32, 256>(),
     make_variant<64, 256>(), make_variant<64, 128>(), make_variant<64, 512>(),
     make_variant<128, 1024>(), make_variant<128, 512>(),
+    make_variant<64, 256, 256>(), make_variant<64, 256, 128>(), make_variant<64, 256, 512>(),
 };
 
 }  // namespace
 
 const Variant* variant_for(int F) {
   for (const Variant& v : kVariants)
-    if (v.F == F) return &v;
+    if (v.F == F && v.kc == 0) return &v;
+  return nullptr;
+}
+
+const Variant* warm_variant_for(int F, int kc) {
+  for (const Variant& v : kVariants)
+    if (v.F == F && v.kc == kc) return &v;
   return nullptr;
 }
 
 int variants_for(int F, const Variant** out, int cap) {
   int n = 0;
   for (const Variant& v : kVariants)
-    if (v.F == F) {
+    if (v.F == F && v.kc == 0) {
       if (n < cap) out[n] = &v;
       ++n;
     }
@@ -499,7 +661,8 @@ size_t lds_bytes(const Variant& v, int iters_cap) {
   const size_t nw = (size_t)v.threads / 64;
   const size_t rows = F + F / nw - 1;
   const size_t cap = (size_t)iters_cap;
-  return rows * F * 8 + F * 8 + 2 * nw * 16 + cap * 8 + cap * 4 + 16;
+  const size_t kc = (size_t)v.kc;
+  return rows * F * 8 + F * 8 + 2 * nw * 16 + (cap + kc) * 8 + (cap + kc) * 4 + 16;
 }
 
 hipError_t launch_class(const Variant& v, const ClassArgs& a, int grid, size_t lds, hipStream_t s) {

@@ -1,0 +1,135 @@
+"""Python binding of the learned warm start (argument marshalling only).
+
+The network, its training and the warm-started FSE all run in libfse's HIP
+kernels; torch tensors provide device memory and streams.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import _lib
+from .fse import _check
+
+N_BINS = 4096
+PATCH = (48, 48, 2)
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "warm_cnn.npz")
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def num_params():
+    return int(_lib.lib().fse_cnn_num_params())
+
+
+class Net:
+    """fse_cnn_t: FP32 master parameters, BF16 working copy, Adam state."""
+
+    def __init__(self, max_batch, seed=0):
+        h = C.c_void_p()
+        _check(_lib.lib().fse_cnn_create(int(max_batch), C.c_uint64(seed), C.byref(h)), "fse_cnn_create")
+        self._h = h
+        self.max_batch = int(max_batch)
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == num_params()
+        _check(_lib.lib().fse_cnn_set_params(self._h, p.ctypes.data_as(C.c_void_p)), "fse_cnn_set_params")
+
+    def get_params(self, grads=False):
+        p = np.empty(num_params(), np.float32)
+        g = np.empty(num_params(), np.float32) if grads else None
+        _check(_lib.lib().fse_cnn_get_params(self._h, p.ctypes.data_as(C.c_void_p),
+                                             g.ctypes.data_as(C.c_void_p) if grads else None),
+               "fse_cnn_get_params")
+        return (p, g) if grads else p
+
+    def forward(self, x, logits, keep=False, stream=None):
+        """x: CUDA bfloat16 [B,48,48,2]; logits: CUDA float32 [B,4096]."""
+        B = x.shape[0]
+        _check(_lib.lib().fse_cnn_forward(self._h, _ptr(x), int(B), _ptr(logits), int(bool(keep)),
+                                          _stream(stream)), "fse_cnn_forward")
+
+    def backward(self, x, logits, target_bits, pos_weight, loss, stream=None):
+        """target_bits: CUDA int32 [B,128]; loss: CUDA float32 [1] (added to)."""
+        _check(_lib.lib().fse_cnn_backward(self._h, _ptr(x), _ptr(logits), _ptr(target_bits), int(x.shape[0]),
+                                           float(pos_weight), _ptr(loss), _stream(stream)), "fse_cnn_backward")
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(_lib.lib().fse_cnn_adam(self._h, float(lr), float(beta1), float(beta2), float(eps),
+                                       _stream(stream)), "fse_cnn_adam")
+
+    def save(self, path):
+        os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+        np.savez_compressed(path, params=self.get_params())
+
+    def load(self, path=WEIGHTS):
+        with np.load(path, allow_pickle=False) as z:
+            self.set_params(z["params"])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib().fse_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def patches(batch, image, avail, x, stream=None):
+    """Network inputs for every block of `batch` (48x48 areas) into x."""
+    _check(_lib.lib().fse_cnn_patches(batch._h, _ptr(image), _ptr(avail), image.stride(1), _ptr(x),
+                                      _stream(stream)), "fse_cnn_patches")
+
+
+def topk(logits, K, cand, flags, stream=None):
+    _check(_lib.lib().fse_cnn_topk(_ptr(logits), int(logits.shape[0]), int(K), _ptr(cand), _ptr(flags),
+                                   _stream(stream)), "fse_cnn_topk")
+
+
+def trace_stride(batch, restricted_iters, fallback_iters):
+    return int(_lib.lib().fse_warm_trace_stride(batch._h, int(restricted_iters), int(fallback_iters)))
+
+
+def warm_extrapolate(batch, image, avail, out, status, cand, flags, kc, restricted_iters, fallback_iters,
+                     trace=None, stream=None):
+    batch._check_tensors(image, avail, out, status)
+    _check(_lib.lib().fse_warm_extrapolate_batch(
+        batch._h, _ptr(image), _ptr(avail), image.stride(1), _ptr(out), out.stride(1), _ptr(status),
+        None if trace is None else _ptr(trace), _ptr(cand), _ptr(flags), int(kc), int(restricted_iters),
+        int(fallback_iters), _stream(stream)), "fse_warm_extrapolate_batch")
+
+
+class WarmStart:
+    """The whole warm-started concealment of one batch: network inputs,
+    forward pass, candidate sets, warm-started FSE. Buffers are allocated
+    once per batch size; run() only launches kernels."""
+
+    def __init__(self, net, batch, kc=256, restricted_iters=75, fallback_iters=100):
+        import torch
+        self.net, self.batch = net, batch
+        self.kc, self.ir, self.fb = int(kc), int(restricted_iters), int(fallback_iters)
+        n = batch.n
+        dev = torch.device("cuda")
+        self.x = torch.empty((n,) + PATCH, dtype=torch.bfloat16, device=dev)
+        self.logits = torch.empty((n, N_BINS), dtype=torch.float32, device=dev)
+        self.cand = torch.empty((n, self.kc), dtype=torch.int16, device=dev)
+        self.flags = torch.empty((n,), dtype=torch.int32, device=dev)
+
+    def run(self, image, avail, out, status, trace=None, stream=None):
+        patches(self.batch, image, avail, self.x, stream)
+        self.net.forward(self.x, self.logits, keep=False, stream=stream)
+        topk(self.logits, self.kc, self.cand, self.flags, stream)
+        warm_extrapolate(self.batch, image, avail, out, status, self.cand, self.flags, self.kc, self.ir, self.fb,
+                         trace, stream)

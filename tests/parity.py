@@ -88,3 +88,36 @@ def psnr_delta(frames, avail, blocks, rho, gamma, out_gpu, processes=1):
     p_gpu = metrics.psnr_lost(frames, out_gpu, mask)
     p_orc = metrics.psnr_lost(frames, ref, mask)
     return abs(p_gpu - p_orc), p_gpu, p_orc, metrics.psnr_between(out_gpu, ref, mask)
+
+
+def replay_warm_block(frames, avail, blk, rho, gamma, trace_row, cand_bins, ir, iters):
+    """Warm-started block: the restricted phase is replayed with the argmax
+    limited to the candidate bins, then the full phase from the oracle's own
+    restricted model. Returns the same figures as replay_block, per phase."""
+    F = int(blk["fft"])
+    s, A, B = cfse.area_of_block(frames, avail, blk)
+    w = cfse.weighting(*s.shape, rho, A)
+    cand = np.zeros(F * F, dtype=bool)
+    cand[np.asarray(cand_bins, dtype=np.int64)] = True
+    cand = cand.reshape(F, F)
+    out = {}
+    seq_r, c_r = gpu_sequence(trace_row, F, ir)
+    r1 = cfse.cfse(s, w, F, gamma, ir, forced=seq_r, cand=cand)
+    seq_f, c_f = gpu_sequence(trace_row[ir:], F, iters)
+    r2 = cfse.cfse(s, w, F, gamma, iters, forced=seq_f, init=dict(r1["coefs"]))
+    for name, seq, c, res in (("restricted", seq_r, c_r, r1), ("full", seq_f, c_f, r2)):
+        n = len(seq)
+        short = np.array(res["short"]) if n else np.zeros(0)
+        free = np.array(res["free"]) if n else np.zeros(0, dtype=int)
+        div = free != seq
+        ag, ao = accumulate(seq, c), accumulate(seq, np.array(res["chat"]))
+        keys = sorted(ao)
+        vo = np.array([ao[k] for k in keys])
+        vg = np.array([ag.get(k, 0) for k in keys])
+        scale = np.abs(vo).max() if len(vo) else 0.0
+        out[name] = dict(ties=int(div.sum()), gap_violations=int((div & (short >= GAP_TOL)).sum()),
+                         coef_max=float(np.abs(vg - vo).max() / scale) if scale > 0 else 0.0,
+                         coef_l2=float(np.linalg.norm(vg - vo) / np.linalg.norm(vo)) if scale > 0 else 0.0)
+    bd, bh, bw = int(blk["border"]), int(blk["bh"]), int(blk["bw"])
+    out["values"] = r2["g"][bd:bd + bh, bd:bd + bw].real.copy()
+    return out

@@ -1,0 +1,230 @@
+"""GPU tests of the learned warm start: network kernels against the FP64
+network oracle, candidate selection, and warm-started FSE against the FP64
+FSE oracle (through the C ABI)."""
+import numpy as np
+import pytest
+
+from oracle import cfse, cnn
+from synth import losses, workloads
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def bf16(x):
+    """Round to BF16 (nearest even), returned as float32."""
+    u = np.ascontiguousarray(np.asarray(x, np.float32)).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return u.view(np.float32)
+
+
+def _relfro(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def _cos(a, b):
+    return float(np.dot(a.ravel(), b.ravel()) / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-30))
+
+
+def _setup(n_blocks=16, seed=0):
+    import torch
+    import paper_2204_14193_amd as fse
+    from paper_2204_14193_amd import warm
+    wl = workloads.subset(workloads.isolated_256(iters=30), np.arange(n_blocks))
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(wl.distorted).to(dev)
+    av = torch.from_numpy(wl.avail).to(dev)
+    plan = fse.Plan(wl.rho, wl.gamma, 4096)
+    batch = fse.Batch(plan, wl.blocks, *wl.frames.shape)
+    x = torch.empty((n_blocks, 48, 48, 2), dtype=torch.bfloat16, device=dev)
+    warm.patches(batch, img, av, x)
+    torch.cuda.synchronize()
+    return wl, img, av, plan, batch, x
+
+
+def test_patches_match_definition():
+    wl, img, av, plan, batch, x = _setup()
+    _say("case cnn patches")
+    got = x.float().cpu().numpy()
+    for i, blk in enumerate(wl.blocks):
+        s, A, B = cfse.area_of_block(wl.frames, wl.avail, blk)
+        mu = s[A].mean()
+        ch0 = np.where(A, (s - mu) / 64.0, 0.0)
+        assert np.array_equal(got[i, :, :, 1], A.astype(np.float32))
+        assert np.abs(got[i, :, :, 0] - ch0).max() <= 2.0 ** -8 * np.abs(ch0).max() + 1e-6
+
+
+def _oracle_forward_bf16(params, x):
+    """The oracle's layers with every activation rounded to BF16, as the
+    GPU stores them."""
+    p = cnn.unflatten(params.astype(np.float64))
+    h = x.astype(np.float64)
+    for i in range(4):
+        h = bf16(np.maximum(cnn.conv_forward(h, p[f"conv{i + 1}.w"], p[f"conv{i + 1}.b"]), 0.0)).astype(np.float64)
+    feat = h.reshape(h.shape[0], -1)
+    return feat @ p["head.w"].T + p["head.b"]
+
+
+def test_forward_matches_oracle():
+    import torch
+    from paper_2204_14193_amd import warm
+    wl, img, av, plan, batch, x = _setup()
+    _say("case cnn forward")
+    params = cnn.init_params(7).astype(np.float32)
+    params[cnn.n_params() - 4096:] = np.random.default_rng(1).normal(0, 0.1, 4096)   # nonzero head bias
+    net = warm.Net(64, seed=0)
+    net.set_params(params)
+    logits = torch.empty((x.shape[0], 4096), dtype=torch.float32, device=x.device)
+    net.forward(x, logits)
+    torch.cuda.synchronize()
+    got = logits.cpu().numpy()
+    ref = _oracle_forward_bf16(bf16(params), x.float().cpu().numpy())
+    _say(f"  logits relfro={_relfro(got, ref):.2e} cos={_cos(got, ref):.6f}")
+    assert _relfro(got, ref) <= 5e-3 and _cos(got, ref) >= 0.9999
+    net.close()
+
+
+def test_backward_matches_oracle_and_adam_step():
+    import torch
+    from paper_2204_14193_amd import warm
+    wl, img, av, plan, batch, x = _setup()
+    _say("case cnn backward")
+    rng = np.random.default_rng(5)
+    params = (cnn.init_params(9) * 0.7).astype(np.float32)
+    net = warm.Net(64, seed=0)
+    net.set_params(params)
+    B = x.shape[0]
+    tgt = rng.random((B, 4096)) < 0.03
+    bits = np.packbits(tgt.reshape(B, 128, 32)[:, :, ::-1], axis=-1, bitorder="big").view(">u4").astype(np.uint32)
+    bits = np.ascontiguousarray(bits.reshape(B, 128)).view(np.int32)
+    tbits = torch.from_numpy(bits).to(x.device)
+    logits = torch.empty((B, 4096), dtype=torch.float32, device=x.device)
+    loss = torch.zeros(1, dtype=torch.float32, device=x.device)
+    net.forward(x, logits, keep=True)
+    net.backward(x, logits, tbits, 4.0, loss)
+    torch.cuda.synchronize()
+    _, g = net.get_params(grads=True)
+    xin = x.float().cpu().numpy().astype(np.float64)
+    pq = cnn.unflatten(bf16(params).astype(np.float64))
+    lo, cache = cnn.forward(pq, xin)
+    l_ref, dl = cnn.bce_loss(lo, tgt.astype(float), 4.0)
+    gref = cnn.flatten_grads(cnn.backward(pq, cache, dl))
+    _say(f"  loss gpu={loss.item():.6f} oracle={l_ref:.6f}")
+    assert abs(loss.item() - l_ref) <= 2e-3 * abs(l_ref)
+    o = 0
+    for name, shp in cnn.param_shapes():
+        n = int(np.prod(shp))
+        a, b = g[o:o + n], gref[o:o + n]
+        _say(f"  {name:8s} relfro={_relfro(a, b):.2e} cos={_cos(a, b):.6f}")
+        assert _relfro(a, b) <= 3e-2 and _cos(a, b) >= 0.9995, name
+        o += n
+    # one Adam step from zero moments: w -= lr * g / (|g| + eps)
+    lr, eps = 1e-3, 1e-8
+    net.adam(lr, 0.9, 0.999, eps)
+    torch.cuda.synchronize()
+    p1, g1 = net.get_params(grads=True)
+    expect = params - lr * g / (np.abs(g) + eps)
+    assert np.allclose(p1, expect, rtol=1e-5, atol=1e-7)
+    assert not g1.any()
+    net.close()
+
+
+def test_topk_exact_with_ties_and_nan():
+    import torch
+    from paper_2204_14193_amd import warm
+    _say("case topk")
+    rng = np.random.default_rng(3)
+    B, K = 6, 256
+    lg = rng.normal(size=(B, 4096)).astype(np.float32)
+    lg[1] = np.round(lg[1] * 2) / 2          # many exact ties
+    lg[2, :] = 1.5                           # all equal
+    lg[3, 100:600] = 7.0                     # ties across the threshold
+    lg[4, 17] = np.nan                       # non-finite row
+    lg[5] = -np.abs(lg[5])
+    lg[5, ::7] = 0.0
+    lg[5, 3::7] = -0.0                       # -0 ties with +0
+    dev = torch.device("cuda:0")
+    t = torch.from_numpy(lg).to(dev)
+    cand = torch.full((B, K), -1, dtype=torch.int16, device=dev)
+    flags = torch.full((B,), -1, dtype=torch.int32, device=dev)
+    warm.topk(t, K, cand, flags)
+    torch.cuda.synchronize()
+    c, f = cand.cpu().numpy(), flags.cpu().numpy()
+    assert f.tolist() == [0, 0, 0, 0, 1, 0]
+    for b in (0, 1, 2, 3, 5):
+        order = np.lexsort((np.arange(4096), -lg[b].astype(np.float64)))
+        assert np.array_equal(c[b], np.sort(order[:K])), b
+
+
+def _warm_case(ir=30, iters=20, fb=40, kc=256, n_blocks=12):
+    import torch
+    import paper_2204_14193_amd as fse
+    from paper_2204_14193_amd import warm
+    wl = workloads.subset(workloads.isolated_256(iters=iters), np.arange(0, 64, 64 // n_blocks)[:n_blocks])
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(wl.distorted).to(dev)
+    av = torch.from_numpy(wl.avail).to(dev)
+    plan = fse.Plan(wl.rho, wl.gamma, 4096)
+    batch = fse.Batch(plan, wl.blocks, *wl.frames.shape)
+    rng = np.random.default_rng(11)
+    # candidate sets: low frequencies plus random bins, ascending
+    cands = []
+    for i in range(len(wl.blocks)):
+        k = np.arange(4096)
+        low = np.flatnonzero((np.minimum(k // 64, 64 - k // 64) < 6) & (np.minimum(k % 64, 64 - k % 64) < 6))
+        rest = rng.choice(np.setdiff1d(k, low), kc - len(low), replace=False)
+        cands.append(np.sort(np.concatenate([low, rest])))
+    cands = np.stack(cands).astype(np.int16)
+    flags = np.zeros(len(wl.blocks), np.int32)
+    flags[3] = 1
+    out = (img * (av != 0)).to(torch.float32)
+    status = torch.full((len(wl.blocks),), -1, dtype=torch.int32, device=dev)
+    stride = warm.trace_stride(batch, ir, fb)
+    tr = torch.zeros((len(wl.blocks), stride * 16), dtype=torch.uint8, device=dev)
+    warm.warm_extrapolate(batch, img, av, out, status, torch.from_numpy(cands).to(dev),
+                          torch.from_numpy(flags).to(dev), kc, ir, fb, trace=tr)
+    torch.cuda.synchronize()
+    trace = tr.cpu().numpy().view(fse.TRACE_DTYPE).reshape(len(wl.blocks), stride)
+    return wl, out.cpu().numpy(), status.cpu().numpy(), trace, cands, flags
+
+
+def test_warm_fse_replays_against_oracle():
+    ir, iters, fb = 30, 20, 40
+    wl, out, st, trace, cands, flags = _warm_case(ir, iters, fb)
+    _say(f"case warm fse: {len(wl.blocks)} blocks, ir={ir} I={iters} fallback={fb}")
+    assert (st == 0).all()
+    for i, blk in enumerate(wl.blocks):
+        if flags[i]:
+            continue
+        r = parity.replay_warm_block(wl.frames, wl.avail, blk, wl.rho, wl.gamma, trace[i], cands[i], ir, iters)
+        for ph in ("restricted", "full"):
+            assert r[ph]["gap_violations"] == 0, (i, ph, r[ph])
+            assert r[ph]["coef_max"] <= parity.COEF_TOL and r[ph]["coef_l2"] <= parity.COEF_TOL, (i, ph, r[ph])
+        g = out[0, blk["y0"]:blk["y0"] + 16, blk["x0"]:blk["x0"] + 16]
+        _say(f"  block {i}: restricted coef {r['restricted']['coef_max']:.1e}, full coef {r['full']['coef_max']:.1e}, "
+             f"pix {np.abs(g - r['values']).max():.1e}")
+        assert np.abs(g - r["values"]).max() < 0.05
+
+
+def test_warm_fallback_is_plain_fse_bitwise():
+    """A block flagged by candidate selection runs exactly plain FSE."""
+    import torch
+    import paper_2204_14193_amd as fse
+    ir, iters, fb = 30, 20, 40
+    wl, out, st, trace, cands, flags = _warm_case(ir, iters, fb)
+    _say("case warm fallback")
+    i = int(np.flatnonzero(flags)[0])
+    sub = workloads.subset(wl, [i])
+    sub.blocks["iters"] = fb
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(sub.distorted).to(dev)
+    av = torch.from_numpy(sub.avail).to(dev)
+    o2, s2, t2 = fse.extrapolate_batch(img, av, sub.blocks, sub.rho, sub.gamma, trace=True)
+    b = wl.blocks[i]
+    sl = (0, slice(b["y0"], b["y0"] + 16), slice(b["x0"], b["x0"] + 16))
+    assert np.array_equal(o2.cpu().numpy()[sl], out[sl])
+    assert np.array_equal(t2[0, :fb], trace[i, :fb])
