@@ -380,15 +380,36 @@ __device__ __forceinline__ uint32_t order_key(float v) {
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xb1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4e, 0xf, 0xf, false);   // quad_perm [2,3,0,1]
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xf, 0xf, false);  // row_half_mirror
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xf, 0xf, false);  // row_mirror
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// Sum over the 256-thread workgroup (four waves), same value in every lane.
+// `slots` holds 2 x 4 words; `par` alternates so one barrier per call suffices.
+__device__ __forceinline__ uint32_t block_sum(uint32_t x, uint32_t* slots, int& par) {
+  const uint32_t w = wave_sum_u32(x);
+  const int wave = threadIdx.x >> 6;
+  slots[par * 4 + wave] = w;
+  __syncthreads();
+  const uint32_t r = slots[par * 4] + slots[par * 4 + 1] + slots[par * 4 + 2] + slots[par * 4 + 3];
+  par ^= 1;
+  return r;
+}
+
 __global__ __launch_bounds__(256) void k_topk(const float* logits, int B, int K, int16_t* cand, int32_t* flags) {
-  __shared__ uint32_t hist[256];
+  __shared__ uint32_t slots[8];
   __shared__ uint32_t scan[256];
-  __shared__ uint32_t sh[4];
   const int b = blockIdx.x;
   if (b >= B) return;
   const int t = threadIdx.x;
   uint32_t key[16];
-  bool nan = false;
+  uint32_t nan = 0;
   const float4* src = reinterpret_cast<const float4*>(logits + (int64_t)b * kBins + 16 * t);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -396,45 +417,28 @@ __global__ __launch_bounds__(256) void k_topk(const float* logits, int B, int K,
     const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      nan = nan || (vv[r] != vv[r]);
+      nan |= (vv[r] != vv[r]) ? 1u : 0u;
       key[4 * q + r] = order_key(vv[r]);
     }
   }
-  if (t == 0) sh[3] = 0;
-  __syncthreads();
-  if (nan) atomicOr(&sh[3], 1u);
-  // radix select of the K-th largest key, 8 bits at a time from the top
-  uint32_t prefix = 0, mask = 0, remaining = (uint32_t)K;
-  for (int shift = 24; shift >= 0; shift -= 8) {
-    hist[t] = 0;
-    __syncthreads();
+  int par = 0;
+  const bool any_nan = block_sum(nan, slots, par) != 0;
+  // T = the K-th largest key: the largest T with #(key >= T) >= K, bit by bit
+  uint32_t T = 0;
+  for (int bit = 31; bit >= 0; --bit) {
+    const uint32_t c = T | (1u << bit);
+    uint32_t n = 0;
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
-      if ((key[j] & mask) == prefix) atomicAdd(&hist[(key[j] >> shift) & 255u], 1u);
-    __syncthreads();
-    if (t == 0) {
-      uint32_t above = 0;
-      int d = 255;
-      for (; d > 0; --d) {
-        if (above + hist[d] >= remaining) break;
-        above += hist[d];
-      }
-      sh[0] = prefix | ((uint32_t)d << shift);
-      sh[1] = remaining - above;
-    }
-    __syncthreads();
-    prefix = sh[0];
-    remaining = sh[1];
-    mask |= 255u << shift;
-    __syncthreads();
+    for (int j = 0; j < 16; ++j) n += key[j] >= c;
+    if (block_sum(n, slots, par) >= (uint32_t)K) T = c;
   }
-  const uint32_t T = prefix;   // the K-th largest key; `remaining` keys equal to T are taken
   uint32_t gt = 0, eq = 0;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     gt += key[j] > T;
     eq += key[j] == T;
   }
+  const uint32_t remaining = (uint32_t)K - block_sum(gt, slots, par);  // ties at T to take, lowest bins first
   // exclusive scan of eq (to rank ties by bin) then of the selected counts
   scan[t] = eq;
   __syncthreads();
@@ -468,7 +472,7 @@ __global__ __launch_bounds__(256) void k_topk(const float* logits, int B, int K,
     }
     if (take && pos < (uint32_t)K) out[pos++] = (int16_t)(16 * t + j);
   }
-  if (t == 0) flags[b] = sh[3] ? 1 : 0;
+  if (t == 0) flags[b] = any_nan ? 1 : 0;
 }
 
 }  // namespace

@@ -393,8 +393,9 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
       }
       __syncthreads();
       // Apply the restricted model to the whole spectrum (eq. (18) once per
-      // distinct bin with its accumulated coefficient).
-      const int nw = __builtin_amdgcn_readfirstlane(s.misc[1]);
+      // distinct bin with its accumulated coefficient); not needed when no
+      // full iteration follows.
+      const int nw = I_full > 0 ? __builtin_amdgcn_readfirstlane(s.misc[1]) : 0;
       for (int q = 0; q < nw; ++q) {
         const int bin = __builtin_amdgcn_readfirstlane(s.wl_idx[q]);
         const float2 c = s.wl_c[q];
@@ -481,7 +482,7 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
       parity ^= 1;
     }
   };
-  select();
+  if (I_full > 0) select();
 
   bool finite = true;
   for (int it = 0; it < I_full; ++it) {
