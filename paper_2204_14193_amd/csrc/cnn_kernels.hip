@@ -97,15 +97,35 @@ __global__ __launch_bounds__(256) void k_patches(const uint8_t* img, const uint8
 // ------------------------------------------------------------------ forward
 // One 3x3 stride-2 convolution with bias and ReLU, activations in LDS
 // (NHWC, BF16), as an implicit GEMM: rows = output pixels, columns = the 32
-// output channels, depth = (tap, input channel).
+// output channels, depth = (tap, input channel). Each wave loads its
+// weight fragments for every depth step into registers once, then runs the
+// row tiles it owns (tile = wave, wave + 4, ...).
 template <int CIN, int HIN>
 __device__ __forceinline__ void conv_layer(const uint16_t* in, uint16_t* out, const uint16_t* w,
                                            const uint16_t* bias, int t) {
-  constexpr int HO = HIN / 2, P = HO * HO, K = 9 * CIN, KP = (K + 15) / 16 * 16;
+  constexpr int HO = HIN / 2, P = HO * HO, K = 9 * CIN, KP = (K + 15) / 16 * 16, KS = KP / 16;
   constexpr int MT = (P + 31) / 32;
   const int lane = t & 63, wave = t >> 6;
   const int n = lane & 31;
   const int kh = 8 * (lane >> 5);
+  uint4 bfr[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int k0 = ks * 16 + kh;
+    if constexpr (CIN == kCh) {
+      bfr[ks] = *reinterpret_cast<const uint4*>(w + n * K + k0);
+    } else {
+      uint32_t b4[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + 2 * q;
+        const uint32_t lo = k < K ? w[n * K + k] : 0u;
+        const uint32_t hi = k + 1 < K ? w[n * K + k + 1] : 0u;
+        b4[q] = lo | (hi << 16);
+      }
+      bfr[ks] = make_uint4(b4[0], b4[1], b4[2], b4[3]);
+    }
+  }
   const float bn = bf2f(bias[n]);
   for (int tile = wave; tile < MT; tile += 4) {
     const int m = tile * 32 + (lane & 31);
@@ -113,15 +133,14 @@ __device__ __forceinline__ void conv_layer(const uint16_t* in, uint16_t* out, co
     const bool mv = m < P;
     f32x16 acc = {};
 #pragma unroll
-    for (int ks = 0; ks < KP / 16; ++ks) {
+    for (int ks = 0; ks < KS; ++ks) {
       const int k0 = ks * 16 + kh;
-      uint4 av = {0u, 0u, 0u, 0u}, bv = {0u, 0u, 0u, 0u};
+      uint4 av = {0u, 0u, 0u, 0u};
       if constexpr (CIN == kCh) {
         const int tap = k0 >> 5, c0 = k0 & 31;
         const int iy = 2 * oy - 1 + tap / 3, ix = 2 * ox - 1 + tap % 3;
         if (mv && iy >= 0 && iy < HIN && ix >= 0 && ix < HIN)
           av = *reinterpret_cast<const uint4*>(in + (iy * HIN + ix) * CIN + c0);
-        bv = *reinterpret_cast<const uint4*>(w + n * K + k0);
       } else {
         uint32_t a4[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
@@ -135,17 +154,8 @@ __device__ __forceinline__ void conv_layer(const uint16_t* in, uint16_t* out, co
           }
         }
         av = make_uint4(a4[0], a4[1], a4[2], a4[3]);
-        uint32_t b4[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int k = k0 + 2 * q;
-          const uint32_t lo = k < K ? w[n * K + k] : 0u;
-          const uint32_t hi = k + 1 < K ? w[n * K + k + 1] : 0u;
-          b4[q] = lo | (hi << 16);
-        }
-        bv = make_uint4(b4[0], b4[1], b4[2], b4[3]);
       }
-      acc = mfma(av, bv, acc);
+      acc = mfma(av, bfr[ks], acc);
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
@@ -155,40 +165,47 @@ __device__ __forceinline__ void conv_layer(const uint16_t* in, uint16_t* out, co
   }
 }
 
+template <int ELEMS>
+__device__ __forceinline__ void copy_act(const uint16_t* src, uint16_t* dst, int t) {
+  static_assert(ELEMS % 8 == 0, "16-byte copies");
+  for (int i = t; i < ELEMS / 8; i += 256)
+    reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
+}
+
 // The whole convolution stack for one sample per workgroup, activations in
-// LDS; writes the 288 features and, for training, every activation.
+// LDS; writes the 288 features and, for training, every activation. LDS is
+// two regions: X holds the input, then layer 2's output; Y holds layer 1's
+// output, then layers 3 and 4.
 __global__ __launch_bounds__(256) void k_forward(const uint16_t* x, int B, const uint16_t* prm, uint16_t* feats,
                                                  uint16_t* acts) {
-  __shared__ __align__(16) uint16_t a0[kPatchElems];
-  __shared__ __align__(16) uint16_t a1[24 * 24 * kCh];
-  __shared__ __align__(16) uint16_t a2[12 * 12 * kCh];
-  __shared__ __align__(16) uint16_t a3[6 * 6 * kCh];
-  __shared__ __align__(16) uint16_t a4[3 * 3 * kCh];
+  static_assert(kPatchElems == 12 * 12 * kCh, "input and layer-2 output share a region");
+  __shared__ __align__(16) uint16_t X[kPatchElems];
+  __shared__ __align__(16) uint16_t Y[24 * 24 * kCh];
+  uint16_t* const a0 = X;
+  uint16_t* const a1 = Y;
+  uint16_t* const a2 = X;
+  uint16_t* const a3 = Y;
+  uint16_t* const a4 = Y + 6 * 6 * kCh;
   const int b = blockIdx.x;
   if (b >= B) return;
   const int t = threadIdx.x;
-  const uint4* src = reinterpret_cast<const uint4*>(x + (int64_t)b * kPatchElems);
-  for (int i = t; i < kPatchElems / 8; i += 256) reinterpret_cast<uint4*>(a0)[i] = src[i];
+  uint16_t* const dst = acts ? acts + (int64_t)b * kActElems : nullptr;
+  copy_act<kPatchElems>(x + (int64_t)b * kPatchElems, a0, t);
   __syncthreads();
   conv_layer<2, 48>(a0, a1, prm + kOffW[0], prm + kOffB[0], t);
   __syncthreads();
+  if (dst) copy_act<24 * 24 * kCh>(a1, dst + kActOff[0], t);
   conv_layer<kCh, 24>(a1, a2, prm + kOffW[1], prm + kOffB[1], t);
   __syncthreads();
+  if (dst) copy_act<12 * 12 * kCh>(a2, dst + kActOff[1], t);
   conv_layer<kCh, 12>(a2, a3, prm + kOffW[2], prm + kOffB[2], t);
   __syncthreads();
+  if (dst) copy_act<6 * 6 * kCh>(a3, dst + kActOff[2], t);
   conv_layer<kCh, 6>(a3, a4, prm + kOffW[3], prm + kOffB[3], t);
   __syncthreads();
   for (int i = t; i < kFeat; i += 256) feats[(int64_t)b * kFeat + i] = a4[i];
-  if (acts) {
-    uint16_t* dst = acts + (int64_t)b * kActElems;
-    for (int i = t; i < 18432 / 8; i += 256)
-      reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(a1)[i];
-    for (int i = t; i < 4608 / 8; i += 256)
-      reinterpret_cast<uint4*>(dst + kActOff[1])[i] = reinterpret_cast<const uint4*>(a2)[i];
-    for (int i = t; i < 1152 / 8; i += 256)
-      reinterpret_cast<uint4*>(dst + kActOff[2])[i] = reinterpret_cast<const uint4*>(a3)[i];
+  if (dst)
     for (int i = t; i < kFeat; i += 256) dst[kActOff[3] + i] = a4[i];
-  }
 }
 
 // ------------------------------------------------------------------ GEMM
@@ -217,6 +234,65 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* A, int lda, con
   for (int i = 0; i < 16; ++i) {
     const int row = tm + drow(i, lane);
     if (row < M) C[(int64_t)row * ldc + col] = acc[i] + bb;
+  }
+}
+
+// C = A * B^T for large outputs: each wave computes WM x WN tiles of 32x32
+// (A and B fragments reused across them), a workgroup 2x2 waves. Same
+// arithmetic per element as k_gemm_nt (one MFMA chain over K in steps of 16).
+template <int WM, int WN>
+__global__ __launch_bounds__(256) void k_gemm_nt_t(const uint16_t* A, int lda, const uint16_t* Bm, int ldb, float* C,
+                                                   int ldc, const uint16_t* bias, int M, int N, int K) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int tm = blockIdx.x * (64 * WM) + (wave & 1) * (32 * WM);
+  const int tn = blockIdx.y * (64 * WN) + (wave >> 1) * (32 * WN);
+  if (tm >= M || tn >= N) return;
+  const int kh = 8 * (lane >> 5);
+  const uint16_t* pa[WM];
+  const uint16_t* pb[WN];
+  bool ma[WM], nb[WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i) {
+    const int m = tm + 32 * i + (lane & 31);
+    ma[i] = m < M;
+    pa[i] = A + (int64_t)(ma[i] ? m : 0) * lda + kh;
+  }
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    const int n = tn + 32 * j + (lane & 31);
+    nb[j] = n < N;
+    pb[j] = Bm + (int64_t)(nb[j] ? n : 0) * ldb + kh;
+  }
+  f32x16 acc[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[i][j] = f32x16{};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    uint4 av[WM], bv[WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+      av[i] = ma[i] ? *reinterpret_cast<const uint4*>(pa[i] + k0) : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+      bv[j] = nb[j] ? *reinterpret_cast<const uint4*>(pb[j] + k0) : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int j = 0; j < WN; ++j) acc[i][j] = mfma(av[i], bv[j], acc[i][j]);
+  }
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    const int col = tn + 32 * j + (lane & 31);
+    if (col >= N) continue;
+    const float bb = bias ? bf2f(bias[col]) : 0.f;
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = tm + 32 * i + drow(r, lane);
+        if (row < M) C[(int64_t)row * ldc + col] = acc[i][j][r] + bb;
+      }
   }
 }
 
@@ -402,9 +478,40 @@ __device__ __forceinline__ uint32_t block_sum(uint32_t x, uint32_t* slots, int& 
   return r;
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_scan_u32(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true);  // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return x;
+}
+
+// Exclusive prefix sum over the 256 threads (four waves) and the total.
+// `slots` holds 2 x 4 words used alternately (see block_sum).
+__device__ __forceinline__ uint32_t block_exscan(uint32_t x, uint32_t* slots, int& par, uint32_t& total) {
+  const uint32_t inc = wave_scan_u32(x);
+  const int wave = threadIdx.x >> 6;
+  slots[par * 4 + wave] = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+  __syncthreads();
+  uint32_t before = 0;
+  const uint32_t s0 = slots[par * 4], s1 = slots[par * 4 + 1], s2 = slots[par * 4 + 2], s3 = slots[par * 4 + 3];
+  before = (wave > 0 ? s0 : 0u) + (wave > 1 ? s1 : 0u) + (wave > 2 ? s2 : 0u);
+  total = s0 + s1 + s2 + s3;
+  par ^= 1;
+  return before + inc - x;
+}
+
+// Exact selection of the K-th largest order key T: its top kPrefixBits bits
+// by bisection over all keys, then the remaining bits by bisection over the
+// keys sharing that prefix only (compacted into LDS).
+constexpr int kPrefixBits = 14;
+
 __global__ __launch_bounds__(256) void k_topk(const float* logits, int B, int K, int16_t* cand, int32_t* flags) {
   __shared__ uint32_t slots[8];
-  __shared__ uint32_t scan[256];
+  __shared__ uint32_t bk[kBins];
   const int b = blockIdx.x;
   if (b >= B) return;
   const int t = threadIdx.x;
@@ -423,14 +530,37 @@ __global__ __launch_bounds__(256) void k_topk(const float* logits, int B, int K,
   }
   int par = 0;
   const bool any_nan = block_sum(nan, slots, par) != 0;
-  // T = the K-th largest key: the largest T with #(key >= T) >= K, bit by bit
+  // T = the largest key value with #(key >= T) >= K: prefix bits first
   uint32_t T = 0;
-  for (int bit = 31; bit >= 0; --bit) {
+  for (int bit = 31; bit >= 32 - kPrefixBits; --bit) {
     const uint32_t c = T | (1u << bit);
     uint32_t n = 0;
 #pragma unroll
     for (int j = 0; j < 16; ++j) n += key[j] >= c;
     if (block_sum(n, slots, par) >= (uint32_t)K) T = c;
+  }
+  {
+    // keys with T's prefix; those above the prefix are all selected
+    const uint32_t hi = T | ((1u << (32 - kPrefixBits)) - 1u);
+    uint32_t above = 0, inb = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      above += key[j] > hi;
+      inb += key[j] >= T && key[j] <= hi;
+    }
+    const uint32_t need = (uint32_t)K - block_sum(above, slots, par);
+    uint32_t m = 0;
+    uint32_t pos = block_exscan(inb, slots, par, m);
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (key[j] >= T && key[j] <= hi) bk[pos++] = key[j];
+    __syncthreads();
+    for (int bit = 31 - kPrefixBits; bit >= 0; --bit) {
+      const uint32_t c = T | (1u << bit);
+      uint32_t n = 0;
+      for (uint32_t i = t; i < m; i += 256) n += bk[i] >= c;
+      if (block_sum(n, slots, par) >= need) T = c;
+    }
   }
   uint32_t gt = 0, eq = 0;
 #pragma unroll
@@ -438,29 +568,17 @@ __global__ __launch_bounds__(256) void k_topk(const float* logits, int B, int K,
     gt += key[j] > T;
     eq += key[j] == T;
   }
-  const uint32_t remaining = (uint32_t)K - block_sum(gt, slots, par);  // ties at T to take, lowest bins first
-  // exclusive scan of eq (to rank ties by bin) then of the selected counts
-  scan[t] = eq;
-  __syncthreads();
-  for (int o = 1; o < 256; o <<= 1) {
-    const uint32_t v = t >= o ? scan[t - o] : 0u;
-    __syncthreads();
-    scan[t] += v;
-    __syncthreads();
-  }
-  const uint32_t eq_before = scan[t] - eq;
-  const uint32_t eq_take = eq_before >= remaining ? 0u : min(eq, remaining - eq_before);
-  const uint32_t mine = gt + eq_take;
-  __syncthreads();
-  scan[t] = mine;
-  __syncthreads();
-  for (int o = 1; o < 256; o <<= 1) {
-    const uint32_t v = t >= o ? scan[t - o] : 0u;
-    __syncthreads();
-    scan[t] += v;
-    __syncthreads();
-  }
-  uint32_t pos = scan[t] - mine;
+  uint32_t ngt = 0, neq = 0;
+  const uint32_t gt_before = block_exscan(gt, slots, par, ngt);
+  const uint32_t remaining = (uint32_t)K - ngt;  // ties at T to take, lowest bins first
+  const uint32_t eq_before = block_exscan(eq, slots, par, neq);
+  // Ties taken before this thread and by it, written with min() only: a
+  // subtraction guarded by a comparison was observed to be speculated with
+  // a no-wrap flag that then let the optimiser drop the first min().
+  const uint32_t taken_before = min(eq_before, remaining);
+  const uint32_t eq_take = min(eq_before + eq, remaining) - taken_before;
+  // selected before this thread: all greater keys, plus the ties taken
+  uint32_t pos = gt_before + taken_before;
   uint32_t eq_seen = 0;
   int16_t* out = cand + (int64_t)b * K;
 #pragma unroll
@@ -495,8 +613,13 @@ hipError_t forward(const uint16_t* x, int32_t B, const uint16_t* prm, uint16_t* 
 hipError_t gemm_nt(const uint16_t* A, int lda, const uint16_t* B, int ldb, float* C, int ldc,
                    const uint16_t* bias_bf16, int M, int N, int K, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gemm_nt, dim3((M + 63) / 64, (N + 63) / 64), dim3(256), 0, s, A, lda, B, ldb, C, ldc,
-                     bias_bf16, M, N, K);
+  if ((int64_t)M * N >= (int64_t)1 << 22) {
+    hipLaunchKernelGGL((k_gemm_nt_t<2, 2>), dim3((M + 127) / 128, (N + 127) / 128), dim3(256), 0, s, A, lda, B, ldb,
+                       C, ldc, bias_bf16, M, N, K);
+  } else {
+    hipLaunchKernelGGL(k_gemm_nt, dim3((M + 63) / 64, (N + 63) / 64), dim3(256), 0, s, A, lda, B, ldb, C, ldc,
+                       bias_bf16, M, N, K);
+  }
   return hipGetLastError();
 }
 

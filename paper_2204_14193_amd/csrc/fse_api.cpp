@@ -74,6 +74,11 @@ struct fse_batch_s {
   } cls[3];
   Cls warm;                                // warm-started launch of the F = 64 class
   int32_t warm_kc = 0, warm_ir = -1, warm_fb = -1;
+  bool warm_split = false;                 // transform kernel + restricted kernel
+  size_t restricted_lds = 0;
+  float2* d_stage_w = nullptr;             // split form's staging (caller's block order)
+  float2* d_stage_r = nullptr;
+  int32_t stage_kc = 0;
   bool all_48 = false;                     // every area is 48 x 48 (network input size)
 };
 
@@ -212,6 +217,8 @@ fse_status_t configure(fse_batch_s* b, fse_batch_s::Cls& c, const fse::Variant* 
 }
 
 void free_batch(fse_batch_s* b) {
+  (void)hipFree(b->d_stage_w);
+  (void)hipFree(b->d_stage_r);
   (void)hipFree(b->d_blocks);
   (void)hipFree(b->d_orig);
   (void)hipFree(b->d_queue);
@@ -344,6 +351,9 @@ extern "C" fse_status_t fse_extrapolate_batch(fse_batch_t batch, const uint8_t* 
 static fse_status_t launch_one(fse_batch_t batch, int ci, const uint8_t* d_image, const uint8_t* d_avail,
                                int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
                                fse_trace_t* d_trace, hipStream_t s, const int16_t* cand, const int32_t* flags) {
+  // the kernels address a frame's pixels with 32-bit offsets
+  if ((int64_t)batch->H * pitch >= ((int64_t)1 << 31))
+    return fail(FSE_ERR_INVALID_ARG, "a frame (H x pitch bytes) must be smaller than 2 GiB");
   {
     const bool warm = cand != nullptr;
     const fse_batch_s::Cls& c = warm ? batch->warm : batch->cls[ci];
@@ -370,12 +380,21 @@ static fse_status_t launch_one(fse_batch_t batch, int ci, const uint8_t* d_image
     a.flags = flags;
     a.ir = warm ? batch->warm_ir : 0;
     a.fb_iters = warm ? batch->warm_fb : 0;
+    a.stage_w = nullptr;
+    a.stage_r = nullptr;
     if (warm) {
       a.iters_cap = c.iters_cap;
       a.trace_stride = batch->warm_ir + std::max(batch->max_iters, batch->warm_fb);
+      if (batch->warm_split) {
+        a.stage_w = batch->d_stage_w;
+        a.stage_r = batch->d_stage_r;
+      }
     }
     if (fse::launch_class(*c.v, a, c.grid, c.lds, s) != hipSuccess)
       return fail(FSE_ERR_HIP, "kernel launch failed");
+    if (warm && batch->warm_split &&
+        fse::launch_restricted(batch->warm_kc, a, batch->restricted_lds, s) != hipSuccess)
+      return fail(FSE_ERR_HIP, "kernel launch failed (restricted iterations)");
   }
   return FSE_OK;
 }
@@ -477,13 +496,43 @@ extern "C" fse_status_t fse_warm_extrapolate_batch(fse_batch_t batch, const uint
   if (hipGetDevice(&dev) != hipSuccess || dev != batch->device)
     return fail(FSE_ERR_INVALID_ARG, "batch was created on another device");
   if (kc != batch->warm_kc || restricted_iters != batch->warm_ir || fallback_iters != batch->warm_fb) {
-    const fse::Variant* v = fse::warm_variant_for(64, kc);
+    // With no full iteration after the restricted ones, the transform and
+    // the restricted iterations run as two kernels (split form); otherwise
+    // one kernel does both phases.
+    const bool split = batch->max_iters == 0;
+    const fse::Variant* v = fse::warm_variant_for(64, kc, split ? fse::kWarmPrep : fse::kWarmFused);
     if (!v) return fail(FSE_ERR_UNSUPPORTED, "no warm-start kernel for this candidate count");
     fse_batch_s::Cls c = batch->cls[ci];
-    c.iters_cap = restricted_iters + std::max(c.iters_cap, fallback_iters);
+    c.iters_cap = split ? std::max(c.iters_cap, fallback_iters)
+                        : restricted_iters + std::max(c.iters_cap, fallback_iters);
     fse_status_t st = configure(batch, c, v);
     if (st != FSE_OK) return st;
+    if (split) {
+      const void* rk = fse::restricted_kernel(kc);
+      const size_t lds = fse::restricted_lds_bytes(restricted_iters);
+      if (!rk) return fail(FSE_ERR_UNSUPPORTED, "no restricted kernel for this candidate count");
+      if (hipFuncSetAttribute(rk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return fail(FSE_ERR_HIP, "hipFuncSetAttribute failed (LDS size)");
+      int per_cu = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rk, 64, lds) != hipSuccess || per_cu < 1)
+        return fail(FSE_ERR_UNSUPPORTED, "restricted kernel does not fit on a compute unit");
+      if (kc != batch->stage_kc) {
+        (void)hipFree(batch->d_stage_r);
+        batch->d_stage_r = nullptr;
+        batch->stage_kc = 0;
+        if (hipMalloc(&batch->d_stage_r, (size_t)batch->n * kc * sizeof(float2)) != hipSuccess)
+          return fail(FSE_ERR_OOM, "hipMalloc failed (warm staging)");
+        batch->stage_kc = kc;
+      }
+      if (!batch->d_stage_w &&
+          hipMalloc(&batch->d_stage_w, (size_t)batch->n * fse::kHalfRows * 64 * sizeof(float2)) != hipSuccess) {
+        batch->d_stage_w = nullptr;
+        return fail(FSE_ERR_OOM, "hipMalloc failed (warm staging)");
+      }
+      batch->restricted_lds = lds;
+    }
     batch->warm = c;
+    batch->warm_split = split;
     batch->warm_kc = kc;
     batch->warm_ir = restricted_iters;
     batch->warm_fb = fallback_iters;

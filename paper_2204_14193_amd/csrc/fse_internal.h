@@ -39,21 +39,41 @@ struct ClassArgs {
   const int32_t* flags;       // [caller's n_blocks]: nonzero = run plain FSE
   int32_t ir;                 // restricted iterations
   int32_t fb_iters;           // full iterations of a block that falls back
+  // split warm-started form: staging written by the transform kernel and
+  // read by the restricted kernel, indexed by the caller's block index
+  float2* stage_w;            // [caller's n_blocks][kHalfRows * 64]: W rows 0..32
+  float2* stage_r;            // [caller's n_blocks][kc]: R_w at the candidates
 };
+
+// Rows of W kept by the split warm start for F = 64: W[k, l] for k <= 32;
+// the others follow from W[-k, -l] = conj(W[k, l]) (w is real).
+constexpr int kHalfRows = 33;
+
+// Kernel modes.
+enum Mode : int { kPlain = 0, kWarmFused = 1, kWarmPrep = 2 };
 
 // One compiled kernel variant for transform size F.
 struct Variant {
   int F;
   int threads;         // workgroup size
   int kc;              // candidates per block (warm-started form), 0 = plain
+  int mode;            // Mode
   const void* fn;      // kernel symbol
 };
 
 // Default kernel variant for transform size F (32, 64, 128), or null.
 const Variant* variant_for(int F);
 
-// Warm-started variant for F with kc candidates per block, or null.
-const Variant* warm_variant_for(int F, int kc);
+// Warm-started variant for F with kc candidates per block in the given mode
+// (kWarmFused or kWarmPrep), or null.
+const Variant* warm_variant_for(int F, int kc, int mode);
+
+// Restricted kernel of the split warm start (F = 64, one 64-lane workgroup
+// per block of the class, grid = class size): null if kc is not compiled.
+const void* restricted_kernel(int kc);
+
+// Dynamic LDS bytes of the restricted kernel for ir restricted iterations.
+size_t restricted_lds_bytes(int ir);
 
 // All compiled plain variants for F; returns their number, fills up to cap.
 int variants_for(int F, const Variant** out, int cap);
@@ -67,5 +87,8 @@ void set_error(const char* msg);
 
 // Launch one class; grid = number of persistent workgroups.
 hipError_t launch_class(const Variant& v, const ClassArgs& a, int grid, size_t lds, hipStream_t s);
+
+// Launch the restricted kernel over the n blocks of a class.
+hipError_t launch_restricted(int kc, const ClassArgs& a, size_t lds, hipStream_t s);
 
 }  // namespace fse

@@ -202,25 +202,55 @@ struct Lds {
   float2* wl_c;    // warm start: their accumulated coefficients
 };
 
+// A block descriptor made wave-uniform (SGPRs), so that the geometry and
+// the frame base addresses live on the scalar unit.
+struct UBlock {
+  int frame, y0, x0, bh, bw, border, iters;
+};
+__device__ __forceinline__ UBlock uniform_block(const fse_block_t* p) {
+  const int* w = reinterpret_cast<const int*>(p);
+  UBlock b;
+  b.frame = __builtin_amdgcn_readfirstlane(w[0]);
+  b.y0 = __builtin_amdgcn_readfirstlane(w[1]);
+  b.x0 = __builtin_amdgcn_readfirstlane(w[2]);
+  const int hw = __builtin_amdgcn_readfirstlane(w[3]);
+  const int bf = __builtin_amdgcn_readfirstlane(w[4]);
+  b.bh = (int)(int16_t)(hw & 0xffff);
+  b.bw = hw >> 16;
+  b.border = (int)(int16_t)(bf & 0xffff);
+  b.iters = __builtin_amdgcn_readfirstlane(w[5]);
+  return b;
+}
+static_assert(sizeof(fse_block_t) == 24, "block descriptor layout");
+
+// Block status of the split warm start's transform kernel: the restricted
+// kernel finishes the block and writes its status.
+constexpr int kPending = 0x7fff;
+
 // Conceal one block with every lane of the workgroup. All values that steer
 // control flow (block geometry, W0, the selected bin) are wave-uniform, so
 // every branch below is taken by all lanes together. Returns FSE_BLOCK_*.
-// KC > 0 compiles the warm-started form: KC candidate bins per block (from
-// the network), KC/64 per lane of wave 0.
-template <int F, int NT, int KC>
+// MODE kWarmFused compiles the warm-started form: KC candidate bins per
+// block (from the network), KC/64 per lane of wave 0. MODE kWarmPrep stops
+// a warm-started block after the transform and stages W (rows 0..F/2) and
+// R_w at its KC candidates for the restricted kernel.
+template <int F, int NT, int KC, int MODE>
 __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, const Lds& s, const int t,
                                              int& parity) {
   using S = Shape<F, NT>;
   constexpr int BPL = S::BPL, NW = S::NW, RPW = S::RPW, PH = S::PH;
   constexpr int CPL = KC > 0 ? KC / 64 : 1;  // candidates per lane of wave 0
+  constexpr bool FUSED = MODE == kWarmFused;
   static_assert(KC % 64 == 0 && KC <= 1024, "candidate count must be a multiple of 64");
+  static_assert((MODE == kPlain) == (KC == 0), "warm modes need candidates");
+  static_assert(MODE != kWarmPrep || F == 64, "the split warm start is compiled for F = 64");
   const int lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int wbase = wave * RPW * F;  // linear index of this wave's first bin
   float2* const Wd = s.Wd;
 
-  const fse_block_t bd = a.blocks[bi];
-  const int orig = a.orig[bi];
+  const UBlock bd = uniform_block(a.blocks + bi);
+  const int orig = __builtin_amdgcn_readfirstlane(a.orig[bi]);
   const int bh = bd.bh, bw = bd.bw, bo = bd.border;
   const int M = bh + 2 * bo, N = bw + 2 * bo;
   const int ya = bd.y0 - bo, xa = bd.x0 - bo;
@@ -228,24 +258,42 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
   const int64_t fofs = (int64_t)bd.frame * a.H;
   const uint8_t* img = a.img + fofs * a.pitch;
   const uint8_t* av = a.avail + fofs * a.pitch;
+  const int pitch = (int)a.pitch;  // a frame is below 2^31 bytes (checked by the host)
 
-  // 1. gather and weight (eq. (3)); z = s*w + j*alpha*w on the F x F grid
-  for (int e = t; e < F * F; e += NT) {
-    const int m = e / F, n = e % F;
-    float2 z = make_float2(0.f, 0.f);
-    if (m < M && n < N) {
-      const int y = ya + m, x = xa + n;
-      const bool inB = (m >= bo) && (m < bo + bh) && (n >= bo) && (n < bo + bw);
-      if (!inB && y >= 0 && y < a.H && x >= 0 && x < a.W) {
-        const int64_t p = (int64_t)y * a.pitch + x;
-        if (av[p] != 0) {
-          const int da = abs(2 * m - (M - 1)), db = abs(2 * n - (N - 1));
-          const float w = a.wtab[da * kWinStride + db];
-          z = make_float2((float)img[p] * w, kAlpha * w);
-        }
+  // 1. gather and weight (eq. (3)); z = s*w + j*alpha*w on the F x F grid.
+  // Loads go to clamped, always valid addresses and are issued in groups of
+  // up to 8 elements per thread before any is used; the mask is applied
+  // afterwards.
+  {
+    constexpr int EPT = F * F / NT;
+    constexpr int G = EPT < 8 ? EPT : 8;
+    static_assert(EPT % G == 0, "gather groups");
+#pragma unroll
+    for (int g0 = 0; g0 < EPT; g0 += G) {
+      uint32_t pix[G], avb[G];
+      float wv[G];
+#pragma unroll
+      for (int r = 0; r < G; ++r) {
+        const int e = t + (g0 + r) * NT;
+        const int m = e / F, n = e % F;
+        const int y = min(max(ya + m, 0), a.H - 1), x = min(max(xa + n, 0), a.W - 1);
+        const uint32_t p = (uint32_t)(y * pitch + x);
+        pix[r] = img[p];
+        avb[r] = av[p];
+        const int da = min(abs(2 * m - (M - 1)), kWinStride - 1), db = min(abs(2 * n - (N - 1)), kWinStride - 1);
+        wv[r] = a.wtab[da * kWinStride + db];
+      }
+#pragma unroll
+      for (int r = 0; r < G; ++r) {
+        const int e = t + (g0 + r) * NT;
+        const int m = e / F, n = e % F;
+        const int y = ya + m, x = xa + n;
+        const bool inB = (m >= bo) && (m < bo + bh) && (n >= bo) && (n < bo + bw);
+        const bool use = m < M && n < N && !inB && y >= 0 && y < a.H && x >= 0 && x < a.W && avb[r] != 0;
+        const float w = wv[r];
+        Wd[e] = use ? make_float2((float)pix[r] * w, kAlpha * w) : make_float2(0.f, 0.f);
       }
     }
-    Wd[e] = z;
   }
   __syncthreads();
 
@@ -259,9 +307,31 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
   // was unusable (flag set) runs plain FSE with the fallback count.
   const bool warm = KC > 0 && __builtin_amdgcn_readfirstlane(a.flags[orig]) == 0;
   const int I_full = KC > 0 && !warm ? a.fb_iters : I;
+  if constexpr (MODE == kWarmPrep) {
+    if (warm) {
+      // stage W[k, l] for k <= F/2 (split as below) and R_w at the candidates
+      float2* ws = a.stage_w + (int64_t)orig * (kHalfRows * F);
+      for (int e = t; e < kHalfRows * F; e += NT) {
+        const int k = e / F, l = e % F;
+        const float2 zk = Wd[e];
+        const float2 zn = Wd[((F - k) & (F - 1)) * F + ((F - l) & (F - 1))];
+        ws[e] = make_float2((zk.y + zn.y) * (0.5f / kAlpha), (zn.x - zk.x) * (0.5f / kAlpha));
+      }
+      float2* rs = a.stage_r + (int64_t)orig * KC;
+      for (int c = t; c < KC; c += NT) {
+        const int ci = a.cand[(int64_t)orig * KC + c];
+        const int k = ci / F, l = ci % F;
+        const float2 zk = Wd[k * F + l];
+        const float2 zn = Wd[((F - k) & (F - 1)) * F + ((F - l) & (F - 1))];
+        rs[c] = make_float2((zk.x + zn.x) * 0.5f, (zk.y - zn.y) * 0.5f);
+      }
+      __syncthreads();  // Wd is overwritten by the next block
+      return kPending;
+    }
+  }
   float cRx[CPL], cRy[CPL];
   int cIdx[CPL];
-  if (KC > 0 && warm && wave == 0) {
+  if (FUSED && warm && wave == 0) {
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
       const int ci = a.cand[(int64_t)orig * KC + j * 64 + lane];
@@ -311,7 +381,7 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
   for (int j = 0; j < BPL; ++j) mb[j] = __float_as_uint(fmaf(Ry[j], Ry[j], Rx[j] * Rx[j]));
 
   int tbase = 0;  // trace position of the first full iteration
-  if constexpr (KC > 0) {
+  if constexpr (FUSED) {
     if (warm) {
       // Restricted phase (wave 0): FSE iterations whose argmax and update run
       // over the candidate bins only; the candidates are in ascending bin
@@ -531,7 +601,7 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
     select();
   }
   __syncthreads();
-  if (KC > 0 && warm) {
+  if (FUSED && warm) {
     // the restricted phase's coefficients must be finite as well
     for (int it = 0; it < a.ir; ++it) {
       const float2 c = s.cl_c[it];
@@ -559,7 +629,7 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
   return FSE_BLOCK_OK;
 }
 
-template <int F, int NT, int KC>
+template <int F, int NT, int KC, int MODE>
 __global__ __launch_bounds__(NT) void fse_persistent(ClassArgs a) {
   using S = Shape<F, NT>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -603,8 +673,8 @@ __global__ __launch_bounds__(NT) void fse_persistent(ClassArgs a) {
     // costs a few instructions.
     int tb = t;
     asm volatile("" : "+v"(tb));
-    const int code = conceal_block<F, NT, KC>(a, bi, s, tb, parity);
-    if (wave == 0) a.status[a.orig[bi]] = code;
+    const int code = conceal_block<F, NT, KC, MODE>(a, bi, s, tb, parity);
+    if (wave == 0 && code != kPending) a.status[a.orig[bi]] = code;
   }
 
   // the last workgroup to leave re-arms the queue for the next launch
@@ -618,9 +688,151 @@ __global__ __launch_bounds__(NT) void fse_persistent(ClassArgs a) {
   }
 }
 
-template <int F, int NT, int KC = 0>
+// ------------------------------------------------------------ restricted
+// Second kernel of the split warm start (F = 64): the restricted iterations
+// of one block per 64-lane workgroup, with W rows 0..32 in LDS (17 KB, so
+// that many blocks share a compute unit and hide each other's latency) and
+// the KC candidates in VGPRs, KC/64 consecutive candidates per lane. Each
+// iteration: argmax of |R_w|^2 over the candidates (eq. (12), lowest bin on
+// ties), c = gamma*R_w[u,v]/W[0,0] (eq. (13)), R_w[k,l] -= c*W[k-u,l-v] at
+// the candidates (eq. (18)); then the model is evaluated on B as in the
+// persistent kernel. The arithmetic of every step is that of the fused
+// warm-started form, so both give the same bits.
+template <int KC>
+__global__ __launch_bounds__(64) void fse_restricted(ClassArgs a) {
+  constexpr int F = 64, CPL = KC / 64;
+  static_assert(KC % 64 == 0 && CPL >= 1 && CPL <= 16, "candidate count must be 64..1024, a multiple of 64");
+  extern __shared__ __align__(16) unsigned char smem[];
+  float2* const Wh = reinterpret_cast<float2*>(smem);  // kHalfRows x F
+  float2* const tw = Wh + kHalfRows * F;                // F twiddles
+  float2* const cl_c = tw + F;                          // ir coefficients
+  int* const cl_idx = reinterpret_cast<int*>(cl_c + a.ir);
+  const int lane = threadIdx.x;
+  const int bi = blockIdx.x;
+  if (bi >= a.n) return;
+  const int orig = __builtin_amdgcn_readfirstlane(a.orig[bi]);
+  if (__builtin_amdgcn_readfirstlane(a.flags[orig]) != 0) return;  // concealed by the transform kernel
+
+  {
+    const float4* src = reinterpret_cast<const float4*>(a.stage_w + (int64_t)orig * (kHalfRows * F));
+    float4* dst = reinterpret_cast<float4*>(Wh);
+    for (int e = lane; e < kHalfRows * F / 2; e += 64) dst[e] = src[e];
+    tw[lane] = a.twid[lane];
+  }
+  // Candidate c = lane*CPL + j. Its bin (k, l) is kept in two packed forms
+  // whose sum with a per-iteration constant gives (k-u) mod F, (l-v) mod F
+  // and their negatives without borrows between the 7-bit fields.
+  float Rx[CPL], Ry[CPL];
+  int xa[CPL], xb[CPL];
+  unsigned mb[CPL];
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) {
+    const int c = lane * CPL + j;
+    const int bin = a.cand[(int64_t)orig * KC + c];
+    const int k = bin / F, l = bin % F;
+    const float2 r = a.stage_r[(int64_t)orig * KC + c];
+    Rx[j] = r.x;
+    Ry[j] = r.y;
+    xa[j] = k * 128 + l;
+    xb[j] = (F - k) * 128 + (F - l);
+    mb[j] = __float_as_uint(fmaf(r.y, r.y, r.x * r.x));
+  }
+  __syncthreads();
+  const float W0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(Wh[0].x)));
+  if (!(W0 > 0.f)) {
+    a.status[orig] = FSE_BLOCK_EMPTY_SUPPORT;
+    return;
+  }
+  const float gW = a.gamma * (1.0f / W0);
+
+  bool finite = true;
+  for (int it = 0; it < a.ir; ++it) {
+    unsigned lm = mb[0];
+#pragma unroll
+    for (int j = 1; j < CPL; ++j) lm = max(lm, mb[j]);
+    const unsigned wm = wave_max_bits(lm);
+    // the lowest candidate holding the maximum: lowest lane, then lowest j
+    float hre = 0.f, him = 0.f;
+    int hx = 0;
+    bool hit = false;
+#pragma unroll
+    for (int j = CPL - 1; j >= 0; --j) {
+      const bool h = mb[j] == wm;
+      hre = h ? Rx[j] : hre;
+      him = h ? Ry[j] : him;
+      hx = h ? xa[j] : hx;
+      hit = hit || h;
+    }
+    const unsigned long long hits = __ballot(hit);
+    const int wl = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(hits));
+    const float re = readlane_f(hre, wl), im = readlane_f(him, wl);
+    const int x = __builtin_amdgcn_readlane(hx, wl);
+    const int u = x >> 7, v = x & 127;
+    const float cre = gW * re, cim = gW * im;  // eq. (13)
+    finite = finite && isfinite(cre) && isfinite(cim);
+    cl_idx[it] = u * F + v;  // uniform stores
+    cl_c[it] = make_float2(cre, cim);
+    if (a.trace) {
+      fse_trace_t rec;
+      rec.u = (uint16_t)u;
+      rec.v = (uint16_t)v;
+      rec.c_re = cre;
+      rec.c_im = cim;
+      rec.r2 = __uint_as_float(wm);
+      a.trace[(int64_t)orig * a.trace_stride + it] = rec;
+    }
+    // eq. (18) at the candidates: W[k-u, l-v] from row (k-u) mod F when
+    // that is <= F/2, else the conjugate of W[u-k, v-l]
+    const int ca = (F - u) * 128 + (F - v);
+    const int cb = u * 128 + v;
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+      const int ya = xa[j] + ca, yb = xb[j] + cb;
+      const int dk = (ya >> 7) & (F - 1);
+      const bool flip = dk > F / 2;
+      const int ia = dk * F + (ya & (F - 1));
+      const int ib = ((yb >> 7) & (F - 1)) * F + (yb & (F - 1));
+      float2 w = Wh[flip ? ib : ia];
+      w.y = flip ? -w.y : w.y;
+      float rx = Rx[j], ry = Ry[j];
+      rx = fmaf(-cre, w.x, rx);
+      rx = fmaf(cim, w.y, rx);
+      ry = fmaf(-cre, w.y, ry);
+      ry = fmaf(-cim, w.x, ry);
+      Rx[j] = rx;
+      Ry[j] = ry;
+      mb[j] = __float_as_uint(fmaf(ry, ry, rx * rx));
+    }
+  }
+  if (!finite) {
+    a.status[orig] = FSE_BLOCK_NONFINITE;
+    return;
+  }
+  __syncthreads();
+  // model on B: Re{ sum_nu c_nu exp(j 2 pi (u m + v n) / F) }
+  const UBlock bd = uniform_block(a.blocks + bi);
+  const int bh = bd.bh, bw = bd.bw, bo = bd.border;
+  const int64_t fofs = (int64_t)bd.frame * a.H;
+  for (int p = lane; p < bh * bw; p += 64) {
+    const int i = p / bw, jj = p % bw;
+    const int m = bo + i, n = bo + jj;
+    float acc = 0.f;
+    for (int it = 0; it < a.ir; ++it) {
+      const int sidx = cl_idx[it];
+      const int q = ((sidx / F) * m + (sidx % F) * n) & (F - 1);
+      const float2 e = tw[q];
+      const float2 c = cl_c[it];
+      acc = fmaf(c.x, e.x, acc);
+      acc = fmaf(c.y, e.y, acc);
+    }
+    a.out[(fofs + bd.y0 + i) * a.out_pitch + bd.x0 + jj] = acc;
+  }
+  a.status[orig] = FSE_BLOCK_OK;
+}
+
+template <int F, int NT, int KC = 0, int MODE = kPlain>
 constexpr Variant make_variant() {
-  return Variant{F, NT, KC, reinterpret_cast<const void*>(&fse_persistent<F, NT, KC>)};
+  return Variant{F, NT, KC, MODE, reinterpret_cast<const void*>(&fse_persistent<F, NT, KC, MODE>)};
 }
 
 // Workgroup shapes compiled for each transform size. The first entry of
@@ -630,7 +842,10 @@ const Variant kVariants[] = {
     make_variant<32, 64>(),  make_variant<32, 128>(), make_variant<32, 256>(),
     make_variant<64, 256>(), make_variant<64, 128>(), make_variant<64, 512>(),
     make_variant<128, 1024>(), make_variant<128, 512>(),
-    make_variant<64, 256, 256>(), make_variant<64, 256, 128>(), make_variant<64, 256, 512>(),
+    make_variant<64, 256, 256, kWarmFused>(), make_variant<64, 256, 128, kWarmFused>(),
+    make_variant<64, 256, 512, kWarmFused>(),
+    make_variant<64, 256, 256, kWarmPrep>(), make_variant<64, 256, 128, kWarmPrep>(),
+    make_variant<64, 256, 512, kWarmPrep>(),
 };
 
 }  // namespace
@@ -641,9 +856,9 @@ const Variant* variant_for(int F) {
   return nullptr;
 }
 
-const Variant* warm_variant_for(int F, int kc) {
+const Variant* warm_variant_for(int F, int kc, int mode) {
   for (const Variant& v : kVariants)
-    if (v.F == F && v.kc == kc) return &v;
+    if (v.F == F && v.kc == kc && kc > 0 && v.mode == mode) return &v;
   return nullptr;
 }
 
@@ -655,6 +870,26 @@ int variants_for(int F, const Variant** out, int cap) {
       ++n;
     }
   return n;
+}
+
+const void* restricted_kernel(int kc) {
+  switch (kc) {
+    case 128: return reinterpret_cast<const void*>(&fse_restricted<128>);
+    case 256: return reinterpret_cast<const void*>(&fse_restricted<256>);
+    case 512: return reinterpret_cast<const void*>(&fse_restricted<512>);
+    default: return nullptr;
+  }
+}
+
+size_t restricted_lds_bytes(int ir) {
+  return (size_t)kHalfRows * 64 * 8 + 64 * 8 + (size_t)ir * 12;
+}
+
+hipError_t launch_restricted(int kc, const ClassArgs& a, size_t lds, hipStream_t s) {
+  const void* fn = restricted_kernel(kc);
+  if (!fn || a.n <= 0) return hipErrorInvalidValue;
+  void* args[] = {const_cast<ClassArgs*>(&a)};
+  return hipLaunchKernel(fn, dim3(a.n), dim3(64), args, lds, s);
 }
 
 size_t lds_bytes(const Variant& v, int iters_cap) {

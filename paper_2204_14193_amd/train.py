@@ -132,9 +132,10 @@ def psnr_lost(reference, reconstruction, avail):
     return float(10.0 * np.log10(255.0 ** 2 / np.mean(err ** 2)))
 
 
-def evaluate(net, seeds=(99,), kc=256, restricted_iters=75, iters=25, plain_iters=100, reps=5, log=print):
+def evaluate(net, seeds=(99,), configs=((256, 100), (512, 100), (512, 125)), plain_iters=100, reps=5, log=print):
     """PSNR over the lost pixels and blocks/s of plain FSE and of the warm
-    start on held-out frames."""
+    start (restricted iterations only; (K, restricted iterations) per
+    config) on held-out frames."""
     import torch
     from . import fse, warm
     from synth import workloads
@@ -146,19 +147,20 @@ def evaluate(net, seeds=(99,), kc=256, restricted_iters=75, iters=25, plain_iter
     n = len(wl.blocks)
     infer = warm.Net(n, seed=0)
     infer.set_params(net.get_params())
-    for mode in ("plain", "warm"):
+    modes = [("plain", None)] + [(f"warm_k{k}_ir{ir}", (k, ir)) for k, ir in configs]
+    for mode, cfg in modes:
         blocks = wl.blocks.copy()
-        if mode == "warm":
-            blocks["iters"] = iters
+        if cfg is not None:
+            blocks["iters"] = 0
         plan = fse.Plan(wl.rho, wl.gamma, 4096)
         batch = fse.Batch(plan, blocks, *wl.frames.shape)
         out = img.to(torch.float32)
         status = torch.zeros(n, dtype=torch.int32, device=dev)
-        if mode == "plain":
+        if cfg is None:
             batch.autotune(img, av, out, status, reps=2)
             run = lambda: batch.run(img, av, out, status)
         else:
-            ws = warm.WarmStart(infer, batch, kc, restricted_iters, plain_iters)
+            ws = warm.WarmStart(infer, batch, cfg[0], cfg[1], plain_iters)
             run = lambda: ws.run(img, av, out, status)
         run()
         torch.cuda.synchronize()
@@ -171,16 +173,17 @@ def evaluate(net, seeds=(99,), kc=256, restricted_iters=75, iters=25, plain_iter
         ms = e0.elapsed_time(e1) / reps
         o = out.cpu().numpy()
         st = status.cpu().numpy()
-        res[mode] = {"psnr": psnr_lost(wl.frames, o, wl.avail), "ms": ms, "blocks_per_s": n / (ms * 1e-3),
-                     "ok": int((st == 0).sum())}
-        if mode == "warm":
-            res[mode]["fallbacks"] = int(ws.flags.sum().item())
-        log(f"{mode}: {res[mode]}")
+        r = {"psnr": psnr_lost(wl.frames, o, wl.avail), "ms": ms, "blocks_per_s": n / (ms * 1e-3),
+             "ok": int((st == 0).sum())}
+        if cfg is not None:
+            r["fallbacks"] = int(ws.flags.sum().item())
+            r["psnr_loss_db"] = res["plain"]["psnr"] - r["psnr"]
+            r["speedup"] = r["blocks_per_s"] / res["plain"]["blocks_per_s"]
+        res[mode] = r
+        log(f"{mode}: {r}")
         batch.close()
         plan.close()
     infer.close()
-    res["psnr_loss_db"] = res["plain"]["psnr"] - res["warm"]["psnr"]
-    res["speedup"] = res["warm"]["blocks_per_s"] / res["plain"]["blocks_per_s"]
     return res
 
 

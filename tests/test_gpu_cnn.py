@@ -160,11 +160,20 @@ def test_topk_exact_with_ties_and_nan():
         assert np.array_equal(c[b], np.sort(order[:K])), b
 
 
-def _warm_case(ir=30, iters=20, fb=40, kc=256, n_blocks=12):
+def _warm_case(ir=30, iters=20, fb=40, kc=256, n_blocks=12, extra_iters=None):
+    """Warm-started FSE on n_blocks isolated blocks with synthetic candidate
+    sets; block 3 is flagged (plain fallback). extra_iters: append one more
+    block with that iteration count (a batch whose largest count is then
+    > 0 runs the single-kernel form)."""
     import torch
     import paper_2204_14193_amd as fse
     from paper_2204_14193_amd import warm
-    wl = workloads.subset(workloads.isolated_256(iters=iters), np.arange(0, 64, 64 // n_blocks)[:n_blocks])
+    idx = list(np.arange(0, 64, 64 // n_blocks)[:n_blocks])
+    if extra_iters is not None:
+        idx.append(63)
+    wl = workloads.subset(workloads.isolated_256(iters=iters), idx)
+    if extra_iters is not None:
+        wl.blocks["iters"][-1] = extra_iters
     dev = torch.device("cuda:0")
     img = torch.from_numpy(wl.distorted).to(dev)
     av = torch.from_numpy(wl.avail).to(dev)
@@ -228,3 +237,40 @@ def test_warm_fallback_is_plain_fse_bitwise():
     sl = (0, slice(b["y0"], b["y0"] + 16), slice(b["x0"], b["x0"] + 16))
     assert np.array_equal(o2.cpu().numpy()[sl], out[sl])
     assert np.array_equal(t2[0, :fb], trace[i, :fb])
+
+
+def test_split_warm_replays_against_oracle():
+    """Restricted iterations only (block iteration count 0): the transform
+    kernel and the restricted kernel."""
+    ir, fb = 40, 30
+    for kc in (128, 256, 512):
+        wl, out, st, trace, cands, flags = _warm_case(ir, 0, fb, kc=kc)
+        _say(f"case split warm fse: kc={kc}, {len(wl.blocks)} blocks, ir={ir} fallback={fb}")
+        assert (st == 0).all()
+        for i, blk in enumerate(wl.blocks):
+            if flags[i]:
+                continue
+            r = parity.replay_warm_block(wl.frames, wl.avail, blk, wl.rho, wl.gamma, trace[i], cands[i], ir, 0)
+            rr = r["restricted"]
+            assert rr["gap_violations"] == 0, (kc, i, rr)
+            assert rr["coef_max"] <= parity.COEF_TOL and rr["coef_l2"] <= parity.COEF_TOL, (kc, i, rr)
+            g = out[0, blk["y0"]:blk["y0"] + 16, blk["x0"]:blk["x0"] + 16]
+            assert np.abs(g - r["values"]).max() < 0.05, (kc, i)
+
+
+def test_split_warm_equals_single_kernel_bitwise():
+    """The two-kernel form computes the same bits as the single-kernel form
+    (which a batch takes when some block also has full iterations)."""
+    ir, fb = 40, 30
+    for kc in (256, 512):
+        _say(f"case split vs single kernel: kc={kc}")
+        wl1, out1, st1, tr1, c1, f1 = _warm_case(ir, 0, fb, kc=kc)
+        wl2, out2, st2, tr2, c2, f2 = _warm_case(ir, 0, fb, kc=kc, extra_iters=5)
+        n = len(wl1.blocks)
+        assert np.array_equal(c1, c2[:n]) and np.array_equal(st1, st2[:n])
+        assert (st1 == 0).all()
+        for i, blk in enumerate(wl1.blocks):
+            sl = (0, slice(blk["y0"], blk["y0"] + 16), slice(blk["x0"], blk["x0"] + 16))
+            assert np.array_equal(out1[sl], out2[sl]), (kc, i)
+            m = fb if f1[i] else ir
+            assert np.array_equal(tr1[i, :m], tr2[i, :m]), (kc, i)
