@@ -1,13 +1,21 @@
-"""Throughput of complex-valued FSE on one MI355X.
+"""Throughput of complex-valued FSE on one MI355X, plain and warm-started.
 
 A step conceals every lost block of a batch of eight synthetic 1920x1080
 frames (804 isolated 16x16 losses per frame, 10% of the 16x16 grid, border
-16 so each area is 48x48, 64x64 transform, rho 0.8, gamma 0.5, 100
-iterations): 6432 blocks in one persistent launch, inputs resident in HBM.
+16 so each area is 48x48, 64x64 transform, rho 0.8, gamma 0.5): 6432 blocks,
+inputs resident in HBM. Two legs are timed, each over the same number of
+steps:
+  plain  FSE with 100 iterations per block (persistent kernel);
+  warm   the learned warm start: network inputs, forward pass, top-K
+         candidate bins, transform kernel, restricted iterations.
+PSNR over the lost pixels (against the undistorted frames) decides: the
+reported value is the warm start's blocks/s if it loses at most 0.1 dB
+against plain FSE, otherwise plain FSE's.
 
-Prints one JSON line: blocks/s (value), lost Mpixel/s, the roofline of the
-dominant kernel, and the FP64 CPU oracle timed on the host's cores over a
-bounded sample of the same blocks.
+Prints one JSON line: blocks/s (value), both legs, the roofline of the
+dominant kernel of the reported leg (durations from HIP events around each
+kernel launch inside the timed steps), and the FP64 CPU oracle timed on the
+host's cores over a bounded sample of the same blocks.
 """
 import argparse
 import hashlib
@@ -22,11 +30,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "FSE blocks/s (16² loss, 64² FFT) plain vs warm-start at ≤0.1 dB PSNR loss"
-PEAK_FP32_TFLOPS = 157.3        # MI355X FP32 vector, published
+PSNR_BAR_DB = 0.1
+PEAK_FP32_TFLOPS = 157.3        # MI355X FP32 vector, published (counts packed FMA)
+NONPACKED_FP32_TFLOPS = 78.6    # 256 CU x 64 lanes x 2 FLOP x 2.4 GHz, without packed FP32
 NOMINAL_LDS_TBPS = 78.6         # 256 CU x 128 B/clk x 2.4 GHz
+PEAK_HBM_TBPS = 8.0
 FLOP_PER_BIN_ITER = 11          # complex multiply-subtract (8) + |R|^2 (3), eq. (18) + eq. (12)
+FLOP_PER_PIXEL_COEF = 4         # Re{c e^{j theta}}: two FMAs, the model on B
 LDS_BYTES_PER_BIN_ITER = 24     # read R_w, read shifted W, write R_w (spectra resident on chip)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fse_persistent_64.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def kernel_source_hash():
@@ -36,18 +48,52 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(n_blocks, workload):
-    """HBM bytes per launch from committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    counts, scaled by the copy-kernel calibration; None when the counters
-    were taken on another version of the kernel."""
+def measured_traffic(kernel, n_blocks, workload):
+    """HBM bytes per launch of `kernel` from committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE counts, scaled by the copy-kernel calibration;
+    None when the counters were taken on another version of the kernel
+    source or another workload."""
     try:
         with open(TRAFFIC_FILE) as fh:
-            t = json.load(fh)
+            t = json.load(fh).get(kernel)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != kernel_source_hash() or t.get("blocks") != n_blocks or t.get("workload") != workload:
+    if not t or t.get("kernel_sha") != kernel_source_hash() or t.get("blocks") != n_blocks \
+            or t.get("workload") != workload:
         return None
     return float(t["bytes_per_launch"])
+
+
+def psnr_lost(frames, out, avail):
+    """10 log10(255^2 / MSE) over the lost pixels, output clipped to [0, 255]."""
+    lost = avail == 0
+    err = np.clip(out[lost].astype(np.float64), 0.0, 255.0) - frames[lost].astype(np.float64)
+    return float(10.0 * np.log10(255.0 ** 2 / np.mean(err ** 2)))
+
+
+def time_steps(run, steps, stream):
+    """Run `steps` steps bracketed by device synchronisation; returns wall
+    ms per step and the mean of per-step HIP event durations."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, e in ev:
+        s.record(stream)
+        run()
+        e.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall * 1e3 / steps, float(np.mean([s.elapsed_time(e) for s, e in ev]))
+
+
+def kernel_summary(batch):
+    """{kind: (launches, mean ms, F)} from the batch's timing records."""
+    acc = {}
+    for kind, F, ms in batch.kernel_times():
+        n, tot, _ = acc.get(kind, (0, 0.0, F))
+        acc[kind] = (n + 1, tot + ms, F)
+    return {k: (n, tot / n, F) for k, (n, tot, F) in acc.items()}
 
 
 def _init_worker():
@@ -103,7 +149,10 @@ def main():
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--workload", default="random-1080p-16x16",
                     choices=["random-1080p-16x16", "random-1080p-8x8", "mixed-4k"],
-                    help="the metric's workload (default) or one of the other configurations")
+                    help="the metric's workload (default) or one of the other configurations (plain only)")
+    ap.add_argument("--kc", type=int, default=512, help="warm start: candidate bins per block")
+    ap.add_argument("--ir", type=int, default=110, help="warm start: restricted iterations")
+    ap.add_argument("--no-warm", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the (untimed) autotuner")
@@ -118,10 +167,12 @@ def main():
     import paper_2204_14193_amd as fse
     from synth import workloads
 
+    warm_ok = args.workload == "random-1080p-16x16" and not args.no_warm
     if args.workload == "random-1080p-16x16":
         wl = workloads.random_1080p_16x16(seeds=tuple(range(99, 99 + args.frames)), iters=args.iters)
         desc = (f"{args.frames}x 1920x1080 synthetic frames, 804 isolated 16x16 losses per frame (10%), "
-                f"border 16 (48x48 area), 64x64 transform, rho 0.8, gamma 0.5, {args.iters} iterations, plain FSE")
+                f"border 16 (48x48 area), 64x64 transform, rho 0.8, gamma 0.5; plain FSE {args.iters} iterations "
+                f"vs learned warm start (top-{args.kc} candidates, {args.ir} restricted iterations)")
     elif args.workload == "random-1080p-8x8":
         wl = workloads.random_1080p_8x8(iters=200)
         desc = ("1920x1080 synthetic frame, 3240 isolated 8x8 losses (10%), border 16 (40x40 area), "
@@ -134,57 +185,103 @@ def main():
     dev = torch.device("cuda:0")
     img = torch.from_numpy(wl.distorted).to(dev)
     av = torch.from_numpy(wl.avail).to(dev)
+    stream = torch.cuda.current_stream()
+    legs = {}
+
+    # ---- plain FSE
     out = img.to(torch.float32)
     status = torch.zeros(n, dtype=torch.int32, device=dev)
     plan = fse.Plan(wl.rho, wl.gamma, int(wl.blocks["iters"].max()))
     batch = fse.Batch(plan, wl.blocks, *wl.frames.shape)
-    stream = torch.cuda.current_stream()
     tuning = batch.autotune(img, av, out, status, reps=2) if not args.no_tune else []
     classes = sorted(set(int(f) for f in wl.blocks["fft"]))
     info = {F: batch.launch_info(F) for F in classes}
-
+    run_plain = lambda: batch.run(img, av, out, status)
     for _ in range(args.warmup):
-        batch.run(img, av, out, status)
+        run_plain()
     torch.cuda.synchronize()
+    batch.set_timing(len(classes) * args.steps)
+    ms, ev_ms = time_steps(run_plain, args.steps, stream)
+    kern = kernel_summary(batch)
+    batch.set_timing(0)
     assert (status.cpu().numpy() == fse.BLOCK_OK).all()
-
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s, e in ev:
-        s.record(stream)
-        batch.run(img, av, out, status)
-        e.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    launch_ms = float(np.mean([s.elapsed_time(e) for s, e in ev]))
-    ms_per_step = wall * 1e3 / args.steps
-
-    blocks_per_s = n / (ms_per_step * 1e-3)
-    lost_px = int(wl.blocks["bh"].astype(np.int64) @ wl.blocks["bw"].astype(np.int64))
     bin_iters = int(np.sum(wl.blocks["fft"].astype(np.int64) ** 2 * wl.blocks["iters"].astype(np.int64)))
-    flop = FLOP_PER_BIN_ITER * bin_iters
-    achieved = flop / (launch_ms * 1e-3) / 1e12
-    lds_bytes = LDS_BYTES_PER_BIN_ITER * bin_iters
+    legs["plain"] = {"blocks_per_s": n / (ms * 1e-3), "ms_per_step": ms, "event_ms": ev_ms,
+                     "psnr_db": psnr_lost(wl.frames, out.cpu().numpy(), wl.avail),
+                     "kernels": {f"fse_persistent<{F},{info[F]['threads']}>": {"ms": kern["plain"][1], **info[F]}
+                                 for F in classes},
+                     "autotune_us": {f"{F}/{t}": round(us, 1) for F, t, us in tuning}}
+    plain_roof = {"kernel": f"fse_persistent<{classes[0]},{info[classes[0]]['threads']}>",
+                  "flop": FLOP_PER_BIN_ITER * bin_iters, "ms": kern["plain"][1]}
+    batch.close()
+    plan.close()
+
+    # ---- learned warm start (restricted iterations only)
+    warm_roof = None
+    if warm_ok:
+        from paper_2204_14193_amd import warm
+        wblocks = wl.blocks.copy()
+        wblocks["iters"] = 0
+        out_w = img.to(torch.float32)
+        status_w = torch.zeros(n, dtype=torch.int32, device=dev)
+        plan_w = fse.Plan(wl.rho, wl.gamma, args.ir + args.iters)
+        batch_w = fse.Batch(plan_w, wblocks, *wl.frames.shape)
+        net = warm.Net(n, seed=0)
+        net.load()
+        ws = warm.WarmStart(net, batch_w, args.kc, args.ir, args.iters)
+        run_warm = lambda: ws.run(img, av, out_w, status_w)
+        for _ in range(args.warmup):
+            run_warm()
+        torch.cuda.synchronize()
+        batch_w.set_timing(2 * args.steps)
+        ms_w, ev_w = time_steps(run_warm, args.steps, stream)
+        kw = kernel_summary(batch_w)
+        batch_w.set_timing(0)
+        assert (status_w.cpu().numpy() == fse.BLOCK_OK).all()
+        fallbacks = int(ws.flags.sum().item())
+        p_w = psnr_lost(wl.frames, out_w.cpu().numpy(), wl.avail)
+        with open(warm.WEIGHTS, "rb") as fh:
+            wsha = hashlib.sha256(fh.read()).hexdigest()[:16]
+        legs["warm"] = {"blocks_per_s": n / (ms_w * 1e-3), "ms_per_step": ms_w, "event_ms": ev_w, "psnr_db": p_w,
+                        "psnr_loss_db": legs["plain"]["psnr_db"] - p_w,
+                        "meets_bar": legs["plain"]["psnr_db"] - p_w <= PSNR_BAR_DB,
+                        "speedup_vs_plain": legs["plain"]["ms_per_step"] / ms_w, "fallbacks": fallbacks,
+                        "kc": args.kc, "restricted_iters": args.ir, "weights_sha": wsha,
+                        "kernels": {("fse_restricted<%d>" % args.kc if k == "restricted" else
+                                     "fse_persistent<64,256,%d,prep>" % args.kc): {"ms": v[1], "launches": v[0]}
+                                    for k, v in kw.items()}}
+        n_pix = int(wl.blocks["bh"].astype(np.int64) @ wl.blocks["bw"].astype(np.int64))
+        warm_roof = {"kernel": "fse_restricted<%d>" % args.kc,
+                     "flop": n * args.ir * args.kc * FLOP_PER_BIN_ITER + n_pix * args.ir * FLOP_PER_PIXEL_COEF,
+                     "ms": kw["restricted"][1], "prep_ms": kw["warm_prep"][1]}
+        batch_w.close()
+        plan_w.close()
+        net.close()
+
+    use_warm = warm_ok and legs["warm"]["meets_bar"]
+    leg = legs["warm" if use_warm else "plain"]
+    roof = warm_roof if use_warm else plain_roof
+    achieved = roof["flop"] / (roof["ms"] * 1e-3) / 1e12
     rec = {
-        "metric": METRIC, "value": blocks_per_s, "unit": "blocks/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "metric": METRIC, "value": leg["blocks_per_s"], "unit": "blocks/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": leg["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": desc, "name": args.workload, "blocks": n,
+        "config": {"workload": desc, "name": args.workload, "blocks": n, "reported_leg": "warm" if use_warm else "plain",
                    "fft": classes[0] if len(classes) == 1 else classes,
                    "iters": int(wl.blocks["iters"][0]) if len(set(wl.blocks["iters"].tolist())) == 1 else "mixed",
                    "rho": wl.rho, "gamma": wl.gamma},
-        "mpixel_per_s": lost_px / (ms_per_step * 1e-3) / 1e6,
-        "launch": {"kernels": {f"fse_persistent<{F},{info[F]['threads']}>": info[F] for F in classes},
-                   "avg_ms": launch_ms, "autotune_us": {f"{F}/{t}": round(us, 1) for F, t, us in tuning}},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(n, args.workload)},
-        "lds_roofline": {"achieved": lds_bytes / (launch_ms * 1e-3) / 1e12, "peak": NOMINAL_LDS_TBPS,
-                         "unit": "TB/s", "frac": lds_bytes / (launch_ms * 1e-3) / 1e12 / NOMINAL_LDS_TBPS,
-                         "note": "algorithmic 24 B/bin/iteration against the nominal LDS bandwidth"},
+        "legs": legs,
+        "roofline": {"bound": "alu", "kernel": roof["kernel"], "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "frac_nonpacked": achieved / NONPACKED_FP32_TFLOPS, "kernel_ms": roof["ms"],
+                     "traffic": measured_traffic(roof["kernel"], n, args.workload)},
     }
+    if not use_warm:
+        lds_bytes = LDS_BYTES_PER_BIN_ITER * bin_iters
+        rec["lds_roofline"] = {"achieved": lds_bytes / (roof["ms"] * 1e-3) / 1e12, "peak": NOMINAL_LDS_TBPS,
+                               "unit": "TB/s", "frac": lds_bytes / (roof["ms"] * 1e-3) / 1e12 / NOMINAL_LDS_TBPS,
+                               "note": "algorithmic 24 B/bin/iteration against the nominal LDS bandwidth"}
     if args.copy_bytes > 0:
         src = torch.randint(0, 255, (args.copy_bytes,), dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -194,8 +291,6 @@ def main():
         rec["copy_calibration_bytes"] = args.copy_bytes
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, n))
-    batch.close()
-    plan.close()
     print(json.dumps(rec), flush=True)
 
 

@@ -167,6 +167,25 @@ fse_status_t fse_batch_autotune(fse_batch_t batch, const uint8_t* d_image, const
                                 float* d_out, int64_t out_pitch, int32_t* d_status, int32_t reps, void* stream,
                                 char* report, size_t report_len);
 
+/* Kernel timing, a profiling hook. fse_batch_set_timing(batch, max_records)
+ * makes every later kernel launch of this batch (fse_extrapolate_batch,
+ * fse_warm_extrapolate_batch; not the autotuner) record a HIP event on its
+ * stream before and after the kernel, for up to max_records kernels;
+ * further launches run untimed. max_records = 0 switches timing off and
+ * frees the events; calling it again restarts the record. Host-side.
+ * fse_batch_kernel_times waits for the recorded kernels and writes, for
+ * the first min(count, cap) of them in launch order, the duration in ms,
+ * the kernel kind (FSE_KERNEL_*) and the transform size; returns the number
+ * recorded (negative fse_status_t on error). */
+enum {
+  FSE_KERNEL_PLAIN = 0,       /* persistent kernel, plain FSE                     */
+  FSE_KERNEL_WARM_FUSED = 1,  /* warm start, restricted and full phases in one    */
+  FSE_KERNEL_WARM_PREP = 2,   /* warm start, transform and staging (split form)   */
+  FSE_KERNEL_RESTRICTED = 3   /* warm start, restricted iterations (split form)   */
+};
+fse_status_t fse_batch_set_timing(fse_batch_t batch, int32_t max_records);
+int32_t fse_batch_kernel_times(fse_batch_t batch, float* ms, int32_t* kind, int32_t* fft, int32_t cap);
+
 /* ------------------------------------------------------------------------
  * Learned warm start. Not part of the paper's method: a small network reads
  * each 48x48 area and scores every bin of the 64x64 transform; the K best

@@ -79,6 +79,10 @@ struct fse_batch_s {
   float2* d_stage_w = nullptr;             // split form's staging (caller's block order)
   float2* d_stage_r = nullptr;
   int32_t stage_kc = 0;
+  // kernel timing hook: event pairs and what each recorded launch was
+  std::vector<hipEvent_t> t_ev;
+  std::vector<int32_t> t_kind, t_fft;
+  int32_t t_count = 0;
   bool all_48 = false;                     // every area is 48 x 48 (network input size)
 };
 
@@ -216,7 +220,33 @@ fse_status_t configure(fse_batch_s* b, fse_batch_s::Cls& c, const fse::Variant* 
   return FSE_OK;
 }
 
+void free_timing(fse_batch_s* b) {
+  for (hipEvent_t e : b->t_ev) (void)hipEventDestroy(e);
+  b->t_ev.clear();
+  b->t_kind.clear();
+  b->t_fft.clear();
+  b->t_count = 0;
+}
+
+// Launch one kernel through `go`, bracketed by the timing events when the
+// batch records timings and slots are left.
+template <class Go>
+hipError_t timed(fse_batch_s* b, int kind, int fft, hipStream_t s, Go go) {
+  const int slot = b->t_count;
+  const bool rec = slot < (int)b->t_kind.size();
+  if (rec && hipEventRecord(b->t_ev[2 * slot], s) != hipSuccess) return hipErrorUnknown;
+  const hipError_t e = go();
+  if (rec && e == hipSuccess) {
+    if (hipEventRecord(b->t_ev[2 * slot + 1], s) != hipSuccess) return hipErrorUnknown;
+    b->t_kind[slot] = kind;
+    b->t_fft[slot] = fft;
+    b->t_count = slot + 1;
+  }
+  return e;
+}
+
 void free_batch(fse_batch_s* b) {
+  free_timing(b);
   (void)hipFree(b->d_stage_w);
   (void)hipFree(b->d_stage_r);
   (void)hipFree(b->d_blocks);
@@ -390,13 +420,47 @@ static fse_status_t launch_one(fse_batch_t batch, int ci, const uint8_t* d_image
         a.stage_r = batch->d_stage_r;
       }
     }
-    if (fse::launch_class(*c.v, a, c.grid, c.lds, s) != hipSuccess)
+    const int kind = !warm ? FSE_KERNEL_PLAIN : batch->warm_split ? FSE_KERNEL_WARM_PREP : FSE_KERNEL_WARM_FUSED;
+    if (timed(batch, kind, c.v->F, s, [&] { return fse::launch_class(*c.v, a, c.grid, c.lds, s); }) != hipSuccess)
       return fail(FSE_ERR_HIP, "kernel launch failed");
     if (warm && batch->warm_split &&
-        fse::launch_restricted(batch->warm_kc, a, batch->restricted_lds, s) != hipSuccess)
+        timed(batch, FSE_KERNEL_RESTRICTED, 64, s,
+              [&] { return fse::launch_restricted(batch->warm_kc, a, batch->restricted_lds, s); }) != hipSuccess)
       return fail(FSE_ERR_HIP, "kernel launch failed (restricted iterations)");
   }
   return FSE_OK;
+}
+
+extern "C" fse_status_t fse_batch_set_timing(fse_batch_t batch, int32_t max_records) {
+  if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
+  if (max_records < 0 || max_records > (1 << 20)) return fail(FSE_ERR_INVALID_ARG, "max_records must lie in [0, 2^20]");
+  free_timing(batch);
+  if (max_records == 0) return FSE_OK;
+  batch->t_ev.assign(2 * (size_t)max_records, nullptr);
+  for (hipEvent_t& e : batch->t_ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+      free_timing(batch);
+      return fail(FSE_ERR_HIP, "hipEventCreate failed");
+    }
+  batch->t_kind.assign(max_records, -1);
+  batch->t_fft.assign(max_records, 0);
+  return FSE_OK;
+}
+
+extern "C" int32_t fse_batch_kernel_times(fse_batch_t batch, float* ms, int32_t* kind, int32_t* fft, int32_t cap) {
+  if (!batch || cap < 0) return fail(FSE_ERR_INVALID_ARG, "bad argument");
+  const int32_t n = std::min(batch->t_count, cap);
+  for (int32_t i = 0; i < n; ++i) {
+    float t = 0.f;
+    if (hipEventSynchronize(batch->t_ev[2 * i + 1]) != hipSuccess ||
+        hipEventElapsedTime(&t, batch->t_ev[2 * i], batch->t_ev[2 * i + 1]) != hipSuccess)
+      return fail(FSE_ERR_HIP, "hipEventElapsedTime failed");
+    if (ms) ms[i] = t;
+    if (kind) kind[i] = batch->t_kind[i];
+    if (fft) fft[i] = batch->t_fft[i];
+  }
+  return batch->t_count;
 }
 
 extern "C" fse_status_t fse_batch_set_variant(fse_batch_t batch, int32_t F, int32_t threads) {

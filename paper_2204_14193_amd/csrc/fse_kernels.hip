@@ -176,6 +176,46 @@ __device__ __forceinline__ void fft_lines(float2* Z, const float2* tw, int t) {
   }
 }
 
+// ------------------------------------------------------------ synthesis
+// The model on B: out(m, n) = Re{ sum_nu c_nu exp(j 2 pi (u m + v n) / F) }
+// (the inverse transform of G restricted to B), for pixel p of the block at
+// area position (bo + p / bw, bo + p % bw). Thread `t` of `NT` takes pixels
+// t, t + NT, ... in passes of Q; each coefficient is read once per pass and
+// its bin made wave-uniform. Per pixel the terms are added in list order.
+template <int F, int NT, int Q>
+__device__ __forceinline__ void synthesize(const int* cl_idx, const float2* cl_c, int n_coef, const float2* tw,
+                                           int bh, int bw, int bo, float* out, int64_t out_pitch, int t) {
+  const int np = bh * bw;
+  for (int p0 = 0; p0 < np; p0 += NT * Q) {
+    if (p0 + (t & ~63) >= np) break;  // wave-uniform: no pixel left for this wave
+    int mq[Q], nq[Q];
+    float acc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int p = min(p0 + t + q * NT, np - 1);
+      mq[q] = bo + p / bw;
+      nq[q] = bo + p % bw;
+      acc[q] = 0.f;
+    }
+    for (int it = 0; it < n_coef; ++it) {
+      const int sidx = __builtin_amdgcn_readfirstlane(cl_idx[it]);
+      const int u = sidx / F, v = sidx % F;
+      const float2 c = cl_c[it];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const float2 e = tw[(u * mq[q] + v * nq[q]) & (F - 1)];  // exp(-j theta): Re{c e^{j theta}} = c.x e.x + c.y e.y
+        acc[q] = fmaf(c.x, e.x, acc[q]);
+        acc[q] = fmaf(c.y, e.y, acc[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int p = p0 + t + q * NT;
+      if (p < np) out[(int64_t)(mq[q] - bo) * out_pitch + (nq[q] - bo)] = acc[q];
+    }
+  }
+}
+
 // ------------------------------------------------------------------ kernel
 
 template <int F, int NT>
@@ -610,22 +650,9 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
   }
   if (!finite) return FSE_BLOCK_NONFINITE;
 
-  // 4. model on B: Re{ sum_nu c_nu exp(j 2 pi (u m + v n) / F) }
-  const int n_coef = tbase + I_full;
-  for (int p = t; p < bh * bw; p += NT) {
-    const int i = p / bw, jj = p % bw;
-    const int m = bo + i, n = bo + jj;
-    float acc = 0.f;
-    for (int it = 0; it < n_coef; ++it) {
-      const int sidx = s.cl_idx[it];
-      const int q = ((sidx / F) * m + (sidx % F) * n) & (F - 1);
-      const float2 e = s.tw[q];  // exp(-j theta): Re{c e^{j theta}} = c.x e.x + c.y e.y
-      const float2 c = s.cl_c[it];
-      acc = fmaf(c.x, e.x, acc);
-      acc = fmaf(c.y, e.y, acc);
-    }
-    a.out[(fofs + bd.y0 + i) * a.out_pitch + bd.x0 + jj] = acc;
-  }
+  // 4. model on B
+  synthesize<F, NT, 1>(s.cl_idx, s.cl_c, tbase + I_full, s.tw, bh, bw, bo,
+                       a.out + (fofs + bd.y0) * a.out_pitch + bd.x0, a.out_pitch, t);
   return FSE_BLOCK_OK;
 }
 
@@ -788,11 +815,9 @@ __global__ __launch_bounds__(64) void fse_restricted(ClassArgs a) {
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
       const int ya = xa[j] + ca, yb = xb[j] + cb;
-      const int dk = (ya >> 7) & (F - 1);
-      const bool flip = dk > F / 2;
-      const int ia = dk * F + (ya & (F - 1));
-      const int ib = ((yb >> 7) & (F - 1)) * F + (yb & (F - 1));
-      float2 w = Wh[flip ? ib : ia];
+      const bool flip = ((ya >> 7) & (F - 1)) > F / 2;
+      const int y = flip ? yb : ya;
+      float2 w = Wh[((y >> 7) & (F - 1)) * F + (y & (F - 1))];
       w.y = flip ? -w.y : w.y;
       float rx = Rx[j], ry = Ry[j];
       rx = fmaf(-cre, w.x, rx);
@@ -809,24 +834,11 @@ __global__ __launch_bounds__(64) void fse_restricted(ClassArgs a) {
     return;
   }
   __syncthreads();
-  // model on B: Re{ sum_nu c_nu exp(j 2 pi (u m + v n) / F) }
+  // model on B, as in the persistent kernel
   const UBlock bd = uniform_block(a.blocks + bi);
-  const int bh = bd.bh, bw = bd.bw, bo = bd.border;
   const int64_t fofs = (int64_t)bd.frame * a.H;
-  for (int p = lane; p < bh * bw; p += 64) {
-    const int i = p / bw, jj = p % bw;
-    const int m = bo + i, n = bo + jj;
-    float acc = 0.f;
-    for (int it = 0; it < a.ir; ++it) {
-      const int sidx = cl_idx[it];
-      const int q = ((sidx / F) * m + (sidx % F) * n) & (F - 1);
-      const float2 e = tw[q];
-      const float2 c = cl_c[it];
-      acc = fmaf(c.x, e.x, acc);
-      acc = fmaf(c.y, e.y, acc);
-    }
-    a.out[(fofs + bd.y0 + i) * a.out_pitch + bd.x0 + jj] = acc;
-  }
+  synthesize<F, 64, 4>(cl_idx, cl_c, a.ir, tw, bd.bh, bd.bw, bd.border,
+                       a.out + (fofs + bd.y0) * a.out_pitch + bd.x0, a.out_pitch, lane);
   a.status[orig] = FSE_BLOCK_OK;
 }
 

@@ -10,6 +10,8 @@ import numpy as np
 from . import _lib
 
 BLOCK_OK, BLOCK_EMPTY_SUPPORT, BLOCK_NONFINITE = 0, 1, 2
+# FSE_KERNEL_* of include/fse.h, by value
+KERNEL_KINDS = ("plain", "warm_fused", "warm_prep", "restricted")
 
 BLOCK_DTYPE = np.dtype([("frame", "<i4"), ("y0", "<i4"), ("x0", "<i4"),
                         ("bh", "<i2"), ("bw", "<i2"), ("border", "<i2"),
@@ -97,6 +99,27 @@ class Batch:
         _check(_lib.lib().fse_batch_launch_info(self._h, int(F), C.byref(t), C.byref(w),
                                                 C.byref(g), C.byref(l)), "fse_batch_launch_info")
         return dict(threads=t.value, wg_per_cu=w.value, grid=g.value, lds_bytes=l.value)
+
+    def set_timing(self, max_records):
+        """Record HIP events around each of the next max_records kernels this
+        batch launches (0 = off); read them with kernel_times()."""
+        _check(_lib.lib().fse_batch_set_timing(self._h, int(max_records)), "fse_batch_set_timing")
+
+    def kernel_times(self):
+        """[(kind, F, ms), ...] of the recorded kernels in launch order; kind
+        is one of KERNEL_KINDS. Waits for them."""
+        n = int(_lib.lib().fse_batch_kernel_times(self._h, None, None, None, 0))
+        if n < 0:
+            _check(n, "fse_batch_kernel_times")
+        ms = np.zeros(max(n, 1), np.float32)
+        kind = np.zeros(max(n, 1), np.int32)
+        fft = np.zeros(max(n, 1), np.int32)
+        got = int(_lib.lib().fse_batch_kernel_times(self._h, ms.ctypes.data_as(C.c_void_p),
+                                                    kind.ctypes.data_as(C.c_void_p),
+                                                    fft.ctypes.data_as(C.c_void_p), n))
+        if got < 0:
+            _check(got, "fse_batch_kernel_times")
+        return [(KERNEL_KINDS[int(kind[i])], int(fft[i]), float(ms[i])) for i in range(min(n, got))]
 
     def set_variant(self, F, threads):
         _check(_lib.lib().fse_batch_set_variant(self._h, int(F), int(threads)), "fse_batch_set_variant")
