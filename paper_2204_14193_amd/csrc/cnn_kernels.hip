@@ -22,13 +22,9 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// FP32 -> BF16, round to nearest even (NaN stays NaN).
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
+// FP32 -> BF16, round to nearest even (NaN stays NaN): the hardware
+// conversion of gfx950 (v_cvt_pk_bf16_f32).
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 __device__ __forceinline__ f32x16 mfma(uint4 a, uint4 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
@@ -37,14 +33,24 @@ __device__ __forceinline__ f32x16 mfma(uint4 a, uint4 b, f32x16 c) {
 
 __device__ __forceinline__ int drow(int i, int lane) { return 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3); }
 
+// Sum over the 64 lanes of a wave, the same value in every lane.
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xb1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4e, 0xf, 0xf, false);   // quad_perm [2,3,0,1]
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xf, 0xf, false);  // row_half_mirror
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xf, 0xf, false);  // row_mirror
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
 // ------------------------------------------------------------------ patches
 // Network input of one 48x48 area: channel 0 = (s - mean_A(s)) / 64 on the
 // support area A, channel 1 = indicator of A; both 0 elsewhere.
 __global__ __launch_bounds__(256) void k_patches(const uint8_t* img, const uint8_t* avail, int64_t pitch, int H,
                                                  int W, const fse_block_t* blocks, const int32_t* orig, int n,
                                                  uint16_t* x) {
-  __shared__ float red_s[256];
-  __shared__ float red_c[256];
+  __shared__ uint32_t red[2][4];
   const int b = blockIdx.x;
   if (b >= n) return;
   const int t = threadIdx.x;
@@ -53,8 +59,9 @@ __global__ __launch_bounds__(256) void k_patches(const uint8_t* img, const uint8
   const int ya = bd.y0 - bo, xa = bd.x0 - bo;
   const uint8_t* im = img + (int64_t)bd.frame * H * pitch;
   const uint8_t* av = avail + (int64_t)bd.frame * H * pitch;
-  float sum = 0.f, cnt = 0.f;
-  float sv[9];
+  // pixel values and counts are integers, so their sums are exact in any order
+  uint32_t sum = 0, cnt = 0;
+  uint32_t sv[9];
   bool ia[9];
 #pragma unroll
   for (int r = 0; r < 9; ++r) {
@@ -62,29 +69,24 @@ __global__ __launch_bounds__(256) void k_patches(const uint8_t* img, const uint8
     const int m = e / kIn, c = e % kIn;
     const int y = ya + m, xx = xa + c;
     const bool inB = m >= bo && m < bo + bd.bh && c >= bo && c < bo + bd.bw;
-    bool a = false;
-    float s = 0.f;
-    if (!inB && y >= 0 && y < H && xx >= 0 && xx < W) {
-      const int64_t p = (int64_t)y * pitch + xx;
-      a = av[p] != 0;
-      s = (float)im[p];
-    }
-    ia[r] = a;
+    const bool inside = !inB && y >= 0 && y < H && xx >= 0 && xx < W;
+    const int64_t p = (int64_t)min(max(y, 0), H - 1) * pitch + min(max(xx, 0), W - 1);
+    const uint32_t a = av[p], s = im[p];
+    ia[r] = inside && a != 0;
     sv[r] = s;
-    sum += a ? s : 0.f;
-    cnt += a ? 1.f : 0.f;
+    sum += ia[r] ? s : 0u;
+    cnt += ia[r] ? 1u : 0u;
   }
-  red_s[t] = sum;
-  red_c[t] = cnt;
+  sum = wave_sum_u32(sum);
+  cnt = wave_sum_u32(cnt);
+  if ((t & 63) == 0) {
+    red[0][t >> 6] = sum;
+    red[1][t >> 6] = cnt;
+  }
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) {
-      red_s[t] += red_s[t + w];
-      red_c[t] += red_c[t + w];
-    }
-    __syncthreads();
-  }
-  const float mu = red_c[0] > 0.f ? red_s[0] / red_c[0] : 0.f;
+  const uint32_t S = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+  const uint32_t N = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  const float mu = N > 0 ? (float)S / (float)N : 0.f;
   uint32_t* out = reinterpret_cast<uint32_t*>(x + (int64_t)orig[b] * kPatchElems);
 #pragma unroll
   for (int r = 0; r < 9; ++r) {
@@ -127,40 +129,59 @@ __device__ __forceinline__ void conv_layer(const uint16_t* in, uint16_t* out, co
     }
   }
   const float bn = bf2f(bias[n]);
-  for (int tile = wave; tile < MT; tile += 4) {
+  // A fragment of output-row tile `tile` for depth step ks (zero outside).
+  auto gather = [&](int tile, int ks) -> uint4 {
     const int m = tile * 32 + (lane & 31);
     const int oy = m / HO, ox = m % HO;
     const bool mv = m < P;
-    f32x16 acc = {};
+    const int k0 = ks * 16 + kh;
+    uint4 av = {0u, 0u, 0u, 0u};
+    if constexpr (CIN == kCh) {
+      const int tap = k0 >> 5, c0 = k0 & 31;
+      const int iy = 2 * oy - 1 + tap / 3, ix = 2 * ox - 1 + tap % 3;
+      if (mv && iy >= 0 && iy < HIN && ix >= 0 && ix < HIN)
+        av = *reinterpret_cast<const uint4*>(in + (iy * HIN + ix) * CIN + c0);
+    } else {
+      uint32_t a4[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int k0 = ks * 16 + kh;
-      uint4 av = {0u, 0u, 0u, 0u};
-      if constexpr (CIN == kCh) {
-        const int tap = k0 >> 5, c0 = k0 & 31;
-        const int iy = 2 * oy - 1 + tap / 3, ix = 2 * ox - 1 + tap % 3;
-        if (mv && iy >= 0 && iy < HIN && ix >= 0 && ix < HIN)
-          av = *reinterpret_cast<const uint4*>(in + (iy * HIN + ix) * CIN + c0);
-      } else {
-        uint32_t a4[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int k = k0 + 2 * q;
-          if (k < K) {
-            const int tap = k / CIN;
-            const int iy = 2 * oy - 1 + tap / 3, ix = 2 * ox - 1 + tap % 3;
-            if (mv && iy >= 0 && iy < HIN && ix >= 0 && ix < HIN)
-              a4[q] = *reinterpret_cast<const uint32_t*>(in + (iy * HIN + ix) * CIN);
-          }
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + 2 * q;
+        if (k < K) {
+          const int tap = k / CIN;
+          const int iy = 2 * oy - 1 + tap / 3, ix = 2 * ox - 1 + tap % 3;
+          if (mv && iy >= 0 && iy < HIN && ix >= 0 && ix < HIN)
+            a4[q] = *reinterpret_cast<const uint32_t*>(in + (iy * HIN + ix) * CIN);
         }
-        av = make_uint4(a4[0], a4[1], a4[2], a4[3]);
       }
-      acc = mfma(av, bfr[ks], acc);
+      av = make_uint4(a4[0], a4[1], a4[2], a4[3]);
     }
+    return av;
+  };
+  auto store = [&](int tile, const f32x16& acc) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int p = tile * 32 + drow(i, lane);
       if (p < P) out[p * kCh + n] = f2bf(fmaxf(acc[i] + bn, 0.f));
+    }
+  };
+  // Tiles wave, wave+4, ... taken two at a time: two independent MFMA
+  // chains per wave.
+  for (int tile = wave; tile < MT; tile += 8) {
+    const int tile2 = tile + 4;
+    f32x16 acc = {}, acc2 = {};
+    if (tile2 < MT) {
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const uint4 a1 = gather(tile, ks), a2 = gather(tile2, ks);
+        acc = mfma(a1, bfr[ks], acc);
+        acc2 = mfma(a2, bfr[ks], acc2);
+      }
+      store(tile, acc);
+      store(tile2, acc2);
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) acc = mfma(gather(tile, ks), bfr[ks], acc);
+      store(tile, acc);
     }
   }
 }
@@ -203,9 +224,11 @@ __global__ __launch_bounds__(256) void k_forward(const uint16_t* x, int B, const
   if (dst) copy_act<6 * 6 * kCh>(a3, dst + kActOff[2], t);
   conv_layer<kCh, 6>(a3, a4, prm + kOffW[3], prm + kOffB[3], t);
   __syncthreads();
-  for (int i = t; i < kFeat; i += 256) feats[(int64_t)b * kFeat + i] = a4[i];
-  if (dst)
-    for (int i = t; i < kFeat; i += 256) dst[kActOff[3] + i] = a4[i];
+  for (int i = t; i < kFeat; i += 256) {
+    const uint16_t v = a4[i];
+    feats[(int64_t)b * kFeat + i] = v;
+    if (dst) dst[kActOff[3] + i] = v;
+  }
 }
 
 // ------------------------------------------------------------------ GEMM
@@ -268,18 +291,28 @@ __global__ __launch_bounds__(256) void k_gemm_nt_t(const uint16_t* A, int lda, c
   for (int i = 0; i < WM; ++i)
 #pragma unroll
     for (int j = 0; j < WN; ++j) acc[i][j] = f32x16{};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    uint4 av[WM], bv[WN];
+  // operands of step k0 + 16 are loaded while step k0 multiplies
+  uint4 av[WM], bv[WN];
+  auto load = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < WM; ++i)
-      av[i] = ma[i] ? *reinterpret_cast<const uint4*>(pa[i] + k0) : make_uint4(0u, 0u, 0u, 0u);
+      av[i] = ma[i] && k0 < K ? *reinterpret_cast<const uint4*>(pa[i] + k0) : make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
     for (int j = 0; j < WN; ++j)
-      bv[j] = nb[j] ? *reinterpret_cast<const uint4*>(pb[j] + k0) : make_uint4(0u, 0u, 0u, 0u);
+      bv[j] = nb[j] && k0 < K ? *reinterpret_cast<const uint4*>(pb[j] + k0) : make_uint4(0u, 0u, 0u, 0u);
+  };
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    uint4 ca[WM], cb[WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i) ca[i] = av[i];
+#pragma unroll
+    for (int j = 0; j < WN; ++j) cb[j] = bv[j];
+    load(k0 + 16);
 #pragma unroll
     for (int i = 0; i < WM; ++i)
 #pragma unroll
-      for (int j = 0; j < WN; ++j) acc[i][j] = mfma(av[i], bv[j], acc[i][j]);
+      for (int j = 0; j < WN; ++j) acc[i][j] = mfma(ca[i], cb[j], acc[i][j]);
   }
 #pragma unroll
   for (int j = 0; j < WN; ++j) {
@@ -456,15 +489,6 @@ __device__ __forceinline__ uint32_t order_key(float v) {
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xb1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4e, 0xf, 0xf, false);   // quad_perm [2,3,0,1]
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xf, 0xf, false);  // row_half_mirror
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xf, 0xf, false);  // row_mirror
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
-  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
-}
 
 // Sum over the 256-thread workgroup (four waves), same value in every lane.
 // `slots` holds 2 x 4 words; `par` alternates so one barrier per call suffices.
@@ -530,14 +554,27 @@ __global__ __launch_bounds__(256) void k_topk(const float* logits, int B, int K,
   }
   int par = 0;
   const bool any_nan = block_sum(nan, slots, par) != 0;
-  // T = the largest key value with #(key >= T) >= K: prefix bits first
+  // T = the largest key value with #(key >= T) >= K: prefix bits first.
+  // Counts are taken with ballots and scalar popcounts (wave totals), then
+  // summed over the four waves.
+  auto count_ge = [&](uint32_t c) {
+    uint32_t n = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) n += (uint32_t)__builtin_popcountll(__ballot(key[j] >= c));
+    return n;
+  };
+  auto block_total = [&](uint32_t wave_n) {
+    const int wave = threadIdx.x >> 6;
+    slots[par * 4 + wave] = wave_n;  // uniform store
+    __syncthreads();
+    const uint32_t r = slots[par * 4] + slots[par * 4 + 1] + slots[par * 4 + 2] + slots[par * 4 + 3];
+    par ^= 1;
+    return r;
+  };
   uint32_t T = 0;
   for (int bit = 31; bit >= 32 - kPrefixBits; --bit) {
     const uint32_t c = T | (1u << bit);
-    uint32_t n = 0;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) n += key[j] >= c;
-    if (block_sum(n, slots, par) >= (uint32_t)K) T = c;
+    if (block_total(count_ge(c)) >= (uint32_t)K) T = c;
   }
   {
     // keys with T's prefix; those above the prefix are all selected
@@ -558,8 +595,11 @@ __global__ __launch_bounds__(256) void k_topk(const float* logits, int B, int K,
     for (int bit = 31 - kPrefixBits; bit >= 0; --bit) {
       const uint32_t c = T | (1u << bit);
       uint32_t n = 0;
-      for (uint32_t i = t; i < m; i += 256) n += bk[i] >= c;
-      if (block_sum(n, slots, par) >= need) T = c;
+      for (uint32_t i0 = 0; i0 < m; i0 += 256) {
+        const uint32_t i = i0 + t;
+        n += (uint32_t)__builtin_popcountll(__ballot(i < m && bk[i < m ? i : 0] >= c));
+      }
+      if (block_total(n) >= need) T = c;
     }
   }
   uint32_t gt = 0, eq = 0;

@@ -68,12 +68,14 @@ const Variant* variant_for(int F);
 // (kWarmFused or kWarmPrep), or null.
 const Variant* warm_variant_for(int F, int kc, int mode);
 
-// Restricted kernel of the split warm start (F = 64, one 64-lane workgroup
-// per block of the class, grid = class size): null if kc is not compiled.
+// Restricted kernel of the split warm start (F = 64, one workgroup per
+// block of the class, grid = class size): null if kc is not compiled.
 const void* restricted_kernel(int kc);
 
-// Dynamic LDS bytes of the restricted kernel for ir restricted iterations.
+// Dynamic LDS bytes of the restricted kernel for ir restricted iterations,
+// and its threads per workgroup.
 size_t restricted_lds_bytes(int ir);
+int restricted_threads();
 
 // All compiled plain variants for F; returns their number, fills up to cap.
 int variants_for(int F, const Variant** out, int cap);

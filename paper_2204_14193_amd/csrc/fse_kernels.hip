@@ -102,9 +102,9 @@ __device__ __forceinline__ float readlane_f(float x, int lane) {
 
 // ------------------------------------------------------------------ FFT
 // Forward DFT (exp(-j...)) of every row, then every column, of the F x F
-// buffer Z, as Stockham passes of radix 4 (plus one radix-2 pass when log2 F
-// is odd). Each pass loads its butterflies into registers, waits, and writes
-// the results back into the same buffer, so one F x F buffer suffices.
+// buffer Z, as Stockham passes of radix 8, 4 or 2. Each pass loads its
+// butterflies into registers, waits, and writes the results back into the
+// same buffer, so one F x F buffer suffices.
 
 template <int R>
 __device__ __forceinline__ void dft_small(float2 (&a)[R]) {
@@ -112,6 +112,31 @@ __device__ __forceinline__ void dft_small(float2 (&a)[R]) {
     const float2 t = a[0];
     a[0] = cadd(t, a[1]);
     a[1] = csub(t, a[1]);
+  } else if constexpr (R == 8) {
+    // two 4-point DFTs of the even and odd samples, then
+    // X[k] = E[k] + w^k O[k], X[k+4] = E[k] - w^k O[k], w = exp(-j 2 pi / 8)
+    constexpr float h = 0.70710678118654752f;
+    const float2 t0 = cadd(a[0], a[4]), t1 = csub(a[0], a[4]);
+    const float2 t2 = cadd(a[2], a[6]), t3 = csub(a[2], a[6]);
+    const float2 t4 = cadd(a[1], a[5]), t5 = csub(a[1], a[5]);
+    const float2 t6 = cadd(a[3], a[7]), t7 = csub(a[3], a[7]);
+    const float2 e0 = cadd(t0, t2), e2 = csub(t0, t2);
+    const float2 e1 = make_float2(t1.x + t3.y, t1.y - t3.x);  // t1 - j*t3
+    const float2 e3 = make_float2(t1.x - t3.y, t1.y + t3.x);  // t1 + j*t3
+    const float2 o0 = cadd(t4, t6), o2 = csub(t4, t6);
+    const float2 o1 = make_float2(t5.x + t7.y, t5.y - t7.x);
+    const float2 o3 = make_float2(t5.x - t7.y, t5.y + t7.x);
+    const float2 w1 = make_float2(h * (o1.x + o1.y), h * (o1.y - o1.x));    // (1 - j)/sqrt2 * o1
+    const float2 w2 = make_float2(o2.y, -o2.x);                            // -j * o2
+    const float2 w3 = make_float2(h * (o3.y - o3.x), -h * (o3.x + o3.y));  // (-1 - j)/sqrt2 * o3
+    a[0] = cadd(e0, o0);
+    a[4] = csub(e0, o0);
+    a[1] = cadd(e1, w1);
+    a[5] = csub(e1, w1);
+    a[2] = cadd(e2, w2);
+    a[6] = csub(e2, w2);
+    a[3] = cadd(e3, w3);
+    a[7] = csub(e3, w3);
   } else {
     const float2 t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
     const float2 t2 = cadd(a[1], a[3]), t3 = csub(a[1], a[3]);
@@ -161,17 +186,22 @@ __device__ __forceinline__ void fft_pass(float2* Z, const float2* tw, int t) {
   __syncthreads();
 }
 
+// F = 64 and 128 use radix-8 passes (fewer LDS round trips and barriers);
+// F = 32 keeps radix 4 so that every compiled workgroup size (down to one
+// butterfly per thread) runs the same passes and gives the same bits.
 template <int F, int NT, bool COLS>
 __device__ __forceinline__ void fft_lines(float2* Z, const float2* tw, int t) {
-  fft_pass<F, NT, 4, 1, COLS>(Z, tw, t);
-  fft_pass<F, NT, 4, 4, COLS>(Z, tw, t);
   if constexpr (F == 32) {
+    fft_pass<F, NT, 4, 1, COLS>(Z, tw, t);
+    fft_pass<F, NT, 4, 4, COLS>(Z, tw, t);
     fft_pass<F, NT, 2, 16, COLS>(Z, tw, t);
   } else if constexpr (F == 64) {
-    fft_pass<F, NT, 4, 16, COLS>(Z, tw, t);
+    fft_pass<F, NT, 8, 1, COLS>(Z, tw, t);
+    fft_pass<F, NT, 8, 8, COLS>(Z, tw, t);
   } else {
     static_assert(F == 128, "unsupported transform size");
-    fft_pass<F, NT, 4, 16, COLS>(Z, tw, t);
+    fft_pass<F, NT, 8, 1, COLS>(Z, tw, t);
+    fft_pass<F, NT, 8, 8, COLS>(Z, tw, t);
     fft_pass<F, NT, 2, 64, COLS>(Z, tw, t);
   }
 }
@@ -717,24 +747,28 @@ __global__ __launch_bounds__(NT) void fse_persistent(ClassArgs a) {
 
 // ------------------------------------------------------------ restricted
 // Second kernel of the split warm start (F = 64): the restricted iterations
-// of one block per 64-lane workgroup, with W rows 0..32 in LDS (17 KB, so
-// that many blocks share a compute unit and hide each other's latency) and
-// the KC candidates in VGPRs, KC/64 consecutive candidates per lane. Each
+// of one block per workgroup of NWB waves, with W rows 0..32 in LDS (17 KB,
+// so that many blocks share a compute unit and hide each other's latency)
+// and the KC candidates in VGPRs: wave w holds candidates
+// [w*KC/NWB, (w+1)*KC/NWB), KC/(64*NWB) consecutive ones per lane. Each
 // iteration: argmax of |R_w|^2 over the candidates (eq. (12), lowest bin on
 // ties), c = gamma*R_w[u,v]/W[0,0] (eq. (13)), R_w[k,l] -= c*W[k-u,l-v] at
 // the candidates (eq. (18)); then the model is evaluated on B as in the
 // persistent kernel. The arithmetic of every step is that of the fused
 // warm-started form, so both give the same bits.
-template <int KC>
-__global__ __launch_bounds__(64) void fse_restricted(ClassArgs a) {
-  constexpr int F = 64, CPL = KC / 64;
-  static_assert(KC % 64 == 0 && CPL >= 1 && CPL <= 16, "candidate count must be 64..1024, a multiple of 64");
+template <int KC, int NWB>
+__global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
+  constexpr int F = 64, NT = 64 * NWB, CPL = KC / NT;
+  static_assert(NWB == 1 || NWB == 2, "one or two waves per block");
+  static_assert(KC % NT == 0 && CPL >= 1 && CPL <= 16, "candidate count must be a multiple of the thread count");
   extern __shared__ __align__(16) unsigned char smem[];
   float2* const Wh = reinterpret_cast<float2*>(smem);  // kHalfRows x F
   float2* const tw = Wh + kHalfRows * F;                // F twiddles
-  float2* const cl_c = tw + F;                          // ir coefficients
+  int4* const xch = reinterpret_cast<int4*>(tw + F);   // 2 x NWB cross-wave argmax slots
+  float2* const cl_c = reinterpret_cast<float2*>(xch + 4);  // ir coefficients
   int* const cl_idx = reinterpret_cast<int*>(cl_c + a.ir);
-  const int lane = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int bi = blockIdx.x;
   if (bi >= a.n) return;
   const int orig = __builtin_amdgcn_readfirstlane(a.orig[bi]);
@@ -743,18 +777,19 @@ __global__ __launch_bounds__(64) void fse_restricted(ClassArgs a) {
   {
     const float4* src = reinterpret_cast<const float4*>(a.stage_w + (int64_t)orig * (kHalfRows * F));
     float4* dst = reinterpret_cast<float4*>(Wh);
-    for (int e = lane; e < kHalfRows * F / 2; e += 64) dst[e] = src[e];
-    tw[lane] = a.twid[lane];
+    for (int e = t; e < kHalfRows * F / 2; e += NT) dst[e] = src[e];
+    if (t < F) tw[t] = a.twid[t];
   }
-  // Candidate c = lane*CPL + j. Its bin (k, l) is kept in two packed forms
-  // whose sum with a per-iteration constant gives (k-u) mod F, (l-v) mod F
-  // and their negatives without borrows between the 7-bit fields.
+  // Candidate c = wave*KC/NWB + lane*CPL + j. Its bin (k, l) is kept in two
+  // packed forms whose sum with a per-iteration constant gives (k-u) mod F,
+  // (l-v) mod F and their negatives without borrows between the 7-bit
+  // fields.
   float Rx[CPL], Ry[CPL];
   int xa[CPL], xb[CPL];
   unsigned mb[CPL];
 #pragma unroll
   for (int j = 0; j < CPL; ++j) {
-    const int c = lane * CPL + j;
+    const int c = wave * (KC / NWB) + lane * CPL + j;
     const int bin = a.cand[(int64_t)orig * KC + c];
     const int k = bin / F, l = bin % F;
     const float2 r = a.stage_r[(int64_t)orig * KC + c];
@@ -767,18 +802,19 @@ __global__ __launch_bounds__(64) void fse_restricted(ClassArgs a) {
   __syncthreads();
   const float W0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(Wh[0].x)));
   if (!(W0 > 0.f)) {
-    a.status[orig] = FSE_BLOCK_EMPTY_SUPPORT;
+    if (wave == 0) a.status[orig] = FSE_BLOCK_EMPTY_SUPPORT;
     return;
   }
   const float gW = a.gamma * (1.0f / W0);
 
   bool finite = true;
+  int parity = 0;
   for (int it = 0; it < a.ir; ++it) {
     unsigned lm = mb[0];
 #pragma unroll
     for (int j = 1; j < CPL; ++j) lm = max(lm, mb[j]);
-    const unsigned wm = wave_max_bits(lm);
-    // the lowest candidate holding the maximum: lowest lane, then lowest j
+    unsigned wm = wave_max_bits(lm);
+    // the wave's lowest candidate holding its maximum: lowest lane, then j
     float hre = 0.f, him = 0.f;
     int hx = 0;
     bool hit = false;
@@ -792,21 +828,41 @@ __global__ __launch_bounds__(64) void fse_restricted(ClassArgs a) {
     }
     const unsigned long long hits = __ballot(hit);
     const int wl = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(hits));
-    const float re = readlane_f(hre, wl), im = readlane_f(him, wl);
-    const int x = __builtin_amdgcn_readlane(hx, wl);
+    float re = readlane_f(hre, wl), im = readlane_f(him, wl);
+    int x = __builtin_amdgcn_readlane(hx, wl);
+    if constexpr (NWB == 2) {
+      // across the two waves: the larger value, wave 0 (the lower
+      // candidates) on a tie; every component made uniform before selecting
+      xch[parity * 2 + wave] = make_int4((int)wm, x, __float_as_int(re), __float_as_int(im));  // uniform
+      __syncthreads();
+      const int4 s0 = xch[parity * 2], s1 = xch[parity * 2 + 1];
+      const unsigned m0 = (unsigned)__builtin_amdgcn_readfirstlane(s0.x);
+      const unsigned m1 = (unsigned)__builtin_amdgcn_readfirstlane(s1.x);
+      const int x0 = __builtin_amdgcn_readfirstlane(s0.y), x1 = __builtin_amdgcn_readfirstlane(s1.y);
+      const int r0 = __builtin_amdgcn_readfirstlane(s0.z), r1 = __builtin_amdgcn_readfirstlane(s1.z);
+      const int i0 = __builtin_amdgcn_readfirstlane(s0.w), i1 = __builtin_amdgcn_readfirstlane(s1.w);
+      const bool second = m1 > m0;
+      wm = second ? m1 : m0;
+      x = second ? x1 : x0;
+      re = __int_as_float(second ? r1 : r0);
+      im = __int_as_float(second ? i1 : i0);
+      parity ^= 1;
+    }
     const int u = x >> 7, v = x & 127;
     const float cre = gW * re, cim = gW * im;  // eq. (13)
     finite = finite && isfinite(cre) && isfinite(cim);
-    cl_idx[it] = u * F + v;  // uniform stores
-    cl_c[it] = make_float2(cre, cim);
-    if (a.trace) {
-      fse_trace_t rec;
-      rec.u = (uint16_t)u;
-      rec.v = (uint16_t)v;
-      rec.c_re = cre;
-      rec.c_im = cim;
-      rec.r2 = __uint_as_float(wm);
-      a.trace[(int64_t)orig * a.trace_stride + it] = rec;
+    if (wave == 0) {
+      cl_idx[it] = u * F + v;  // uniform stores
+      cl_c[it] = make_float2(cre, cim);
+      if (a.trace) {
+        fse_trace_t rec;
+        rec.u = (uint16_t)u;
+        rec.v = (uint16_t)v;
+        rec.c_re = cre;
+        rec.c_im = cim;
+        rec.r2 = __uint_as_float(wm);
+        a.trace[(int64_t)orig * a.trace_stride + it] = rec;
+      }
     }
     // eq. (18) at the candidates: W[k-u, l-v] from row (k-u) mod F when
     // that is <= F/2, else the conjugate of W[u-k, v-l]
@@ -830,16 +886,16 @@ __global__ __launch_bounds__(64) void fse_restricted(ClassArgs a) {
     }
   }
   if (!finite) {
-    a.status[orig] = FSE_BLOCK_NONFINITE;
+    if (wave == 0) a.status[orig] = FSE_BLOCK_NONFINITE;
     return;
   }
   __syncthreads();
   // model on B, as in the persistent kernel
   const UBlock bd = uniform_block(a.blocks + bi);
   const int64_t fofs = (int64_t)bd.frame * a.H;
-  synthesize<F, 64, 4>(cl_idx, cl_c, a.ir, tw, bd.bh, bd.bw, bd.border,
-                       a.out + (fofs + bd.y0) * a.out_pitch + bd.x0, a.out_pitch, lane);
-  a.status[orig] = FSE_BLOCK_OK;
+  synthesize<F, NT, 4 / NWB>(cl_idx, cl_c, a.ir, tw, bd.bh, bd.bw, bd.border,
+                             a.out + (fofs + bd.y0) * a.out_pitch + bd.x0, a.out_pitch, t);
+  if (wave == 0) a.status[orig] = FSE_BLOCK_OK;
 }
 
 template <int F, int NT, int KC = 0, int MODE = kPlain>
@@ -884,24 +940,32 @@ int variants_for(int F, const Variant** out, int cap) {
   return n;
 }
 
+// Waves per block of the restricted kernel.
+#ifndef FSE_RESTRICTED_WAVES
+#define FSE_RESTRICTED_WAVES 2
+#endif
+constexpr int kRestrictedWaves = FSE_RESTRICTED_WAVES;
+
 const void* restricted_kernel(int kc) {
   switch (kc) {
-    case 128: return reinterpret_cast<const void*>(&fse_restricted<128>);
-    case 256: return reinterpret_cast<const void*>(&fse_restricted<256>);
-    case 512: return reinterpret_cast<const void*>(&fse_restricted<512>);
+    case 128: return reinterpret_cast<const void*>(&fse_restricted<128, kRestrictedWaves>);
+    case 256: return reinterpret_cast<const void*>(&fse_restricted<256, kRestrictedWaves>);
+    case 512: return reinterpret_cast<const void*>(&fse_restricted<512, kRestrictedWaves>);
     default: return nullptr;
   }
 }
 
+int restricted_threads() { return 64 * kRestrictedWaves; }
+
 size_t restricted_lds_bytes(int ir) {
-  return (size_t)kHalfRows * 64 * 8 + 64 * 8 + (size_t)ir * 12;
+  return (size_t)kHalfRows * 64 * 8 + 64 * 8 + 4 * 16 + (size_t)ir * 12;
 }
 
 hipError_t launch_restricted(int kc, const ClassArgs& a, size_t lds, hipStream_t s) {
   const void* fn = restricted_kernel(kc);
   if (!fn || a.n <= 0) return hipErrorInvalidValue;
   void* args[] = {const_cast<ClassArgs*>(&a)};
-  return hipLaunchKernel(fn, dim3(a.n), dim3(64), args, lds, s);
+  return hipLaunchKernel(fn, dim3(a.n), dim3(restricted_threads()), args, lds, s);
 }
 
 size_t lds_bytes(const Variant& v, int iters_cap) {
