@@ -256,12 +256,19 @@ fse_status_t fse_cnn_topk(const float* d_logits, int32_t B, int32_t K, int16_t* 
 
 /* Warm-started cFSE for a batch whose blocks all use F = 64. For block i
  * with d_flags[i] == 0: restricted_iters iterations over the kc candidates
- * d_cand[i][0..kc) (ascending bins; kc in {128, 256, 512}), their distinct
- * coefficients applied to the whole spectrum, then the block's `iters` full
- * iterations. A block with d_flags[i] != 0 runs fallback_iters plain
- * iterations instead. Output, status and threading as
- * fse_extrapolate_batch; d_trace (optional) rows have
- * fse_warm_trace_stride(...) entries: the restricted selections first. */
+ * d_cand[i][0..kc) (ascending bins), their distinct coefficients applied
+ * to the whole spectrum, then the block's `iters` full iterations. A block
+ * with d_flags[i] != 0 runs fallback_iters plain iterations instead
+ * (bit-identical to fse_extrapolate_batch with that count). When every
+ * block's `iters` is 0 the work runs as two kernels (transform and staging
+ * of W rows 0..32 and of R_w at the candidates, then one workgroup per
+ * block for the restricted iterations) with kc in {128, 256, 384, 512};
+ * otherwise as one kernel with kc in {128, 256, 512}. Both forms give the
+ * same results. Output, status and threading as fse_extrapolate_batch;
+ * d_trace (optional) rows have fse_warm_trace_stride(...) entries: the
+ * restricted selections first. The staging buffer of the two-kernel form
+ * (n_blocks x (16896 + 8*kc) bytes) is allocated on the first call and kept
+ * by the batch. */
 fse_status_t fse_warm_extrapolate_batch(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail,
                                         int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
                                         fse_trace_t* d_trace, const int16_t* d_cand, const int32_t* d_flags,

@@ -291,29 +291,36 @@ __global__ __launch_bounds__(256) void k_gemm_nt_t(const uint16_t* A, int lda, c
   for (int i = 0; i < WM; ++i)
 #pragma unroll
     for (int j = 0; j < WN; ++j) acc[i][j] = f32x16{};
-  // operands of step k0 + 16 are loaded while step k0 multiplies
-  uint4 av[WM], bv[WN];
-  auto load = [&](int k0) {
+  // Two register stages: the operands of the next depth step are loaded
+  // before the current step multiplies (scheduling barriers keep that
+  // order). The loads are unconditional (rows and columns past the edge
+  // read row 0 and are never stored; a step past the end re-reads the last
+  // one), so no branch forces a wait for all outstanding loads.
+  uint4 a0[WM], b0[WN], a1[WM], b1[WN];
+  auto load = [&](uint4 (&av)[WM], uint4 (&bv)[WN], int k0) {
+    const int kk = min(k0, K - 16);
 #pragma unroll
-    for (int i = 0; i < WM; ++i)
-      av[i] = ma[i] && k0 < K ? *reinterpret_cast<const uint4*>(pa[i] + k0) : make_uint4(0u, 0u, 0u, 0u);
+    for (int i = 0; i < WM; ++i) av[i] = *reinterpret_cast<const uint4*>(pa[i] + kk);
 #pragma unroll
-    for (int j = 0; j < WN; ++j)
-      bv[j] = nb[j] && k0 < K ? *reinterpret_cast<const uint4*>(pb[j] + k0) : make_uint4(0u, 0u, 0u, 0u);
+    for (int j = 0; j < WN; ++j) bv[j] = *reinterpret_cast<const uint4*>(pb[j] + kk);
   };
-  load(0);
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    uint4 ca[WM], cb[WN];
-#pragma unroll
-    for (int i = 0; i < WM; ++i) ca[i] = av[i];
-#pragma unroll
-    for (int j = 0; j < WN; ++j) cb[j] = bv[j];
-    load(k0 + 16);
+  auto mma = [&](const uint4 (&av)[WM], const uint4 (&bv)[WN]) {
 #pragma unroll
     for (int i = 0; i < WM; ++i)
 #pragma unroll
-      for (int j = 0; j < WN; ++j) acc[i][j] = mfma(ca[i], cb[j], acc[i][j]);
+      for (int j = 0; j < WN; ++j) acc[i][j] = mfma(av[i], bv[j], acc[i][j]);
+  };
+  load(a0, b0, 0);
+  int k0 = 0;
+  for (; k0 + 16 < K; k0 += 32) {
+    load(a1, b1, k0 + 16);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(a0, b0);
+    load(a0, b0, k0 + 32);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(a1, b1);
   }
+  if (k0 < K) mma(a0, b0);  // an odd number of steps leaves the last in stage 0
 #pragma unroll
   for (int j = 0; j < WN; ++j) {
     const int col = tn + 32 * j + (lane & 31);

@@ -780,12 +780,14 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
     for (int e = t; e < kHalfRows * F / 2; e += NT) dst[e] = src[e];
     if (t < F) tw[t] = a.twid[t];
   }
-  // Candidate c = wave*KC/NWB + lane*CPL + j. Its bin (k, l) is kept in two
-  // packed forms whose sum with a per-iteration constant gives (k-u) mod F,
-  // (l-v) mod F and their negatives without borrows between the 7-bit
-  // fields.
+  // Candidate c = wave*KC/NWB + lane*CPL + j. Its bin (k, l) is kept as
+  // xa = k*4096 + l*8: adding (64-u)*4096 + (64-v)*8 gives (k-u+64) above
+  // bit 12 and (l-v+64)*8 in bits 3..9 (no borrow between the fields), so
+  // the byte offset of W[(k-u) mod 64, (l-v) mod 64] (row pitch 512 B) is
+  // ((y >> 3) & 0x7e00) | (y & 0x1f8); subtracting xa from
+  // (64+u)*4096 + (64+v)*8 gives the mirrored bin the same way.
   float Rx[CPL], Ry[CPL];
-  int xa[CPL], xb[CPL];
+  int xa[CPL];
   unsigned mb[CPL];
 #pragma unroll
   for (int j = 0; j < CPL; ++j) {
@@ -795,10 +797,10 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
     const float2 r = a.stage_r[(int64_t)orig * KC + c];
     Rx[j] = r.x;
     Ry[j] = r.y;
-    xa[j] = k * 128 + l;
-    xb[j] = (F - k) * 128 + (F - l);
+    xa[j] = k * 4096 + l * 8;
     mb[j] = __float_as_uint(fmaf(r.y, r.y, r.x * r.x));
   }
+  const char* const Wb = reinterpret_cast<const char*>(Wh);
   __syncthreads();
   const float W0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(Wh[0].x)));
   if (!(W0 > 0.f)) {
@@ -807,7 +809,6 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
   }
   const float gW = a.gamma * (1.0f / W0);
 
-  bool finite = true;
   int parity = 0;
   for (int it = 0; it < a.ir; ++it) {
     unsigned lm = mb[0];
@@ -848,9 +849,8 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
       im = __int_as_float(second ? i1 : i0);
       parity ^= 1;
     }
-    const int u = x >> 7, v = x & 127;
+    const int u = x >> 12, v = (x >> 3) & 511;
     const float cre = gW * re, cim = gW * im;  // eq. (13)
-    finite = finite && isfinite(cre) && isfinite(cim);
     if (wave == 0) {
       cl_idx[it] = u * F + v;  // uniform stores
       cl_c[it] = make_float2(cre, cim);
@@ -866,14 +866,14 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
     }
     // eq. (18) at the candidates: W[k-u, l-v] from row (k-u) mod F when
     // that is <= F/2, else the conjugate of W[u-k, v-l]
-    const int ca = (F - u) * 128 + (F - v);
-    const int cb = u * 128 + v;
+    const int ca = (F - u) * 4096 + (F - v) * 8;
+    const int cb = (F + u) * 4096 + (F + v) * 8;
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
-      const int ya = xa[j] + ca, yb = xb[j] + cb;
-      const bool flip = ((ya >> 7) & (F - 1)) > F / 2;
+      const int ya = xa[j] + ca, yb = cb - xa[j];
+      const bool flip = (ya & 0x3f000) > (F / 2) * 4096;
       const int y = flip ? yb : ya;
-      float2 w = Wh[((y >> 7) & (F - 1)) * F + (y & (F - 1))];
+      float2 w = *reinterpret_cast<const float2*>(Wb + (((y >> 3) & 0x7e00) | (y & 0x1f8)));
       w.y = flip ? -w.y : w.y;
       float rx = Rx[j], ry = Ry[j];
       rx = fmaf(-cre, w.x, rx);
@@ -885,11 +885,17 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
       mb[j] = __float_as_uint(fmaf(ry, ry, rx * rx));
     }
   }
-  if (!finite) {
+  __syncthreads();
+  // every coefficient must be finite
+  bool finite = true;
+  for (int it = t; it < a.ir; it += NT) {
+    const float2 c = cl_c[it];
+    finite = finite && isfinite(c.x) && isfinite(c.y);
+  }
+  if (__syncthreads_or(!finite)) {
     if (wave == 0) a.status[orig] = FSE_BLOCK_NONFINITE;
     return;
   }
-  __syncthreads();
   // model on B, as in the persistent kernel
   const UBlock bd = uniform_block(a.blocks + bi);
   const int64_t fofs = (int64_t)bd.frame * a.H;
@@ -913,7 +919,7 @@ const Variant kVariants[] = {
     make_variant<64, 256, 256, kWarmFused>(), make_variant<64, 256, 128, kWarmFused>(),
     make_variant<64, 256, 512, kWarmFused>(),
     make_variant<64, 256, 256, kWarmPrep>(), make_variant<64, 256, 128, kWarmPrep>(),
-    make_variant<64, 256, 512, kWarmPrep>(),
+    make_variant<64, 256, 512, kWarmPrep>(), make_variant<64, 256, 384, kWarmPrep>(),
 };
 
 }  // namespace
@@ -950,6 +956,7 @@ const void* restricted_kernel(int kc) {
   switch (kc) {
     case 128: return reinterpret_cast<const void*>(&fse_restricted<128, kRestrictedWaves>);
     case 256: return reinterpret_cast<const void*>(&fse_restricted<256, kRestrictedWaves>);
+    case 384: return reinterpret_cast<const void*>(&fse_restricted<384, kRestrictedWaves>);
     case 512: return reinterpret_cast<const void*>(&fse_restricted<512, kRestrictedWaves>);
     default: return nullptr;
   }

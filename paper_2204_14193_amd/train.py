@@ -7,7 +7,7 @@ this library's GPU kernels) selects. The network learns to score bins so
 that its top-K set covers them (binary cross-entropy, positives weighted).
 Forward, backward and Adam run in libfse; torch only holds the buffers.
 
-    python -m paper_2204_14193_amd.train --blocks 200000 --epochs 20
+    python -m paper_2204_14193_amd.train --blocks 800000 --epochs 32
 """
 import argparse
 import json
@@ -132,7 +132,8 @@ def psnr_lost(reference, reconstruction, avail):
     return float(10.0 * np.log10(255.0 ** 2 / np.mean(err ** 2)))
 
 
-def evaluate(net, seeds=(99,), configs=((256, 100), (512, 100), (512, 125)), plain_iters=100, reps=5, log=print):
+def evaluate(net, seeds=tuple(range(99, 107)), configs=((384, 110), (512, 100), (512, 110)), plain_iters=100, reps=5,
+             log=print):
     """PSNR over the lost pixels and blocks/s of plain FSE and of the warm
     start (restricted iterations only; (K, restricted iterations) per
     config) on held-out frames."""
@@ -189,14 +190,16 @@ def evaluate(net, seeds=(99,), configs=((256, 100), (512, 100), (512, 125)), pla
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--blocks", type=int, default=200000)
-    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--blocks", type=int, default=800000)
+    ap.add_argument("--epochs", type=int, default=32)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--pos-weight", type=float, default=4.0)
     ap.add_argument("--first-seed", type=int, default=1000)
     ap.add_argument("--out", default=None)
     ap.add_argument("--report", default=None)
+    ap.add_argument("--eval", default="384:110,512:100,512:110",
+                    help="warm-start settings to evaluate, K:restricted_iters,...")
     args = ap.parse_args()
     import torch
     dev = torch.device("cuda:0")
@@ -207,7 +210,8 @@ def main():
         net.save(args.out)
         log(f"saved {args.out}")
     del x, bits
-    res = evaluate(net, log=log)
+    configs = tuple(tuple(int(v) for v in c.split(":")) for c in args.eval.split(","))
+    res = evaluate(net, configs=configs, log=log)
     res.update(blocks=args.blocks, epochs=args.epochs, batch=args.batch, lr=args.lr, pos_weight=args.pos_weight,
                loss_history=hist)
     if args.report:

@@ -277,7 +277,7 @@ def test_split_warm_equals_single_kernel_bitwise():
 
 
 def test_warm_start_quality_bar_and_timing_hook():
-    """The packaged network at the benchmark's setting (top-512 candidates,
+    """The packaged network at the benchmark's setting (top-384 candidates,
     110 restricted iterations) loses at most 0.1 dB of PSNR over the lost
     pixels against plain FSE with 100 iterations, on the eight held-out
     benchmark frames; the timing hook records both kernels of the split
@@ -304,7 +304,7 @@ def test_warm_start_quality_bar_and_timing_hook():
     bw = fse.Batch(plan, wb, *wl.frames.shape)
     net = warm.Net(n)
     net.load()
-    ws = warm.WarmStart(net, bw, 512, 110, 100)
+    ws = warm.WarmStart(net, bw, 384, 110, 100)
     out_w = img.to(torch.float32)
     st_w = torch.zeros(n, dtype=torch.int32, device=dev)
     bw.set_timing(2)
