@@ -228,6 +228,16 @@ fse_status_t fse_cnn_get_params(fse_cnn_t net, float* h_params, float* h_grads);
 fse_status_t fse_cnn_patches(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail, int64_t pitch,
                              uint16_t* d_x, void* stream);
 
+/* Forward pass for every block of a batch whose areas are all 48x48, the
+ * network inputs built on the fly from the frames (the inputs
+ * fse_cnn_patches would write): d_logits [n_blocks][4096] FP32, row i for
+ * block i of the caller's list, the same values as fse_cnn_patches followed
+ * by fse_cnn_forward. n_blocks must not exceed the network's max_batch; no
+ * activations are kept. Returns FSE_ERR_UNSUPPORTED for other area sizes.
+ * Asynchronous. */
+fse_status_t fse_cnn_forward_blocks(fse_cnn_t net, fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail,
+                                    int64_t pitch, float* d_logits, void* stream);
+
 /* Forward pass: d_logits [B][4096] FP32. keep_activations != 0 stores what
  * fse_cnn_backward needs. Asynchronous. */
 fse_status_t fse_cnn_forward(fse_cnn_t net, const uint16_t* d_x, int32_t B, float* d_logits,

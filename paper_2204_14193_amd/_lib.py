@@ -48,6 +48,7 @@ SIGNATURES = {
     "fse_cnn_get_params": (I32, [P, P, P]),
     "fse_cnn_patches": (I32, [P, P, P, I64, P, P]),
     "fse_cnn_forward": (I32, [P, P, I32, P, I32, P]),
+    "fse_cnn_forward_blocks": (I32, [P, P, P, P, I64, P, P]),
     "fse_cnn_backward": (I32, [P, P, P, P, I32, C.c_float, P, P]),
     "fse_cnn_adam": (I32, [P, C.c_float, C.c_float, C.c_float, C.c_float, P]),
     "fse_cnn_topk": (I32, [P, I32, I32, P, P, P]),

@@ -180,6 +180,27 @@ extern "C" fse_status_t fse_cnn_forward(fse_cnn_t net, const uint16_t* d_x, int3
   return FSE_OK;
 }
 
+namespace fse {
+namespace cnn {
+// Forward pass from the frames for the blocks of a batch (see
+// fse_cnn_forward_blocks); argument checks on the batch are the caller's.
+fse_status_t net_forward_blocks(fse_cnn_t net, const uint8_t* img, const uint8_t* avail, int64_t pitch, int32_t H,
+                                int32_t W, const void* blocks, const int32_t* orig, int32_t n, float* d_logits,
+                                hipStream_t s) {
+  if (!net || !d_logits) return cfail(FSE_ERR_INVALID_ARG, "null argument");
+  if (n > net->max_batch) return cfail(FSE_ERR_INVALID_ARG, "more blocks than the network's max_batch");
+  if (!check_device(net)) return cfail(FSE_ERR_INVALID_ARG, "network was created on another device");
+  if (n == 0) return FSE_OK;
+  if (forward_blocks(img, avail, pitch, H, W, blocks, orig, n, net->work, net->feats, s) != hipSuccess ||
+      gemm_nt(net->feats, kFeat, net->work + kOffHeadW, kFeat, d_logits, kBins, net->work + kOffHeadB, n, kBins,
+              kFeat, s) != hipSuccess)
+    return cfail(FSE_ERR_HIP, "kernel launch failed");
+  net->kept = false;
+  return FSE_OK;
+}
+}  // namespace cnn
+}  // namespace fse
+
 extern "C" fse_status_t fse_cnn_backward(fse_cnn_t net, const uint16_t* d_x, const float* d_logits,
                                          const uint32_t* d_target_bits, int32_t B, float pos_weight, float* d_loss,
                                          void* stream) {

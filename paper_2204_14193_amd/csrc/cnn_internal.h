@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fse.h"
+
 namespace fse {
 namespace cnn {
 
@@ -38,6 +40,16 @@ hipError_t patches(const uint8_t* img, const uint8_t* avail, int64_t pitch, int3
                    hipStream_t s);
 hipError_t forward(const uint16_t* x, int32_t B, const uint16_t* prm, uint16_t* feats, uint16_t* acts,
                    hipStream_t s);
+// Forward pass from the frames for the n blocks of a batch, FP32 logits to
+// rows orig[b] (implemented with the network's state in cnn_api.cpp).
+fse_status_t net_forward_blocks(fse_cnn_t net, const uint8_t* img, const uint8_t* avail, int64_t pitch, int32_t H,
+                                int32_t W, const void* blocks, const int32_t* orig, int32_t n, float* d_logits,
+                                hipStream_t s);
+// Network inputs built from the frames for the n blocks of a batch (class
+// order, features to row orig[b]) and the convolution stack, no activations.
+hipError_t forward_blocks(const uint8_t* img, const uint8_t* avail, int64_t pitch, int32_t H, int32_t W,
+                          const void* blocks, const int32_t* orig, int32_t n, const uint16_t* prm, uint16_t* feats,
+                          hipStream_t s);
 // C[M x N] (FP32, ldc) = A[M x K] * B[N x K]^T (+ bias[N]), A and B BF16 with
 // K contiguous; K % 16 == 0, lda and ldb multiples of 8.
 hipError_t gemm_nt(const uint16_t* A, int lda, const uint16_t* B, int ldb, float* C, int ldc,

@@ -47,14 +47,11 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
 // ------------------------------------------------------------------ patches
 // Network input of one 48x48 area: channel 0 = (s - mean_A(s)) / 64 on the
 // support area A, channel 1 = indicator of A; both 0 elsewhere.
-__global__ __launch_bounds__(256) void k_patches(const uint8_t* img, const uint8_t* avail, int64_t pitch, int H,
-                                                 int W, const fse_block_t* blocks, const int32_t* orig, int n,
-                                                 uint16_t* x) {
-  __shared__ uint32_t red[2][4];
-  const int b = blockIdx.x;
-  if (b >= n) return;
-  const int t = threadIdx.x;
-  const fse_block_t bd = blocks[b];
+// Network input of block `b` (48x48 area) into `out` (2304 words: the two
+// BF16 channels of each pixel), by the 256 threads of a workgroup; `red` is
+// 8 words of LDS. Channel 0 = (s - mean over A)/64 on A, channel 1 = 1 on A.
+__device__ __forceinline__ void build_input(const uint8_t* img, const uint8_t* avail, int64_t pitch, int H, int W,
+                                            const fse_block_t& bd, uint32_t* out, uint32_t (*red)[4], int t) {
   const int bo = bd.border;
   const int ya = bd.y0 - bo, xa = bd.x0 - bo;
   const uint8_t* im = img + (int64_t)bd.frame * H * pitch;
@@ -87,13 +84,21 @@ __global__ __launch_bounds__(256) void k_patches(const uint8_t* img, const uint8
   const uint32_t S = red[0][0] + red[0][1] + red[0][2] + red[0][3];
   const uint32_t N = red[1][0] + red[1][1] + red[1][2] + red[1][3];
   const float mu = N > 0 ? (float)S / (float)N : 0.f;
-  uint32_t* out = reinterpret_cast<uint32_t*>(x + (int64_t)orig[b] * kPatchElems);
 #pragma unroll
   for (int r = 0; r < 9; ++r) {
     const int e = t + 256 * r;
-    const uint32_t v = ia[r] ? ((uint32_t)f2bf((sv[r] - mu) * (1.0f / 64.0f)) | (0x3f80u << 16)) : 0u;
-    out[e] = v;
+    out[e] = ia[r] ? ((uint32_t)f2bf((sv[r] - mu) * (1.0f / 64.0f)) | (0x3f80u << 16)) : 0u;
   }
+}
+
+__global__ __launch_bounds__(256) void k_patches(const uint8_t* img, const uint8_t* avail, int64_t pitch, int H,
+                                                 int W, const fse_block_t* blocks, const int32_t* orig, int n,
+                                                 uint16_t* x) {
+  __shared__ uint32_t red[2][4];
+  const int b = blockIdx.x;
+  if (b >= n) return;
+  build_input(img, avail, pitch, H, W, blocks[b], reinterpret_cast<uint32_t*>(x + (int64_t)orig[b] * kPatchElems),
+              red, threadIdx.x);
 }
 
 // ------------------------------------------------------------------ forward
@@ -196,23 +201,16 @@ __device__ __forceinline__ void copy_act(const uint16_t* src, uint16_t* dst, int
 // The whole convolution stack for one sample per workgroup, activations in
 // LDS; writes the 288 features and, for training, every activation. LDS is
 // two regions: X holds the input, then layer 2's output; Y holds layer 1's
-// output, then layers 3 and 4.
-__global__ __launch_bounds__(256) void k_forward(const uint16_t* x, int B, const uint16_t* prm, uint16_t* feats,
-                                                 uint16_t* acts) {
-  static_assert(kPatchElems == 12 * 12 * kCh, "input and layer-2 output share a region");
-  __shared__ __align__(16) uint16_t X[kPatchElems];
-  __shared__ __align__(16) uint16_t Y[24 * 24 * kCh];
+// output, then layers 3 and 4. The input is in X on entry.
+static_assert(kPatchElems == 12 * 12 * kCh, "input and layer-2 output share a region");
+
+__device__ __forceinline__ void conv_stack(uint16_t* X, uint16_t* Y, const uint16_t* prm, uint16_t* feat_row,
+                                           uint16_t* dst, int t) {
   uint16_t* const a0 = X;
   uint16_t* const a1 = Y;
   uint16_t* const a2 = X;
   uint16_t* const a3 = Y;
   uint16_t* const a4 = Y + 6 * 6 * kCh;
-  const int b = blockIdx.x;
-  if (b >= B) return;
-  const int t = threadIdx.x;
-  uint16_t* const dst = acts ? acts + (int64_t)b * kActElems : nullptr;
-  copy_act<kPatchElems>(x + (int64_t)b * kPatchElems, a0, t);
-  __syncthreads();
   conv_layer<2, 48>(a0, a1, prm + kOffW[0], prm + kOffB[0], t);
   __syncthreads();
   if (dst) copy_act<24 * 24 * kCh>(a1, dst + kActOff[0], t);
@@ -226,9 +224,38 @@ __global__ __launch_bounds__(256) void k_forward(const uint16_t* x, int B, const
   __syncthreads();
   for (int i = t; i < kFeat; i += 256) {
     const uint16_t v = a4[i];
-    feats[(int64_t)b * kFeat + i] = v;
+    feat_row[i] = v;
     if (dst) dst[kActOff[3] + i] = v;
   }
+}
+
+__global__ __launch_bounds__(256) void k_forward(const uint16_t* x, int B, const uint16_t* prm, uint16_t* feats,
+                                                 uint16_t* acts) {
+  __shared__ __align__(16) uint16_t X[kPatchElems];
+  __shared__ __align__(16) uint16_t Y[24 * 24 * kCh];
+  const int b = blockIdx.x;
+  if (b >= B) return;
+  const int t = threadIdx.x;
+  copy_act<kPatchElems>(x + (int64_t)b * kPatchElems, X, t);
+  __syncthreads();
+  conv_stack(X, Y, prm, feats + (int64_t)b * kFeat, acts ? acts + (int64_t)b * kActElems : nullptr, t);
+}
+
+// The same with the input of block b built in LDS straight from the frames;
+// the features go to row orig[b].
+__global__ __launch_bounds__(256) void k_forward_blocks(const uint8_t* img, const uint8_t* avail, int64_t pitch,
+                                                        int H, int W, const fse_block_t* blocks,
+                                                        const int32_t* orig, int n, const uint16_t* prm,
+                                                        uint16_t* feats) {
+  __shared__ __align__(16) uint16_t X[kPatchElems];
+  __shared__ __align__(16) uint16_t Y[24 * 24 * kCh];
+  __shared__ uint32_t red[2][4];
+  const int b = blockIdx.x;
+  if (b >= n) return;
+  const int t = threadIdx.x;
+  build_input(img, avail, pitch, H, W, blocks[b], reinterpret_cast<uint32_t*>(X), red, t);
+  __syncthreads();
+  conv_stack(X, Y, prm, feats + (int64_t)orig[b] * kFeat, nullptr, t);
 }
 
 // ------------------------------------------------------------------ GEMM
@@ -497,18 +524,6 @@ __device__ __forceinline__ uint32_t order_key(float v) {
 }
 
 
-// Sum over the 256-thread workgroup (four waves), same value in every lane.
-// `slots` holds 2 x 4 words; `par` alternates so one barrier per call suffices.
-__device__ __forceinline__ uint32_t block_sum(uint32_t x, uint32_t* slots, int& par) {
-  const uint32_t w = wave_sum_u32(x);
-  const int wave = threadIdx.x >> 6;
-  slots[par * 4 + wave] = w;
-  __syncthreads();
-  const uint32_t r = slots[par * 4] + slots[par * 4 + 1] + slots[par * 4 + 2] + slots[par * 4 + 3];
-  par ^= 1;
-  return r;
-}
-
 // Inclusive prefix sum over the 64 lanes of a wave.
 __device__ __forceinline__ uint32_t wave_scan_u32(uint32_t x) {
   x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);  // row_shr:1
@@ -520,124 +535,106 @@ __device__ __forceinline__ uint32_t wave_scan_u32(uint32_t x) {
   return x;
 }
 
-// Exclusive prefix sum over the 256 threads (four waves) and the total.
-// `slots` holds 2 x 4 words used alternately (see block_sum).
-__device__ __forceinline__ uint32_t block_exscan(uint32_t x, uint32_t* slots, int& par, uint32_t& total) {
-  const uint32_t inc = wave_scan_u32(x);
-  const int wave = threadIdx.x >> 6;
-  slots[par * 4 + wave] = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
-  __syncthreads();
-  uint32_t before = 0;
-  const uint32_t s0 = slots[par * 4], s1 = slots[par * 4 + 1], s2 = slots[par * 4 + 2], s3 = slots[par * 4 + 3];
-  before = (wave > 0 ? s0 : 0u) + (wave > 1 ? s1 : 0u) + (wave > 2 ? s2 : 0u);
-  total = s0 + s1 + s2 + s3;
-  par ^= 1;
-  return before + inc - x;
-}
-
-// Exact selection of the K-th largest order key T: its top kPrefixBits bits
-// by bisection over all keys, then the remaining bits by bisection over the
-// keys sharing that prefix only (compacted into LDS).
+// Exact selection of the K-th largest order key T, one wave per sample
+// (no workgroup barriers): lane l holds the 64 keys of bins 64l..64l+63.
+// The top kPrefixBits bits of T come from bisection over all keys, the rest
+// from bisection over the keys sharing that prefix only, compacted into the
+// wave's LDS region (up to kBracketCap of them; beyond that the bisection
+// continues over all keys). Counts are per-lane sums reduced with DPP.
 constexpr int kPrefixBits = 14;
+constexpr int kBracketCap = 1024;
 
 __global__ __launch_bounds__(256) void k_topk(const float* logits, int B, int K, int16_t* cand, int32_t* flags) {
-  __shared__ uint32_t slots[8];
-  __shared__ uint32_t bk[kBins];
-  const int b = blockIdx.x;
-  if (b >= B) return;
-  const int t = threadIdx.x;
-  uint32_t key[16];
-  uint32_t nan = 0;
-  const float4* src = reinterpret_cast<const float4*>(logits + (int64_t)b * kBins + 16 * t);
+  __shared__ uint32_t bk[4][kBracketCap];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int b = blockIdx.x * 4 + wave;
+  if (b >= B) return;  // wave-uniform
+  uint32_t key[64];
+  bool nan = false;
+  const float4* src = reinterpret_cast<const float4*>(logits + (int64_t)b * kBins + 64 * lane);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < 16; ++q) {
     const float4 v = src[q];
     const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      nan |= (vv[r] != vv[r]) ? 1u : 0u;
+      nan = nan || (vv[r] != vv[r]);
       key[4 * q + r] = order_key(vv[r]);
     }
   }
-  int par = 0;
-  const bool any_nan = block_sum(nan, slots, par) != 0;
-  // T = the largest key value with #(key >= T) >= K: prefix bits first.
-  // Counts are taken with ballots and scalar popcounts (wave totals), then
-  // summed over the four waves.
+  const bool any_nan = __ballot(nan) != 0;
   auto count_ge = [&](uint32_t c) {
     uint32_t n = 0;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) n += (uint32_t)__builtin_popcountll(__ballot(key[j] >= c));
-    return n;
+    for (int j = 0; j < 64; ++j) n += key[j] >= c;
+    return wave_sum_u32(n);
   };
-  auto block_total = [&](uint32_t wave_n) {
-    const int wave = threadIdx.x >> 6;
-    slots[par * 4 + wave] = wave_n;  // uniform store
-    __syncthreads();
-    const uint32_t r = slots[par * 4] + slots[par * 4 + 1] + slots[par * 4 + 2] + slots[par * 4 + 3];
-    par ^= 1;
-    return r;
-  };
+  // T = the largest key value with #(key >= T) >= K: prefix bits first
   uint32_t T = 0;
   for (int bit = 31; bit >= 32 - kPrefixBits; --bit) {
     const uint32_t c = T | (1u << bit);
-    if (block_total(count_ge(c)) >= (uint32_t)K) T = c;
+    if (count_ge(c) >= (uint32_t)K) T = c;
   }
   {
     // keys with T's prefix; those above the prefix are all selected
     const uint32_t hi = T | ((1u << (32 - kPrefixBits)) - 1u);
     uint32_t above = 0, inb = 0;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
+    for (int j = 0; j < 64; ++j) {
       above += key[j] > hi;
       inb += key[j] >= T && key[j] <= hi;
     }
-    const uint32_t need = (uint32_t)K - block_sum(above, slots, par);
-    uint32_t m = 0;
-    uint32_t pos = block_exscan(inb, slots, par, m);
+    const uint32_t need = (uint32_t)K - wave_sum_u32(above);
+    const uint32_t inc = wave_scan_u32(inb);
+    const uint32_t m = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+    if (m <= (uint32_t)kBracketCap) {
+      uint32_t pos = inc - inb;
+      uint32_t* wb = bk[wave];
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
-      if (key[j] >= T && key[j] <= hi) bk[pos++] = key[j];
-    __syncthreads();
-    for (int bit = 31 - kPrefixBits; bit >= 0; --bit) {
-      const uint32_t c = T | (1u << bit);
-      uint32_t n = 0;
-      for (uint32_t i0 = 0; i0 < m; i0 += 256) {
-        const uint32_t i = i0 + t;
-        n += (uint32_t)__builtin_popcountll(__ballot(i < m && bk[i < m ? i : 0] >= c));
+      for (int j = 0; j < 64; ++j)
+        if (key[j] >= T && key[j] <= hi) wb[pos++] = key[j];
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      for (int bit = 31 - kPrefixBits; bit >= 0; --bit) {
+        const uint32_t c = T | (1u << bit);
+        uint32_t n = 0;
+        for (uint32_t i = lane; i < m; i += 64) n += wb[i] >= c;
+        if (wave_sum_u32(n) >= need) T = c;
       }
-      if (block_total(n) >= need) T = c;
+    } else {
+      for (int bit = 31 - kPrefixBits; bit >= 0; --bit) {
+        const uint32_t c = T | (1u << bit);
+        if (count_ge(c) >= (uint32_t)K) T = c;
+      }
     }
   }
   uint32_t gt = 0, eq = 0;
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
+  for (int j = 0; j < 64; ++j) {
     gt += key[j] > T;
     eq += key[j] == T;
   }
-  uint32_t ngt = 0, neq = 0;
-  const uint32_t gt_before = block_exscan(gt, slots, par, ngt);
+  const uint32_t gt_inc = wave_scan_u32(gt), eq_inc = wave_scan_u32(eq);
+  const uint32_t ngt = (uint32_t)__builtin_amdgcn_readlane((int)gt_inc, 63);
+  const uint32_t gt_before = gt_inc - gt, eq_before = eq_inc - eq;
   const uint32_t remaining = (uint32_t)K - ngt;  // ties at T to take, lowest bins first
-  const uint32_t eq_before = block_exscan(eq, slots, par, neq);
-  // Ties taken before this thread and by it, written with min() only: a
+  // Ties taken before this lane and by it, written with min() only: a
   // subtraction guarded by a comparison was observed to be speculated with
   // a no-wrap flag that then let the optimiser drop the first min().
   const uint32_t taken_before = min(eq_before, remaining);
   const uint32_t eq_take = min(eq_before + eq, remaining) - taken_before;
-  // selected before this thread: all greater keys, plus the ties taken
   uint32_t pos = gt_before + taken_before;
   uint32_t eq_seen = 0;
   int16_t* out = cand + (int64_t)b * K;
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
+  for (int j = 0; j < 64; ++j) {
     bool take = key[j] > T;
     if (key[j] == T) {
       take = eq_seen < eq_take;
       ++eq_seen;
     }
-    if (take && pos < (uint32_t)K) out[pos++] = (int16_t)(16 * t + j);
+    if (take && pos < (uint32_t)K) out[pos++] = (int16_t)(64 * lane + j);
   }
-  if (t == 0) flags[b] = any_nan ? 1 : 0;
+  if (lane == 0) flags[b] = any_nan ? 1 : 0;
 }
 
 }  // namespace
@@ -654,6 +651,15 @@ hipError_t forward(const uint16_t* x, int32_t B, const uint16_t* prm, uint16_t* 
                    hipStream_t s) {
   if (B <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_forward, dim3(B), dim3(256), 0, s, x, B, prm, feats, acts);
+  return hipGetLastError();
+}
+
+hipError_t forward_blocks(const uint8_t* img, const uint8_t* avail, int64_t pitch, int32_t H, int32_t W,
+                          const void* blocks, const int32_t* orig, int32_t n, const uint16_t* prm, uint16_t* feats,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_forward_blocks, dim3(n), dim3(256), 0, s, img, avail, pitch, H, W,
+                     reinterpret_cast<const fse_block_t*>(blocks), orig, n, prm, feats);
   return hipGetLastError();
 }
 
@@ -744,7 +750,7 @@ hipError_t adam(float* master, float* grad, float* m, float* v, uint16_t* work, 
 
 hipError_t topk(const float* logits, int32_t B, int32_t K, int16_t* cand, int32_t* flags, hipStream_t s) {
   if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_topk, dim3(B), dim3(256), 0, s, logits, B, K, cand, flags);
+  hipLaunchKernelGGL(k_topk, dim3((B + 3) / 4), dim3(256), 0, s, logits, B, K, cand, flags);
   return hipGetLastError();
 }
 

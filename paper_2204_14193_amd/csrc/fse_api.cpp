@@ -537,6 +537,16 @@ extern "C" fse_status_t fse_cnn_patches(fse_batch_t batch, const uint8_t* d_imag
   return FSE_OK;
 }
 
+extern "C" fse_status_t fse_cnn_forward_blocks(fse_cnn_t net, fse_batch_t batch, const uint8_t* d_image,
+                                               const uint8_t* d_avail, int64_t pitch, float* d_logits,
+                                               void* stream) {
+  if (!batch || !d_image || !d_avail) return fail(FSE_ERR_INVALID_ARG, "null argument");
+  if (!batch->all_48) return fail(FSE_ERR_UNSUPPORTED, "network inputs need 48x48 areas");
+  if (pitch < batch->W) return fail(FSE_ERR_INVALID_ARG, "pitch smaller than the width");
+  return fse::cnn::net_forward_blocks(net, d_image, d_avail, pitch, batch->H, batch->W, batch->d_blocks,
+                                      batch->d_orig, batch->n, d_logits, reinterpret_cast<hipStream_t>(stream));
+}
+
 extern "C" int32_t fse_warm_trace_stride(fse_batch_t batch, int32_t restricted_iters, int32_t fallback_iters) {
   return batch ? restricted_iters + std::max(batch->max_iters, fallback_iters) : 0;
 }

@@ -58,6 +58,11 @@ class Net:
         _check(_lib.lib().fse_cnn_forward(self._h, _ptr(x), int(B), _ptr(logits), int(bool(keep)),
                                           _stream(stream)), "fse_cnn_forward")
 
+    def forward_blocks(self, batch, image, avail, logits, stream=None):
+        """Logits for every block of `batch`, inputs built from the frames."""
+        _check(_lib.lib().fse_cnn_forward_blocks(self._h, batch._h, _ptr(image), _ptr(avail), image.stride(1),
+                                                 _ptr(logits), _stream(stream)), "fse_cnn_forward_blocks")
+
     def backward(self, x, logits, target_bits, pos_weight, loss, stream=None):
         """target_bits: CUDA int32 [B,128]; loss: CUDA float32 [1] (added to)."""
         _check(_lib.lib().fse_cnn_backward(self._h, _ptr(x), _ptr(logits), _ptr(target_bits), int(x.shape[0]),
@@ -112,8 +117,8 @@ def warm_extrapolate(batch, image, avail, out, status, cand, flags, kc, restrict
 
 
 class WarmStart:
-    """The whole warm-started concealment of one batch: network inputs,
-    forward pass, candidate sets, warm-started FSE. Buffers are allocated
+    """The whole warm-started concealment of one batch: forward pass (inputs
+    built from the frames), candidate sets, warm-started FSE. Buffers are allocated
     once per batch size; run() only launches kernels."""
 
     def __init__(self, net, batch, kc=256, restricted_iters=75, fallback_iters=100):
@@ -122,14 +127,12 @@ class WarmStart:
         self.kc, self.ir, self.fb = int(kc), int(restricted_iters), int(fallback_iters)
         n = batch.n
         dev = torch.device("cuda")
-        self.x = torch.empty((n,) + PATCH, dtype=torch.bfloat16, device=dev)
         self.logits = torch.empty((n, N_BINS), dtype=torch.float32, device=dev)
         self.cand = torch.empty((n, self.kc), dtype=torch.int16, device=dev)
         self.flags = torch.empty((n,), dtype=torch.int32, device=dev)
 
     def run(self, image, avail, out, status, trace=None, stream=None):
-        patches(self.batch, image, avail, self.x, stream)
-        self.net.forward(self.x, self.logits, keep=False, stream=stream)
+        self.net.forward_blocks(self.batch, image, avail, self.logits, stream)
         topk(self.logits, self.kc, self.cand, self.flags, stream)
         warm_extrapolate(self.batch, image, avail, out, status, self.cand, self.flags, self.kc, self.ir, self.fb,
                          trace, stream)

@@ -88,6 +88,34 @@ def test_forward_matches_oracle():
     net.close()
 
 
+def test_forward_from_frames_equals_patches_then_forward():
+    """fse_cnn_forward_blocks builds the inputs in LDS; its logits are the
+    bits of fse_cnn_patches followed by fse_cnn_forward (a batch with frame
+    edges, in a non-trivial block order)."""
+    import torch
+    import paper_2204_14193_amd as fse
+    from paper_2204_14193_amd import warm
+    _say("case forward from frames")
+    wl = workloads.subset(workloads.isolated_256(iters=30), np.arange(64)[::-1].copy())
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(wl.distorted).to(dev)
+    av = torch.from_numpy(wl.avail).to(dev)
+    plan = fse.Plan(wl.rho, wl.gamma, 4096)
+    batch = fse.Batch(plan, wl.blocks, *wl.frames.shape)
+    n = len(wl.blocks)
+    net = warm.Net(n)
+    net.load()
+    x = torch.empty((n, 48, 48, 2), dtype=torch.bfloat16, device=dev)
+    warm.patches(batch, img, av, x)
+    a = torch.empty((n, 4096), dtype=torch.float32, device=dev)
+    b = torch.full((n, 4096), float("nan"), dtype=torch.float32, device=dev)
+    net.forward(x, a)
+    net.forward_blocks(batch, img, av, b)
+    torch.cuda.synchronize()
+    assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+    net.close()
+
+
 def test_backward_matches_oracle_and_adam_step():
     import torch
     from paper_2204_14193_amd import warm
