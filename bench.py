@@ -248,7 +248,7 @@ def main():
                         "speedup_vs_plain": legs["plain"]["ms_per_step"] / ms_w, "fallbacks": fallbacks,
                         "kc": args.kc, "restricted_iters": args.ir, "weights_sha": wsha,
                         "kernels": {("fse_restricted<%d>" % args.kc if k == "restricted" else
-                                     "fse_persistent<64,256,%d,prep>" % args.kc): {"ms": v[1], "launches": v[0]}
+                                     "fse_persistent<64,512,%d,prep>" % args.kc): {"ms": v[1], "launches": v[0]}
                                     for k, v in kw.items()}}
         n_pix = int(wl.blocks["bh"].astype(np.int64) @ wl.blocks["bw"].astype(np.int64))
         warm_roof = {"kernel": "fse_restricted<%d>" % args.kc,

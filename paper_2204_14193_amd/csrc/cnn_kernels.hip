@@ -524,6 +524,18 @@ __device__ __forceinline__ uint32_t order_key(float v) {
 }
 
 
+// Sum over the 256-thread workgroup (four waves), same value in every lane.
+// `slots` holds 2 x 4 words; `par` alternates so one barrier per call suffices.
+__device__ __forceinline__ uint32_t block_sum(uint32_t x, uint32_t* slots, int& par) {
+  const uint32_t w = wave_sum_u32(x);
+  const int wave = threadIdx.x >> 6;
+  slots[par * 4 + wave] = w;
+  __syncthreads();
+  const uint32_t r = slots[par * 4] + slots[par * 4 + 1] + slots[par * 4 + 2] + slots[par * 4 + 3];
+  par ^= 1;
+  return r;
+}
+
 // Inclusive prefix sum over the 64 lanes of a wave.
 __device__ __forceinline__ uint32_t wave_scan_u32(uint32_t x) {
   x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);  // row_shr:1
@@ -535,106 +547,124 @@ __device__ __forceinline__ uint32_t wave_scan_u32(uint32_t x) {
   return x;
 }
 
-// Exact selection of the K-th largest order key T, one wave per sample
-// (no workgroup barriers): lane l holds the 64 keys of bins 64l..64l+63.
-// The top kPrefixBits bits of T come from bisection over all keys, the rest
-// from bisection over the keys sharing that prefix only, compacted into the
-// wave's LDS region (up to kBracketCap of them; beyond that the bisection
-// continues over all keys). Counts are per-lane sums reduced with DPP.
+// Exclusive prefix sum over the 256 threads (four waves) and the total.
+// `slots` holds 2 x 4 words used alternately (see block_sum).
+__device__ __forceinline__ uint32_t block_exscan(uint32_t x, uint32_t* slots, int& par, uint32_t& total) {
+  const uint32_t inc = wave_scan_u32(x);
+  const int wave = threadIdx.x >> 6;
+  slots[par * 4 + wave] = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+  __syncthreads();
+  uint32_t before = 0;
+  const uint32_t s0 = slots[par * 4], s1 = slots[par * 4 + 1], s2 = slots[par * 4 + 2], s3 = slots[par * 4 + 3];
+  before = (wave > 0 ? s0 : 0u) + (wave > 1 ? s1 : 0u) + (wave > 2 ? s2 : 0u);
+  total = s0 + s1 + s2 + s3;
+  par ^= 1;
+  return before + inc - x;
+}
+
+// Exact selection of the K-th largest order key T: its top kPrefixBits bits
+// by bisection over all keys, then the remaining bits by bisection over the
+// keys sharing that prefix only (compacted into LDS).
 constexpr int kPrefixBits = 14;
-constexpr int kBracketCap = 1024;
 
 __global__ __launch_bounds__(256) void k_topk(const float* logits, int B, int K, int16_t* cand, int32_t* flags) {
-  __shared__ uint32_t bk[4][kBracketCap];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int b = blockIdx.x * 4 + wave;
-  if (b >= B) return;  // wave-uniform
-  uint32_t key[64];
-  bool nan = false;
-  const float4* src = reinterpret_cast<const float4*>(logits + (int64_t)b * kBins + 64 * lane);
+  __shared__ uint32_t slots[8];
+  __shared__ uint32_t bk[kBins];
+  const int b = blockIdx.x;
+  if (b >= B) return;
+  const int t = threadIdx.x;
+  uint32_t key[16];
+  uint32_t nan = 0;
+  const float4* src = reinterpret_cast<const float4*>(logits + (int64_t)b * kBins + 16 * t);
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
+  for (int q = 0; q < 4; ++q) {
     const float4 v = src[q];
     const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      nan = nan || (vv[r] != vv[r]);
+      nan |= (vv[r] != vv[r]) ? 1u : 0u;
       key[4 * q + r] = order_key(vv[r]);
     }
   }
-  const bool any_nan = __ballot(nan) != 0;
+  int par = 0;
+  const bool any_nan = block_sum(nan, slots, par) != 0;
+  // T = the largest key value with #(key >= T) >= K: prefix bits first.
+  // Counts are taken with ballots and scalar popcounts (wave totals), then
+  // summed over the four waves.
   auto count_ge = [&](uint32_t c) {
     uint32_t n = 0;
 #pragma unroll
-    for (int j = 0; j < 64; ++j) n += key[j] >= c;
-    return wave_sum_u32(n);
+    for (int j = 0; j < 16; ++j) n += (uint32_t)__builtin_popcountll(__ballot(key[j] >= c));
+    return n;
   };
-  // T = the largest key value with #(key >= T) >= K: prefix bits first
+  auto block_total = [&](uint32_t wave_n) {
+    const int wave = threadIdx.x >> 6;
+    slots[par * 4 + wave] = wave_n;  // uniform store
+    __syncthreads();
+    const uint32_t r = slots[par * 4] + slots[par * 4 + 1] + slots[par * 4 + 2] + slots[par * 4 + 3];
+    par ^= 1;
+    return r;
+  };
   uint32_t T = 0;
   for (int bit = 31; bit >= 32 - kPrefixBits; --bit) {
     const uint32_t c = T | (1u << bit);
-    if (count_ge(c) >= (uint32_t)K) T = c;
+    if (block_total(count_ge(c)) >= (uint32_t)K) T = c;
   }
   {
     // keys with T's prefix; those above the prefix are all selected
     const uint32_t hi = T | ((1u << (32 - kPrefixBits)) - 1u);
     uint32_t above = 0, inb = 0;
 #pragma unroll
-    for (int j = 0; j < 64; ++j) {
+    for (int j = 0; j < 16; ++j) {
       above += key[j] > hi;
       inb += key[j] >= T && key[j] <= hi;
     }
-    const uint32_t need = (uint32_t)K - wave_sum_u32(above);
-    const uint32_t inc = wave_scan_u32(inb);
-    const uint32_t m = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
-    if (m <= (uint32_t)kBracketCap) {
-      uint32_t pos = inc - inb;
-      uint32_t* wb = bk[wave];
+    const uint32_t need = (uint32_t)K - block_sum(above, slots, par);
+    uint32_t m = 0;
+    uint32_t pos = block_exscan(inb, slots, par, m);
 #pragma unroll
-      for (int j = 0; j < 64; ++j)
-        if (key[j] >= T && key[j] <= hi) wb[pos++] = key[j];
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      for (int bit = 31 - kPrefixBits; bit >= 0; --bit) {
-        const uint32_t c = T | (1u << bit);
-        uint32_t n = 0;
-        for (uint32_t i = lane; i < m; i += 64) n += wb[i] >= c;
-        if (wave_sum_u32(n) >= need) T = c;
+    for (int j = 0; j < 16; ++j)
+      if (key[j] >= T && key[j] <= hi) bk[pos++] = key[j];
+    __syncthreads();
+    for (int bit = 31 - kPrefixBits; bit >= 0; --bit) {
+      const uint32_t c = T | (1u << bit);
+      uint32_t n = 0;
+      for (uint32_t i0 = 0; i0 < m; i0 += 256) {
+        const uint32_t i = i0 + t;
+        n += (uint32_t)__builtin_popcountll(__ballot(i < m && bk[i < m ? i : 0] >= c));
       }
-    } else {
-      for (int bit = 31 - kPrefixBits; bit >= 0; --bit) {
-        const uint32_t c = T | (1u << bit);
-        if (count_ge(c) >= (uint32_t)K) T = c;
-      }
+      if (block_total(n) >= need) T = c;
     }
   }
   uint32_t gt = 0, eq = 0;
 #pragma unroll
-  for (int j = 0; j < 64; ++j) {
+  for (int j = 0; j < 16; ++j) {
     gt += key[j] > T;
     eq += key[j] == T;
   }
-  const uint32_t gt_inc = wave_scan_u32(gt), eq_inc = wave_scan_u32(eq);
-  const uint32_t ngt = (uint32_t)__builtin_amdgcn_readlane((int)gt_inc, 63);
-  const uint32_t gt_before = gt_inc - gt, eq_before = eq_inc - eq;
+  uint32_t ngt = 0, neq = 0;
+  const uint32_t gt_before = block_exscan(gt, slots, par, ngt);
   const uint32_t remaining = (uint32_t)K - ngt;  // ties at T to take, lowest bins first
-  // Ties taken before this lane and by it, written with min() only: a
+  const uint32_t eq_before = block_exscan(eq, slots, par, neq);
+  // Ties taken before this thread and by it, written with min() only: a
   // subtraction guarded by a comparison was observed to be speculated with
   // a no-wrap flag that then let the optimiser drop the first min().
   const uint32_t taken_before = min(eq_before, remaining);
   const uint32_t eq_take = min(eq_before + eq, remaining) - taken_before;
+  // selected before this thread: all greater keys, plus the ties taken
   uint32_t pos = gt_before + taken_before;
   uint32_t eq_seen = 0;
   int16_t* out = cand + (int64_t)b * K;
 #pragma unroll
-  for (int j = 0; j < 64; ++j) {
+  for (int j = 0; j < 16; ++j) {
     bool take = key[j] > T;
     if (key[j] == T) {
       take = eq_seen < eq_take;
       ++eq_seen;
     }
-    if (take && pos < (uint32_t)K) out[pos++] = (int16_t)(64 * lane + j);
+    if (take && pos < (uint32_t)K) out[pos++] = (int16_t)(16 * t + j);
   }
-  if (lane == 0) flags[b] = any_nan ? 1 : 0;
+  if (t == 0) flags[b] = any_nan ? 1 : 0;
 }
 
 }  // namespace
@@ -750,7 +780,7 @@ hipError_t adam(float* master, float* grad, float* m, float* v, uint16_t* work, 
 
 hipError_t topk(const float* logits, int32_t B, int32_t K, int16_t* cand, int32_t* flags, hipStream_t s) {
   if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_topk, dim3((B + 3) / 4), dim3(256), 0, s, logits, B, K, cand, flags);
+  hipLaunchKernelGGL(k_topk, dim3(B), dim3(256), 0, s, logits, B, K, cand, flags);
   return hipGetLastError();
 }
 

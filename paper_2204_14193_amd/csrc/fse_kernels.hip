@@ -918,8 +918,8 @@ const Variant kVariants[] = {
     make_variant<128, 1024>(), make_variant<128, 512>(),
     make_variant<64, 256, 256, kWarmFused>(), make_variant<64, 256, 128, kWarmFused>(),
     make_variant<64, 256, 512, kWarmFused>(),
-    make_variant<64, 256, 256, kWarmPrep>(), make_variant<64, 256, 128, kWarmPrep>(),
-    make_variant<64, 256, 512, kWarmPrep>(), make_variant<64, 256, 384, kWarmPrep>(),
+    make_variant<64, 512, 256, kWarmPrep>(), make_variant<64, 512, 128, kWarmPrep>(),
+    make_variant<64, 512, 512, kWarmPrep>(), make_variant<64, 512, 384, kWarmPrep>(),
 };
 
 }  // namespace
