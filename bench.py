@@ -150,7 +150,7 @@ def main():
     ap.add_argument("--workload", default="random-1080p-16x16",
                     choices=["random-1080p-16x16", "random-1080p-8x8", "mixed-4k"],
                     help="the metric's workload (default) or one of the other configurations (plain only)")
-    ap.add_argument("--kc", type=int, default=384, help="warm start: candidate bins per block")
+    ap.add_argument("--kc", type=int, default=256, help="warm start: candidate bins per block")
     ap.add_argument("--ir", type=int, default=110, help="warm start: restricted iterations")
     ap.add_argument("--no-warm", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2048)

@@ -102,6 +102,14 @@ __global__ __launch_bounds__(256) void k_patches(const uint8_t* img, const uint8
 }
 
 // ------------------------------------------------------------------ forward
+// 32-channel activations sit in LDS as four planes of 8 channels
+// (plane g, pixel p at element g*P*8 + p*8): the stride-2 reads of a layer
+// (consecutive lanes take input pixels two apart) then fall 32 bytes apart
+// and spread over all LDS banks, where the 64-byte pixels of a plain NHWC
+// layout would put them 128 bytes apart on a few banks.
+template <int P>
+__device__ __forceinline__ int plane_idx(int p, int c) { return (c >> 3) * (P * 8) + p * 8 + (c & 7); }
+
 // One 3x3 stride-2 convolution with bias and ReLU, activations in LDS
 // (NHWC, BF16), as an implicit GEMM: rows = output pixels, columns = the 32
 // output channels, depth = (tap, input channel). Each wave loads its
@@ -145,7 +153,7 @@ __device__ __forceinline__ void conv_layer(const uint16_t* in, uint16_t* out, co
       const int tap = k0 >> 5, c0 = k0 & 31;
       const int iy = 2 * oy - 1 + tap / 3, ix = 2 * ox - 1 + tap % 3;
       if (mv && iy >= 0 && iy < HIN && ix >= 0 && ix < HIN)
-        av = *reinterpret_cast<const uint4*>(in + (iy * HIN + ix) * CIN + c0);
+        av = *reinterpret_cast<const uint4*>(in + plane_idx<HIN * HIN>(iy * HIN + ix, c0));
     } else {
       uint32_t a4[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
@@ -166,7 +174,7 @@ __device__ __forceinline__ void conv_layer(const uint16_t* in, uint16_t* out, co
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int p = tile * 32 + drow(i, lane);
-      if (p < P) out[p * kCh + n] = f2bf(fmaxf(acc[i] + bn, 0.f));
+      if (p < P) out[plane_idx<P>(p, n)] = f2bf(fmaxf(acc[i] + bn, 0.f));
     }
   };
   // Tiles wave, wave+4, ... taken two at a time: two independent MFMA
@@ -198,6 +206,15 @@ __device__ __forceinline__ void copy_act(const uint16_t* src, uint16_t* dst, int
     reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
 }
 
+// A planar 32-channel activation of P pixels to NHWC in global memory.
+template <int P>
+__device__ __forceinline__ void copy_act_nhwc(const uint16_t* src, uint16_t* dst, int t) {
+  for (int i = t; i < P * 4; i += 256) {
+    const int px = i >> 2, g = i & 3;
+    reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[g * P + px];
+  }
+}
+
 // The whole convolution stack for one sample per workgroup, activations in
 // LDS; writes the 288 features and, for training, every activation. LDS is
 // two regions: X holds the input, then layer 2's output; Y holds layer 1's
@@ -213,17 +230,17 @@ __device__ __forceinline__ void conv_stack(uint16_t* X, uint16_t* Y, const uint1
   uint16_t* const a4 = Y + 6 * 6 * kCh;
   conv_layer<2, 48>(a0, a1, prm + kOffW[0], prm + kOffB[0], t);
   __syncthreads();
-  if (dst) copy_act<24 * 24 * kCh>(a1, dst + kActOff[0], t);
+  if (dst) copy_act_nhwc<24 * 24>(a1, dst + kActOff[0], t);
   conv_layer<kCh, 24>(a1, a2, prm + kOffW[1], prm + kOffB[1], t);
   __syncthreads();
-  if (dst) copy_act<12 * 12 * kCh>(a2, dst + kActOff[1], t);
+  if (dst) copy_act_nhwc<12 * 12>(a2, dst + kActOff[1], t);
   conv_layer<kCh, 12>(a2, a3, prm + kOffW[2], prm + kOffB[2], t);
   __syncthreads();
-  if (dst) copy_act<6 * 6 * kCh>(a3, dst + kActOff[2], t);
+  if (dst) copy_act_nhwc<6 * 6>(a3, dst + kActOff[2], t);
   conv_layer<kCh, 6>(a3, a4, prm + kOffW[3], prm + kOffB[3], t);
   __syncthreads();
   for (int i = t; i < kFeat; i += 256) {
-    const uint16_t v = a4[i];
+    const uint16_t v = a4[plane_idx<9>(i / kCh, i % kCh)];
     feat_row[i] = v;
     if (dst) dst[kActOff[3] + i] = v;
   }

@@ -866,8 +866,9 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
     }
     // eq. (18) at the candidates: W[k-u, l-v] from row (k-u) mod F when
     // that is <= F/2, else the conjugate of W[u-k, v-l]
-    const int ca = (F - u) * 4096 + (F - v) * 8;
-    const int cb = (F + u) * 4096 + (F + v) * 8;
+    int ca = (F - u) * 4096 + (F - v) * 8;
+    int cb = (F + u) * 4096 + (F + v) * 8;
+    asm volatile("" : "+s"(ca), "+s"(cb));  // opaque: one add per candidate, not two
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
       const int ya = xa[j] + ca, yb = cb - xa[j];
@@ -892,9 +893,17 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
     const float2 c = cl_c[it];
     finite = finite && isfinite(c.x) && isfinite(c.y);
   }
-  if (__syncthreads_or(!finite)) {
-    if (wave == 0) a.status[orig] = FSE_BLOCK_NONFINITE;
-    return;
+  {
+    int* const bad = reinterpret_cast<int*>(xch);  // the exchange slots are free now
+    bad[wave] = __ballot(!finite) != 0 ? 1 : 0;    // uniform store
+    __syncthreads();
+    bool any_bad = false;
+#pragma unroll
+    for (int w = 0; w < NWB; ++w) any_bad = any_bad || bad[w] != 0;
+    if (any_bad) {
+      if (wave == 0) a.status[orig] = FSE_BLOCK_NONFINITE;
+      return;
+    }
   }
   // model on B, as in the persistent kernel
   const UBlock bd = uniform_block(a.blocks + bi);

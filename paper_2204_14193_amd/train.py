@@ -7,7 +7,7 @@ this library's GPU kernels) selects. The network learns to score bins so
 that its top-K set covers them (binary cross-entropy, positives weighted).
 Forward, backward and Adam run in libfse; torch only holds the buffers.
 
-    python -m paper_2204_14193_amd.train --blocks 800000 --epochs 32
+    python -m paper_2204_14193_amd.train --blocks 1600000 --epochs 40
 """
 import argparse
 import json
@@ -190,8 +190,8 @@ def evaluate(net, seeds=tuple(range(99, 107)), configs=((384, 110), (512, 100), 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--blocks", type=int, default=800000)
-    ap.add_argument("--epochs", type=int, default=32)
+    ap.add_argument("--blocks", type=int, default=1600000)
+    ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--pos-weight", type=float, default=4.0)

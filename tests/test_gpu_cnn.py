@@ -305,7 +305,7 @@ def test_split_warm_equals_single_kernel_bitwise():
 
 
 def test_warm_start_quality_bar_and_timing_hook():
-    """The packaged network at the benchmark's setting (top-384 candidates,
+    """The packaged network at the benchmark's setting (top-256 candidates,
     110 restricted iterations) loses at most 0.1 dB of PSNR over the lost
     pixels against plain FSE with 100 iterations, on the eight held-out
     benchmark frames; the timing hook records both kernels of the split
@@ -332,7 +332,7 @@ def test_warm_start_quality_bar_and_timing_hook():
     bw = fse.Batch(plan, wb, *wl.frames.shape)
     net = warm.Net(n)
     net.load()
-    ws = warm.WarmStart(net, bw, 384, 110, 100)
+    ws = warm.WarmStart(net, bw, 256, 110, 100)
     out_w = img.to(torch.float32)
     st_w = torch.zeros(n, dtype=torch.int32, device=dev)
     bw.set_timing(2)
