@@ -588,7 +588,7 @@ extern "C" fse_status_t fse_warm_extrapolate_batch(fse_batch_t batch, const uint
       if (hipFuncSetAttribute(rk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return fail(FSE_ERR_HIP, "hipFuncSetAttribute failed (LDS size)");
       int per_cu = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rk, fse::restricted_threads(), lds) != hipSuccess ||
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rk, fse::restricted_threads(kc), lds) != hipSuccess ||
           per_cu < 1)
         return fail(FSE_ERR_UNSUPPORTED, "restricted kernel does not fit on a compute unit");
       if (kc != batch->stage_kc) {

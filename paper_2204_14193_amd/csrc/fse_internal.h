@@ -75,7 +75,7 @@ const void* restricted_kernel(int kc);
 // Dynamic LDS bytes of the restricted kernel for ir restricted iterations,
 // and its threads per workgroup.
 size_t restricted_lds_bytes(int ir);
-int restricted_threads();
+int restricted_threads(int kc);
 
 // All compiled plain variants for F; returns their number, fills up to cap.
 int variants_for(int F, const Variant** out, int cap);

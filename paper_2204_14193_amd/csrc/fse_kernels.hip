@@ -809,6 +809,25 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
   }
   const float gW = a.gamma * (1.0f / W0);
 
+  // The model on B (as in the persistent kernel) is accumulated inside the
+  // loop when the block has at most NT*QI pixels (QI per thread), in the
+  // same per-pixel order as the list-based synthesis after the loop, which
+  // larger blocks use.
+  constexpr int QI = 4 / NWB;
+  const UBlock bd = uniform_block(a.blocks + bi);
+  const int np = bd.bh * bd.bw;
+  const bool inloop = np <= NT * QI;
+  int mq[QI], nq[QI];
+  float acc[QI];
+#pragma unroll
+  for (int q = 0; q < QI; ++q) {
+    const int p = min(t + q * NT, np - 1);
+    mq[q] = bd.border + p / bd.bw;
+    nq[q] = bd.border + p % bd.bw;
+    acc[q] = 0.f;
+  }
+
+  bool finite = true;
   int parity = 0;
   for (int it = 0; it < a.ir; ++it) {
     unsigned lm = mb[0];
@@ -851,9 +870,20 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
     }
     const int u = x >> 12, v = (x >> 3) & 511;
     const float cre = gW * re, cim = gW * im;  // eq. (13)
+    finite = finite && isfinite(cre) && isfinite(cim);
+    if (inloop) {
+#pragma unroll
+      for (int q = 0; q < QI; ++q) {
+        const float2 e = tw[(u * mq[q] + v * nq[q]) & (F - 1)];  // Re{c e^{j theta}} = c.x e.x + c.y e.y
+        acc[q] = fmaf(cre, e.x, acc[q]);
+        acc[q] = fmaf(cim, e.y, acc[q]);
+      }
+    }
     if (wave == 0) {
-      cl_idx[it] = u * F + v;  // uniform stores
-      cl_c[it] = make_float2(cre, cim);
+      if (!inloop) {
+        cl_idx[it] = u * F + v;  // uniform stores
+        cl_c[it] = make_float2(cre, cim);
+      }
       if (a.trace) {
         fse_trace_t rec;
         rec.u = (uint16_t)u;
@@ -886,30 +916,21 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
       mb[j] = __float_as_uint(fmaf(ry, ry, rx * rx));
     }
   }
-  __syncthreads();
-  // every coefficient must be finite
-  bool finite = true;
-  for (int it = t; it < a.ir; it += NT) {
-    const float2 c = cl_c[it];
-    finite = finite && isfinite(c.x) && isfinite(c.y);
+  // every coefficient must be finite (all waves computed the same ones)
+  if (!finite) {
+    if (wave == 0) a.status[orig] = FSE_BLOCK_NONFINITE;
+    return;
   }
-  {
-    int* const bad = reinterpret_cast<int*>(xch);  // the exchange slots are free now
-    bad[wave] = __ballot(!finite) != 0 ? 1 : 0;    // uniform store
-    __syncthreads();
-    bool any_bad = false;
-#pragma unroll
-    for (int w = 0; w < NWB; ++w) any_bad = any_bad || bad[w] != 0;
-    if (any_bad) {
-      if (wave == 0) a.status[orig] = FSE_BLOCK_NONFINITE;
-      return;
-    }
-  }
-  // model on B, as in the persistent kernel
-  const UBlock bd = uniform_block(a.blocks + bi);
   const int64_t fofs = (int64_t)bd.frame * a.H;
-  synthesize<F, NT, 4 / NWB>(cl_idx, cl_c, a.ir, tw, bd.bh, bd.bw, bd.border,
-                             a.out + (fofs + bd.y0) * a.out_pitch + bd.x0, a.out_pitch, t);
+  float* const ob = a.out + (fofs + bd.y0) * a.out_pitch + bd.x0;
+  if (inloop) {
+#pragma unroll
+    for (int q = 0; q < QI; ++q)
+      if (t + q * NT < np) ob[(int64_t)(mq[q] - bd.border) * a.out_pitch + (nq[q] - bd.border)] = acc[q];
+  } else {
+    __syncthreads();
+    synthesize<F, NT, 4 / NWB>(cl_idx, cl_c, a.ir, tw, bd.bh, bd.bw, bd.border, ob, a.out_pitch, t);
+  }
   if (wave == 0) a.status[orig] = FSE_BLOCK_OK;
 }
 
@@ -955,23 +976,22 @@ int variants_for(int F, const Variant** out, int cap) {
   return n;
 }
 
-// Waves per block of the restricted kernel.
-#ifndef FSE_RESTRICTED_WAVES
-#define FSE_RESTRICTED_WAVES 2
-#endif
-constexpr int kRestrictedWaves = FSE_RESTRICTED_WAVES;
+// Waves per block of the restricted kernel: one up to 256 candidates (the
+// per-iteration reductions would dominate two waves of two candidates per
+// lane), two above.
+constexpr int restricted_waves(int kc) { return kc <= 256 ? 1 : 2; }
 
 const void* restricted_kernel(int kc) {
   switch (kc) {
-    case 128: return reinterpret_cast<const void*>(&fse_restricted<128, kRestrictedWaves>);
-    case 256: return reinterpret_cast<const void*>(&fse_restricted<256, kRestrictedWaves>);
-    case 384: return reinterpret_cast<const void*>(&fse_restricted<384, kRestrictedWaves>);
-    case 512: return reinterpret_cast<const void*>(&fse_restricted<512, kRestrictedWaves>);
+    case 128: return reinterpret_cast<const void*>(&fse_restricted<128, restricted_waves(128)>);
+    case 256: return reinterpret_cast<const void*>(&fse_restricted<256, restricted_waves(256)>);
+    case 384: return reinterpret_cast<const void*>(&fse_restricted<384, restricted_waves(384)>);
+    case 512: return reinterpret_cast<const void*>(&fse_restricted<512, restricted_waves(512)>);
     default: return nullptr;
   }
 }
 
-int restricted_threads() { return 64 * kRestrictedWaves; }
+int restricted_threads(int kc) { return 64 * restricted_waves(kc); }
 
 size_t restricted_lds_bytes(int ir) {
   return (size_t)kHalfRows * 64 * 8 + 64 * 8 + 4 * 16 + (size_t)ir * 12;
@@ -981,7 +1001,7 @@ hipError_t launch_restricted(int kc, const ClassArgs& a, size_t lds, hipStream_t
   const void* fn = restricted_kernel(kc);
   if (!fn || a.n <= 0) return hipErrorInvalidValue;
   void* args[] = {const_cast<ClassArgs*>(&a)};
-  return hipLaunchKernel(fn, dim3(a.n), dim3(restricted_threads()), args, lds, s);
+  return hipLaunchKernel(fn, dim3(a.n), dim3(restricted_threads(kc)), args, lds, s);
 }
 
 size_t lds_bytes(const Variant& v, int iters_cap) {

@@ -353,3 +353,55 @@ def test_warm_start_quality_bar_and_timing_hook():
     p_plain, p_warm = psnr(out_p.cpu().numpy()), psnr(out_w.cpu().numpy())
     _say(f"  plain {p_plain:.3f} dB, warm {p_warm:.3f} dB")
     assert p_plain - p_warm <= 0.1
+
+
+def test_split_warm_large_blocks_use_the_list_synthesis():
+    """Blocks with more pixels than the restricted kernel keeps in registers
+    (32x32 losses, border 8: 48x48 areas) take the coefficient-list
+    synthesis; replayed against the oracle and bit-identical to the single
+    kernel form."""
+    import torch
+    import paper_2204_14193_amd as fse
+    from paper_2204_14193_amd import warm
+    from synth import images, losses
+    _say("case split warm, 32x32 blocks")
+    ir, fb = 30, 20
+    frame = images.synthetic_image(256, 256, 4)[None]
+    blk = losses.blocks_to_array(losses.isolated_grid_losses(256, 256, 32, 8, 64, 0))
+    avail = losses.availability_mask(frame.shape, losses.array_to_blocks(blk))
+    rng = np.random.default_rng(5)
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(frame * avail).to(dev)
+    av = torch.from_numpy(avail).to(dev)
+    n = len(blk)
+    outs = []
+    for extra in (False, True):
+        b = blk.copy()
+        if extra:  # one more block with full iterations: single-kernel form
+            b = np.concatenate([b, losses.blocks_to_array([losses.Block(0, 0, 0, 8, 8, 8, 64, 3)])])
+        plan = fse.Plan(0.8, 0.5, 4096)
+        batch = fse.Batch(plan, b, 1, 256, 256)
+        rng = np.random.default_rng(5)
+        cands = np.stack([np.sort(rng.choice(4096, 256, replace=False)) for _ in range(len(b))]).astype(np.int16)
+        flags = np.zeros(len(b), np.int32)
+        out = (img * (av != 0)).to(torch.float32)
+        st = torch.full((len(b),), -1, dtype=torch.int32, device=dev)
+        stride = warm.trace_stride(batch, ir, fb)
+        tr = torch.zeros((len(b), stride * 16), dtype=torch.uint8, device=dev)
+        warm.warm_extrapolate(batch, img, av, out, st, torch.from_numpy(cands).to(dev),
+                              torch.from_numpy(flags).to(dev), 256, ir, fb, trace=tr)
+        torch.cuda.synchronize()
+        assert (st.cpu().numpy() == 0).all()
+        outs.append((out.cpu().numpy(), tr.cpu().numpy().view(fse.TRACE_DTYPE).reshape(len(b), stride), cands))
+    (o1, t1, c1), (o2, t2, c2) = outs
+    for i in range(n):
+        y0, x0 = int(blk["y0"][i]), int(blk["x0"][i])
+        sl = (0, slice(y0, y0 + 32), slice(x0, x0 + 32))
+        assert np.array_equal(o1[sl], o2[sl]), i
+        assert np.array_equal(t1[i, :ir], t2[i, :ir]), i
+    for i in range(0, n, 4):
+        r = parity.replay_warm_block(frame, avail, blk[i], 0.8, 0.5, t1[i], c1[i], ir, 0)
+        rr = r["restricted"]
+        assert rr["gap_violations"] == 0 and rr["coef_max"] <= parity.COEF_TOL, (i, rr)
+        y0, x0 = int(blk["y0"][i]), int(blk["x0"][i])
+        assert np.abs(o1[0, y0:y0 + 32, x0:x0 + 32] - r["values"]).max() < 0.05, i
