@@ -45,13 +45,13 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
 }
 
 // ------------------------------------------------------------------ patches
-// Network input of one 48x48 area: channel 0 = (s - mean_A(s)) / 64 on the
-// support area A, channel 1 = indicator of A; both 0 elsewhere.
-// Network input of block `b` (48x48 area) into `out` (2304 words: the two
-// BF16 channels of each pixel), by the 256 threads of a workgroup; `red` is
-// 8 words of LDS. Channel 0 = (s - mean over A)/64 on A, channel 1 = 1 on A.
+// Network input of block `b` (48x48 area) into `out` (one word per pixel:
+// the two BF16 channels; rows of 48 words, or rows of `grid` words from
+// (1, 1) on), by the 256 threads of a workgroup; `red` is 8 words of LDS.
+// Channel 0 = (s - mean over A)/64 on A, channel 1 = 1 on A.
 __device__ __forceinline__ void build_input(const uint8_t* img, const uint8_t* avail, int64_t pitch, int H, int W,
-                                            const fse_block_t& bd, uint32_t* out, uint32_t (*red)[4], int t) {
+                                            const fse_block_t& bd, uint32_t* out, uint32_t (*red)[4], int t,
+                                            int grid = 0) {
   const int bo = bd.border;
   const int ya = bd.y0 - bo, xa = bd.x0 - bo;
   const uint8_t* im = img + (int64_t)bd.frame * H * pitch;
@@ -87,7 +87,8 @@ __device__ __forceinline__ void build_input(const uint8_t* img, const uint8_t* a
 #pragma unroll
   for (int r = 0; r < 9; ++r) {
     const int e = t + 256 * r;
-    out[e] = ia[r] ? ((uint32_t)f2bf((sv[r] - mu) * (1.0f / 64.0f)) | (0x3f80u << 16)) : 0u;
+    const int o = grid ? (e / kIn + 1) * grid + e % kIn + 1 : e;  // dense rows, or the guarded grid
+    out[o] = ia[r] ? ((uint32_t)f2bf((sv[r] - mu) * (1.0f / 64.0f)) | (0x3f80u << 16)) : 0u;
   }
 }
 
@@ -102,33 +103,46 @@ __global__ __launch_bounds__(256) void k_patches(const uint8_t* img, const uint8
 }
 
 // ------------------------------------------------------------------ forward
-// 32-channel activations sit in LDS as four planes of 8 channels
-// (plane g, pixel p at element g*P*8 + p*8): the stride-2 reads of a layer
-// (consecutive lanes take input pixels two apart) then fall 32 bytes apart
-// and spread over all LDS banks, where the 64-byte pixels of a plain NHWC
-// layout would put them 128 bytes apart on a few banks.
-template <int P>
-__device__ __forceinline__ int plane_idx(int p, int c) { return (c >> 3) * (P * 8) + p * 8 + (c & 7); }
+// Layouts in LDS. A layer's input sits on a (H+1) x (H+1) grid whose row 0
+// and column 0 are zero, the pixel (y, x) at (y+1, x+1): the taps of a 3x3
+// stride-2 convolution with padding 1 then never leave the grid, and every
+// A-operand read is a per-lane base plus a compile-time offset. The network
+// input (2 channels) is one 32-bit word per grid point; 32-channel
+// activations are four planes of 8 channels (16 bytes per grid point per
+// plane), so that the stride-2 reads of consecutive lanes fall 32 bytes
+// apart across the LDS banks.
+template <int G>
+__device__ __forceinline__ constexpr int plane_elems() { return G * G * 8; }
 
-// One 3x3 stride-2 convolution with bias and ReLU, activations in LDS
-// (NHWC, BF16), as an implicit GEMM: rows = output pixels, columns = the 32
-// output channels, depth = (tap, input channel). Each wave loads its
-// weight fragments for every depth step into registers once, then runs the
-// row tiles it owns (tile = wave, wave + 4, ...).
-template <int CIN, int HIN>
-__device__ __forceinline__ void conv_layer(const uint16_t* in, uint16_t* out, const uint16_t* w,
-                                           const uint16_t* bias, int t) {
-  constexpr int HO = HIN / 2, P = HO * HO, K = 9 * CIN, KP = (K + 15) / 16 * 16, KS = KP / 16;
-  constexpr int MT = (P + 31) / 32;
-  const int lane = t & 63, wave = t >> 6;
-  const int n = lane & 31;
-  const int kh = 8 * (lane >> 5);
-  uint4 bfr[KS];
+// Zero row 0 and column 0 of the four planes of a G x G grid.
+template <int G>
+__device__ __forceinline__ void zero_guard(uint16_t* buf, int t) {
+  constexpr int PER = 2 * G - 1;
+  for (int i = t; i < 4 * PER; i += 256) {
+    const int g = i / PER, j = i % PER;
+    const int px = j < G ? j : (j - G + 1) * G;
+    reinterpret_cast<uint4*>(buf + g * plane_elems<G>())[px] = make_uint4(0u, 0u, 0u, 0u);
+  }
+}
+
+// Weights of one layer as MFMA A fragments: lane l holds output channel
+// l & 31 and depth values 16 ks + 8 (l >> 5) .. + 8 of step ks, and the
+// biases of the output channels its accumulators hold (8 g + 4 (l >> 5) +
+// 0..3 for g = 0..3), as BF16.
+struct LayerW {
+  uint4 w[18];
+  uint2 b[4];
+};
+
+template <int CIN>
+__device__ __forceinline__ void load_layer(const uint16_t* w, const uint16_t* bias, LayerW& L, int lane) {
+  constexpr int K = 9 * CIN, KS = (K + 15) / 16;
+  const int n = lane & 31, h = lane >> 5;
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) {
-    const int k0 = ks * 16 + kh;
+    const int k0 = ks * 16 + 8 * h;
     if constexpr (CIN == kCh) {
-      bfr[ks] = *reinterpret_cast<const uint4*>(w + n * K + k0);
+      L.w[ks] = *reinterpret_cast<const uint4*>(w + n * K + k0);
     } else {
       uint32_t b4[4];
 #pragma unroll
@@ -138,141 +152,205 @@ __device__ __forceinline__ void conv_layer(const uint16_t* in, uint16_t* out, co
         const uint32_t hi = k + 1 < K ? w[n * K + k + 1] : 0u;
         b4[q] = lo | (hi << 16);
       }
-      bfr[ks] = make_uint4(b4[0], b4[1], b4[2], b4[3]);
+      L.w[ks] = make_uint4(b4[0], b4[1], b4[2], b4[3]);
     }
   }
-  const float bn = bf2f(bias[n]);
-  // A fragment of output-row tile `tile` for depth step ks (zero outside).
-  auto gather = [&](int tile, int ks) -> uint4 {
-    const int m = tile * 32 + (lane & 31);
-    const int oy = m / HO, ox = m % HO;
-    const bool mv = m < P;
-    const int k0 = ks * 16 + kh;
-    uint4 av = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int g = 0; g < 4; ++g) L.b[g] = *reinterpret_cast<const uint2*>(bias + 8 * g + 4 * h);
+}
+
+__device__ __forceinline__ uint32_t relu_pack(float a, float b) {
+  return (uint32_t)f2bf(fmaxf(a, 0.f)) | ((uint32_t)f2bf(fmaxf(b, 0.f)) << 16);
+}
+
+// One 3x3 stride-2 convolution with bias and ReLU as an implicit GEMM:
+// D[channel][pixel] = W[channel][depth] X[depth][pixel], depth = (tap,
+// input channel), pixels in tiles of 32 (tile = wave, wave + 4, ... run two
+// at a time). Each lane of the result holds one pixel and 16 output
+// channels, 4 consecutive ones per 8-channel plane, stored as one 8-byte
+// write per plane. The output goes to a guarded grid (PAD) or, for the last
+// layer, to an unguarded 3x3 planar buffer.
+template <int CIN, int HIN, bool PAD>
+__device__ __forceinline__ void conv_layer(const uint16_t* in, uint16_t* out, const LayerW& L, int t) {
+  constexpr int HO = HIN / 2, P = HO * HO, K = 9 * CIN, KS = (K + 15) / 16;
+  constexpr int MT = (P + 31) / 32;
+  constexpr int G = HIN + 1;            // input grid
+  constexpr int GO = HO + 1;            // output grid (PAD)
+  const int lane = t & 63, wave = t >> 6;
+  const int h = lane >> 5;              // which 8 of the 16 depth values of a step
+  // grid index of tap (0, 0) of the output pixel in column `lane & 31` of a
+  // tile (columns past the end repeat the last pixel; they are not stored)
+  auto base_of = [&](int tile) {
+    const int m = min(tile * 32 + (lane & 31), P - 1);
+    return 2 * (m / HO) * G + 2 * (m % HO);
+  };
+  auto gather = [&](int base, int ks) -> uint4 {
     if constexpr (CIN == kCh) {
-      const int tap = k0 >> 5, c0 = k0 & 31;
-      const int iy = 2 * oy - 1 + tap / 3, ix = 2 * ox - 1 + tap % 3;
-      if (mv && iy >= 0 && iy < HIN && ix >= 0 && ix < HIN)
-        av = *reinterpret_cast<const uint4*>(in + plane_idx<HIN * HIN>(iy * HIN + ix, c0));
+      // step ks: tap ks/2, input channels (ks & 1)*16 + 8h .. +8, i.e. plane (ks & 1)*2 + h
+      const int tap = ks >> 1;
+      const uint16_t* p = in + ((ks & 1) * 2 + h) * plane_elems<G>() + (base + (tap / 3) * G + tap % 3) * 8;
+      return *reinterpret_cast<const uint4*>(p);
     } else {
-      uint32_t a4[4] = {0u, 0u, 0u, 0u};
+      // step ks, word q: tap 8*ks + 4h + q (both input channels), zero past tap 8
+      const uint32_t* gw = reinterpret_cast<const uint32_t*>(in);
+      uint32_t a4[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int k = k0 + 2 * q;
-        if (k < K) {
-          const int tap = k / CIN;
-          const int iy = 2 * oy - 1 + tap / 3, ix = 2 * ox - 1 + tap % 3;
-          if (mv && iy >= 0 && iy < HIN && ix >= 0 && ix < HIN)
-            a4[q] = *reinterpret_cast<const uint32_t*>(in + (iy * HIN + ix) * CIN);
-        }
+        const int t0 = 8 * ks + q, t1 = 8 * ks + 4 + q;  // the tap for h = 0 and h = 1
+        const int o0 = t0 < 9 ? (t0 / 3) * G + t0 % 3 : 0;
+        const int o1 = t1 < 9 ? (t1 / 3) * G + t1 % 3 : 0;
+        const uint32_t v = gw[base + (h ? o1 : o0)];
+        a4[q] = (h ? t1 < 9 : t0 < 9) ? v : 0u;
       }
-      av = make_uint4(a4[0], a4[1], a4[2], a4[3]);
+      return make_uint4(a4[0], a4[1], a4[2], a4[3]);
     }
-    return av;
   };
   auto store = [&](int tile, const f32x16& acc) {
+    const int p = tile * 32 + (lane & 31);
+    if (p >= P) return;
+    const int px = PAD ? (p / HO + 1) * GO + p % HO + 1 : p;
+    constexpr int PE = PAD ? plane_elems<GO>() : P * 8;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int p = tile * 32 + drow(i, lane);
-      if (p < P) out[plane_idx<P>(p, n)] = f2bf(fmaxf(acc[i] + bn, 0.f));
+    for (int g = 0; g < 4; ++g) {
+      const uint2 bb = L.b[g];
+      const uint2 v = make_uint2(relu_pack(acc[4 * g] + bf2f(bb.x & 0xffff), acc[4 * g + 1] + bf2f(bb.x >> 16)),
+                                 relu_pack(acc[4 * g + 2] + bf2f(bb.y & 0xffff), acc[4 * g + 3] + bf2f(bb.y >> 16)));
+      *reinterpret_cast<uint2*>(out + g * PE + px * 8 + 4 * h) = v;
     }
   };
-  // Tiles wave, wave+4, ... taken two at a time: two independent MFMA
-  // chains per wave.
   for (int tile = wave; tile < MT; tile += 8) {
     const int tile2 = tile + 4;
+    const int b1 = base_of(tile);
     f32x16 acc = {}, acc2 = {};
     if (tile2 < MT) {
+      const int b2 = base_of(tile2);
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        const uint4 a1 = gather(tile, ks), a2 = gather(tile2, ks);
-        acc = mfma(a1, bfr[ks], acc);
-        acc2 = mfma(a2, bfr[ks], acc2);
+        const uint4 a1 = gather(b1, ks), a2 = gather(b2, ks);
+        acc = mfma(L.w[ks], a1, acc);
+        acc2 = mfma(L.w[ks], a2, acc2);
       }
       store(tile, acc);
       store(tile2, acc2);
     } else {
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) acc = mfma(gather(tile, ks), bfr[ks], acc);
+      for (int ks = 0; ks < KS; ++ks) acc = mfma(L.w[ks], gather(b1, ks), acc);
       store(tile, acc);
     }
   }
 }
 
-template <int ELEMS>
-__device__ __forceinline__ void copy_act(const uint16_t* src, uint16_t* dst, int t) {
-  static_assert(ELEMS % 8 == 0, "16-byte copies");
-  for (int i = t; i < ELEMS / 8; i += 256)
-    reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
-}
-
-// A planar 32-channel activation of P pixels to NHWC in global memory.
-template <int P>
+// A guarded planar 32-channel activation (H x H pixels) to NHWC in global
+// memory.
+template <int H>
 __device__ __forceinline__ void copy_act_nhwc(const uint16_t* src, uint16_t* dst, int t) {
-  for (int i = t; i < P * 4; i += 256) {
+  constexpr int G = H + 1;
+  for (int i = t; i < H * H * 4; i += 256) {
     const int px = i >> 2, g = i & 3;
-    reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[g * P + px];
+    const int y = px / H, x = px % H;
+    reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[g * G * G + (y + 1) * G + x + 1];
   }
 }
 
 // The whole convolution stack for one sample per workgroup, activations in
-// LDS; writes the 288 features and, for training, every activation. LDS is
-// two regions: X holds the input, then layer 2's output; Y holds layer 1's
-// output, then layers 3 and 4. The input is in X on entry.
-static_assert(kPatchElems == 12 * 12 * kCh, "input and layer-2 output share a region");
+// LDS; writes the 288 features and, for training, every activation (NHWC).
+// Two regions: X holds the input grid (49 x 49 words), then layer 2's
+// output grid; Y holds layer 1's output grid, then layer 3's and layer 4's
+// outputs. On entry the input grid (with its zero guard) is in X.
+constexpr int kGridIn = kIn + 1;                                     // 49
+constexpr int kXElems = 4 * 13 * 13 * 8;                             // layer-2 output grid, the larger user of X
+constexpr int kYElems = 4 * 25 * 25 * 8;                             // layer-1 output grid
+static_assert(kGridIn * kGridIn * 2 <= kXElems, "input grid fits region X");
+constexpr int kA4Off = 4 * 7 * 7 * 8;                                // layer-4 output after layer 3's grid
 
-__device__ __forceinline__ void conv_stack(uint16_t* X, uint16_t* Y, const uint16_t* prm, uint16_t* feat_row,
-                                           uint16_t* dst, int t) {
-  uint16_t* const a0 = X;
-  uint16_t* const a1 = Y;
-  uint16_t* const a2 = X;
-  uint16_t* const a3 = Y;
-  uint16_t* const a4 = Y + 6 * 6 * kCh;
-  conv_layer<2, 48>(a0, a1, prm + kOffW[0], prm + kOffB[0], t);
+// Number of 32-pixel tiles of the layer with input size HIN: the waves
+// below it run the layer and load its weights.
+constexpr int tiles_of(int hin) { return ((hin / 2) * (hin / 2) + 31) / 32; }
+
+// Weights of layers 1 and 2, loaded before the input is built so that
+// their latency overlaps it.
+__device__ __forceinline__ void load_first_layers(const uint16_t* prm, LayerW& L1, LayerW& L2, int t) {
+  const int lane = t & 63;
+  load_layer<2>(prm + kOffW[0], prm + kOffB[0], L1, lane);
+  load_layer<kCh>(prm + kOffW[1], prm + kOffB[1], L2, lane);
+}
+
+// Each later layer's weights are requested before the barrier that ends
+// the previous layer.
+__device__ __forceinline__ void conv_stack(uint16_t* X, uint16_t* Y, const uint16_t* prm, const LayerW& L1,
+                                           const LayerW& L2, uint16_t* feat_row, uint16_t* dst, int t) {
+  const int lane = t & 63, wave = t >> 6;
+  uint16_t* const a4 = Y + kA4Off;
+  conv_layer<2, 48, true>(X, Y, L1, t);
   __syncthreads();
-  if (dst) copy_act_nhwc<24 * 24>(a1, dst + kActOff[0], t);
-  conv_layer<kCh, 24>(a1, a2, prm + kOffW[1], prm + kOffB[1], t);
+  if (dst) copy_act_nhwc<24>(Y, dst + kActOff[0], t);
+  zero_guard<13>(X, t);  // the input grid is no longer read
+  conv_layer<kCh, 24, true>(Y, X, L2, t);
+  LayerW L3;
+  if (wave < tiles_of(12)) load_layer<kCh>(prm + kOffW[2], prm + kOffB[2], L3, lane);
   __syncthreads();
-  if (dst) copy_act_nhwc<12 * 12>(a2, dst + kActOff[1], t);
-  conv_layer<kCh, 12>(a2, a3, prm + kOffW[2], prm + kOffB[2], t);
+  if (dst) copy_act_nhwc<12>(X, dst + kActOff[1], t);
+  zero_guard<7>(Y, t);   // layer 1's grid is no longer read
+  conv_layer<kCh, 12, true>(X, Y, L3, t);
+  LayerW L4;
+  if (wave < tiles_of(6)) load_layer<kCh>(prm + kOffW[3], prm + kOffB[3], L4, lane);
   __syncthreads();
-  if (dst) copy_act_nhwc<6 * 6>(a3, dst + kActOff[2], t);
-  conv_layer<kCh, 6>(a3, a4, prm + kOffW[3], prm + kOffB[3], t);
+  if (dst) copy_act_nhwc<6>(Y, dst + kActOff[2], t);
+  conv_layer<kCh, 6, false>(Y, a4, L4, t);
   __syncthreads();
   for (int i = t; i < kFeat; i += 256) {
-    const uint16_t v = a4[plane_idx<9>(i / kCh, i % kCh)];
+    const int px = i / kCh, c = i % kCh;
+    const uint16_t v = a4[(c >> 3) * (9 * 8) + px * 8 + (c & 7)];
     feat_row[i] = v;
     if (dst) dst[kActOff[3] + i] = v;
   }
 }
 
-__global__ __launch_bounds__(256) void k_forward(const uint16_t* x, int B, const uint16_t* prm, uint16_t* feats,
+// Zero guard (row 0, column 0) of the 49 x 49 input grid of words.
+__device__ __forceinline__ void zero_input_guard(uint32_t* grid, int t) {
+  for (int i = t; i < 2 * kGridIn - 1; i += 256) grid[i < kGridIn ? i : (i - kGridIn + 1) * kGridIn] = 0u;
+}
+
+// Three workgroups per compute unit (the LDS allows three): at most 168
+// registers per lane.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_forward(const uint16_t* x, int B, const uint16_t* prm, uint16_t* feats,
                                                  uint16_t* acts) {
-  __shared__ __align__(16) uint16_t X[kPatchElems];
-  __shared__ __align__(16) uint16_t Y[24 * 24 * kCh];
+  __shared__ __align__(16) uint16_t X[kXElems];
+  __shared__ __align__(16) uint16_t Y[kYElems];
   const int b = blockIdx.x;
   if (b >= B) return;
   const int t = threadIdx.x;
-  copy_act<kPatchElems>(x + (int64_t)b * kPatchElems, X, t);
+  uint32_t* const grid = reinterpret_cast<uint32_t*>(X);
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(x + (int64_t)b * kPatchElems);
+  for (int e = t; e < kIn * kIn; e += 256) grid[(e / kIn + 1) * kGridIn + e % kIn + 1] = src[e];
+  LayerW L1, L2;
+  load_first_layers(prm, L1, L2, t);
+  zero_input_guard(grid, t);
+  zero_guard<25>(Y, t);
   __syncthreads();
-  conv_stack(X, Y, prm, feats + (int64_t)b * kFeat, acts ? acts + (int64_t)b * kActElems : nullptr, t);
+  conv_stack(X, Y, prm, L1, L2, feats + (int64_t)b * kFeat, acts ? acts + (int64_t)b * kActElems : nullptr, t);
 }
 
 // The same with the input of block b built in LDS straight from the frames;
 // the features go to row orig[b].
-__global__ __launch_bounds__(256) void k_forward_blocks(const uint8_t* img, const uint8_t* avail, int64_t pitch,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_forward_blocks(const uint8_t* img, const uint8_t* avail, int64_t pitch,
                                                         int H, int W, const fse_block_t* blocks,
                                                         const int32_t* orig, int n, const uint16_t* prm,
                                                         uint16_t* feats) {
-  __shared__ __align__(16) uint16_t X[kPatchElems];
-  __shared__ __align__(16) uint16_t Y[24 * 24 * kCh];
+  __shared__ __align__(16) uint16_t X[kXElems];
+  __shared__ __align__(16) uint16_t Y[kYElems];
   __shared__ uint32_t red[2][4];
   const int b = blockIdx.x;
   if (b >= n) return;
   const int t = threadIdx.x;
-  build_input(img, avail, pitch, H, W, blocks[b], reinterpret_cast<uint32_t*>(X), red, t);
+  uint32_t* const grid = reinterpret_cast<uint32_t*>(X);
+  LayerW L1, L2;
+  load_first_layers(prm, L1, L2, t);
+  build_input(img, avail, pitch, H, W, blocks[b], grid, red, t, kGridIn);
+  zero_input_guard(grid, t);
+  zero_guard<25>(Y, t);
   __syncthreads();
-  conv_stack(X, Y, prm, feats + (int64_t)orig[b] * kFeat, nullptr, t);
+  conv_stack(X, Y, prm, L1, L2, feats + (int64_t)orig[b] * kFeat, nullptr, t);
 }
 
 // ------------------------------------------------------------------ GEMM
