@@ -38,6 +38,10 @@ struct fse_cnn_s {
   float* v = nullptr;
   uint16_t* work = nullptr;  // BF16 working copy used by every kernel
   uint16_t* feats = nullptr; // [max_batch][288]
+  // inference head: features and head weights in fragment layout
+  uint16_t* feats_frag = nullptr;  // [ceil(max_batch / 32) * 32][288]
+  uint16_t* head_frag = nullptr;   // [4096][288]
+  bool head_stale = true;          // `work` changed since head_frag was made
   // training scratch, allocated on the first backward call
   uint16_t* acts = nullptr;   // [max_batch][kActElems]
   float* dlog = nullptr;      // [B][4096]
@@ -59,7 +63,7 @@ struct fse_cnn_s {
 
 namespace {
 void free_net(fse_cnn_s* n) {
-  void* ptrs[] = {n->master, n->grad, n->m, n->v, n->work, n->feats, n->acts, n->dlog, n->dlog_b,
+  void* ptrs[] = {n->master, n->grad, n->m, n->v, n->work, n->feats, n->feats_frag, n->head_frag, n->acts, n->dlog, n->dlog_b,
                   n->dlog_t, n->feat_t, n->head_t, n->w_t, n->da, n->dz, n->dz_b, n->dz_t, n->col,
                   n->col_t, n->dcol};
   for (void* p : ptrs) (void)hipFree(p);
@@ -105,7 +109,9 @@ extern "C" fse_status_t fse_cnn_create(int32_t max_batch, uint64_t seed, fse_cnn
   }
   const size_t P = (size_t)kNumParams;
   if (!dalloc(&n->master, P) || !dalloc(&n->grad, P) || !dalloc(&n->m, P) || !dalloc(&n->v, P) ||
-      !dalloc(&n->work, P) || !dalloc(&n->feats, (size_t)max_batch * kFeat)) {
+      !dalloc(&n->work, P) || !dalloc(&n->feats, (size_t)max_batch * kFeat) ||
+      !dalloc(&n->feats_frag, (size_t)(max_batch + 31) / 32 * 32 * kFeat) ||
+      !dalloc(&n->head_frag, (size_t)kBins * kFeat)) {
     free_net(n);
     return cfail(FSE_ERR_OOM, "hipMalloc failed (parameters)");
   }
@@ -146,6 +152,7 @@ extern "C" fse_status_t fse_cnn_set_params(fse_cnn_t net, const float* h_params)
       f32_to_bf16(net->master, (int64_t)P, net->work, nullptr) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess)
     return cfail(FSE_ERR_HIP, "parameter upload failed");
+  net->head_stale = true;
   return FSE_OK;
 }
 
@@ -191,9 +198,13 @@ fse_status_t net_forward_blocks(fse_cnn_t net, const uint8_t* img, const uint8_t
   if (n > net->max_batch) return cfail(FSE_ERR_INVALID_ARG, "more blocks than the network's max_batch");
   if (!check_device(net)) return cfail(FSE_ERR_INVALID_ARG, "network was created on another device");
   if (n == 0) return FSE_OK;
-  if (forward_blocks(img, avail, pitch, H, W, blocks, orig, n, net->work, net->feats, s) != hipSuccess ||
-      gemm_nt(net->feats, kFeat, net->work + kOffHeadW, kFeat, d_logits, kBins, net->work + kOffHeadB, n, kBins,
-              kFeat, s) != hipSuccess)
+  if (net->head_stale) {
+    if (permute_head(net->work + kOffHeadW, net->head_frag, s) != hipSuccess)
+      return cfail(FSE_ERR_HIP, "kernel launch failed");
+    net->head_stale = false;
+  }
+  if (forward_blocks(img, avail, pitch, H, W, blocks, orig, n, net->work, net->feats_frag, s) != hipSuccess ||
+      head_frag(net->feats_frag, net->head_frag, net->work + kOffHeadB, d_logits, n, s) != hipSuccess)
     return cfail(FSE_ERR_HIP, "kernel launch failed");
   net->kept = false;
   return FSE_OK;
@@ -255,6 +266,7 @@ extern "C" fse_status_t fse_cnn_adam(fse_cnn_t net, float lr, float beta1, float
   if (adam(net->master, net->grad, net->m, net->v, net->work, kNumParams, lr, beta1, beta2, eps, c1, c2,
            reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
     return cfail(FSE_ERR_HIP, "kernel launch failed");
+  net->head_stale = true;
   return FSE_OK;
 }
 

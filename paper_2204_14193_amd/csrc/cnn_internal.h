@@ -17,6 +17,7 @@ constexpr int kIn = 48;
 constexpr int kFeat = 3 * 3 * kCh;  // 288
 constexpr int kBins = 4096;
 constexpr int kPatchElems = kIn * kIn * 2;
+constexpr int kSteps = kFeat / 16;  // MFMA depth steps of the head product
 
 // Offsets (elements) of the parameter tensors in the flat parameter vector:
 // conv weights [32][3][3][Cin], biases [32], head weight [4096][288], bias.
@@ -46,10 +47,19 @@ fse_status_t net_forward_blocks(fse_cnn_t net, const uint8_t* img, const uint8_t
                                 int32_t W, const void* blocks, const int32_t* orig, int32_t n, float* d_logits,
                                 hipStream_t s);
 // Network inputs built from the frames for the n blocks of a batch (class
-// order, features to row orig[b]) and the convolution stack, no activations.
+// order) and the convolution stack, no activations; the features go to row
+// orig[b] of `feats` in fragment layout (rows in blocks of 32, see
+// head_frag).
 hipError_t forward_blocks(const uint8_t* img, const uint8_t* avail, int64_t pitch, int32_t H, int32_t W,
                           const void* blocks, const int32_t* orig, int32_t n, const uint16_t* prm, uint16_t* feats,
                           hipStream_t s);
+// Head weights (row-major [4096][288] BF16) to fragment layout (same size).
+hipError_t permute_head(const uint16_t* w, uint16_t* frag, hipStream_t s);
+// logits[M x 4096] = features (fragment layout, ceil(M/32) row blocks) x
+// head weights (fragment layout)^T + bias; bitwise equal to gemm_nt on the
+// row-major operands.
+hipError_t head_frag(const uint16_t* feats_frag, const uint16_t* w_frag, const uint16_t* bias, float* logits, int32_t M,
+                     hipStream_t s);
 // C[M x N] (FP32, ldc) = A[M x K] * B[N x K]^T (+ bias[N]), A and B BF16 with
 // K contiguous; K % 16 == 0, lda and ldb multiples of 8.
 hipError_t gemm_nt(const uint16_t* A, int lda, const uint16_t* B, int ldb, float* C, int ldc,

@@ -276,9 +276,10 @@ __device__ __forceinline__ void load_first_layers(const uint16_t* prm, LayerW& L
 }
 
 // Each later layer's weights are requested before the barrier that ends
-// the previous layer.
-__device__ __forceinline__ void conv_stack(uint16_t* X, uint16_t* Y, const uint16_t* prm, const LayerW& L1,
-                                           const LayerW& L2, uint16_t* feat_row, uint16_t* dst, int t) {
+// the previous layer. Returns the 3x3x32 features (planar: 8-channel plane
+// g of pixel px at 72 g + 8 px), complete in LDS for every thread.
+__device__ __forceinline__ const uint16_t* conv_stack(uint16_t* X, uint16_t* Y, const uint16_t* prm,
+                                                      const LayerW& L1, const LayerW& L2, uint16_t* dst, int t) {
   const int lane = t & 63, wave = t >> 6;
   uint16_t* const a4 = Y + kA4Off;
   conv_layer<2, 48, true>(X, Y, L1, t);
@@ -298,12 +299,7 @@ __device__ __forceinline__ void conv_stack(uint16_t* X, uint16_t* Y, const uint1
   if (dst) copy_act_nhwc<6>(Y, dst + kActOff[2], t);
   conv_layer<kCh, 6, false>(Y, a4, L4, t);
   __syncthreads();
-  for (int i = t; i < kFeat; i += 256) {
-    const int px = i / kCh, c = i % kCh;
-    const uint16_t v = a4[(c >> 3) * (9 * 8) + px * 8 + (c & 7)];
-    feat_row[i] = v;
-    if (dst) dst[kActOff[3] + i] = v;
-  }
+  return a4;
 }
 
 // Zero guard (row 0, column 0) of the 49 x 49 input grid of words.
@@ -328,11 +324,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
   zero_input_guard(grid, t);
   zero_guard<25>(Y, t);
   __syncthreads();
-  conv_stack(X, Y, prm, L1, L2, feats + (int64_t)b * kFeat, acts ? acts + (int64_t)b * kActElems : nullptr, t);
+  uint16_t* const dst = acts ? acts + (int64_t)b * kActElems : nullptr;
+  const uint16_t* a4 = conv_stack(X, Y, prm, L1, L2, dst, t);
+  for (int i = t; i < kFeat; i += 256) {
+    const int px = i / kCh, c = i % kCh;
+    const uint16_t v = a4[(c >> 3) * (9 * 8) + px * 8 + (c & 7)];
+    feats[(int64_t)b * kFeat + i] = v;
+    if (dst) dst[kActOff[3] + i] = v;
+  }
 }
 
 // The same with the input of block b built in LDS straight from the frames;
-// the features go to row orig[b].
+// the features go to row orig[b] of a matrix in fragment layout (see
+// k_head_frag).
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_forward_blocks(const uint8_t* img, const uint8_t* avail, int64_t pitch,
                                                         int H, int W, const fse_block_t* blocks,
                                                         const int32_t* orig, int n, const uint16_t* prm,
@@ -350,7 +354,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
   zero_input_guard(grid, t);
   zero_guard<25>(Y, t);
   __syncthreads();
-  conv_stack(X, Y, prm, L1, L2, feats + (int64_t)orig[b] * kFeat, nullptr, t);
+  const uint16_t* a4 = conv_stack(X, Y, prm, L1, L2, nullptr, t);
+  // features to row r = orig[b] of the fragment layout: 8 features (one
+  // 8-channel plane of one pixel) per 16-byte piece
+  if (t < kFeat / 8) {
+    const int r = orig[b], s16 = t >> 1, h = t & 1;
+    const uint4 v = *reinterpret_cast<const uint4*>(a4 + (t & 3) * 72 + (t >> 2) * 8);
+    reinterpret_cast<uint4*>(feats)[((int64_t)(r >> 5) * kSteps + s16) * 64 + h * 32 + (r & 31)] = v;
+  }
 }
 
 // ------------------------------------------------------------------ GEMM
@@ -455,6 +466,81 @@ __global__ __launch_bounds__(256) void k_gemm_nt_t(const uint16_t* A, int lda, c
         const int row = tm + 32 * i + drow(r, lane);
         if (row < M) C[(int64_t)row * ldc + col] = acc[i][j][r] + bb;
       }
+  }
+}
+
+// ------------------------------------------------------------------ head
+// Fragment layout of a matrix with 288 columns (the depth of the head
+// product): rows in blocks of 32, and for block rb, depth step s (16
+// columns) and lane l, the 16 bytes that lane l of an MFMA operand reads in
+// step s: row 32 rb + (l & 31), columns 16 s + 8 (l >> 5) .. + 8, at uint4
+// index (rb * 18 + s) * 64 + l. Each fragment read of a wave is then one
+// contiguous 1 KiB.
+
+// Head weights [4096][288] (row-major) to fragment layout.
+__global__ __launch_bounds__(256) void k_permute_head(const uint16_t* w, uint4* frag) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= kBins / 32 * kSteps * 64) return;
+  const int l = i & 63, s16 = (i >> 6) % kSteps, cb = (i >> 6) / kSteps;
+  frag[i] = *reinterpret_cast<const uint4*>(w + (int64_t)(cb * 32 + (l & 31)) * kFeat + 16 * s16 + 8 * (l >> 5));
+}
+
+// logits[M x 4096] (FP32, row-major) = F W^T + bias with F [M x 288] and the
+// head weights W [4096 x 288] both in fragment layout (F with
+// ceil(M / 32) row blocks). Workgroup tile 128 x 128, each wave 64 x 64
+// (2 x 2 MFMA tiles of 32 x 32); the same arithmetic per element as
+// k_gemm_nt (one MFMA chain over the depth in steps of 16, then the bias).
+__global__ __launch_bounds__(256) void k_head_frag(const uint4* F, const uint4* Wf, const uint16_t* bias,
+                                                   float* C, int M) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int rb0 = blockIdx.x * 4 + (wave & 1) * 2;   // row blocks rb0, rb0 + 1
+  const int cb0 = blockIdx.y * 4 + (wave >> 1) * 2;  // column blocks
+  const int nrb = (M + 31) >> 5;
+  if (rb0 >= nrb) return;
+  const int rb1 = min(rb0 + 1, nrb - 1);             // a block past the end repeats the last (never stored)
+  const uint4* pa0 = F + (int64_t)rb0 * kSteps * 64 + lane;
+  const uint4* pa1 = F + (int64_t)rb1 * kSteps * 64 + lane;
+  const uint4* pb0 = Wf + (int64_t)cb0 * kSteps * 64 + lane;
+  const uint4* pb1 = pb0 + kSteps * 64;
+  f32x16 acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};
+  uint4 a0[2], b0[2], a1[2], b1[2];
+  auto load = [&](uint4 (&av)[2], uint4 (&bv)[2], int st) {
+    const int o = min(st, kSteps - 1) * 64;
+    av[0] = pa0[o];
+    av[1] = pa1[o];
+    bv[0] = pb0[o];
+    bv[1] = pb1[o];
+  };
+  auto mma = [&](const uint4 (&av)[2], const uint4 (&bv)[2]) {
+    acc00 = mfma(av[0], bv[0], acc00);
+    acc01 = mfma(av[0], bv[1], acc01);
+    acc10 = mfma(av[1], bv[0], acc10);
+    acc11 = mfma(av[1], bv[1], acc11);
+  };
+  load(a0, b0, 0);
+#pragma unroll
+  for (int st = 0; st < kSteps; st += 2) {
+    load(a1, b1, st + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(a0, b0);
+    load(a0, b0, st + 2);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(a1, b1);
+  }
+  auto store = [&](const f32x16& acc, int rb, int cb) {
+    const int col = cb * 32 + (lane & 31);
+    const float bb = bf2f(bias[col]);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = rb * 32 + drow(r, lane);
+      if (row < M) C[(int64_t)row * kBins + col] = acc[r] + bb;
+    }
+  };
+  store(acc00, rb0, cb0);
+  store(acc01, rb0, cb0 + 1);
+  if (rb0 + 1 < nrb) {
+    store(acc10, rb0 + 1, cb0);
+    store(acc11, rb0 + 1, cb0 + 1);
   }
 }
 
@@ -785,6 +871,21 @@ hipError_t forward_blocks(const uint8_t* img, const uint8_t* avail, int64_t pitc
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_forward_blocks, dim3(n), dim3(256), 0, s, img, avail, pitch, H, W,
                      reinterpret_cast<const fse_block_t*>(blocks), orig, n, prm, feats);
+  return hipGetLastError();
+}
+
+hipError_t permute_head(const uint16_t* w, uint16_t* frag, hipStream_t s) {
+  hipLaunchKernelGGL(k_permute_head, dim3(kBins / 32 * kSteps * 64 / 256), dim3(256), 0, s, w,
+                     reinterpret_cast<uint4*>(frag));
+  return hipGetLastError();
+}
+
+hipError_t head_frag(const uint16_t* feats_frag, const uint16_t* w_frag, const uint16_t* bias, float* logits, int32_t M,
+                     hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_head_frag, dim3((M + 127) / 128, kBins / 128), dim3(256), 0, s,
+                     reinterpret_cast<const uint4*>(feats_frag), reinterpret_cast<const uint4*>(w_frag), bias, logits,
+                     M);
   return hipGetLastError();
 }
 
