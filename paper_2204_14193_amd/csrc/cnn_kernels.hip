@@ -743,35 +743,24 @@ __device__ __forceinline__ uint32_t block_exscan(uint32_t x, uint32_t* slots, in
   return before + inc - x;
 }
 
-// Exact selection of the K-th largest order key T: its top kPrefixBits bits
-// by bisection over all keys, then the remaining bits by bisection over the
-// keys sharing that prefix only (compacted into LDS).
+// Number of keys >= c among m keys in LDS, counted by one wave.
+__device__ __forceinline__ uint32_t wave_count_ge(const uint32_t* v, uint32_t m, uint32_t c, int lane) {
+  uint32_t n = 0;
+  for (uint32_t i0 = 0; i0 < m; i0 += 64) {
+    const uint32_t i = i0 + lane;
+    n += (uint32_t)__builtin_popcountll(__ballot(i < m && v[i < m ? i : 0] >= c));
+  }
+  return n;
+}
+
+// Exact K-th largest order key T of the row, by bisection with block-wide
+// counts: its top kPrefixBits bits over all keys, then the remaining bits
+// over the keys sharing that prefix (compacted into bk). Every thread
+// returns T.
 constexpr int kPrefixBits = 14;
 
-__global__ __launch_bounds__(256) void k_topk(const float* logits, int B, int K, int16_t* cand, int32_t* flags) {
-  __shared__ uint32_t slots[8];
-  __shared__ uint32_t bk[kBins];
-  const int b = blockIdx.x;
-  if (b >= B) return;
-  const int t = threadIdx.x;
-  uint32_t key[16];
-  uint32_t nan = 0;
-  const float4* src = reinterpret_cast<const float4*>(logits + (int64_t)b * kBins + 16 * t);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const float4 v = src[q];
-    const float vv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      nan |= (vv[r] != vv[r]) ? 1u : 0u;
-      key[4 * q + r] = order_key(vv[r]);
-    }
-  }
-  int par = 0;
-  const bool any_nan = block_sum(nan, slots, par) != 0;
-  // T = the largest key value with #(key >= T) >= K: prefix bits first.
-  // Counts are taken with ballots and scalar popcounts (wave totals), then
-  // summed over the four waves.
+__device__ __forceinline__ uint32_t threshold_by_bisection(const uint32_t (&key)[16], uint32_t K, uint32_t* slots,
+                                                           int& par, uint32_t* bk, int t) {
   auto count_ge = [&](uint32_t c) {
     uint32_t n = 0;
 #pragma unroll
@@ -789,44 +778,212 @@ __global__ __launch_bounds__(256) void k_topk(const float* logits, int B, int K,
   uint32_t T = 0;
   for (int bit = 31; bit >= 32 - kPrefixBits; --bit) {
     const uint32_t c = T | (1u << bit);
-    if (block_total(count_ge(c)) >= (uint32_t)K) T = c;
+    if (block_total(count_ge(c)) >= K) T = c;
   }
-  {
-    // keys with T's prefix; those above the prefix are all selected
-    const uint32_t hi = T | ((1u << (32 - kPrefixBits)) - 1u);
-    uint32_t above = 0, inb = 0;
+  // keys with T's prefix; those above the prefix are all selected
+  const uint32_t hi = T | ((1u << (32 - kPrefixBits)) - 1u);
+  uint32_t above = 0, inb = 0;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      above += key[j] > hi;
-      inb += key[j] >= T && key[j] <= hi;
+  for (int j = 0; j < 16; ++j) {
+    above += key[j] > hi;
+    inb += key[j] >= T && key[j] <= hi;
+  }
+  const uint32_t need = K - block_sum(above, slots, par);
+  uint32_t m = 0;
+  uint32_t pos = block_exscan(inb, slots, par, m);
+#pragma unroll
+  for (int j = 0; j < 16; ++j)
+    if (key[j] >= T && key[j] <= hi) bk[pos++] = key[j];
+  __syncthreads();
+  for (int bit = 31 - kPrefixBits; bit >= 0; --bit) {
+    const uint32_t c = T | (1u << bit);
+    uint32_t n = 0;
+    for (uint32_t i0 = 0; i0 < m; i0 += 256) {
+      const uint32_t i = i0 + t;
+      n += (uint32_t)__builtin_popcountll(__ballot(i < m && bk[i < m ? i : 0] >= c));
     }
-    const uint32_t need = (uint32_t)K - block_sum(above, slots, par);
+    if (block_total(n) >= need) T = c;
+  }
+  return T;
+}
+
+// Sort the 256 values v[j] of lane l (element 4 l + j) of a wave into
+// descending order (bitonic network; partners in other lanes via lane
+// shuffles).
+__device__ __forceinline__ void wave_sort256_desc(uint32_t (&v)[4], int lane) {
+#pragma unroll
+  for (int k = 2; k <= 256; k <<= 1) {
+#pragma unroll
+    for (int d = k >> 1; d > 0; d >>= 1) {
+      if (d >= 4) {
+        const int ld = d >> 2;
+        const bool lower = (lane & ld) == 0;  // this lane holds the lower index of each pair
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int e = 4 * lane + j;
+          const bool desc = (e & k) == 0;      // this block of the merge sorts descending
+          const uint32_t o = (uint32_t)__shfl_xor((int)v[j], ld);
+          // the lower index keeps the larger value in a descending block
+          const bool keep_max = lower == desc;
+          v[j] = keep_max ? max(v[j], o) : min(v[j], o);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if ((j & d) != 0) continue;
+          const int e = 4 * lane + j;
+          const bool desc = (e & k) == 0;
+          const uint32_t a = v[j], b = v[j + d];
+          v[j] = desc ? max(a, b) : min(a, b);
+          v[j + d] = desc ? min(a, b) : max(a, b);
+        }
+      }
+    }
+  }
+}
+
+// Element i (0-based, uniform) of a wave's 256 values held as above.
+__device__ __forceinline__ uint32_t wave_elem256(const uint32_t (&v)[4], int i) {
+  const int j = i & 3;
+  const uint32_t x = j == 0 ? v[0] : j == 1 ? v[1] : j == 2 ? v[2] : v[3];
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, i >> 2);
+}
+
+// Top K of each row of 4096 logits (ties to the lowest bin), as the bins in
+// increasing order; flags[b] = 1 if the row holds a NaN. Exact selection of
+// the K-th largest order key T in a few block-wide steps:
+//  1. a sample of 256 keys (one per thread, spread over the columns of the
+//     64 x 64 bin grid), sorted by one wave, brackets T between two sample
+//     order statistics, K/16 -+ (3 standard deviations of a binomial count
+//     + 2) in rank;
+//  2. one pass counts the keys above the bracket and in it; if the bracket
+//     holds the K-th key (it almost always does), the keys in it are
+//     compacted and one wave finds T among them by bisection;
+//  3. otherwise T comes from a bisection over all keys.
+// The result depends only on the keys, never on the sample.
+constexpr int kBracketRegs = 10;  // brackets of up to 640 keys are searched in registers
+
+__global__ __launch_bounds__(256) void k_topk(const float* logits, int B, int K, int16_t* cand, int32_t* flags) {
+  __shared__ uint32_t slots[8];
+  __shared__ uint32_t red[3][4];
+  __shared__ uint32_t bc[2];
+  __shared__ uint32_t bk[kBins];
+  const int b = blockIdx.x;
+  if (b >= B) return;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  uint32_t key[16];
+  uint32_t nan = 0;
+  const float4* src = reinterpret_cast<const float4*>(logits + (int64_t)b * kBins + 16 * t);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float4 v = src[q];
+    const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      nan |= (vv[r] != vv[r]) ? 1u : 0u;
+      key[4 * q + r] = order_key(vv[r]);
+    }
+  }
+  // 1. sample key: bin 16 t + ((t ^ (t >> 4)) & 15)
+  {
+    const int js = (t ^ (t >> 4)) & 15;
+    uint32_t sv = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) sv = j == js ? key[j] : sv;
+    bk[t] = sv;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    const float p = (float)K * (1.0f / kBins);
+    const int r = (K + 8) / 16;                                        // expected rank of T in the sample
+    const int mg = (int)(3.0f * sqrtf(256.0f * p * (1.0f - p))) + 2;   // margin
+    const int r_hi = r - mg, r_lo = r + mg;
+    uint32_t sv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) sv[j] = bk[4 * lane + j];
+    wave_sort256_desc(sv, lane);
+    // the rank-r sample (1-based) is element r - 1 of the sorted sample
+    const uint32_t qh = wave_elem256(sv, max(r_hi, 1) - 1), ql = wave_elem256(sv, min(r_lo, 256) - 1);
+    if (lane == 0) {
+      bc[0] = r_hi >= 1 ? qh : 0xffffffffu;  // no sample bound above: nothing is above the bracket
+      bc[1] = r_lo <= 256 ? ql : 0u;         // none below: every key is at or above it
+    }
+  }
+  __syncthreads();
+  const uint32_t t_hi = bc[0], t_lo = bc[1];
+  // 2. keys above the bracket, at or above its lower end, NaN flag
+  uint32_t n_gt = 0, n_ge = 0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    n_gt += key[j] > t_hi;
+    n_ge += key[j] >= t_lo;
+  }
+  n_gt = wave_sum_u32(n_gt);
+  n_ge = wave_sum_u32(n_ge);
+  nan = wave_sum_u32(nan);
+  if (lane == 0) {
+    red[0][wave] = n_gt;
+    red[1][wave] = n_ge;
+    red[2][wave] = nan;
+  }
+  __syncthreads();
+  const uint32_t c_gt = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+  const uint32_t c_ge = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  const bool any_nan = (red[2][0] | red[2][1] | red[2][2] | red[2][3]) != 0;
+  int par = 0;
+  uint32_t T;
+  if (c_gt < (uint32_t)K && (uint32_t)K <= c_ge) {
+    uint32_t inb = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) inb += key[j] >= t_lo && key[j] <= t_hi;
     uint32_t m = 0;
-    uint32_t pos = block_exscan(inb, slots, par, m);
+    uint32_t pos = block_exscan(inb, slots, par, m);  // m = c_ge - c_gt
 #pragma unroll
     for (int j = 0; j < 16; ++j)
-      if (key[j] >= T && key[j] <= hi) bk[pos++] = key[j];
+      if (key[j] >= t_lo && key[j] <= t_hi) bk[pos++] = key[j];
     __syncthreads();
-    for (int bit = 31 - kPrefixBits; bit >= 0; --bit) {
-      const uint32_t c = T | (1u << bit);
-      uint32_t n = 0;
-      for (uint32_t i0 = 0; i0 < m; i0 += 256) {
-        const uint32_t i = i0 + t;
-        n += (uint32_t)__builtin_popcountll(__ballot(i < m && bk[i < m ? i : 0] >= c));
+    if (wave == 0) {
+      // T in [t_lo, t_hi]: the bits above their highest differing bit are fixed
+      const uint32_t need = (uint32_t)K - c_gt;
+      const uint32_t d = t_lo ^ t_hi;
+      const int top = d ? 31 - __builtin_clz(d) : -1;
+      uint32_t v = top >= 31 ? 0u : (t_lo >> (top + 1)) << (top + 1);
+      if (m <= 64 * kBracketRegs) {
+        // the bracket in registers (0 pads: every tested value is >= 1)
+        uint32_t r[kBracketRegs];
+#pragma unroll
+        for (int i = 0; i < kBracketRegs; ++i) r[i] = (uint32_t)(lane + 64 * i) < m ? bk[lane + 64 * i] : 0u;
+        for (int bit = top; bit >= 0; --bit) {
+          const uint32_t c = v | (1u << bit);
+          uint32_t n = 0;
+#pragma unroll
+          for (int i = 0; i < kBracketRegs; ++i) n += r[i] >= c ? 1u : 0u;
+          if (wave_sum_u32(n) >= need) v = c;
+        }
+      } else {
+        for (int bit = top; bit >= 0; --bit) {
+          const uint32_t c = v | (1u << bit);
+          if (wave_count_ge(bk, m, c, lane) >= need) v = c;
+        }
       }
-      if (block_total(n) >= need) T = c;
+      if (lane == 0) bc[0] = v;
     }
+    __syncthreads();
+    T = bc[0];
+  } else {
+    T = threshold_by_bisection(key, (uint32_t)K, slots, par, bk, t);
   }
+  // output: greater keys, then ties at T from the lowest bins
   uint32_t gt = 0, eq = 0;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     gt += key[j] > T;
     eq += key[j] == T;
   }
-  uint32_t ngt = 0, neq = 0;
-  const uint32_t gt_before = block_exscan(gt, slots, par, ngt);
-  const uint32_t remaining = (uint32_t)K - ngt;  // ties at T to take, lowest bins first
-  const uint32_t eq_before = block_exscan(eq, slots, par, neq);
+  uint32_t tot = 0;
+  const uint32_t before = block_exscan((gt << 16) | eq, slots, par, tot);  // both counts < 2^16
+  const uint32_t gt_before = before >> 16, eq_before = before & 0xffffu;
+  const uint32_t remaining = (uint32_t)K - (tot >> 16);  // ties at T to take, lowest bins first
   // Ties taken before this thread and by it, written with min() only: a
   // subtraction guarded by a comparison was observed to be speculated with
   // a no-wrap flag that then let the optimiser drop the first min().

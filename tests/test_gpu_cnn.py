@@ -188,6 +188,35 @@ def test_topk_exact_with_ties_and_nan():
         assert np.array_equal(c[b], np.sort(order[:K])), b
 
 
+def test_topk_when_the_sample_misses_the_threshold():
+    """Rows whose sampled bins (one per thread: bin 16 t + ((t ^ (t >> 4)) & 15))
+    hold the largest values, so that the sample's bracket misses the K-th
+    key and the selection falls back to a bisection over all keys; K values
+    over the whole accepted range."""
+    import torch
+    from paper_2204_14193_amd import warm
+    _say("case topk fallback")
+    rng = np.random.default_rng(11)
+    t = np.arange(256)
+    sample_bins = 16 * t + ((t ^ (t >> 4)) & 15)
+    dev = torch.device("cuda:0")
+    for K in (1, 17, 255, 256, 300, 1000, 4095, 4096):
+        lg = rng.normal(size=(4, 4096)).astype(np.float32)
+        lg[0, sample_bins] = 10.0 + rng.random(256).astype(np.float32)   # sample far above the rest
+        lg[1, sample_bins] = -10.0 - rng.random(256).astype(np.float32)  # far below
+        lg[2, sample_bins] = 3.0                                         # tied block of the sample
+        t_ = torch.from_numpy(lg).to(dev)
+        cand = torch.full((4, K), -1, dtype=torch.int16, device=dev)
+        flags = torch.full((4,), -1, dtype=torch.int32, device=dev)
+        warm.topk(t_, K, cand, flags)
+        torch.cuda.synchronize()
+        c = cand.cpu().numpy()
+        assert flags.cpu().numpy().tolist() == [0, 0, 0, 0]
+        for b in range(4):
+            order = np.lexsort((np.arange(4096), -lg[b].astype(np.float64)))
+            assert np.array_equal(c[b], np.sort(order[:K])), (K, b)
+
+
 def _warm_case(ir=30, iters=20, fb=40, kc=256, n_blocks=12, extra_iters=None):
     """Warm-started FSE on n_blocks isolated blocks with synthetic candidate
     sets; block 3 is flagged (plain fallback). extra_iters: append one more
