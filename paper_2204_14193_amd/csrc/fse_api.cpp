@@ -84,6 +84,8 @@ struct fse_batch_s {
   std::vector<int32_t> t_kind, t_fft;
   int32_t t_count = 0;
   bool all_48 = false;                     // every area is 48 x 48 (network input size)
+  bool all_small_b = false;                // every B has at most 256 pixels (restricted kernel
+                                           // synthesises in its loop, no coefficient list)
 };
 
 extern "C" const char* fse_last_error(void) { return g_error; }
@@ -283,8 +285,12 @@ extern "C" fse_status_t fse_batch_create(fse_plan_t plan, const fse_block_t* h_b
     return h_blocks[x].iters > h_blocks[y].iters;
   });
   b->all_48 = true;
-  for (int32_t i = 0; i < n_blocks; ++i)
-    b->all_48 = b->all_48 && h_blocks[i].bh + 2 * h_blocks[i].border == 48 && h_blocks[i].bw + 2 * h_blocks[i].border == 48;
+  b->all_small_b = true;
+  for (int32_t i = 0; i < n_blocks; ++i) {
+    const fse_block_t& hb = h_blocks[i];
+    b->all_48 = b->all_48 && hb.bh + 2 * hb.border == 48 && hb.bw + 2 * hb.border == 48;
+    b->all_small_b = b->all_small_b && (int)hb.bh * hb.bw <= fse::kRestrictedInloopPixels;
+  }
   std::vector<fse_block_t> sorted(n_blocks);
   for (int32_t i = 0; i < n_blocks; ++i) {
     sorted[i] = h_blocks[order[i]];
@@ -583,7 +589,9 @@ extern "C" fse_status_t fse_warm_extrapolate_batch(fse_batch_t batch, const uint
     if (st != FSE_OK) return st;
     if (split) {
       const void* rk = fse::restricted_kernel(kc);
-      const size_t lds = fse::restricted_lds_bytes(restricted_iters);
+      // without coefficient lists (and, with one wave, without the
+      // cross-wave slots) a block needs 17 KB of LDS: nine per compute unit
+      const size_t lds = fse::restricted_lds_bytes(kc, restricted_iters, !batch->all_small_b);
       if (!rk) return fail(FSE_ERR_UNSUPPORTED, "no restricted kernel for this candidate count");
       if (hipFuncSetAttribute(rk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return fail(FSE_ERR_HIP, "hipFuncSetAttribute failed (LDS size)");

@@ -74,7 +74,11 @@ const void* restricted_kernel(int kc);
 
 // Dynamic LDS bytes of the restricted kernel for ir restricted iterations,
 // and its threads per workgroup.
-size_t restricted_lds_bytes(int ir);
+// Dynamic LDS of the restricted kernel for kc candidates; `lists` = room
+// for the per-block coefficient list, needed only by blocks with more than
+// kRestrictedInloopPixels pixels in B.
+size_t restricted_lds_bytes(int kc, int ir, bool lists);
+constexpr int kRestrictedInloopPixels = 256;
 int restricted_threads(int kc);
 
 // All compiled plain variants for F; returns their number, fills up to cap.

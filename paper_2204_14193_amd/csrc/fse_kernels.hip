@@ -764,8 +764,8 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   float2* const Wh = reinterpret_cast<float2*>(smem);  // kHalfRows x F
   float2* const tw = Wh + kHalfRows * F;                // F twiddles
-  int4* const xch = reinterpret_cast<int4*>(tw + F);   // 2 x NWB cross-wave argmax slots
-  float2* const cl_c = reinterpret_cast<float2*>(xch + 4);  // ir coefficients
+  int4* const xch = reinterpret_cast<int4*>(tw + F);   // 2 x NWB cross-wave argmax slots (two waves)
+  float2* const cl_c = reinterpret_cast<float2*>(xch + (NWB == 2 ? 4 : 0));  // ir coefficients
   int* const cl_idx = reinterpret_cast<int*>(cl_c + a.ir);
   const int t = threadIdx.x, lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -814,6 +814,7 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
   // same per-pixel order as the list-based synthesis after the loop, which
   // larger blocks use.
   constexpr int QI = 4 / NWB;
+  static_assert(NT * QI == kRestrictedInloopPixels, "in-loop synthesis bound known to the host");
   const UBlock bd = uniform_block(a.blocks + bi);
   const int np = bd.bh * bd.bw;
   const bool inloop = np <= NT * QI;
@@ -993,8 +994,9 @@ const void* restricted_kernel(int kc) {
 
 int restricted_threads(int kc) { return 64 * restricted_waves(kc); }
 
-size_t restricted_lds_bytes(int ir) {
-  return (size_t)kHalfRows * 64 * 8 + 64 * 8 + 4 * 16 + (size_t)ir * 12;
+size_t restricted_lds_bytes(int kc, int ir, bool lists) {
+  return (size_t)kHalfRows * 64 * 8 + 64 * 8 + (restricted_waves(kc) == 2 ? 4 * 16 : 0) +
+         (lists ? (size_t)ir * 12 : 0);
 }
 
 hipError_t launch_restricted(int kc, const ClassArgs& a, size_t lds, hipStream_t s) {
