@@ -100,6 +100,14 @@ __device__ __forceinline__ float readlane_f(float x, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
 }
 
+// Workgroup barrier that orders LDS accesses only: global loads issued
+// before it stay in flight (a full __syncthreads waits for them too).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ------------------------------------------------------------------ FFT
 // Forward DFT (exp(-j...)) of every row, then every column, of the F x F
 // buffer Z, as Stockham passes of radix 8, 4 or 2. Each pass loads its
@@ -170,7 +178,7 @@ __device__ __forceinline__ void fft_pass(float2* Z, const float2* tw, int t) {
     }
     dft_small<R>(v[i]);
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int b = t + i * NT;
@@ -183,7 +191,7 @@ __device__ __forceinline__ void fft_pass(float2* Z, const float2* tw, int t) {
       if (COLS) Z[e * F + line] = v[i][r]; else Z[line * F + e] = v[i][r];
     }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // F = 64 and 128 use radix-8 passes (fewer LDS round trips and barriers);
@@ -365,7 +373,7 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   // 2. forward transform (eq. (7) on the F x F grid)
   fft_lines<F, NT, false>(Wd, s.tw, t);
@@ -395,7 +403,7 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
         const float2 zn = Wd[((F - k) & (F - 1)) * F + ((F - l) & (F - 1))];
         rs[c] = make_float2((zk.x + zn.x) * 0.5f, (zk.y - zn.y) * 0.5f);
       }
-      __syncthreads();  // Wd is overwritten by the next block
+      lds_barrier();  // Wd is overwritten by the next block
       return kPending;
     }
   }
@@ -713,6 +721,19 @@ __global__ __launch_bounds__(NT) void fse_persistent(ClassArgs a) {
   // let the other lanes run ahead into the next pass.)
   const int lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  if constexpr (MODE == kWarmPrep) {
+    // The transform kernel of the split warm start costs the same for every
+    // block: workgroup g takes blocks g, g + grid, ... without the queue,
+    // whose single counter, contended by every workgroup, cost more per
+    // block than the gather.
+    for (int bi = blockIdx.x; bi < a.n; bi += gridDim.x) {
+      int tb = t;
+      asm volatile("" : "+v"(tb));
+      const int code = conceal_block<F, NT, KC, MODE>(a, bi, s, tb, parity);
+      if (wave == 0 && code != kPending) a.status[a.orig[bi]] = code;
+    }
+    return;
+  }
   for (;;) {
     int bi;
     if constexpr (S::NW == 1) {
