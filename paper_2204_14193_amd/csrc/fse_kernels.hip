@@ -734,17 +734,13 @@ __global__ __launch_bounds__(NT) void fse_persistent(ClassArgs a) {
     }
     return;
   }
+  // The first block of a workgroup is its own index; each later one is
+  // grid + (the queue's next value), popped as the previous block starts so
+  // that the atomic's latency overlaps that block's work.
+  int bi = blockIdx.x;  // the grid never exceeds the class's block count
   for (;;) {
-    int bi;
-    if constexpr (S::NW == 1) {
-      bi = __builtin_amdgcn_readfirstlane(atomicAdd(&a.queue[0], lane == 0 ? 1 : 0));
-    } else {
-      if (wave == 0) s.misc[0] = __builtin_amdgcn_readfirstlane(atomicAdd(&a.queue[0], lane == 0 ? 1 : 0));
-      __syncthreads();
-      bi = __builtin_amdgcn_readfirstlane(s.misc[0]);
-      __syncthreads();
-    }
-    if (bi >= a.n) break;
+    int nxv = 0;
+    if (wave == 0) nxv = atomicAdd(&a.queue[0], lane == 0 ? 1 : 0);  // read after the block
     // An opaque copy of the thread index keeps the compiler from hoisting
     // every index-derived LDS address out of this loop, where they would
     // stay live in VGPRs for the whole kernel; recomputing them per block
@@ -753,6 +749,15 @@ __global__ __launch_bounds__(NT) void fse_persistent(ClassArgs a) {
     asm volatile("" : "+v"(tb));
     const int code = conceal_block<F, NT, KC, MODE>(a, bi, s, tb, parity);
     if (wave == 0 && code != kPending) a.status[a.orig[bi]] = code;
+    if constexpr (S::NW == 1) {
+      bi = __builtin_amdgcn_readfirstlane(nxv) + (int)gridDim.x;
+    } else {
+      if (wave == 0) s.misc[0] = __builtin_amdgcn_readfirstlane(nxv) + (int)gridDim.x;
+      __syncthreads();
+      bi = __builtin_amdgcn_readfirstlane(s.misc[0]);
+      __syncthreads();
+    }
+    if (bi >= a.n) break;
   }
 
   // the last workgroup to leave re-arms the queue for the next launch
