@@ -100,6 +100,18 @@ __device__ __forceinline__ float readlane_f(float x, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
 }
 
+// (u m + v n) mod F for the phase factor of pixel (m, n) and bin (u, v),
+// all below 2^8: two full-rate 24-bit multiplies (the compiler, seeing that
+// only the low bits are kept, would otherwise pick the quarter-rate 32-bit
+// multiply and a 64-bit multiply-add).
+template <int F>
+__device__ __forceinline__ uint32_t phase_index(uint32_t u, uint32_t v, uint32_t m, uint32_t n) {
+  uint32_t vn, r;
+  asm("v_mul_u32_u24 %0, %1, %2" : "=v"(vn) : "v"(v), "v"(n));
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(u), "v"(m), "v"(vn));
+  return r & (F - 1);
+}
+
 // Workgroup barrier that orders LDS accesses only: global loads issued
 // before it stay in flight (a full __syncthreads waits for them too).
 __device__ __forceinline__ void lds_barrier() {
@@ -901,7 +913,7 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
     if (inloop) {
 #pragma unroll
       for (int q = 0; q < QI; ++q) {
-        const float2 e = tw[(u * mq[q] + v * nq[q]) & (F - 1)];  // Re{c e^{j theta}} = c.x e.x + c.y e.y
+        const float2 e = tw[phase_index<F>(u, v, mq[q], nq[q])];  // as in synthesize: Re{c e^{j theta}} = c.x e.x + c.y e.y
         acc[q] = fmaf(cre, e.x, acc[q]);
         acc[q] = fmaf(cim, e.y, acc[q]);
       }
