@@ -31,6 +31,11 @@ Readings of the paper taken here:
 * I iterations are always run (no early stop);
 * the window centre is ((M-1)/2, (N-1)/2) of the area; pixels outside the
   frame, lost pixels of other blocks and B itself get w = 0.
+* arbitrary loss shapes (the concealment and inpainting setting the paper
+  names in Section I, "masked" below): the block's rectangle only bounds
+  the loss; B is the set of its pixels that were not received, received
+  pixels inside the rectangle belong to the support A, and only B is
+  written.
 """
 import numpy as np
 
@@ -47,11 +52,13 @@ def window(M, N, rho):
     return np.power(float(rho), dist)
 
 
-def area_of_block(frames, avail, blk):
+def area_of_block(frames, avail, blk, masked=False):
     """Cut the area L of block ``blk`` (fields frame, y0, x0, bh, bw, border).
 
     Returns (s, A, B): the signal as float64 (0 where unknown), the support
-    mask A (received, inside the frame, not in B) and the loss mask B."""
+    mask A (received, inside the frame, not in B) and the loss mask B (the
+    block's rectangle, or with ``masked`` its pixels that were not
+    received)."""
     f, y0, x0 = int(blk["frame"]), int(blk["y0"]), int(blk["x0"])
     bh, bw, bd = int(blk["bh"]), int(blk["bw"]), int(blk["border"])
     M, N = bh + 2 * bd, bw + 2 * bd
@@ -66,6 +73,8 @@ def area_of_block(frames, avail, blk):
         A[r0 - ya:r1 - ya, c0 - xa:c1 - xa] = avail[f, r0:r1, c0:c1] != 0
     B = np.zeros((M, N), dtype=bool)
     B[bd:bd + bh, bd:bd + bw] = True
+    if masked:
+        B &= ~A  # the rectangle lies inside the frame (a validated block)
     A &= ~B
     s = np.where(A, s, 0.0)
     return s, A, B
@@ -201,11 +210,12 @@ def cfse(s, w, F, gamma, iters, offset=(0, 0), forced=None, init=None, cand=None
 
 
 def extrapolate_block(frames, avail, blk, rho, gamma, forced=None, init=None, cand=None,
-                      iters=None):
+                      iters=None, masked=False):
     """cFSE for one block descriptor; returns the run dict plus 'values' =
-    Re{g} on B as a bh x bw float64 array (Algorithm 1, last loop), or None
-    for the run when the block has no support."""
-    s, A, B = area_of_block(frames, avail, blk)
+    Re{g} on the block's rectangle as a bh x bw float64 array (Algorithm 1,
+    last loop) and 'lost' = B on the rectangle, or None for the run when the
+    block has no support."""
+    s, A, B = area_of_block(frames, avail, blk, masked)
     M, N = s.shape
     w = weighting(M, N, rho, A)
     F = int(blk["fft"])
@@ -215,6 +225,7 @@ def extrapolate_block(frames, avail, blk, rho, gamma, forced=None, init=None, ca
     res = cfse(s, w, F, gamma, I, forced=forced, init=init, cand=cand)
     bd, bh, bw = int(blk["border"]), int(blk["bh"]), int(blk["bw"])
     res["values"] = res["g"][bd:bd + bh, bd:bd + bw].real.copy()
+    res["lost"] = B[bd:bd + bh, bd:bd + bw].copy()
     return res
 
 
@@ -231,17 +242,18 @@ def _one_blas_thread():
 
 
 def _block_worker(i):
-    frames, avail, blocks, rho, gamma = _SHARED["job"]
-    res = extrapolate_block(frames, avail, blocks[i], rho, gamma)
-    return None if res is None else res["values"]
+    frames, avail, blocks, rho, gamma, masked = _SHARED["job"]
+    res = extrapolate_block(frames, avail, blocks[i], rho, gamma, masked=masked)
+    return None if res is None else (res["values"], res["lost"])
 
 
-def extrapolate_frames(frames, avail, blocks, rho, gamma, processes=1):
+def extrapolate_frames(frames, avail, blocks, rho, gamma, processes=1, masked=False):
     """Conceal every block of ``blocks`` (a BLOCK_DTYPE array): returns a
-    float64 copy of the distorted frames with each B replaced by Re{g}.
+    float64 copy of the distorted frames with each B replaced by Re{g}
+    (with ``masked``, B = the lost pixels of each block's rectangle).
     Blocks whose area has no support keep the distorted value (0)."""
     out = (frames * (avail != 0)).astype(np.float64)
-    _SHARED["job"] = (frames, avail, blocks, rho, gamma)
+    _SHARED["job"] = (frames, avail, blocks, rho, gamma, masked)
     try:
         if processes > 1:
             import multiprocessing as mp
@@ -255,5 +267,6 @@ def extrapolate_frames(frames, avail, blocks, rho, gamma, processes=1):
     for b, v in zip(blocks, vals):
         if v is not None:
             f, y0, x0 = int(b["frame"]), int(b["y0"]), int(b["x0"])
-            out[f, y0:y0 + int(b["bh"]), x0:x0 + int(b["bw"])] = v
+            sub = out[f, y0:y0 + int(b["bh"]), x0:x0 + int(b["bw"])]
+            sub[v[1]] = v[0][v[1]]
     return out

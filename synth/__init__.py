@@ -12,8 +12,9 @@ noise.
 """
 from .images import synthetic_image, synthetic_frames
 from .losses import (Block, BLOCK_DTYPE, blocks_to_array, isolated_grid_losses,
-                     random_grid_losses, mixed_size_losses, fft_size_for_area)
+                     random_grid_losses, mixed_size_losses, fft_size_for_area, stroke_mask,
+                     blocks_from_mask)
 
 __all__ = ["synthetic_image", "synthetic_frames", "Block", "BLOCK_DTYPE",
            "blocks_to_array", "isolated_grid_losses", "random_grid_losses",
-           "mixed_size_losses", "fft_size_for_area"]
+           "mixed_size_losses", "fft_size_for_area", "stroke_mask", "blocks_from_mask"]

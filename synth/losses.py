@@ -139,3 +139,50 @@ def availability_mask(shape, blocks):
     for b in blocks:
         avail[b.frame, b.y0:b.y0 + b.bh, b.x0:b.x0 + b.bw] = 0
     return avail
+
+
+def stroke_mask(height, width, seed, density=0.06, width_range=(2, 7), frame_count=1):
+    """Irregular losses (inpainting-like scribbles): random polyline strokes
+    of random width until ``density`` of the pixels are lost. Returns a
+    ``uint8`` availability mask ``(frame_count, H, W)`` (1 = received)."""
+    rng = np.random.default_rng(seed + LOSS_SEED_OFFSET)
+    avail = np.ones((frame_count, height, width), dtype=np.uint8)
+    yy, xx = np.mgrid[0:height, 0:width]
+    for f in range(frame_count):
+        lost = np.zeros((height, width), dtype=bool)
+        while lost.mean() < density:
+            y, x = rng.uniform(0, height), rng.uniform(0, width)
+            r = rng.uniform(width_range[0], width_range[1]) / 2
+            for _ in range(int(rng.integers(3, 9))):
+                ang = rng.uniform(0, 2 * np.pi)
+                ln = rng.uniform(10, 60)
+                y1 = min(max(y + ln * np.sin(ang), 0), height - 1)
+                x1 = min(max(x + ln * np.cos(ang), 0), width - 1)
+                # pixels within r of the segment (y, x) -> (y1, x1), in its bounding box
+                ya, yb = int(max(min(y, y1) - r - 1, 0)), int(min(max(y, y1) + r + 2, height))
+                xa, xb = int(max(min(x, x1) - r - 1, 0)), int(min(max(x, x1) + r + 2, width))
+                py, px = yy[ya:yb, xa:xb], xx[ya:yb, xa:xb]
+                dy, dx = y1 - y, x1 - x
+                t = np.clip(((py - y) * dy + (px - x) * dx) / max(dy * dy + dx * dx, 1e-9), 0, 1)
+                d2 = (py - (y + t * dy)) ** 2 + (px - (x + t * dx)) ** 2
+                lost[ya:yb, xa:xb] |= d2 <= r * r
+                y, x = y1, x1
+        avail[f][lost] = 0
+    return avail
+
+
+def blocks_from_mask(avail, cell, border, fft, iters):
+    """Cover the lost pixels of an availability mask with blocks: the frame
+    is cut into ``cell x cell`` tiles from (0, 0) (clipped at the right and
+    bottom edges) and every tile holding a lost pixel becomes one block,
+    frame-major, then row-major. With a mask-driven loss area, each block
+    conceals only its tile's lost pixels."""
+    nf, H, W = avail.shape
+    out = []
+    for f in range(nf):
+        for y0 in range(0, H, cell):
+            for x0 in range(0, W, cell):
+                bh, bw = min(cell, H - y0), min(cell, W - x0)
+                if (avail[f, y0:y0 + bh, x0:x0 + bw] == 0).any():
+                    out.append(Block(f, y0, x0, bh, bw, border, fft, iters))
+    return out

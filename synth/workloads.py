@@ -9,8 +9,8 @@ from dataclasses import dataclass
 import numpy as np
 
 from .images import synthetic_image
-from .losses import (array_to_blocks, availability_mask, blocks_to_array,
-                     isolated_grid_losses, mixed_size_losses, random_grid_losses)
+from .losses import (array_to_blocks, availability_mask, blocks_from_mask, blocks_to_array,
+                     isolated_grid_losses, mixed_size_losses, random_grid_losses, stroke_mask)
 
 
 @dataclass
@@ -74,6 +74,28 @@ def mixed_4k(seeds=tuple(range(2, 10))):
         frames.append(synthetic_image(2160, 3840, s))
         blocks += mixed_size_losses(2160, 3840, s, frame=f)
     return _finish("mixed-4k", np.stack(frames), blocks)
+
+
+def strokes_1080p(seeds=(31,), iters=100, density=0.06):
+    """1920x1080 frames with irregular scribble losses (6% of the pixels,
+    strokes 2-7 px wide), covered by 16x16 tiles with border 16 (48x48
+    areas) and F=64; each block conceals only its tile's lost pixels (a
+    mask-driven loss area)."""
+    frames, avails = [], []
+    for s in seeds:
+        frames.append(synthetic_image(1080, 1920, s))
+        avails.append(stroke_mask(1080, 1920, s, density)[0])
+    avail = np.stack(avails)
+    blocks = blocks_from_mask(avail, 16, 16, 64, iters)
+    return Workload("strokes-1080p", np.stack(frames), avail, blocks_to_array(blocks), 0.8, 0.5)
+
+
+def strokes_256(seed=5, iters=60, density=0.08):
+    """256x256 frame with scribble losses, 16x16 tiles, border 16, F=64."""
+    frames = synthetic_image(256, 256, seed)[None]
+    avail = stroke_mask(256, 256, seed, density)
+    blocks = blocks_from_mask(avail, 16, 16, 64, iters)
+    return Workload("strokes-256", frames, avail, blocks_to_array(blocks), 0.8, 0.5)
 
 
 def subset(w, idx):

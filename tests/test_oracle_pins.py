@@ -332,3 +332,63 @@ def test_frequency_domain_update_matches_projection():
         # free-running: the same tie rule gives the same selections
         seq_free, _, _ = alg1.cfse_fft(s, w, 64, 0.5, 100)
         assert seq_free == res["seq"]
+
+
+# ------------------------------------------------- arbitrary loss shapes
+
+def _strokes_case():
+    from synth import workloads
+    wl = workloads.strokes_256(iters=30)
+    # a tile with both lost and received pixels
+    for i, b in enumerate(wl.blocks):
+        t = wl.avail[0, b["y0"]:b["y0"] + b["bh"], b["x0"]:b["x0"] + b["bw"]]
+        if 0.2 < (t == 0).mean() < 0.8:
+            return wl, i
+    raise AssertionError("no partially lost tile")
+
+
+def test_masked_loss_area_reduces_to_the_rectangle():
+    """With every pixel of the block's rectangle lost, the mask-driven loss
+    area is the rectangle: identical selections and values."""
+    from synth import workloads
+    wl = workloads.isolated_256(iters=30)
+    for i in (5, 27):
+        a = cfse.extrapolate_block(wl.frames, wl.avail, wl.blocks[i], 0.8, 0.5)
+        b = cfse.extrapolate_block(wl.frames, wl.avail, wl.blocks[i], 0.8, 0.5, masked=True)
+        assert a["seq"] == b["seq"]
+        np.testing.assert_array_equal(a["values"], b["values"])
+        assert b["lost"].all()
+
+
+def test_masked_loss_area_constant_signal_is_exact():
+    """A constant signal with an irregular loss inside the rectangle: the
+    first selection is the DC bin and with gamma = 1 its coefficient is the
+    constant itself, so every lost pixel is reproduced exactly."""
+    wl, i = _strokes_case()
+    frames = np.full_like(wl.frames, 123)
+    res = cfse.extrapolate_block(frames, wl.avail, wl.blocks[i], 0.8, 1.0, iters=1, masked=True)
+    assert res["seq"] == [0]
+    lost = res["lost"]
+    assert 0 < lost.sum() < lost.size
+    np.testing.assert_allclose(res["values"][lost], 123.0, rtol=0, atol=1e-9)
+
+
+def test_masked_loss_area_uses_received_pixels_of_the_rectangle():
+    """Received pixels inside the rectangle are support, not loss: the loss
+    mask is exactly the rectangle's lost pixels, the frame output keeps every
+    received pixel, and changing a received pixel inside the rectangle
+    changes the extrapolation (it is part of eq. (3)'s support)."""
+    wl, i = _strokes_case()
+    blk = wl.blocks[i]
+    y0, x0, bh, bw = (int(blk[k]) for k in ("y0", "x0", "bh", "bw"))
+    rect = wl.avail[0, y0:y0 + bh, x0:x0 + bw]
+    res = cfse.extrapolate_block(wl.frames, wl.avail, blk, 0.8, 0.5, masked=True)
+    assert np.array_equal(res["lost"], rect == 0)
+    out = cfse.extrapolate_frames(wl.frames, wl.avail, wl.blocks[i:i + 1], 0.8, 0.5, masked=True)
+    recv = wl.avail != 0
+    np.testing.assert_array_equal(out[recv], wl.frames[recv].astype(np.float64))
+    changed = np.argwhere(rect != 0)[0]
+    frames = wl.frames.copy()
+    frames[0, y0 + changed[0], x0 + changed[1]] ^= 0x40
+    other = cfse.extrapolate_block(frames, wl.avail, blk, 0.8, 0.5, masked=True)
+    assert not np.array_equal(other["values"][res["lost"]], res["values"][res["lost"]])
