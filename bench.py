@@ -106,12 +106,12 @@ def _init_worker():
 
 def _oracle_block(args):
     from oracle import cfse
-    frames, avail, blk, rho, gamma = args
-    cfse.extrapolate_block(frames, avail, blk, rho, gamma)
+    frames, avail, blk, rho, gamma, masked = args
+    cfse.extrapolate_block(frames, avail, blk, rho, gamma, masked=masked)
     return 1
 
 
-def cpu_baseline(wl, n_sample, seed=5):
+def cpu_baseline(wl, n_sample, seed=5, masked=False):
     """FP64 oracle, as it stands, over a seeded sample of the workload's
     blocks, one process per host core."""
     import multiprocessing as mp
@@ -123,7 +123,7 @@ def cpu_baseline(wl, n_sample, seed=5):
         b = wl.blocks[i].copy()
         f = int(b["frame"])
         b["frame"] = 0
-        jobs.append((wl.frames[f:f + 1], wl.avail[f:f + 1], b, wl.rho, wl.gamma))
+        jobs.append((wl.frames[f:f + 1], wl.avail[f:f + 1], b, wl.rho, wl.gamma, masked))
     with mp.get_context("fork").Pool(cores, initializer=_init_worker) as pool:
         pool.map(_oracle_block, jobs[:cores])            # warm the workers
         t0 = time.perf_counter()
@@ -148,7 +148,7 @@ def main():
     ap.add_argument("--frames", type=int, default=8)
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--workload", default="random-1080p-16x16",
-                    choices=["random-1080p-16x16", "random-1080p-8x8", "mixed-4k"],
+                    choices=["random-1080p-16x16", "random-1080p-8x8", "mixed-4k", "strokes-1080p"],
                     help="the metric's workload (default) or one of the other configurations (plain only)")
     ap.add_argument("--kc", type=int, default=256, help="warm start: candidate bins per block")
     ap.add_argument("--ir", type=int, default=110, help="warm start: restricted iterations")
@@ -177,10 +177,17 @@ def main():
         wl = workloads.random_1080p_8x8(iters=200)
         desc = ("1920x1080 synthetic frame, 3240 isolated 8x8 losses (10%), border 16 (40x40 area), "
                 "64x64 transform, rho 0.8, gamma 0.5, 200 iterations, plain FSE")
+    elif args.workload == "strokes-1080p":
+        nfr = min(args.frames, 3)
+        wl = workloads.strokes_1080p(seeds=tuple(range(31, 31 + nfr)), iters=args.iters)
+        desc = (f"{nfr}x 1920x1080 synthetic frames, scribble losses (6% of the pixels, strokes 2-7 px wide) "
+                f"covered by 16x16 tiles, border 16 (48x48 area), 64x64 transform, rho 0.8, gamma 0.5, "
+                f"{args.iters} iterations, plain FSE with mask-driven loss areas")
     else:
         wl = workloads.mixed_4k(seeds=tuple(range(2, 2 + args.frames)))
         desc = (f"{args.frames}x 3840x2160 synthetic frames, 305 losses each of 4, 8, 16, 32 px per frame (5%), "
                 "border 8-16, transform 32/64/128, 50-500 iterations, plain FSE")
+    masked = args.workload == "strokes-1080p"
     n = len(wl.blocks)
     dev = torch.device("cuda:0")
     img = torch.from_numpy(wl.distorted).to(dev)
@@ -191,7 +198,7 @@ def main():
     # ---- plain FSE
     out = img.to(torch.float32)
     status = torch.zeros(n, dtype=torch.int32, device=dev)
-    plan = fse.Plan(wl.rho, wl.gamma, int(wl.blocks["iters"].max()))
+    plan = fse.Plan(wl.rho, wl.gamma, int(wl.blocks["iters"].max()), masked=masked)
     batch = fse.Batch(plan, wl.blocks, *wl.frames.shape)
     tuning = batch.autotune(img, av, out, status, reps=2) if not args.no_tune else []
     classes = sorted(set(int(f) for f in wl.blocks["fft"]))
@@ -290,7 +297,7 @@ def main():
         torch.cuda.synchronize()
         rec["copy_calibration_bytes"] = args.copy_bytes
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, n))
+        rec["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, n), masked=masked)
     print(json.dumps(rec), flush=True)
 
 

@@ -78,8 +78,16 @@ typedef struct {
   float rho;          /* window decay rho in (0, 1], eq. (3)                  */
   float gamma;        /* orthogonality deficiency compensation, [0, 1], eq. (13) */
   int32_t max_iters;  /* largest per-block iteration count accepted (<= 4096) */
-  uint32_t flags;     /* reserved, must be 0                                  */
+  uint32_t flags;     /* FSE_PLAN_* bits; others must be 0                    */
 } fse_plan_desc_t;
+
+/* Mask-driven loss areas (arbitrary loss shapes, the concealment and
+ * inpainting setting of Section I): a block's bh x bw rectangle only bounds
+ * its loss; B is the set of the rectangle's pixels with avail == 0, the
+ * rectangle's received pixels belong to the support A (eq. (3)), and only
+ * the pixels of B are written. Plain FSE only (the warm start refuses such
+ * plans). See fse_blocks_from_mask for covering an arbitrary mask. */
+#define FSE_PLAN_MASKED_B 1u
 
 /* One record per block and iteration when tracing: selected bin (u, v),
  * coefficient c of eq. (13) and |R_w[u,v]|^2 as seen by the argmax. */
@@ -111,6 +119,20 @@ void fse_plan_destroy(fse_plan_t plan);
  * block index, or -1. */
 fse_status_t fse_validate_blocks(fse_plan_t plan, const fse_block_t* h_blocks, int32_t n_blocks,
                                  int32_t n_frames, int32_t H, int32_t W, int32_t* bad_index);
+
+/* Cover the lost pixels of an availability mask with blocks, host-side:
+ * frame f of h_avail (uint8 [n_frames][H][pitch], 0 = lost) is cut into
+ * cell x cell tiles from (0, 0), clipped at the right and bottom edges, and
+ * every tile holding a lost pixel becomes one block {f, y0, x0, bh, bw,
+ * border, fft, iters}, frame-major then row-major, for a plan with
+ * FSE_PLAN_MASKED_B. Writes the first min(count, cap) blocks to h_out (may be
+ * null when cap = 0) and the count to *n_out. FSE_ERR_INVALID_ARG for a null
+ * mask or n_out, non-positive sizes, pitch < W, cell < 1 or border < 0;
+ * FSE_ERR_UNSUPPORTED when cell + 2*border exceeds fft or fft is not 32, 64
+ * or 128. */
+fse_status_t fse_blocks_from_mask(const uint8_t* h_avail, int32_t n_frames, int32_t H, int32_t W, int64_t pitch,
+                                  int32_t cell, int32_t border, int32_t fft, int32_t iters, fse_block_t* h_out,
+                                  int32_t cap, int32_t* n_out);
 
 /* Prepare a batch: validates h_blocks (as fse_validate_blocks), groups the
  * blocks by transform size, orders each group longest-first by F*F*I,

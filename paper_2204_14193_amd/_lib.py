@@ -31,6 +31,7 @@ SIGNATURES = {
     "fse_plan_create": (I32, [C.POINTER(fse_plan_desc_t), C.POINTER(P)]),
     "fse_plan_destroy": (None, [P]),
     "fse_validate_blocks": (I32, [P, P, I32, I32, I32, I32, PI32]),
+    "fse_blocks_from_mask": (I32, [P, I32, I32, I32, I64, I32, I32, I32, I32, P, I32, PI32]),
     "fse_batch_create": (I32, [P, P, I32, I32, I32, I32, C.POINTER(P)]),
     "fse_batch_destroy": (None, [P]),
     "fse_batch_max_iters": (I32, [P]),

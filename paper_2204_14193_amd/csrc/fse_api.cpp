@@ -51,6 +51,7 @@ struct DeviceTables {
 struct fse_plan_s {
   float rho = 0.f, gamma = 0.f;
   int32_t max_iters = 0;
+  uint32_t flags = 0;
   std::vector<float> wtab;                 // host copy, FP64-computed
   std::vector<float2> twid[3];             // per class
   std::mutex mu;
@@ -97,12 +98,13 @@ extern "C" fse_status_t fse_plan_create(const fse_plan_desc_t* desc, fse_plan_t*
   if (!(desc->gamma >= 0.f && desc->gamma <= 1.f)) return fail(FSE_ERR_INVALID_ARG, "gamma must lie in [0, 1]");
   if (desc->max_iters < 0 || desc->max_iters > fse::kMaxIters)
     return fail(FSE_ERR_INVALID_ARG, "max_iters must lie in [0, 4096]");
-  if (desc->flags != 0) return fail(FSE_ERR_INVALID_ARG, "flags must be 0");
+  if ((desc->flags & ~(uint32_t)FSE_PLAN_MASKED_B) != 0) return fail(FSE_ERR_INVALID_ARG, "unknown plan flag");
   fse_plan_s* p = new (std::nothrow) fse_plan_s;
   if (!p) return fail(FSE_ERR_OOM, "host allocation failed");
   p->rho = desc->rho;
   p->gamma = desc->gamma;
   p->max_iters = desc->max_iters;
+  p->flags = desc->flags;
   // eq. (3): rho^distance, distance = sqrt(a^2 + b^2) / 2 for doubled offsets
   const int S = fse::kWinStride;
   p->wtab.resize((size_t)S * S);
@@ -178,6 +180,47 @@ extern "C" fse_status_t fse_validate_blocks(fse_plan_t plan, const fse_block_t* 
     }
   }
   if (bad_index) *bad_index = -1;
+  return FSE_OK;
+}
+
+extern "C" fse_status_t fse_blocks_from_mask(const uint8_t* h_avail, int32_t n_frames, int32_t H, int32_t W,
+                                             int64_t pitch, int32_t cell, int32_t border, int32_t fft,
+                                             int32_t iters, fse_block_t* h_out, int32_t cap, int32_t* n_out) {
+  if (!h_avail || !n_out || (cap > 0 && !h_out)) return fail(FSE_ERR_INVALID_ARG, "null argument");
+  *n_out = 0;
+  if (n_frames <= 0 || H <= 0 || W <= 0 || pitch < W || cell < 1 || border < 0 || cap < 0 || iters < 0)
+    return fail(FSE_ERR_INVALID_ARG, "bad mask or tile size");
+  if (class_of(fft) < 0) return fail(FSE_ERR_UNSUPPORTED, "fft must be 32, 64 or 128");
+  if (cell + 2 * border > fft) return fail(FSE_ERR_UNSUPPORTED, "area larger than the transform");
+  int64_t count = 0;
+  for (int32_t f = 0; f < n_frames; ++f)
+    for (int32_t y0 = 0; y0 < H; y0 += cell)
+      for (int32_t x0 = 0; x0 < W; x0 += cell) {
+        const int32_t bh = std::min(cell, H - y0), bw = std::min(cell, W - x0);
+        bool lost = false;
+        for (int32_t y = y0; y < y0 + bh && !lost; ++y) {
+          const uint8_t* row = h_avail + ((int64_t)f * H + y) * pitch + x0;
+          for (int32_t x = 0; x < bw; ++x)
+            if (row[x] == 0) {
+              lost = true;
+              break;
+            }
+        }
+        if (!lost) continue;
+        if (count < cap) {
+          fse_block_t& b = h_out[count];
+          b.frame = f;
+          b.y0 = y0;
+          b.x0 = x0;
+          b.bh = (int16_t)bh;
+          b.bw = (int16_t)bw;
+          b.border = (int16_t)border;
+          b.fft = (int16_t)fft;
+          b.iters = iters;
+        }
+        if (++count > INT32_MAX) return fail(FSE_ERR_INVALID_ARG, "too many blocks");
+      }
+  *n_out = (int32_t)count;
   return FSE_OK;
 }
 
@@ -411,6 +454,7 @@ static fse_status_t launch_one(fse_batch_t batch, int ci, const uint8_t* d_image
     a.wtab = batch->tables->wtab;
     a.twid = batch->tables->twid[ci];
     a.gamma = batch->plan->gamma;
+    a.masked_b = (batch->plan->flags & FSE_PLAN_MASKED_B) ? 1 : 0;
     a.queue = batch->d_queue + 32 * ci;
     a.cand = cand;
     a.flags = flags;
@@ -536,6 +580,8 @@ extern "C" fse_status_t fse_cnn_patches(fse_batch_t batch, const uint8_t* d_imag
                                         int64_t pitch, uint16_t* d_x, void* stream) {
   if (!batch || !d_image || !d_avail || !d_x) return fail(FSE_ERR_INVALID_ARG, "null argument");
   if (!batch->all_48) return fail(FSE_ERR_UNSUPPORTED, "network inputs need 48x48 areas");
+  if (batch->plan->flags & FSE_PLAN_MASKED_B)
+    return fail(FSE_ERR_UNSUPPORTED, "the warm start needs rectangular loss areas");
   if (pitch < batch->W) return fail(FSE_ERR_INVALID_ARG, "pitch smaller than the width");
   if (fse::cnn::patches(d_image, d_avail, pitch, batch->H, batch->W, batch->d_blocks, batch->d_orig, batch->n, d_x,
                         reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
@@ -548,6 +594,8 @@ extern "C" fse_status_t fse_cnn_forward_blocks(fse_cnn_t net, fse_batch_t batch,
                                                void* stream) {
   if (!batch || !d_image || !d_avail) return fail(FSE_ERR_INVALID_ARG, "null argument");
   if (!batch->all_48) return fail(FSE_ERR_UNSUPPORTED, "network inputs need 48x48 areas");
+  if (batch->plan->flags & FSE_PLAN_MASKED_B)
+    return fail(FSE_ERR_UNSUPPORTED, "the warm start needs rectangular loss areas");
   if (pitch < batch->W) return fail(FSE_ERR_INVALID_ARG, "pitch smaller than the width");
   return fse::cnn::net_forward_blocks(net, d_image, d_avail, pitch, batch->H, batch->W, batch->d_blocks,
                                       batch->d_orig, batch->n, d_logits, reinterpret_cast<hipStream_t>(stream));
@@ -563,6 +611,8 @@ extern "C" fse_status_t fse_warm_extrapolate_batch(fse_batch_t batch, const uint
                                                    const int16_t* d_cand, const int32_t* d_flags, int32_t kc,
                                                    int32_t restricted_iters, int32_t fallback_iters, void* stream) {
   if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
+  if (batch->plan->flags & FSE_PLAN_MASKED_B)
+    return fail(FSE_ERR_UNSUPPORTED, "the warm start needs rectangular loss areas");
   if (batch->n == 0) return FSE_OK;
   if (!d_image || !d_avail || !d_out || !d_status || !d_cand || !d_flags)
     return fail(FSE_ERR_INVALID_ARG, "null device pointer");

@@ -33,6 +33,7 @@ struct ClassArgs {
   const float* wtab;          // window table (see kWinStride)
   const float2* twid;         // F entries: exp(-j 2 pi q / F)
   float gamma;
+  int32_t masked_b;           // nonzero: B = the lost pixels of each block's rectangle
   int32_t* queue;             // [2]: next block, finished workgroups
   // warm-started form only
   const int16_t* cand;        // [caller's n_blocks][kc] candidate bins, ascending

@@ -234,7 +234,8 @@ __device__ __forceinline__ void fft_lines(float2* Z, const float2* tw, int t) {
 // its bin made wave-uniform. Per pixel the terms are added in list order.
 template <int F, int NT, int Q>
 __device__ __forceinline__ void synthesize(const int* cl_idx, const float2* cl_c, int n_coef, const float2* tw,
-                                           int bh, int bw, int bo, float* out, int64_t out_pitch, int t) {
+                                           int bh, int bw, int bo, float* out, int64_t out_pitch, int t,
+                                           const uint8_t* lost_only = nullptr, int64_t av_pitch = 0) {
   const int np = bh * bw;
   for (int p0 = 0; p0 < np; p0 += NT * Q) {
     if (p0 + (t & ~63) >= np) break;  // wave-uniform: no pixel left for this wave
@@ -261,7 +262,9 @@ __device__ __forceinline__ void synthesize(const int* cl_idx, const float2* cl_c
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int p = p0 + t + q * NT;
-      if (p < np) out[(int64_t)(mq[q] - bo) * out_pitch + (nq[q] - bo)] = acc[q];
+      // with a mask-driven loss area only the rectangle's lost pixels are written
+      if (p < np && (!lost_only || lost_only[(int64_t)(mq[q] - bo) * av_pitch + (nq[q] - bo)] == 0))
+        out[(int64_t)(mq[q] - bo) * out_pitch + (nq[q] - bo)] = acc[q];
     }
   }
 }
@@ -378,7 +381,9 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
         const int e = t + (g0 + r) * NT;
         const int m = e / F, n = e % F;
         const int y = ya + m, x = xa + n;
-        const bool inB = (m >= bo) && (m < bo + bh) && (n >= bo) && (n < bo + bw);
+        // B: the rectangle, or with a mask-driven loss area its lost pixels
+        // (received pixels of the rectangle are then support)
+        const bool inB = !a.masked_b && (m >= bo) && (m < bo + bh) && (n >= bo) && (n < bo + bw);
         const bool use = m < M && n < N && !inB && y >= 0 && y < a.H && x >= 0 && x < a.W && avb[r] != 0;
         const float w = wv[r];
         Wd[e] = use ? make_float2((float)pix[r] * w, kAlpha * w) : make_float2(0.f, 0.f);
@@ -702,7 +707,8 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
 
   // 4. model on B
   synthesize<F, NT, 1>(s.cl_idx, s.cl_c, tbase + I_full, s.tw, bh, bw, bo,
-                       a.out + (fofs + bd.y0) * a.out_pitch + bd.x0, a.out_pitch, t);
+                       a.out + (fofs + bd.y0) * a.out_pitch + bd.x0, a.out_pitch, t,
+                       a.masked_b ? av + (int64_t)bd.y0 * pitch + bd.x0 : nullptr, pitch);
   return FSE_BLOCK_OK;
 }
 

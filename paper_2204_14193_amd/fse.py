@@ -44,16 +44,22 @@ def _blocks_array(blocks):
     return arr
 
 
-class Plan:
-    """fse_plan_t: window decay rho, compensation gamma, iteration limit."""
+PLAN_MASKED_B = 1  # FSE_PLAN_MASKED_B of include/fse.h
 
-    def __init__(self, rho=0.8, gamma=0.5, max_iters=4096):
+
+class Plan:
+    """fse_plan_t: window decay rho, compensation gamma, iteration limit;
+    masked=True makes every block's loss area the lost pixels of its
+    rectangle (arbitrary loss shapes, FSE_PLAN_MASKED_B)."""
+
+    def __init__(self, rho=0.8, gamma=0.5, max_iters=4096, masked=False):
         L = _lib.lib()
-        desc = _lib.fse_plan_desc_t(float(rho), float(gamma), int(max_iters), 0)
+        desc = _lib.fse_plan_desc_t(float(rho), float(gamma), int(max_iters), PLAN_MASKED_B if masked else 0)
         h = C.c_void_p()
         _check(L.fse_plan_create(C.byref(desc), C.byref(h)), "fse_plan_create")
         self._h = h
         self.rho, self.gamma, self.max_iters = float(rho), float(gamma), int(max_iters)
+        self.masked = bool(masked)
 
     @property
     def handle(self):
@@ -183,17 +189,37 @@ class Batch:
             pass
 
 
-def extrapolate_batch(image, avail, blocks, rho=0.8, gamma=0.5, trace=False, out=None):
+def blocks_from_mask(avail, cell=16, border=16, fft=64, iters=100):
+    """Blocks covering the lost pixels of ``avail`` (uint8 numpy [F,H,W] or
+    [H,W], 0 = lost) with cell x cell tiles (fse_blocks_from_mask), for a
+    plan with masked=True. Host-only."""
+    av = np.ascontiguousarray(avail, dtype=np.uint8)
+    if av.ndim == 2:
+        av = av[None]
+    nf, H, W = av.shape
+    L = _lib.lib()
+    n = C.c_int32(0)
+    args = (av.ctypes.data_as(C.c_void_p), nf, H, W, W, int(cell), int(border), int(fft), int(iters))
+    _check(L.fse_blocks_from_mask(*args, None, 0, C.byref(n)), "fse_blocks_from_mask")
+    arr = np.zeros(n.value, dtype=BLOCK_DTYPE)
+    got = C.c_int32(0)
+    _check(L.fse_blocks_from_mask(*args, arr.ctypes.data_as(C.c_void_p), len(arr), C.byref(got)),
+           "fse_blocks_from_mask")
+    return arr
+
+
+def extrapolate_batch(image, avail, blocks, rho=0.8, gamma=0.5, trace=False, out=None, masked=False):
     """Conceal ``blocks`` in frames ``image`` (uint8 CUDA tensor [F,H,W] or
     [H,W]) with availability ``avail``. Returns (out float32, status int32
     numpy, trace numpy of TRACE_DTYPE [n, max_iters] or None). ``out``
-    defaults to the distorted frames as float32."""
+    defaults to the distorted frames as float32. ``masked``: mask-driven
+    loss areas (see Plan)."""
     import torch
     if image.dim() == 2:
         image, avail = image[None], avail[None]
     arr = _blocks_array(blocks)
     nf, H, W = image.shape
-    plan = Plan(rho, gamma, max(4096, int(arr["iters"].max()) if len(arr) else 0))
+    plan = Plan(rho, gamma, max(4096, int(arr["iters"].max()) if len(arr) else 0), masked=masked)
     batch = Batch(plan, arr, nf, H, W)
     if out is None:
         out = (image * (avail != 0)).to(torch.float32)

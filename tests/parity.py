@@ -35,11 +35,11 @@ def accumulate(seq, c):
     return acc
 
 
-def replay_block(frames, avail, blk, rho, gamma, trace_row):
+def replay_block(frames, avail, blk, rho, gamma, trace_row, masked=False):
     """Returns a dict of per-block parity figures (raises nothing)."""
     F, I = int(blk["fft"]), int(blk["iters"])
     seq, c = gpu_sequence(trace_row, F, I)
-    res = cfse.extrapolate_block(frames, avail, blk, rho, gamma, forced=seq)
+    res = cfse.extrapolate_block(frames, avail, blk, rho, gamma, forced=seq, masked=masked)
     short = np.array(res["short"]) if I else np.zeros(0)
     free = np.array(res["free"]) if I else np.zeros(0, dtype=int)
     diverged = free != seq
@@ -56,20 +56,21 @@ def replay_block(frames, avail, blk, rho, gamma, trace_row):
         max_short=float(short[diverged].max()) if diverged.any() else 0.0,
         coef_max=float(d.max() / scale) if scale > 0 else 0.0,
         coef_l2=float(np.linalg.norm(vg - vo) / np.linalg.norm(vo)) if scale > 0 else 0.0,
-        values=res["values"])
+        values=res["values"], lost=res["lost"])
 
 
-def check_blocks(frames, avail, blocks, rho, gamma, trace, out_gpu, idx=None):
+def check_blocks(frames, avail, blocks, rho, gamma, trace, out_gpu, idx=None, masked=False):
     """Replay every block in ``idx`` (default all); assert the per-block bars
-    and return the per-block figures."""
+    and return the per-block figures (pixel differences over the block's
+    loss area)."""
     idx = range(len(blocks)) if idx is None else idx
     rows = []
     for i in idx:
         blk = blocks[i]
-        r = replay_block(frames, avail, blk, rho, gamma, trace[i])
+        r = replay_block(frames, avail, blk, rho, gamma, trace[i], masked)
         f, y0, x0 = int(blk["frame"]), int(blk["y0"]), int(blk["x0"])
         g = out_gpu[f, y0:y0 + int(blk["bh"]), x0:x0 + int(blk["bw"])].astype(np.float64)
-        r["pix_maxabs"] = float(np.abs(g - r["values"]).max())
+        r["pix_maxabs"] = float(np.abs(g - r["values"])[r["lost"]].max())
         r["index"] = int(i)
         rows.append(r)
         assert r["gap_violations"] == 0, (i, r)
@@ -77,14 +78,15 @@ def check_blocks(frames, avail, blocks, rho, gamma, trace, out_gpu, idx=None):
     return rows
 
 
-def psnr_delta(frames, avail, blocks, rho, gamma, out_gpu, processes=1):
+def psnr_delta(frames, avail, blocks, rho, gamma, out_gpu, processes=1, masked=False):
     """|PSNR(GPU) - PSNR(free-running oracle)| over the lost pixels of the
     given blocks (other lost pixels are ignored), plus both PSNRs."""
-    ref = cfse.extrapolate_frames(frames, avail, blocks, rho, gamma, processes=processes)
+    ref = cfse.extrapolate_frames(frames, avail, blocks, rho, gamma, processes=processes, masked=masked)
     mask = np.ones_like(avail)
     for b in blocks:
-        mask[int(b["frame"]), int(b["y0"]):int(b["y0"]) + int(b["bh"]),
-             int(b["x0"]):int(b["x0"]) + int(b["bw"])] = 0
+        sl = (int(b["frame"]), slice(int(b["y0"]), int(b["y0"]) + int(b["bh"])),
+              slice(int(b["x0"]), int(b["x0"]) + int(b["bw"])))
+        mask[sl] = avail[sl] if masked else 0
     p_gpu = metrics.psnr_lost(frames, out_gpu, mask)
     p_orc = metrics.psnr_lost(frames, ref, mask)
     return abs(p_gpu - p_orc), p_gpu, p_orc, metrics.psnr_between(out_gpu, ref, mask)

@@ -89,3 +89,42 @@ def test_validation_of_workloads():
     plan = fse.Plan(0.8, 0.5, 500)
     for wl in (workloads.isolated_256(), workloads.random_1080p_8x8()):
         assert plan.validate(wl.blocks, *wl.frames.shape) == (0, -1)
+
+
+def test_plan_flags():
+    """FSE_PLAN_MASKED_B is the only accepted plan flag."""
+    from paper_2204_14193_amd import _lib
+    import paper_2204_14193_amd as fse
+    fse.Plan(0.8, 0.5, 100, masked=True).close()
+    desc = _lib.fse_plan_desc_t(0.8, 0.5, 100, 2)
+    h = C.c_void_p()
+    assert _lib.lib().fse_plan_create(C.byref(desc), C.byref(h)) == -1
+
+
+def test_blocks_from_mask_matches_the_tile_cover():
+    """fse_blocks_from_mask (C++) against the generator's own tile cover
+    (Python): the same blocks in the same order, for full tiles, tiles
+    clipped at the frame edge and several frames; the count-only call and
+    argument errors."""
+    import paper_2204_14193_amd as fse
+    from paper_2204_14193_amd import _lib
+    av = losses.stroke_mask(100, 150, 7, density=0.05, frame_count=2)
+    for cell, border, F in ((16, 16, 64), (10, 8, 32), (40, 40, 128)):
+        got = fse.blocks_from_mask(av, cell, border, F, 77)
+        ref = losses.blocks_to_array(losses.blocks_from_mask(av, cell, border, F, 77))
+        assert len(got) > 0 and np.array_equal(got, ref), (cell, border, F)
+        # every lost pixel is covered once; every block holds a lost pixel
+        cover = np.zeros(av.shape, dtype=np.int32)
+        for b in got:
+            t = av[b["frame"], b["y0"]:b["y0"] + b["bh"], b["x0"]:b["x0"] + b["bw"]]
+            assert (t == 0).any()
+            cover[b["frame"], b["y0"]:b["y0"] + b["bh"], b["x0"]:b["x0"] + b["bw"]] += 1
+        assert cover.max() == 1 and (cover[av == 0] == 1).all()
+    n = C.c_int32(-1)
+    L = _lib.lib()
+    assert L.fse_blocks_from_mask(av.ctypes.data_as(C.c_void_p), 2, 100, 150, 150, 16, 16, 64, 1, None, 0,
+                                  C.byref(n)) == 0 and n.value == len(fse.blocks_from_mask(av))
+    assert L.fse_blocks_from_mask(av.ctypes.data_as(C.c_void_p), 2, 100, 150, 100, 16, 16, 64, 1, None, 0,
+                                  C.byref(n)) == -1  # pitch < W
+    assert L.fse_blocks_from_mask(av.ctypes.data_as(C.c_void_p), 2, 100, 150, 150, 40, 16, 64, 1, None, 0,
+                                  C.byref(n)) == -2  # area larger than the transform

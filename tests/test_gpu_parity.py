@@ -11,14 +11,14 @@ from tests import parity
 pytestmark = pytest.mark.gpu
 
 
-def _run(wl, trace=True, rho=None, gamma=None):
+def _run(wl, trace=True, rho=None, gamma=None, masked=False):
     import torch
     import paper_2204_14193_amd as fse
     dev = torch.device("cuda:0")
     img = torch.from_numpy(wl.distorted).to(dev)
     av = torch.from_numpy(wl.avail).to(dev)
     out, status, tr = fse.extrapolate_batch(img, av, wl.blocks, wl.rho if rho is None else rho,
-                                            wl.gamma if gamma is None else gamma, trace=trace)
+                                            wl.gamma if gamma is None else gamma, trace=trace, masked=masked)
     return out.cpu().numpy(), status, tr
 
 
@@ -262,3 +262,56 @@ def test_graph_capture_replays_match_eager():
     del g
     batch.close()
     plan.close()
+
+
+def test_masked_loss_areas_parity():
+    """Arbitrary loss shapes: scribble losses in a 256x256 frame covered by
+    16x16 tiles (border 16, F=64, I=60), each block concealing only its
+    tile's lost pixels. Every block replayed against the oracle's
+    mask-driven loss area; frame PSNR within 0.01 dB; received pixels,
+    including those inside the tiles, untouched."""
+    wl = workloads.strokes_256()
+    part = sum(1 for b in wl.blocks
+               if (wl.avail[0, b["y0"]:b["y0"] + b["bh"], b["x0"]:b["x0"] + b["bw"]] != 0).any())
+    _say(f"case strokes-256 masked: {len(wl.blocks)} blocks ({part} partly received) F=64 I=60")
+    assert part > len(wl.blocks) // 2
+    out, st, tr = _run(wl, masked=True)
+    assert (st == 0).all()
+    rows = parity.check_blocks(wl.frames, wl.avail, wl.blocks, wl.rho, wl.gamma, tr, out, masked=True)
+    d, pg, po, pb = parity.psnr_delta(wl.frames, wl.avail, wl.blocks, wl.rho, wl.gamma, out, masked=True)
+    _say(f"ties={sum(r['ties'] for r in rows)} coef_max={max(r['coef_max'] for r in rows):.2e} "
+         f"pix={max(r['pix_maxabs'] for r in rows):.2e} psnr gpu={pg:.4f} oracle={po:.4f}")
+    assert d <= parity.PSNR_TOL
+    assert max(r["pix_maxabs"] for r in rows) < 0.05
+    recv = wl.avail != 0
+    assert np.array_equal(out[recv], wl.distorted[recv].astype(np.float32))
+
+
+def test_masked_plan_on_rectangular_losses_is_bitwise_plain():
+    """When every pixel of each rectangle is lost, the mask-driven plan is
+    the rectangular one: same selections, coefficients and output bits."""
+    wl = workloads.isolated_256(iters=40)
+    _say("case isolated-256 masked vs rectangular")
+    o1, s1, t1 = _run(wl)
+    o2, s2, t2 = _run(wl, masked=True)
+    assert (s1 == 0).all() and np.array_equal(s1, s2)
+    assert np.array_equal(o1, o2) and np.array_equal(t1, t2)
+
+
+def test_warm_start_refuses_masked_plans():
+    import torch
+    import paper_2204_14193_amd as fse
+    from paper_2204_14193_amd import warm
+    wl = workloads.subset(workloads.isolated_256(iters=0), [0, 1])
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(wl.distorted).to(dev)
+    av = torch.from_numpy(wl.avail).to(dev)
+    plan = fse.Plan(wl.rho, wl.gamma, 4096, masked=True)
+    batch = fse.Batch(plan, wl.blocks, *wl.frames.shape)
+    out = img.to(torch.float32)
+    st = torch.zeros(2, dtype=torch.int32, device=dev)
+    cand = torch.zeros((2, 256), dtype=torch.int16, device=dev)
+    flags = torch.zeros(2, dtype=torch.int32, device=dev)
+    with pytest.raises(fse.FseError) as e:
+        warm.warm_extrapolate(batch, img, av, out, st, cand, flags, 256, 10, 10)
+    assert e.value.code == -2
