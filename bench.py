@@ -269,6 +269,11 @@ def main():
     leg = legs["warm" if use_warm else "plain"]
     roof = warm_roof if use_warm else plain_roof
     achieved = roof["flop"] / (roof["ms"] * 1e-3) / 1e12
+    if masked:
+        lost_px = int(sum(int((wl.avail[int(b["frame"]), int(b["y0"]):int(b["y0"]) + int(b["bh"]),
+                                        int(b["x0"]):int(b["x0"]) + int(b["bw"])] == 0).sum()) for b in wl.blocks))
+    else:
+        lost_px = int(wl.blocks["bh"].astype(np.int64) @ wl.blocks["bw"].astype(np.int64))
     rec = {
         "metric": METRIC, "value": leg["blocks_per_s"], "unit": "blocks/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": leg["ms_per_step"],
@@ -279,6 +284,8 @@ def main():
                    "iters": int(wl.blocks["iters"][0]) if len(set(wl.blocks["iters"].tolist())) == 1 else "mixed",
                    "rho": wl.rho, "gamma": wl.gamma},
         "legs": legs,
+        # lost pixels concealed per second (each block's B; masked tiles count their lost pixels only)
+        "mpixel_per_s": lost_px / (leg["ms_per_step"] * 1e-3) / 1e6,
         "roofline": {"bound": "alu", "kernel": roof["kernel"], "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "frac_nonpacked": achieved / NONPACKED_FP32_TFLOPS, "kernel_ms": roof["ms"],

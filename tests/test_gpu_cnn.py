@@ -380,8 +380,18 @@ def test_warm_start_quality_bar_and_timing_hook():
         return 10 * np.log10(255.0 ** 2 / np.mean(e ** 2))
 
     p_plain, p_warm = psnr(out_p.cpu().numpy()), psnr(out_w.cpu().numpy())
-    _say(f"  plain {p_plain:.3f} dB, warm {p_warm:.3f} dB")
+    # what the network gains: plain FSE given about the warm start's time
+    # (half the iterations; the warm step costs about half of plain-100)
+    wl50 = wl.blocks.copy()
+    wl50["iters"] = 50
+    b50 = fse.Batch(plan, wl50, *wl.frames.shape)
+    out_50 = img.to(torch.float32)
+    b50.run(img, av, out_50, st_p)
+    torch.cuda.synchronize()
+    p_50 = psnr(out_50.cpu().numpy())
+    _say(f"  plain-100 {p_plain:.3f} dB, warm {p_warm:.3f} dB, plain-50 {p_50:.3f} dB")
     assert p_plain - p_warm <= 0.1
+    assert p_warm - p_50 >= 0.5
 
 
 def test_split_warm_large_blocks_use_the_list_synthesis():
