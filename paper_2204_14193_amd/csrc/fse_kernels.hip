@@ -713,7 +713,11 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
 }
 
 template <int F, int NT, int KC, int MODE>
-__global__ __launch_bounds__(NT) void fse_persistent(ClassArgs a) {
+// The transform kernel of the split warm start is held to 64 registers: with
+// its LDS (38 KB without the fused form's lists) four 512-thread workgroups
+// then share a compute unit.
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MODE == kWarmPrep ? 8 : 1))) void fse_persistent(
+    ClassArgs a) {
   using S = Shape<F, NT>;
   extern __shared__ __align__(16) unsigned char smem[];
   Lds s;
@@ -721,10 +725,12 @@ __global__ __launch_bounds__(NT) void fse_persistent(ClassArgs a) {
   s.tw = s.Wd + S::WROWS * F;
   s.red = reinterpret_cast<int4*>(s.tw + F);
   s.cl_c = reinterpret_cast<float2*>(s.red + 2 * S::NW);
+  // the distinct-bin lists of the restricted phase exist in the fused form only
+  constexpr int KCL = MODE == kWarmFused ? KC : 0;
   s.wl_c = s.cl_c + a.iters_cap;
-  s.cl_idx = reinterpret_cast<int*>(s.wl_c + KC);
+  s.cl_idx = reinterpret_cast<int*>(s.wl_c + KCL);
   s.wl_idx = s.cl_idx + a.iters_cap;
-  s.misc = s.wl_idx + KC;
+  s.misc = s.wl_idx + KCL;
 
   const int t = threadIdx.x;
   for (int i = t; i < F; i += NT) s.tw[i] = a.twid[i];
@@ -1055,7 +1061,7 @@ size_t lds_bytes(const Variant& v, int iters_cap) {
   const size_t nw = (size_t)v.threads / 64;
   const size_t rows = F + F / nw - 1;
   const size_t cap = (size_t)iters_cap;
-  const size_t kc = (size_t)v.kc;
+  const size_t kc = v.mode == kWarmFused ? (size_t)v.kc : 0;  // as KCL in the kernel
   return rows * F * 8 + F * 8 + 2 * nw * 16 + (cap + kc) * 8 + (cap + kc) * 4 + 16;
 }
 
