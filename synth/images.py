@@ -70,3 +70,19 @@ def synthetic_image(height, width, seed, n_waves=8, n_polygons=6, noise_sigma=2.
 def synthetic_frames(height, width, seeds):
     """Stack of independent frames, one per seed: ``uint8[len(seeds)][H][W]``."""
     return np.stack([synthetic_image(height, width, s) for s in seeds])
+
+
+def synthetic_clip(height, width, n_frames, seed, max_shift=3):
+    """A video clip: one synthetic image of a larger canvas, viewed through a
+    window that moves by a random integer translation of up to +-max_shift
+    pixels per frame (clamped to the canvas): ``uint8[n_frames][H][W]``."""
+    rng = np.random.default_rng(seed + 2 * 10 ** 6)
+    pad = max_shift * n_frames
+    canvas = synthetic_image(height + 2 * pad, width + 2 * pad, seed)
+    y = x = pad
+    out = np.empty((n_frames, height, width), dtype=np.uint8)
+    for f in range(n_frames):
+        out[f] = canvas[y:y + height, x:x + width]
+        y = int(np.clip(y + rng.integers(-max_shift, max_shift + 1), 0, 2 * pad))
+        x = int(np.clip(x + rng.integers(-max_shift, max_shift + 1), 0, 2 * pad))
+    return out

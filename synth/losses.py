@@ -22,6 +22,16 @@ BLOCK_DTYPE = np.dtype([("frame", "<i4"), ("y0", "<i4"), ("x0", "<i4"),
                         ("fft", "<i2"), ("iters", "<i4")])
 assert BLOCK_DTYPE.itemsize == 24
 
+#: Layout of one lost volume of a clip (three dimensions), identical to
+#: ``fse_volume_t`` in ``include/fse.h`` (32 bytes): B is bh x bw pixels of
+#: frames frame .. frame + bt - 1; its area grows it by ``border`` pixels and
+#: ``tborder`` frames on every side; fft x fft x fft_t transform.
+VOLUME_DTYPE = np.dtype([("frame", "<i4"), ("y0", "<i4"), ("x0", "<i4"),
+                         ("bt", "<i2"), ("bh", "<i2"), ("bw", "<i2"), ("border", "<i2"),
+                         ("tborder", "<i2"), ("fft", "<i2"), ("fft_t", "<i2"), ("pad", "<i2"),
+                         ("iters", "<i4")])
+assert VOLUME_DTYPE.itemsize == 32
+
 FFT_SIZES = (32, 64, 128)
 LOSS_SEED_OFFSET = 10 ** 6
 
@@ -186,3 +196,38 @@ def blocks_from_mask(avail, cell, border, fft, iters):
                 if (avail[f, y0:y0 + bh, x0:x0 + bw] == 0).any():
                     out.append(Block(f, y0, x0, bh, bw, border, fft, iters))
     return out
+
+
+def random_volume_losses(n_frames, height, width, bs, bt, fraction, seed, border, tborder, fft, fft_t, iters):
+    """Lost volumes of bs x bs pixels x bt frames on the (bt, bs, bs) grid of
+    the clip, drawn until ``fraction`` of the voxels are lost, no two
+    sharing a face, edge or corner of the grid (so every volume sees its
+    neighbourhood). Returns a VOLUME_DTYPE array, in grid order."""
+    rng = np.random.default_rng(seed + LOSS_SEED_OFFSET)
+    gt, gy, gx = n_frames // bt, height // bs, width // bs
+    taken = np.zeros((gt, gy, gx), dtype=bool)
+    want = int(round(fraction * gt * gy * gx))
+    order = rng.permutation(gt * gy * gx)
+    cells = []
+    for c in order:
+        if len(cells) >= want:
+            break
+        t, y, x = np.unravel_index(c, (gt, gy, gx))
+        if taken[max(t - 1, 0):t + 2, max(y - 1, 0):y + 2, max(x - 1, 0):x + 2].any():
+            continue
+        taken[t, y, x] = True
+        cells.append((t, y, x))
+    cells.sort()
+    out = np.zeros(len(cells), dtype=VOLUME_DTYPE)
+    for i, (t, y, x) in enumerate(cells):
+        out[i] = (t * bt, y * bs, x * bs, bt, bs, bs, border, tborder, fft, fft_t, 0, iters)
+    return out
+
+
+def volume_availability(shape, vols):
+    """``uint8`` mask (frames, H, W): 0 inside every lost volume, else 1."""
+    avail = np.ones(shape, dtype=np.uint8)
+    for v in vols:
+        f, y0, x0 = int(v["frame"]), int(v["y0"]), int(v["x0"])
+        avail[f:f + int(v["bt"]), y0:y0 + int(v["bh"]), x0:x0 + int(v["bw"])] = 0
+    return avail

@@ -8,9 +8,10 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .images import synthetic_image
+from .images import synthetic_clip, synthetic_image
 from .losses import (array_to_blocks, availability_mask, blocks_from_mask, blocks_to_array,
-                     isolated_grid_losses, mixed_size_losses, random_grid_losses, stroke_mask)
+                     isolated_grid_losses, mixed_size_losses, random_grid_losses, random_volume_losses,
+                     stroke_mask, volume_availability)
 
 
 @dataclass
@@ -103,3 +104,19 @@ def subset(w, idx):
     dropped blocks stay marked lost, so every kept block sees exactly the
     availability it had in the full workload."""
     return Workload(w.name + "-subset", w.frames, w.avail, w.blocks[np.asarray(idx)], w.rho, w.gamma)
+
+
+def clip_1080p_16x16x2(n_frames=16, seed=41, iters=200, fraction=0.05):
+    """A 1920x1080x16-frame clip (one synthetic image moving by up to +-3 px
+    per frame), 16x16x2 lost volumes at 5% of the volume grid, border 16 in
+    space and 2 in time (48x48x6 area), 64x64x8 transform."""
+    frames = synthetic_clip(1080, 1920, n_frames, seed)
+    vols = random_volume_losses(n_frames, 1080, 1920, 16, 2, fraction, seed, 16, 2, 64, 8, iters)
+    return Workload("clip-1080p-16x16x2", frames, volume_availability(frames.shape, vols), vols, 0.8, 0.5)
+
+
+def clip_small(n_frames=8, seed=43, iters=40, fraction=0.05):
+    """A 256x256x8-frame clip, 16x16x2 lost volumes (border 16, 2), 64x64x8."""
+    frames = synthetic_clip(256, 256, n_frames, seed)
+    vols = random_volume_losses(n_frames, 256, 256, 16, 2, fraction, seed, 16, 2, 64, 8, iters)
+    return Workload("clip-256", frames, volume_availability(frames.shape, vols), vols, 0.8, 0.5)

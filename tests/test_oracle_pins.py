@@ -392,3 +392,75 @@ def test_masked_loss_area_uses_received_pixels_of_the_rectangle():
     frames[0, y0 + changed[0], x0 + changed[1]] ^= 0x40
     other = cfse.extrapolate_block(frames, wl.avail, blk, 0.8, 0.5, masked=True)
     assert not np.array_equal(other["values"][res["lost"]], res["values"][res["lost"]])
+
+
+# ------------------------------------------------------------ 3-D (video)
+
+def _vol(**kw):
+    from synth import losses
+    v = np.zeros(1, dtype=losses.VOLUME_DTYPE)[0]
+    for k, x in kw.items():
+        v[k] = x
+    return v
+
+
+def test_3d_reduces_to_2d_with_one_frame():
+    """A single-frame volume with a one-point temporal transform is the 2-D
+    algorithm: the same selections, coefficients and values."""
+    from oracle import cfse3
+    from synth import workloads
+    wl = workloads.isolated_256(iters=25)
+    b = wl.blocks[27]
+    r2 = cfse.extrapolate_block(wl.frames, wl.avail, b, 0.8, 0.5)
+    v = _vol(frame=0, y0=b["y0"], x0=b["x0"], bt=1, bh=b["bh"], bw=b["bw"], border=b["border"],
+             tborder=0, fft=b["fft"], fft_t=1, iters=25)
+    r3 = cfse3.extrapolate_volume(wl.frames, wl.avail, v, 0.8, 0.5)
+    assert r3["seq"] == r2["seq"]
+    np.testing.assert_allclose(r3["chat"], r2["chat"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(r3["values"][:, :, 0], r2["values"], rtol=0, atol=1e-9)
+
+
+def test_3d_projection_is_dft_bruteforce():
+    """eq. (7) in 3-D: the separable projection equals the triple sum."""
+    from oracle import cfse3
+    rng = np.random.default_rng(4)
+    M, N, T, F, Ft = 3, 4, 2, 4, 4
+    x = rng.normal(size=(M, N, T)) + 1j * rng.normal(size=(M, N, T))
+    got = cfse3.project(x, cfse.analysis_matrix(F, M), cfse.analysis_matrix(F, N), cfse.analysis_matrix(Ft, T))
+    ref = np.zeros((F, F, Ft), dtype=complex)
+    for k in range(F):
+        for l in range(F):
+            for s in range(Ft):
+                for m in range(M):
+                    for n in range(N):
+                        for t in range(T):
+                            ref[k, l, s] += x[m, n, t] * cmath.exp(-2j * math.pi * (k * m / F + l * n / F + s * t / Ft))
+    np.testing.assert_allclose(got, ref, atol=1e-12)
+
+
+@pytest.mark.parametrize("k0,l0,s0", [(0, 0, 0), (3, 5, 1), (7, 1, 3)])
+def test_3d_single_basis_function(k0, l0, s0):
+    """A signal that is one 3-D basis function on the support is recovered
+    exactly in one iteration with gamma = 1, also on the loss volume."""
+    from oracle import cfse3
+    F, Ft, M, N, T = 8, 4, 6, 6, 4
+    phi = cfse3.basis(F, Ft, M, N, T, k0, l0, s0)
+    A = np.ones((M, N, T), dtype=bool)
+    A[2:4, 2:4, 1:3] = False
+    w = np.where(A, cfse3.window(M, N, T, 0.8), 0.0)
+    res = cfse3.cfse3(np.where(A, phi, 0), w, F, Ft, 1.0, 1)
+    assert res["seq"] == [(k0 * F + l0) * Ft + s0]
+    np.testing.assert_allclose(res["g"], phi, atol=1e-12)
+
+
+def test_3d_energy_monotone():
+    """Weighted residual energy never increases for 0 < gamma <= 1."""
+    from oracle import cfse3
+    rng = np.random.default_rng(9)
+    M, N, T = 10, 10, 4
+    s = rng.normal(size=(M, N, T)) * 20 + 100
+    A = rng.random((M, N, T)) > 0.2
+    w = np.where(A, cfse3.window(M, N, T, 0.8), 0.0)
+    for gamma in (0.3, 1.0):
+        e = cfse3.cfse3(np.where(A, s, 0), w, 16, 8, gamma, 12)["energy"]
+        assert all(b <= a * (1 + 1e-12) for a, b in zip(e, e[1:]))
