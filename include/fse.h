@@ -73,6 +73,22 @@ typedef struct {
   int32_t iters;
 } fse_block_t;
 
+/* One lost volume of a video clip (three dimensions): B is bh x bw pixels
+ * at (y0, x0) in frames frame .. frame + bt - 1; its area extends `border`
+ * pixels and `tborder` frames beyond B on every side (M x N x T =
+ * (bh + 2 border) x (bw + 2 border) x (bt + 2 tborder)), transformed on an
+ * fft x fft x fft_t grid (64 x 64 x 8 in this library). `pad` must be 0.
+ * 32 bytes, natural alignment. */
+typedef struct {
+  int32_t frame;
+  int32_t y0, x0;
+  int16_t bt, bh, bw;
+  int16_t border, tborder;
+  int16_t fft, fft_t;
+  int16_t pad;
+  int32_t iters;
+} fse_volume_t;
+
 /* Plan parameters shared by every block run with the plan. */
 typedef struct {
   float rho;          /* window decay rho in (0, 1], eq. (3)                  */
@@ -90,7 +106,8 @@ typedef struct {
 #define FSE_PLAN_MASKED_B 1u
 
 /* One record per block and iteration when tracing: selected bin (u, v),
- * coefficient c of eq. (13) and |R_w[u,v]|^2 as seen by the argmax. */
+ * coefficient c of eq. (13) and |R_w[u,v]|^2 as seen by the argmax. For a
+ * volume, u = k and v = l * fft_t + s for the selected bin (k, l, s). */
 typedef struct {
   uint16_t u, v;
   float c_re, c_im;
@@ -309,6 +326,35 @@ fse_status_t fse_warm_extrapolate_batch(fse_batch_t batch, const uint8_t* d_imag
 
 /* restricted_iters + max(largest block iteration count, fallback_iters). */
 int32_t fse_warm_trace_stride(fse_batch_t batch, int32_t restricted_iters, int32_t fallback_iters);
+
+/* ------------------------------------------------------------------------
+ * Three dimensions (video). cFSE extends to more dimensions (Section II and
+ * the Conclusion): the same iteration on an F x F x Ft grid, the window
+ * rho^(distance) in pixel and frame units, B a lost volume. One workgroup
+ * of 1024 threads per volume: R_w in registers (32 bins per thread), the
+ * half of W with l <= 32 in LDS (132 KB), the transform as 2-D FFTs of the
+ * frames followed by Ft-point DFTs through a scratch buffer in HBM.
+ *
+ * fse_batch3d_create validates h_volumes (fft = 64, fft_t = 8, area within
+ * the transform, B inside the clip, 0 <= iters <= the plan's max_iters, no
+ * two B overlapping; the plan must not have FSE_PLAN_MASKED_B), uploads
+ * them, the 3-D window table and the scratch buffers (256 KB per resident
+ * workgroup) to the current device. Synchronous. *bad_index (if not null)
+ * receives the first offending volume or -1. */
+typedef struct fse_batch3d_s* fse_batch3d_t;
+fse_status_t fse_batch3d_create(fse_plan_t plan, const fse_volume_t* h_volumes, int32_t n_volumes,
+                                int32_t n_frames, int32_t H, int32_t W, fse_batch3d_t* out_batch,
+                                int32_t* bad_index);
+void fse_batch3d_destroy(fse_batch3d_t batch);
+
+/* Conceal every volume of the batch: frames and avail are uint8
+ * [n_frames][H][pitch], d_out float32 [n_frames][H][out_pitch] (only the
+ * voxels of each B are written), d_status int32 [n_volumes] (FSE_BLOCK_*),
+ * d_trace null or fse_trace_t [n_volumes][max iters of the batch].
+ * Asynchronous on `stream`; no allocation. */
+fse_status_t fse_extrapolate3d_batch(fse_batch3d_t batch, const uint8_t* d_frames, const uint8_t* d_avail,
+                                     int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
+                                     fse_trace_t* d_trace, void* stream);
 
 /* Static description of the most recent error on this thread (never null). */
 const char* fse_last_error(void);

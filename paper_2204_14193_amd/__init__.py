@@ -5,8 +5,9 @@ declared in ``include/fse.h``); this package only marshals arguments. There
 is no CPU fallback: if the library is not built, importing the binding
 raises.
 """
-from .fse import (Plan, Batch, extrapolate_batch, blocks_from_mask, BLOCK_DTYPE, TRACE_DTYPE,
-                  BLOCK_OK, BLOCK_EMPTY_SUPPORT, BLOCK_NONFINITE, FseError)
+from .fse import (Plan, Batch, Batch3d, extrapolate_batch, extrapolate3d, blocks_from_mask, BLOCK_DTYPE,
+                  VOLUME_DTYPE, TRACE_DTYPE, BLOCK_OK, BLOCK_EMPTY_SUPPORT, BLOCK_NONFINITE, FseError)
 
-__all__ = ["Plan", "Batch", "extrapolate_batch", "blocks_from_mask", "BLOCK_DTYPE", "TRACE_DTYPE",
+__all__ = ["Plan", "Batch", "Batch3d", "extrapolate_batch", "extrapolate3d", "blocks_from_mask", "BLOCK_DTYPE",
+           "VOLUME_DTYPE", "TRACE_DTYPE",
            "BLOCK_OK", "BLOCK_EMPTY_SUPPORT", "BLOCK_NONFINITE", "FseError"]

@@ -11,6 +11,13 @@ class fse_block_t(C.Structure):
                 ("fft", C.c_int16), ("iters", C.c_int32)]
 
 
+class fse_volume_t(C.Structure):
+    _fields_ = [("frame", C.c_int32), ("y0", C.c_int32), ("x0", C.c_int32),
+                ("bt", C.c_int16), ("bh", C.c_int16), ("bw", C.c_int16), ("border", C.c_int16),
+                ("tborder", C.c_int16), ("fft", C.c_int16), ("fft_t", C.c_int16), ("pad", C.c_int16),
+                ("iters", C.c_int32)]
+
+
 class fse_plan_desc_t(C.Structure):
     _fields_ = [("rho", C.c_float), ("gamma", C.c_float), ("max_iters", C.c_int32),
                 ("flags", C.c_uint32)]
@@ -32,6 +39,9 @@ SIGNATURES = {
     "fse_plan_destroy": (None, [P]),
     "fse_validate_blocks": (I32, [P, P, I32, I32, I32, I32, PI32]),
     "fse_blocks_from_mask": (I32, [P, I32, I32, I32, I64, I32, I32, I32, I32, P, I32, PI32]),
+    "fse_batch3d_create": (I32, [P, P, I32, I32, I32, I32, C.POINTER(P), PI32]),
+    "fse_batch3d_destroy": (None, [P]),
+    "fse_extrapolate3d_batch": (I32, [P, P, P, I64, P, I64, P, P, P]),
     "fse_batch_create": (I32, [P, P, I32, I32, I32, I32, C.POINTER(P)]),
     "fse_batch_destroy": (None, [P]),
     "fse_batch_max_iters": (I32, [P]),

@@ -673,3 +673,168 @@ extern "C" fse_status_t fse_warm_extrapolate_batch(fse_batch_t batch, const uint
   return launch_one(batch, ci, d_image, d_avail, pitch, d_out, out_pitch, d_status, d_trace,
                     reinterpret_cast<hipStream_t>(stream), d_cand, d_flags);
 }
+
+// ------------------------------------------------------------ 3-D (video)
+
+struct fse_batch3d_s {
+  fse_plan_t plan = nullptr;
+  int device = 0;
+  int32_t n = 0, n_frames = 0, H = 0, W = 0, max_iters = 0;
+  int32_t grid = 0;
+  size_t lds = 0;
+  const DeviceTables* tables = nullptr;
+  fse_volume_t* d_vols = nullptr;
+  float* d_wtab3 = nullptr;
+  float2* d_scratch = nullptr;
+};
+
+namespace {
+void free_batch3d(fse_batch3d_s* b) {
+  (void)hipFree(b->d_vols);
+  (void)hipFree(b->d_wtab3);
+  (void)hipFree(b->d_scratch);
+  delete b;
+}
+
+fse_status_t validate_volumes(fse_plan_t plan, const fse_volume_t* v, int32_t n, int32_t n_frames, int32_t H,
+                              int32_t W, int32_t* bad) {
+  if (bad) *bad = -1;
+  if (!plan) return fail(FSE_ERR_INVALID_ARG, "null plan");
+  if (plan->flags & FSE_PLAN_MASKED_B) return fail(FSE_ERR_UNSUPPORTED, "volumes need rectangular loss areas");
+  if (n < 0 || (n > 0 && !v)) return fail(FSE_ERR_INVALID_ARG, "bad volume list");
+  if (n_frames <= 0 || H <= 0 || W <= 0) return fail(FSE_ERR_INVALID_ARG, "clip dimensions must be positive");
+  for (int32_t i = 0; i < n; ++i) {
+    const fse_volume_t& b = v[i];
+    if (bad) *bad = i;
+    if (b.fft != fse::kF3 || b.fft_t != fse::kFt3) return fail(FSE_ERR_UNSUPPORTED, "volumes need a 64 x 64 x 8 transform");
+    if (b.pad != 0) return fail(FSE_ERR_INVALID_ARG, "pad must be 0");
+    if (b.bt < 1 || b.bh < 1 || b.bw < 1 || b.border < 0 || b.tborder < 0)
+      return fail(FSE_ERR_INVALID_ARG, "volume size must be >= 1, borders >= 0");
+    if (b.bh + 2 * b.border > b.fft || b.bw + 2 * b.border > b.fft || b.bt + 2 * b.tborder > b.fft_t)
+      return fail(FSE_ERR_UNSUPPORTED, "area larger than the transform");
+    if (b.iters < 0 || b.iters > plan->max_iters) return fail(FSE_ERR_INVALID_ARG, "iters outside [0, max_iters]");
+    if (b.frame < 0 || (int64_t)b.frame + b.bt > n_frames || b.y0 < 0 || b.x0 < 0 || (int64_t)b.y0 + b.bh > H ||
+        (int64_t)b.x0 + b.bw > W)
+      return fail(FSE_ERR_INVALID_ARG, "lost volume outside the clip");
+  }
+  const size_t nvox = (size_t)n_frames * H * W;
+  std::vector<uint64_t> bits((nvox + 63) / 64, 0);
+  for (int32_t i = 0; i < n; ++i) {
+    const fse_volume_t& b = v[i];
+    for (int f = b.frame; f < b.frame + b.bt; ++f)
+      for (int y = b.y0; y < b.y0 + b.bh; ++y)
+        for (int x = b.x0; x < b.x0 + b.bw; ++x) {
+          const size_t p = ((size_t)f * H + y) * W + x;
+          const uint64_t m = 1ull << (p & 63);
+          if (bits[p >> 6] & m) {
+            if (bad) *bad = i;
+            return fail(FSE_ERR_OVERLAP, "loss volumes of two entries overlap");
+          }
+          bits[p >> 6] |= m;
+        }
+  }
+  if (bad) *bad = -1;
+  return FSE_OK;
+}
+}  // namespace
+
+extern "C" fse_status_t fse_batch3d_create(fse_plan_t plan, const fse_volume_t* h_volumes, int32_t n_volumes,
+                                           int32_t n_frames, int32_t H, int32_t W, fse_batch3d_t* out_batch,
+                                           int32_t* bad_index) {
+  if (!out_batch) return fail(FSE_ERR_INVALID_ARG, "null argument");
+  *out_batch = nullptr;
+  fse_status_t st = validate_volumes(plan, h_volumes, n_volumes, n_frames, H, W, bad_index);
+  if (st != FSE_OK) return st;
+  fse_batch3d_s* b = new (std::nothrow) fse_batch3d_s;
+  if (!b) return fail(FSE_ERR_OOM, "host allocation failed");
+  b->plan = plan;
+  b->n = n_volumes;
+  b->n_frames = n_frames;
+  b->H = H;
+  b->W = W;
+  for (int32_t i = 0; i < n_volumes; ++i) b->max_iters = std::max(b->max_iters, h_volumes[i].iters);
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&b->device) != hipSuccess || hipGetDeviceProperties(&prop, b->device) != hipSuccess) {
+    delete b;
+    return fail(FSE_ERR_HIP, "hipGetDevice failed");
+  }
+  b->lds = fse::lds_bytes3d(std::max(b->max_iters, 1));
+  const void* fn = fse::fse3d_kernel();
+  int per_cu = 0;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, fse::kNT3, b->lds) != hipSuccess || per_cu < 1) {
+    delete b;
+    return fail(FSE_ERR_UNSUPPORTED, "3-D kernel does not fit on a compute unit (iteration count too large)");
+  }
+  b->grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(n_volumes, (int64_t)per_cu * prop.multiProcessorCount));
+  st = upload_tables(plan, b->device, &b->tables);
+  if (st != FSE_OK) {
+    delete b;
+    return st;
+  }
+  // eq. (3) in 3-D: rho^(sqrt(a^2 + b^2 + c^2) / 2) for doubled offsets, FP64, rounded once
+  const int S = fse::kWinStride, ST = fse::kWinStrideT;
+  std::vector<float> w3((size_t)ST * S * S);
+  for (int c = 0; c < ST; ++c)
+    for (int a = 0; a < S; ++a)
+      for (int d = 0; d < S; ++d)
+        w3[((size_t)c * S + a) * S + d] =
+            (float)std::pow((double)plan->rho, 0.5 * std::sqrt((double)a * a + (double)d * d + (double)c * c));
+  const size_t nv = (size_t)std::max(n_volumes, 1);
+  if (hipMalloc(&b->d_vols, nv * sizeof(fse_volume_t)) != hipSuccess ||
+      hipMalloc(&b->d_wtab3, w3.size() * sizeof(float)) != hipSuccess ||
+      hipMalloc(&b->d_scratch, (size_t)b->grid * fse::kFt3 * fse::kF3 * fse::kF3 * sizeof(float2)) != hipSuccess) {
+    free_batch3d(b);
+    return fail(FSE_ERR_OOM, "hipMalloc failed (3-D batch)");
+  }
+  if ((n_volumes > 0 && hipMemcpy(b->d_vols, h_volumes, (size_t)n_volumes * sizeof(fse_volume_t),
+                                  hipMemcpyHostToDevice) != hipSuccess) ||
+      hipMemcpy(b->d_wtab3, w3.data(), w3.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+    free_batch3d(b);
+    return fail(FSE_ERR_HIP, "upload failed (3-D batch)");
+  }
+  *out_batch = b;
+  return FSE_OK;
+}
+
+extern "C" void fse_batch3d_destroy(fse_batch3d_t batch) {
+  if (!batch) return;
+  (void)hipDeviceSynchronize();
+  free_batch3d(batch);
+}
+
+extern "C" fse_status_t fse_extrapolate3d_batch(fse_batch3d_t batch, const uint8_t* d_frames, const uint8_t* d_avail,
+                                                int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
+                                                fse_trace_t* d_trace, void* stream) {
+  if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
+  if (batch->n == 0) return FSE_OK;
+  if (!d_frames || !d_avail || !d_out || !d_status) return fail(FSE_ERR_INVALID_ARG, "null device pointer");
+  if (pitch < batch->W || out_pitch < batch->W) return fail(FSE_ERR_INVALID_ARG, "pitch smaller than the width");
+  if ((int64_t)batch->H * pitch >= ((int64_t)1 << 31))
+    return fail(FSE_ERR_INVALID_ARG, "a frame (H x pitch bytes) must be smaller than 2 GiB");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != batch->device)
+    return fail(FSE_ERR_INVALID_ARG, "batch was created on another device");
+  fse::Vol3Args a;
+  a.img = d_frames;
+  a.avail = d_avail;
+  a.pitch = pitch;
+  a.out = d_out;
+  a.out_pitch = out_pitch;
+  a.n_frames = batch->n_frames;
+  a.H = batch->H;
+  a.W = batch->W;
+  a.vols = batch->d_vols;
+  a.n = batch->n;
+  a.iters_cap = std::max(batch->max_iters, 1);
+  a.status = d_status;
+  a.trace = d_trace;
+  a.trace_stride = batch->max_iters;
+  a.wtab3 = batch->d_wtab3;
+  a.twid = batch->tables->twid[class_of(fse::kF3)];
+  a.gamma = batch->plan->gamma;
+  a.scratch = batch->d_scratch;
+  if (fse::launch_fse3d(a, batch->grid, batch->lds, reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+    return fail(FSE_ERR_HIP, "kernel launch failed (3-D)");
+  return FSE_OK;
+}

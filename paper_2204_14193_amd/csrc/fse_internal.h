@@ -50,6 +50,37 @@ struct ClassArgs {
 // the others follow from W[-k, -l] = conj(W[k, l]) (w is real).
 constexpr int kHalfRows = 33;
 
+// Three dimensions: one workgroup of kNT3 threads per volume, F x F x Ft
+// transform with F = 64, Ft = 8.
+constexpr int kF3 = 64, kFt3 = 8, kNT3 = 1024;
+constexpr int kHalfCols3 = kF3 / 2 + 1;  // W kept for l <= 32
+// 3-D window table: wtab3[(c * kWinStride + a) * kWinStride + b] =
+// rho^(sqrt(a*a + b*b + c*c) / 2) for doubled integer offsets a, b, c.
+constexpr int kWinStrideT = 16;
+
+struct Vol3Args {
+  const uint8_t* img;    // [n_frames][H][pitch]
+  const uint8_t* avail;  // [n_frames][H][pitch]
+  int64_t pitch;
+  float* out;            // [n_frames][H][out_pitch]
+  int64_t out_pitch;
+  int32_t n_frames, H, W;
+  const fse_volume_t* vols;
+  int32_t n;
+  int32_t iters_cap;
+  int32_t* status;
+  fse_trace_t* trace;    // null or [n][trace_stride]
+  int32_t trace_stride;
+  const float* wtab3;
+  const float2* twid;    // 64 entries exp(-j 2 pi q / 64)
+  float gamma;
+  float2* scratch;       // [grid][kFt3][kF3][kF3]
+};
+
+size_t lds_bytes3d(int iters_cap);
+hipError_t launch_fse3d(const Vol3Args& a, int grid, size_t lds, hipStream_t s);
+const void* fse3d_kernel();
+
 // Kernel modes.
 enum Mode : int { kPlain = 0, kWarmFused = 1, kWarmPrep = 2 };
 

@@ -1003,6 +1003,242 @@ const Variant kVariants[] = {
     make_variant<64, 512, 512, kWarmPrep>(), make_variant<64, 512, 384, kWarmPrep>(),
 };
 
+
+// ------------------------------------------------------------ 3-D (video)
+// cFSE of one lost volume per workgroup of kNT3 = 1024 threads, F = 64,
+// Ft = 8 (the iteration of Section III on a 3-D grid). Thread t owns the 32
+// bins with linear index (k F + l) Ft + s = 32 t + j, i.e. the columns
+// (k, l) = 4 t + j / 8 and s = j % 8, so lane, wave and j order is the
+// bin order and the lowest-index tie-break of the argmax falls out of
+// "first maximum". LDS holds W for l <= 32 as [l][k][s] (the other half is
+// W[-k,-l,-s] conjugated), 132 KB; before that the same bytes hold four
+// 64 x 64 FFT buffers.
+__device__ __forceinline__ uint32_t bits_max_first(uint32_t bits, uint32_t& best) {
+  return bits > best ? (best = bits, 1u) : 0u;
+}
+
+__global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
+  constexpr int F = kF3, FT = kFt3, NT = kNT3, BPT = F * F * FT / NT;  // 32 bins per thread
+  constexpr int WH = kHalfCols3 * F * FT;                              // 16896 entries of W
+  extern __shared__ __align__(16) unsigned char smem[];
+  float2* const Wl = reinterpret_cast<float2*>(smem);
+  float2* const tw = Wl + WH;
+  int4* const xch = reinterpret_cast<int4*>(tw + F);                   // 2 x 16 argmax slots
+  float2* const cl_c = reinterpret_cast<float2*>(xch + 2 * (NT / 64));
+  int* const cl_idx = reinterpret_cast<int*>(cl_c + a.iters_cap);
+  static_assert(4 * F * F <= WH, "four FFT buffers fit the W region");
+  const int t0 = threadIdx.x;
+  if (t0 < F) tw[t0] = a.twid[t0];
+  float2* const Z = a.scratch + (int64_t)blockIdx.x * (FT * F * F);
+  int parity = 0;
+  for (int vi = blockIdx.x; vi < a.n; vi += gridDim.x) {
+    // opaque thread index: keeps index-derived addresses out of the volume loop
+    int t = t0;
+    asm volatile("" : "+v"(t));
+    const int wave = t >> 6;
+    const fse_volume_t* vp = a.vols + vi;
+    const int f0 = __builtin_amdgcn_readfirstlane(vp->frame);
+    const int y0 = __builtin_amdgcn_readfirstlane(vp->y0), x0 = __builtin_amdgcn_readfirstlane(vp->x0);
+    const int bt = __builtin_amdgcn_readfirstlane(vp->bt), bh = __builtin_amdgcn_readfirstlane(vp->bh);
+    const int bw = __builtin_amdgcn_readfirstlane(vp->bw), bd = __builtin_amdgcn_readfirstlane(vp->border);
+    const int td = __builtin_amdgcn_readfirstlane(vp->tborder), I = __builtin_amdgcn_readfirstlane(vp->iters);
+    const int M = bh + 2 * bd, N = bw + 2 * bd, T = bt + 2 * td;
+    const int ya = y0 - bd, xa = x0 - bd, ta = f0 - td;
+
+    // 1. gather, window (eq. (3)), z = s w + j alpha w, and the 2-D FFT of
+    // every frame of the area; four frames at a time, one per 256 threads
+    {
+      const int g = t >> 8, tg = t & 255;
+      float2* const buf = Wl + g * (F * F);
+      for (int r0 = 0; r0 < T; r0 += 4) {
+        const int sl = r0 + g;
+        const int f = ta + sl;
+        const bool frame_ok = sl < T && f >= 0 && f < a.n_frames;
+        const uint8_t* img = a.img + (int64_t)(frame_ok ? f : 0) * a.H * a.pitch;
+        const uint8_t* av = a.avail + (int64_t)(frame_ok ? f : 0) * a.H * a.pitch;
+        const int dc = min(abs(2 * sl - (T - 1)), kWinStrideT - 1);
+        for (int e = tg; e < F * F; e += 256) {
+          const int m = e / F, n = e % F;
+          const int y = ya + m, x = xa + n;
+          const bool inB = m >= bd && m < bd + bh && n >= bd && n < bd + bw && sl >= td && sl < td + bt;
+          bool use = frame_ok && m < M && n < N && !inB && y >= 0 && y < a.H && x >= 0 && x < a.W;
+          float2 z = make_float2(0.f, 0.f);
+          if (use) {
+            const uint32_t p = (uint32_t)(y * (int)a.pitch + x);
+            if (av[p] != 0) {
+              const int da = min(abs(2 * m - (M - 1)), kWinStride - 1), db = min(abs(2 * n - (N - 1)), kWinStride - 1);
+              const float w = a.wtab3[(dc * kWinStride + da) * kWinStride + db];
+              z = make_float2((float)img[p] * w, kAlpha * w);
+            }
+          }
+          buf[e] = z;
+        }
+        __syncthreads();
+        fft_lines<F, 256, false>(buf, tw, tg);
+        fft_lines<F, 256, true>(buf, tw, tg);
+        if (sl < T)
+          for (int e = tg; e < F * F; e += 256) Z[sl * (F * F) + e] = buf[e];
+        __syncthreads();  // the buffers are reused; the scratch is read by other threads
+      }
+    }
+    // 2. Ft-point DFT along time of every column (k, l), in place in the
+    // scratch (a thread reads and writes only its own columns)
+    for (int c = t; c < F * F; c += NT) {
+      float2 zt[FT];
+#pragma unroll
+      for (int q = 0; q < FT; ++q) zt[q] = q < T ? Z[q * (F * F) + c] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int sq = 0; sq < FT; ++sq) {
+        float2 acc = zt[0];
+#pragma unroll
+        for (int q = 1; q < FT; ++q) acc = cadd(acc, cmul(zt[q], tw[(sq * q * (F / FT)) & (F - 1)]));
+        Z[sq * (F * F) + c] = acc;
+      }
+    }
+    __syncthreads();
+    // 3. split Z = R_w + j alpha W by conjugate symmetry: R_w of the
+    // thread's bins into registers, W for l <= 32 into LDS
+    float Rx[BPT], Ry[BPT];
+    int xkl[BPT / FT];  // packed (k, l) of the thread's columns: k * 2^14 + l * 2^7
+#pragma unroll
+    for (int cc = 0; cc < BPT / FT; ++cc) {
+      const int c = (BPT / FT) * t + cc, k = c / F, l = c % F;
+      xkl[cc] = (k << 14) | (l << 7);
+#pragma unroll
+      for (int s3 = 0; s3 < FT; ++s3) {
+        const float2 zk = Z[s3 * (F * F) + c];
+        const float2 zn = Z[((FT - s3) & (FT - 1)) * (F * F) + ((F - k) & (F - 1)) * F + ((F - l) & (F - 1))];
+        Rx[cc * FT + s3] = (zk.x + zn.x) * 0.5f;
+        Ry[cc * FT + s3] = (zk.y - zn.y) * 0.5f;
+      }
+    }
+    for (int e = t; e < WH; e += NT) {
+      const int l = e / (F * FT), k = (e / FT) % F, s3 = e % FT;
+      const float2 zk = Z[s3 * (F * F) + k * F + l];
+      const float2 zn = Z[((FT - s3) & (FT - 1)) * (F * F) + ((F - k) & (F - 1)) * F + ((F - l) & (F - 1))];
+      Wl[e] = make_float2((zk.y + zn.y) * (0.5f / kAlpha), (zn.x - zk.x) * (0.5f / kAlpha));
+    }
+    __syncthreads();
+    const float W0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(Wl[0].x)));
+    if (!(W0 > 0.f)) {
+      if (t == 0) a.status[vi] = FSE_BLOCK_EMPTY_SUPPORT;
+      __syncthreads();  // Wl and the scratch are overwritten by the next volume
+      continue;
+    }
+    const float gW = a.gamma * (1.0f / W0);
+    // per-thread first maximum of |R_w|^2 (bits) and where it is
+    uint32_t best = 0;
+    int bj = 0;
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const uint32_t b2 = __float_as_uint(fmaf(Ry[j], Ry[j], Rx[j] * Rx[j]));
+      if (bits_max_first(b2, best)) bj = j;
+    }
+    bool finite = true;
+    // 4. iterations (eqs. (12), (13), (18))
+    for (int it = 0; it < I; ++it) {
+      // the thread's candidate, then the wave's (first lane), then the
+      // workgroup's (first wave)
+      float bre = 0.f, bim = 0.f;
+#pragma unroll
+      for (int j = 0; j < BPT; ++j) {
+        bre = j == bj ? Rx[j] : bre;
+        bim = j == bj ? Ry[j] : bim;
+      }
+      const uint32_t wm = wave_max_bits(best);
+      const unsigned long long hits = __ballot(best == wm);
+      const int wl = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(hits));
+      const int widx = __builtin_amdgcn_readlane(BPT * t + bj, wl);
+      const float wre = readlane_f(bre, wl), wim = readlane_f(bim, wl);
+      xch[parity * (NT / 64) + wave] = make_int4((int)wm, widx, __float_as_int(wre), __float_as_int(wim));  // uniform
+      __syncthreads();
+      uint32_t gm = 0;
+      int gidx = 0;
+      float gre = 0.f, gim = 0.f;
+#pragma unroll
+      for (int w2 = 0; w2 < NT / 64; ++w2) {
+        const int4 v = xch[parity * (NT / 64) + w2];
+        const uint32_t m2 = (uint32_t)__builtin_amdgcn_readfirstlane(v.x);
+        const bool take = w2 == 0 || m2 > gm;  // the first wave wins ties (lower bins)
+        gm = take ? m2 : gm;
+        gidx = take ? __builtin_amdgcn_readfirstlane(v.y) : gidx;
+        gre = take ? __int_as_float(__builtin_amdgcn_readfirstlane(v.z)) : gre;
+        gim = take ? __int_as_float(__builtin_amdgcn_readfirstlane(v.w)) : gim;
+      }
+      parity ^= 1;
+      const int s3 = gidx & (FT - 1), v = (gidx >> 3) & (F - 1), u = gidx >> 9;
+      const float cre = gW * gre, cim = gW * gim;  // eq. (13)
+      finite = finite && isfinite(cre) && isfinite(cim);
+      if (wave == 0) {
+        cl_idx[it] = gidx;  // uniform stores
+        cl_c[it] = make_float2(cre, cim);
+        if (a.trace) {
+          fse_trace_t rec;
+          rec.u = (uint16_t)u;
+          rec.v = (uint16_t)(v * FT + s3);
+          rec.c_re = cre;
+          rec.c_im = cim;
+          rec.r2 = __uint_as_float(gm);
+          a.trace[(int64_t)vi * a.trace_stride + it] = rec;
+        }
+      }
+      // eq. (18): R_w[k,l,s] -= c W[k-u, l-v, s-s0], W from [l'][k'][s'] when
+      // l' = (l - v) mod 64 <= 32, else the conjugate of W[u-k, v-l, s0-s].
+      // Packed bins k * 2^14 + l * 2^7 + s: adding (64-u) 2^14 + (64-v) 2^7 +
+      // (8-s0) gives all three differences plus their offsets without borrows.
+      int ca = ((F - u) << 14) + ((F - v) << 7) + (FT - s3);
+      int cb = ((F + u) << 14) + ((F + v) << 7) + (FT + s3);
+      asm volatile("" : "+s"(ca), "+s"(cb));
+      best = 0;
+      bj = 0;
+#pragma unroll
+      for (int j = 0; j < BPT; ++j) {
+        const int xa = xkl[j / FT] + (j % FT);
+        const int yA = xa + ca, yB = cb - xa;
+        const bool flip = ((yA >> 7) & (F - 1)) > F / 2;
+        const int y = flip ? yB : yA;
+        const int off = (((y >> 7) & (F - 1)) << 9) | (((y >> 14) & (F - 1)) << 3) | (y & (FT - 1));
+        float2 w = Wl[off];
+        w.y = flip ? -w.y : w.y;
+        float rx = Rx[j], ry = Ry[j];
+        rx = fmaf(-cre, w.x, rx);
+        rx = fmaf(cim, w.y, rx);
+        ry = fmaf(-cre, w.y, ry);
+        ry = fmaf(-cim, w.x, ry);
+        Rx[j] = rx;
+        Ry[j] = ry;
+        if (bits_max_first(__float_as_uint(fmaf(ry, ry, rx * rx)), best)) bj = j;
+        // at most eight bins' loads in flight: the registers of all 32 would
+        // not fit beside R_w
+        if (j % 8 == 7) __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    __syncthreads();  // the coefficient list is complete
+    if (!finite) {
+      if (t == 0) a.status[vi] = FSE_BLOCK_NONFINITE;
+      __syncthreads();
+      continue;
+    }
+    // 5. model on B (Algorithm 1, last loop, in 3-D): Re{sum c e^{j theta}}
+    const int np = bh * bw * bt;
+    for (int p = t; p < np; p += NT) {
+      const int tt = p / (bh * bw), rem = p % (bh * bw), i = rem / bw, jj = rem % bw;
+      const uint32_t m = (uint32_t)(bd + i), n = (uint32_t)(bd + jj), q = (uint32_t)(td + tt);
+      float acc = 0.f;
+      for (int it = 0; it < I; ++it) {
+        const int gidx = __builtin_amdgcn_readfirstlane(cl_idx[it]);
+        const uint32_t s3 = gidx & (FT - 1), v = (gidx >> 3) & (F - 1), u = gidx >> 9;
+        const float2 c = cl_c[it];
+        const float2 e = tw[(u * m + v * n + (F / FT) * s3 * q) & (F - 1)];  // exp(-j theta)
+        acc = fmaf(c.x, e.x, acc);
+        acc = fmaf(c.y, e.y, acc);
+      }
+      a.out[((int64_t)(f0 + tt) * a.H + y0 + i) * a.out_pitch + x0 + jj] = acc;
+    }
+    if (t == 0) a.status[vi] = FSE_BLOCK_OK;
+    __syncthreads();  // Wl, the list and the scratch are overwritten by the next volume
+  }
+}
 }  // namespace
 
 const Variant* variant_for(int F) {
@@ -1070,4 +1306,17 @@ hipError_t launch_class(const Variant& v, const ClassArgs& a, int grid, size_t l
   return hipLaunchKernel(v.fn, dim3(grid), dim3(v.threads), args, lds, s);
 }
 
+}  // namespace fse
+
+namespace fse {
+size_t lds_bytes3d(int iters_cap) {
+  return (size_t)kHalfCols3 * kF3 * kFt3 * 8 + kF3 * 8 + 2 * (kNT3 / 64) * 16 + (size_t)iters_cap * 12;
+}
+
+const void* fse3d_kernel() { return reinterpret_cast<const void*>(&fse3d); }
+
+hipError_t launch_fse3d(const Vol3Args& a, int grid, size_t lds, hipStream_t s) {
+  void* args[] = {const_cast<Vol3Args*>(&a)};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&fse3d), dim3(grid), dim3(kNT3), args, lds, s);
+}
 }  // namespace fse

@@ -18,7 +18,12 @@ BLOCK_DTYPE = np.dtype([("frame", "<i4"), ("y0", "<i4"), ("x0", "<i4"),
                         ("fft", "<i2"), ("iters", "<i4")])
 TRACE_DTYPE = np.dtype([("u", "<u2"), ("v", "<u2"), ("c_re", "<f4"),
                         ("c_im", "<f4"), ("r2", "<f4")])
+VOLUME_DTYPE = np.dtype([("frame", "<i4"), ("y0", "<i4"), ("x0", "<i4"),
+                         ("bt", "<i2"), ("bh", "<i2"), ("bw", "<i2"), ("border", "<i2"),
+                         ("tborder", "<i2"), ("fft", "<i2"), ("fft_t", "<i2"), ("pad", "<i2"),
+                         ("iters", "<i4")])
 assert BLOCK_DTYPE.itemsize == C.sizeof(_lib.fse_block_t) == 24
+assert VOLUME_DTYPE.itemsize == C.sizeof(_lib.fse_volume_t) == 32
 assert TRACE_DTYPE.itemsize == C.sizeof(_lib.fse_trace_t) == 16
 
 _STATUS = {0: "FSE_OK", -1: "FSE_ERR_INVALID_ARG", -2: "FSE_ERR_UNSUPPORTED",
@@ -187,6 +192,77 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Batch3d:
+    """fse_batch3d_t: validated lost volumes of a clip, resident on the GPU
+    (3-D cFSE, 64 x 64 x 8 transform)."""
+
+    def __init__(self, plan, volumes, n_frames, H, W):
+        arr = np.ascontiguousarray(volumes)
+        if arr.dtype != VOLUME_DTYPE:
+            arr = arr.astype(VOLUME_DTYPE)
+        h = C.c_void_p()
+        bad = C.c_int32(-1)
+        st = _lib.lib().fse_batch3d_create(plan.handle, arr.ctypes.data_as(C.c_void_p), len(arr), int(n_frames),
+                                           int(H), int(W), C.byref(h), C.byref(bad))
+        _check(st, f"fse_batch3d_create (volume {bad.value})")
+        self._h = h
+        self.plan = plan
+        self.n = len(arr)
+        self.shape = (int(n_frames), int(H), int(W))
+        self.max_iters = int(arr["iters"].max()) if len(arr) else 0
+
+    def run(self, frames, avail, out, status, trace=None, stream=None):
+        """frames/avail uint8 [F,H,W], out float32 [F,H,W] (CUDA, dense
+        frames), status int32 [n], trace None or uint8 [n, max_iters*16]."""
+        import torch
+        Batch._check_tensors(self, frames, avail, out, status)
+        tptr = None
+        if trace is not None:
+            if not trace.is_cuda or trace.numel() * trace.element_size() < self.n * self.max_iters * 16:
+                raise ValueError("trace buffer too small")
+            tptr = C.c_void_p(trace.data_ptr())
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(_lib.lib().fse_extrapolate3d_batch(
+            self._h, C.c_void_p(frames.data_ptr()), C.c_void_p(avail.data_ptr()), frames.stride(1),
+            C.c_void_p(out.data_ptr()), out.stride(1), C.c_void_p(status.data_ptr()), tptr,
+            C.c_void_p(s.cuda_stream)), "fse_extrapolate3d_batch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib().fse_batch3d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def extrapolate3d(frames, avail, volumes, rho=0.8, gamma=0.5, trace=False, out=None):
+    """3-D cFSE of lost ``volumes`` (VOLUME_DTYPE) in a clip ``frames`` (uint8
+    CUDA [F,H,W]) with availability ``avail``. Returns (out float32, status
+    numpy, trace numpy [n, max_iters] of TRACE_DTYPE or None)."""
+    import torch
+    arr = np.ascontiguousarray(volumes).astype(VOLUME_DTYPE)
+    nf, H, W = frames.shape
+    plan = Plan(rho, gamma, max(4096, int(arr["iters"].max()) if len(arr) else 0))
+    batch = Batch3d(plan, arr, nf, H, W)
+    if out is None:
+        out = (frames * (avail != 0)).to(torch.float32)
+    status = torch.full((max(len(arr), 1),), -1, dtype=torch.int32, device=frames.device)
+    tbuf = None
+    if trace and batch.max_iters > 0:
+        tbuf = torch.zeros((len(arr), batch.max_iters * 16), dtype=torch.uint8, device=frames.device)
+    batch.run(frames, avail, out, status, tbuf)
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()[:len(arr)]
+    tr = None if tbuf is None else tbuf.cpu().numpy().view(TRACE_DTYPE).reshape(len(arr), batch.max_iters)
+    batch.close()
+    plan.close()
+    return out, st, tr
 
 
 def blocks_from_mask(avail, cell=16, border=16, fft=64, iters=100):

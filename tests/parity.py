@@ -123,3 +123,33 @@ def replay_warm_block(frames, avail, blk, rho, gamma, trace_row, cand_bins, ir, 
     bd, bh, bw = int(blk["border"]), int(blk["bh"]), int(blk["bw"])
     out["values"] = r2["g"][bd:bd + bh, bd:bd + bw].real.copy()
     return out
+
+
+def replay_volume(frames, avail, vol, rho, gamma, trace_row):
+    """3-D counterpart of replay_block: the trace's (u, v) are (k, l Ft + s),
+    so the linear bin (k F + l) Ft + s is u F Ft + v."""
+    from oracle import cfse3
+    F, Ft, I = int(vol["fft"]), int(vol["fft_t"]), int(vol["iters"])
+    rec = trace_row[:I]
+    seq = rec["u"].astype(np.int64) * (F * Ft) + rec["v"].astype(np.int64)
+    c = rec["c_re"].astype(np.float64) + 1j * rec["c_im"].astype(np.float64)
+    res = cfse3.extrapolate_volume(frames, avail, vol, rho, gamma, forced=seq)
+    short = np.array(res["short"]) if I else np.zeros(0)
+    free = np.array(res["free"]) if I else np.zeros(0, dtype=int)
+    div = free != seq
+    ag, ao = accumulate(seq, c), accumulate(seq, np.array(res["chat"]))
+    keys = sorted(ao)
+    vo = np.array([ao[k] for k in keys])
+    vg = np.array([ag.get(k, 0) for k in keys])
+    scale = np.abs(vo).max() if len(vo) else 0.0
+    return dict(ties=int(div.sum()), gap_violations=int((div & (short >= GAP_TOL)).sum()),
+                max_short=float(short[div].max()) if div.any() else 0.0,
+                coef_max=float(np.abs(vg - vo).max() / scale) if scale > 0 else 0.0,
+                coef_l2=float(np.linalg.norm(vg - vo) / np.linalg.norm(vo)) if scale > 0 else 0.0,
+                values=res["values"])
+
+
+def volume_slices(vol):
+    """(frames, rows, cols) slices of a volume's lost voxels."""
+    f, y, x = int(vol["frame"]), int(vol["y0"]), int(vol["x0"])
+    return (slice(f, f + int(vol["bt"])), slice(y, y + int(vol["bh"])), slice(x, x + int(vol["bw"])))

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     src = open(os.path.join(ROOT, "include", "fse.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(fse_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(fse_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_function():
@@ -128,3 +128,35 @@ def test_blocks_from_mask_matches_the_tile_cover():
                                   C.byref(n)) == -1  # pitch < W
     assert L.fse_blocks_from_mask(av.ctypes.data_as(C.c_void_p), 2, 100, 150, 150, 40, 16, 64, 1, None, 0,
                                   C.byref(n)) == -2  # area larger than the transform
+
+
+def test_volume_layout_and_validation():
+    """fse_volume_t is VOLUME_DTYPE (32 bytes); fse_batch3d_create rejects a
+    wrong transform, an area larger than the transform, a volume outside the
+    clip, overlapping volumes and masked plans (host checks, before any
+    device work)."""
+    from paper_2204_14193_amd import _lib
+    import paper_2204_14193_amd as fse
+    assert C.sizeof(_lib.fse_volume_t) == 32 and fse.VOLUME_DTYPE == losses.VOLUME_DTYPE
+    plan = fse.Plan(0.8, 0.5, 300)
+    good = dict(frame=2, y0=32, x0=32, bt=2, bh=16, bw=16, border=16, tborder=2, fft=64, fft_t=8, iters=10)
+
+    def status(vols, p=plan):
+        arr = np.zeros(len(vols), dtype=losses.VOLUME_DTYPE)
+        for i, v in enumerate(vols):
+            for k, x in v.items():
+                arr[i][k] = x
+        h = C.c_void_p()
+        bad = C.c_int32(-7)
+        st = _lib.lib().fse_batch3d_create(p.handle, arr.ctypes.data_as(C.c_void_p), len(arr), 8, 128, 128,
+                                           C.byref(h), C.byref(bad))
+        assert not h.value
+        return st, bad.value
+
+    assert status([dict(good, fft=32)]) == (-2, 0)
+    assert status([dict(good, tborder=4)]) == (-2, 0)          # T = 10 > 8
+    assert status([dict(good, frame=7)]) == (-1, 0)            # frames 7, 8 of 8
+    assert status([dict(good, iters=301)]) == (-1, 0)
+    assert status([good, dict(good, y0=40)]) == (-5, 1)        # overlap
+    masked = fse.Plan(0.8, 0.5, 300, masked=True)
+    assert status([good], masked)[0] == -2
