@@ -140,6 +140,91 @@ def cpu_baseline(wl, n_sample, seed=5, masked=False):
                       f"{int(wl.blocks[idx[0]]['iters'])} iterations each), {dt:.1f} s wall on {cpu}"}
 
 
+def _oracle_volume(args):
+    from oracle import cfse3
+    frames, avail, vol, rho, gamma = args
+    cfse3.extrapolate_volume(frames, avail, vol, rho, gamma)
+    return 1
+
+
+def cpu_baseline_volumes(wl, n_sample, seed=5):
+    """FP64 3-D oracle over a seeded sample of the clip's volumes, one
+    process per host core."""
+    import multiprocessing as mp
+    cores = len(os.sched_getaffinity(0))
+    idx = np.sort(np.random.default_rng(seed).choice(len(wl.blocks), n_sample, replace=False))
+    jobs = []
+    for i in idx:
+        v = wl.blocks[i].copy()
+        f0 = max(int(v["frame"]) - int(v["tborder"]), 0)
+        f1 = min(int(v["frame"]) + int(v["bt"]) + int(v["tborder"]), len(wl.frames))
+        v["frame"] -= f0
+        jobs.append((wl.distorted[f0:f1], wl.avail[f0:f1], v, wl.rho, wl.gamma))
+    with mp.get_context("fork").Pool(cores, initializer=_init_worker) as pool:
+        pool.map(_oracle_volume, jobs[:cores])
+        t0 = time.perf_counter()
+        pool.map(_oracle_volume, jobs, chunksize=1)
+        dt = time.perf_counter() - t0
+    return {"value": n_sample / dt, "unit": "volumes/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_sample} seeded volumes of the same clip (FP64 direct 3-D projection, "
+                      f"{int(wl.blocks[idx[0]]['iters'])} iterations each), {dt:.1f} s wall"}
+
+
+def bench_clip(args):
+    """3-D (video) cFSE: lost 16x16x2 volumes of a 1920x1080x16 clip, one
+    kernel launch per step; reported in volumes/s (not the blocks/s
+    metric of the 2-D path)."""
+    import torch
+    import paper_2204_14193_amd as fse
+    from synth import workloads
+
+    iters = 200 if args.iters == 100 else args.iters
+    wl = workloads.clip_1080p_16x16x2(iters=iters)
+    n = len(wl.blocks)
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(wl.distorted).to(dev)
+    av = torch.from_numpy(wl.avail).to(dev)
+    out = img.to(torch.float32)
+    status = torch.zeros(n, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    plan = fse.Plan(wl.rho, wl.gamma, iters)
+    batch = fse.Batch3d(plan, wl.blocks, *wl.frames.shape)
+    run = lambda: batch.run(img, av, out, status)
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    # one launch per step: the step's HIP event pair brackets the kernel alone
+    ms, ev_ms = time_steps(run, args.steps, stream)
+    assert (status.cpu().numpy() == fse.BLOCK_OK).all()
+    bins = 64 * 64 * 8
+    vox = int(np.sum(wl.blocks["bt"].astype(np.int64) * wl.blocks["bh"] * wl.blocks["bw"]))
+    flop = n * iters * bins * FLOP_PER_BIN_ITER + vox * iters * FLOP_PER_PIXEL_COEF
+    achieved = flop / (ev_ms * 1e-3) / 1e12
+    lds = n * iters * bins * 8 / (ev_ms * 1e-3) / 1e12      # the shifted W read; R_w stays in registers
+    rec = {
+        "metric": "3-D FSE volumes/s (16x16x2 loss, 64x64x8 FFT)", "value": n / (ms * 1e-3), "unit": "volumes/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "16x 1920x1080 synthetic frames (one image moving up to 3 px per frame), "
+                               f"{n} lost 16x16x2 volumes (5% of the volume grid), border 16 px and 2 frames "
+                               f"(48x48x6 area), 64x64x8 transform, rho 0.8, gamma 0.5, {iters} iterations",
+                   "name": "clip-1080p", "volumes": n, "iters": iters},
+        "mvoxel_per_s": vox / (ms * 1e-3) / 1e6,
+        "psnr_db": psnr_lost(wl.frames, out.cpu().numpy(), wl.avail),
+        "roofline": {"bound": "alu", "kernel": "fse3d", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "frac_nonpacked": achieved / NONPACKED_FP32_TFLOPS, "kernel_ms": ev_ms,
+                     "traffic": measured_traffic("fse3d", n, "clip-1080p")},
+        "lds_roofline": {"achieved": lds, "peak": NOMINAL_LDS_TBPS, "unit": "TB/s", "frac": lds / NOMINAL_LDS_TBPS,
+                         "note": "algorithmic 8 B/bin/iteration (shifted W) against the nominal LDS bandwidth"},
+    }
+    batch.close()
+    plan.close()
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline_volumes(wl, min(args.cpu_sample, 384, n))
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,7 +233,7 @@ def main():
     ap.add_argument("--frames", type=int, default=8)
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--workload", default="random-1080p-16x16",
-                    choices=["random-1080p-16x16", "random-1080p-8x8", "mixed-4k", "strokes-1080p"],
+                    choices=["random-1080p-16x16", "random-1080p-8x8", "mixed-4k", "strokes-1080p", "clip-1080p"],
                     help="the metric's workload (default) or one of the other configurations (plain only)")
     ap.add_argument("--kc", type=int, default=256, help="warm start: candidate bins per block")
     ap.add_argument("--ir", type=int, default=110, help="warm start: restricted iterations")
@@ -162,6 +247,10 @@ def main():
     if args.gpus != 1:
         print("this benchmark runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "clip-1080p":
+        bench_clip(args)
+        return
 
     import torch
     import paper_2204_14193_amd as fse

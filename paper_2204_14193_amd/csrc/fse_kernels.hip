@@ -1077,7 +1077,7 @@ __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
         fft_lines<F, 256, false>(buf, tw, tg);
         fft_lines<F, 256, true>(buf, tw, tg);
         if (sl < T)
-          for (int e = tg; e < F * F; e += 256) Z[sl * (F * F) + e] = buf[e];
+          for (int e = tg; e < F * F; e += 256) Z[sl * (F * F) + e] = buf[(e & (F - 1)) * F + (e >> 6)];  // [l][k]
         __syncthreads();  // the buffers are reused; the scratch is read by other threads
       }
     }
@@ -1097,25 +1097,24 @@ __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
     }
     __syncthreads();
     // 3. split Z = R_w + j alpha W by conjugate symmetry: R_w of the
-    // thread's bins into registers, W for l <= 32 into LDS
+    // thread's bins into registers, W for l <= 32 into LDS as [l][s][k]
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6), kk = t & (F - 1);
     float Rx[BPT], Ry[BPT];
-    int xkl[BPT / FT];  // packed (k, l) of the thread's columns: k * 2^14 + l * 2^7
 #pragma unroll
     for (int cc = 0; cc < BPT / FT; ++cc) {
-      const int c = (BPT / FT) * t + cc, k = c / F, l = c % F;
-      xkl[cc] = (k << 14) | (l << 7);
+      const int l = (BPT / FT) * wv + cc;
 #pragma unroll
       for (int s3 = 0; s3 < FT; ++s3) {
-        const float2 zk = Z[s3 * (F * F) + c];
-        const float2 zn = Z[((FT - s3) & (FT - 1)) * (F * F) + ((F - k) & (F - 1)) * F + ((F - l) & (F - 1))];
+        const float2 zk = Z[(s3 * F + l) * F + kk];
+        const float2 zn = Z[(((FT - s3) & (FT - 1)) * F + ((F - l) & (F - 1))) * F + ((F - kk) & (F - 1))];
         Rx[cc * FT + s3] = (zk.x + zn.x) * 0.5f;
         Ry[cc * FT + s3] = (zk.y - zn.y) * 0.5f;
       }
     }
     for (int e = t; e < WH; e += NT) {
-      const int l = e / (F * FT), k = (e / FT) % F, s3 = e % FT;
-      const float2 zk = Z[s3 * (F * F) + k * F + l];
-      const float2 zn = Z[((FT - s3) & (FT - 1)) * (F * F) + ((F - k) & (F - 1)) * F + ((F - l) & (F - 1))];
+      const int l = e / (F * FT), s3 = (e / F) % FT, k = e % F;
+      const float2 zk = Z[(s3 * F + l) * F + k];
+      const float2 zn = Z[(((FT - s3) & (FT - 1)) * F + ((F - l) & (F - 1))) * F + ((F - k) & (F - 1))];
       Wl[e] = make_float2((zk.y + zn.y) * (0.5f / kAlpha), (zn.x - zk.x) * (0.5f / kAlpha));
     }
     __syncthreads();
@@ -1137,80 +1136,88 @@ __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
     bool finite = true;
     // 4. iterations (eqs. (12), (13), (18))
     for (int it = 0; it < I; ++it) {
-      // the thread's candidate, then the wave's (first lane), then the
-      // workgroup's (first wave)
-      float bre = 0.f, bim = 0.f;
-#pragma unroll
-      for (int j = 0; j < BPT; ++j) {
-        bre = j == bj ? Rx[j] : bre;
-        bim = j == bj ? Ry[j] : bim;
-      }
+      // the thread's candidate, then the wave's (first lane: lowest k), then
+      // the workgroup's (largest value, lowest bin index among equals)
       const uint32_t wm = wave_max_bits(best);
       const unsigned long long hits = __ballot(best == wm);
       const int wl = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(hits));
-      const int widx = __builtin_amdgcn_readlane(BPT * t + bj, wl);
-      const float wre = readlane_f(bre, wl), wim = readlane_f(bim, wl);
-      xch[parity * (NT / 64) + wave] = make_int4((int)wm, widx, __float_as_int(wre), __float_as_int(wim));  // uniform
+      const int jw = __builtin_amdgcn_readlane(bj, wl);  // uniform: one indexed register read
+      const int widx = wl * (F * FT) + wv * BPT + jw;
+      const float wre = readlane_f(Rx[jw], wl), wim = readlane_f(Ry[jw], wl);
+      xch[parity * (NT / 64) + wv] = make_int4((int)wm, widx, __float_as_int(wre), __float_as_int(wim));  // uniform
       __syncthreads();
-      uint32_t gm = 0;
-      int gidx = 0;
-      float gre = 0.f, gim = 0.f;
-#pragma unroll
-      for (int w2 = 0; w2 < NT / 64; ++w2) {
-        const int4 v = xch[parity * (NT / 64) + w2];
-        const uint32_t m2 = (uint32_t)__builtin_amdgcn_readfirstlane(v.x);
-        const bool take = w2 == 0 || m2 > gm;  // the first wave wins ties (lower bins)
-        gm = take ? m2 : gm;
-        gidx = take ? __builtin_amdgcn_readfirstlane(v.y) : gidx;
-        gre = take ? __int_as_float(__builtin_amdgcn_readfirstlane(v.z)) : gre;
-        gim = take ? __int_as_float(__builtin_amdgcn_readfirstlane(v.w)) : gim;
-      }
+      int4 sv = make_int4(0, 0x7fffffff, 0, 0);
+      if (kk < NT / 64) sv = xch[parity * (NT / 64) + kk];
       parity ^= 1;
-      const int s3 = gidx & (FT - 1), v = (gidx >> 3) & (F - 1), u = gidx >> 9;
+      unsigned hi = (unsigned)sv.x, lo = ~(unsigned)sv.y;
+      dpp_max64<kQuadXor1>(hi, lo);
+      dpp_max64<kQuadXor2>(hi, lo);
+      dpp_max64<kRowHalfMirror>(hi, lo);
+      dpp_max64<kRowMirror>(hi, lo);  // lanes 0-15: the maximum over the 16 slots
+      const uint32_t gm = (uint32_t)__builtin_amdgcn_readlane((int)hi, 0);
+      const int gidx = (int)~(unsigned)__builtin_amdgcn_readlane((int)lo, 0);
+      const int ws = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(__ballot(kk < NT / 64 && sv.y == gidx)));
+      const float gre = __int_as_float(__builtin_amdgcn_readlane(sv.z, ws));
+      const float gim = __int_as_float(__builtin_amdgcn_readlane(sv.w, ws));
+      const int s0 = gidx & (FT - 1), v0 = (gidx >> 3) & (F - 1), u0 = gidx >> 9;
       const float cre = gW * gre, cim = gW * gim;  // eq. (13)
       finite = finite && isfinite(cre) && isfinite(cim);
-      if (wave == 0) {
+      if (wv == 0) {
         cl_idx[it] = gidx;  // uniform stores
         cl_c[it] = make_float2(cre, cim);
         if (a.trace) {
           fse_trace_t rec;
-          rec.u = (uint16_t)u;
-          rec.v = (uint16_t)(v * FT + s3);
+          rec.u = (uint16_t)u0;
+          rec.v = (uint16_t)(v0 * FT + s0);
           rec.c_re = cre;
           rec.c_im = cim;
           rec.r2 = __uint_as_float(gm);
           a.trace[(int64_t)vi * a.trace_stride + it] = rec;
         }
       }
-      // eq. (18): R_w[k,l,s] -= c W[k-u, l-v, s-s0], W from [l'][k'][s'] when
-      // l' = (l - v) mod 64 <= 32, else the conjugate of W[u-k, v-l, s0-s].
-      // Packed bins k * 2^14 + l * 2^7 + s: adding (64-u) 2^14 + (64-v) 2^7 +
-      // (8-s0) gives all three differences plus their offsets without borrows.
-      int ca = ((F - u) << 14) + ((F - v) << 7) + (FT - s3);
-      int cb = ((F + u) << 14) + ((F + v) << 7) + (FT + s3);
-      asm volatile("" : "+s"(ca), "+s"(cb));
+      // eq. (18): R_w[k,l,s] -= c W[k-u, l-v, s-s0]. The row l' = (l - v)
+      // mod 64 is uniform per column; for l' > 32 the stored value is
+      // W[u-k, v-l, s0-s] and its conjugate is used, which swaps the sign of
+      // two of the four products.
+      const int kq = ((kk - u0) & (F - 1)) * 8, kqf = ((u0 - kk) & (F - 1)) * 8;  // byte offsets
+      const unsigned creb = __float_as_uint(cre), cimb = __float_as_uint(cim);
+      const float* const Wb = reinterpret_cast<const float*>(Wl);
       best = 0;
       bj = 0;
 #pragma unroll
-      for (int j = 0; j < BPT; ++j) {
-        const int xa = xkl[j / FT] + (j % FT);
-        const int yA = xa + ca, yB = cb - xa;
-        const bool flip = ((yA >> 7) & (F - 1)) > F / 2;
-        const int y = flip ? yB : yA;
-        const int off = (((y >> 7) & (F - 1)) << 9) | (((y >> 14) & (F - 1)) << 3) | (y & (FT - 1));
-        float2 w = Wl[off];
-        w.y = flip ? -w.y : w.y;
-        float rx = Rx[j], ry = Ry[j];
-        rx = fmaf(-cre, w.x, rx);
-        rx = fmaf(cim, w.y, rx);
-        ry = fmaf(-cre, w.y, ry);
-        ry = fmaf(-cim, w.x, ry);
-        Rx[j] = rx;
-        Ry[j] = ry;
-        if (bits_max_first(__float_as_uint(fmaf(ry, ry, rx * rx)), best)) bj = j;
-        // at most eight bins' loads in flight: the registers of all 32 would
-        // not fit beside R_w
-        if (j % 8 == 7) __builtin_amdgcn_sched_barrier(0);
+      for (int cc = 0; cc < BPT / FT; ++cc) {
+        const int lp = ((BPT / FT) * wv + cc - v0) & (F - 1);
+        const bool flip = lp > F / 2;
+        const int lrow = flip ? (F - lp) & (F - 1) : lp;
+        const int base = (flip ? kqf : kq) + lrow * (FT * F * 8);
+        const float A = __uint_as_float(flip ? cimb ^ 0x80000000u : cimb);
+        const float Bc = __uint_as_float(flip ? creb : creb ^ 0x80000000u);
+        // the column's eight W values first, so that their loads overlap
+        float2 wc[FT];
+#pragma unroll
+        for (int s3 = 0; s3 < FT; ++s3) {
+          const int srot = (flip ? s0 - s3 : s3 - s0) & (FT - 1);
+          wc[s3] = *reinterpret_cast<const float2*>(reinterpret_cast<const unsigned char*>(Wb) + base +
+                                                    srot * (F * 8));
+        }
+        // keeps the eight loads ahead of the arithmetic (the scheduler would
+        // otherwise wait for each load before issuing the next)
+        asm volatile("" : "+v"(wc[0].x), "+v"(wc[0].y), "+v"(wc[1].x), "+v"(wc[1].y), "+v"(wc[2].x), "+v"(wc[2].y),
+                     "+v"(wc[3].x), "+v"(wc[3].y), "+v"(wc[4].x), "+v"(wc[4].y), "+v"(wc[5].x), "+v"(wc[5].y),
+                     "+v"(wc[6].x), "+v"(wc[6].y), "+v"(wc[7].x), "+v"(wc[7].y));
+#pragma unroll
+        for (int s3 = 0; s3 < FT; ++s3) {
+          const int j = cc * FT + s3;
+          const float2 w = wc[s3];
+          float rx = Rx[j], ry = Ry[j];
+          rx = fmaf(-cre, w.x, rx);
+          rx = fmaf(A, w.y, rx);
+          ry = fmaf(Bc, w.y, ry);
+          ry = fmaf(-cim, w.x, ry);
+          Rx[j] = rx;
+          Ry[j] = ry;
+          if (bits_max_first(__float_as_uint(fmaf(ry, ry, rx * rx)), best)) bj = j;
+        }
       }
     }
     __syncthreads();  // the coefficient list is complete
