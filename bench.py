@@ -140,6 +140,19 @@ def cpu_baseline(wl, n_sample, seed=5, masked=False):
                       f"{int(wl.blocks[idx[0]]['iters'])} iterations each), {dt:.1f} s wall on {cpu}"}
 
 
+def copy_calibration(args, rec, dev):
+    """Three plain device copies of --copy-bytes bytes, the reference for
+    scaling the FETCH_SIZE / WRITE_SIZE counters of a profiled run."""
+    import torch
+    if args.copy_bytes > 0:
+        src = torch.randint(0, 255, (args.copy_bytes,), dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        rec["copy_calibration_bytes"] = args.copy_bytes
+
+
 def _oracle_volume(args):
     from oracle import cfse3
     frames, avail, vol, rho, gamma = args
@@ -220,6 +233,7 @@ def bench_clip(args):
     }
     batch.close()
     plan.close()
+    copy_calibration(args, rec, dev)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline_volumes(wl, min(args.cpu_sample, 384, n))
     print(json.dumps(rec), flush=True)
@@ -385,13 +399,7 @@ def main():
         rec["lds_roofline"] = {"achieved": lds_bytes / (roof["ms"] * 1e-3) / 1e12, "peak": NOMINAL_LDS_TBPS,
                                "unit": "TB/s", "frac": lds_bytes / (roof["ms"] * 1e-3) / 1e12 / NOMINAL_LDS_TBPS,
                                "note": "algorithmic 24 B/bin/iteration against the nominal LDS bandwidth"}
-    if args.copy_bytes > 0:
-        src = torch.randint(0, 255, (args.copy_bytes,), dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        rec["copy_calibration_bytes"] = args.copy_bytes
+    copy_calibration(args, rec, dev)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, n), masked=masked)
     print(json.dumps(rec), flush=True)
