@@ -464,3 +464,112 @@ def test_3d_energy_monotone():
     for gamma in (0.3, 1.0):
         e = cfse3.cfse3(np.where(A, s, 0), w, 16, 8, gamma, 12)["energy"]
         assert all(b <= a * (1 + 1e-12) for a, b in zip(e, e[1:]))
+
+
+# ------------------------------------------------------------------ rFSE
+
+def _rfse_case(seed=21, M=12, N=10, F=16):
+    rng = np.random.default_rng(seed)
+    r = rng.normal(size=(M, N)) * 30 + 90
+    A = rng.random((M, N)) > 0.25
+    A[4:7, 3:6] = False
+    w = np.where(A, cfse.window(M, N, 0.8), 0.0)
+    return r, w, A, F
+
+
+def _pair_lstsq(r, w, F, k, l):
+    """Brute-force weighted least squares of r on the real span of the pair
+    (k, l), (-k, -l): returns (c, energy decrease); the model is
+    Re{c phi*} = Re(c) cos(theta) + Im(c) sin(theta)."""
+    M, N = r.shape
+    m = np.arange(M)[:, None]
+    n = np.arange(N)[None, :]
+    th = 2 * math.pi * (k * m + l * n) / F
+    cols = [np.cos(th).ravel()]
+    if not ((2 * k) % F == 0 and (2 * l) % F == 0):
+        cols.append(np.sin(th).ravel())
+    X = np.stack(cols, axis=1)
+    sw = np.sqrt(w.ravel())
+    beta = np.linalg.lstsq(X * sw[:, None], r.ravel() * sw, rcond=None)[0]
+    res = r.ravel() - X @ beta
+    dec = float(np.sum(w.ravel() * r.ravel() ** 2) - np.sum(w.ravel() * res ** 2))
+    c = beta[0] + (1j * beta[1] if len(beta) > 1 else 0)
+    return c, dec
+
+
+def test_rfse_pair_fit_is_weighted_least_squares():
+    """The closed-form coefficient and energy decrease of every pair equal a
+    brute-force weighted least-squares fit on {cos, sin} (one column for the
+    four self-conjugate bins); pins the derivation from eq. (2)."""
+    from oracle import rfse
+    r, w, A, F = _rfse_case()
+    M, N = r.shape
+    EM, EN = cfse.analysis_matrix(F, M), cfse.analysis_matrix(F, N)
+    P = cfse.project(w * r + 0j, EM, EN)
+    Q = rfse.double_freq(cfse.project(w + 0j, EM, EN))
+    c, dec = rfse.pair_fit(P, float(w.sum()), Q, rfse.self_conjugate(F))
+    for k in range(F):
+        for l in range(F):
+            cb, db = _pair_lstsq(r, w, F, k, l)
+            assert abs(c[k, l] - cb) <= 1e-9 * max(1.0, abs(cb)), (k, l, c[k, l], cb)
+            assert abs(dec[k, l] - db) <= 1e-9 * max(1.0, abs(db)), (k, l, dec[k, l], db)
+
+
+def test_rfse_selection_and_energy_identity():
+    """Each iteration selects the lower-index bin of the pair with the
+    largest brute-force decrease, the weighted energy falls by exactly
+    gamma (2 - gamma) times that decrease, and the model stays real."""
+    from oracle import rfse
+    r, w, A, F = _rfse_case(seed=5)
+    s = np.where(A, r, 0.0)
+    gamma = 0.6
+    res = rfse.rfse(s, w, F, gamma, 6)
+    resid = s.copy()
+    for it, idx in enumerate(res["seq"]):
+        decs = np.array([[_pair_lstsq(resid, w, F, k, l)[1] for l in range(F)] for k in range(F)])
+        assert idx == int(np.flatnonzero(decs.ravel() >= decs.max() * (1 - 1e-9))[0])
+        e0, e1 = res["energy"][it], res["energy"][it + 1]
+        assert abs((e0 - e1) - gamma * (2 - gamma) * decs.ravel()[idx]) <= 1e-9 * e0
+        u, v = divmod(idx, F)
+        m = np.arange(s.shape[0])[:, None]
+        n = np.arange(s.shape[1])[None, :]
+        th = 2 * math.pi * (u * m + v * n) / F
+        ch = res["chat"][it]
+        resid = resid - (ch.real * np.cos(th) + ch.imag * np.sin(th))
+    assert np.isrealobj(res["g"])
+    np.testing.assert_allclose(res["g"], s - resid, atol=1e-9)
+
+
+@pytest.mark.parametrize("k0,l0", [(3, 5), (13, 2), (0, 0), (8, 0), (0, 8), (8, 8)])
+def test_rfse_recovers_a_real_sinusoid(k0, l0):
+    """A real sinusoid a cos(theta + p) on the support (a constant or an
+    alternating pattern for the self-conjugate bins) is the whole model
+    after one iteration at gamma = 1, also on the loss area, and the
+    selected bin is the lower index of its pair."""
+    from oracle import rfse
+    M, N, F = 12, 12, 16
+    m = np.arange(M)[:, None]
+    n = np.arange(N)[None, :]
+    th = 2 * math.pi * (k0 * m + l0 * n) / F
+    sc = (2 * k0) % F == 0 and (2 * l0) % F == 0
+    x = 37.0 * np.cos(th + (0.0 if sc else 0.7)) + (5.0 if (k0, l0) == (0, 0) else 0.0)
+    A = np.ones((M, N), dtype=bool)
+    A[4:8, 4:8] = False
+    w = np.where(A, cfse.window(M, N, 0.8), 0.0)
+    res = rfse.rfse(np.where(A, x, 0.0), w, F, 1.0, 1)
+    assert res["seq"] == [min(k0 * F + l0, rfse.pair_index(F, k0 * F + l0))]
+    np.testing.assert_allclose(res["g"], x, atol=1e-9)
+
+
+def test_rfse_pairs_tie_exactly():
+    """Both bins of a pair have bit-identical decreases (so the tie rule,
+    not rounding, picks the lower index)."""
+    from oracle import rfse
+    r, w, A, F = _rfse_case(seed=8, F=32)
+    M, N = r.shape
+    EM, EN = cfse.analysis_matrix(F, M), cfse.analysis_matrix(F, N)
+    P = cfse.project(w * r + 0j, EM, EN)
+    Q = rfse.double_freq(cfse.project(w + 0j, EM, EN))
+    _, dec = rfse.pair_fit(P, float(w.sum()), Q, rfse.self_conjugate(F))
+    flip = dec[(-np.arange(F)) % F][:, (-np.arange(F)) % F]
+    assert np.array_equal(dec, flip)
