@@ -87,6 +87,8 @@ struct fse_batch_s {
   bool all_48 = false;                     // every area is 48 x 48 (network input size)
   bool all_small_b = false;                // every B has at most 256 pixels (restricted kernel
                                            // synthesises in its loop, no coefficient list)
+  int32_t real_grid = 0;                   // rFSE launch (plan flag FSE_PLAN_REAL)
+  size_t real_lds = 0;
 };
 
 extern "C" const char* fse_last_error(void) { return g_error; }
@@ -98,7 +100,10 @@ extern "C" fse_status_t fse_plan_create(const fse_plan_desc_t* desc, fse_plan_t*
   if (!(desc->gamma >= 0.f && desc->gamma <= 1.f)) return fail(FSE_ERR_INVALID_ARG, "gamma must lie in [0, 1]");
   if (desc->max_iters < 0 || desc->max_iters > fse::kMaxIters)
     return fail(FSE_ERR_INVALID_ARG, "max_iters must lie in [0, 4096]");
-  if ((desc->flags & ~(uint32_t)FSE_PLAN_MASKED_B) != 0) return fail(FSE_ERR_INVALID_ARG, "unknown plan flag");
+  if ((desc->flags & ~(uint32_t)(FSE_PLAN_MASKED_B | FSE_PLAN_REAL)) != 0)
+    return fail(FSE_ERR_INVALID_ARG, "unknown plan flag");
+  if ((desc->flags & FSE_PLAN_MASKED_B) && (desc->flags & FSE_PLAN_REAL))
+    return fail(FSE_ERR_UNSUPPORTED, "rFSE plans take rectangular loss areas");
   fse_plan_s* p = new (std::nothrow) fse_plan_s;
   if (!p) return fail(FSE_ERR_OOM, "host allocation failed");
   p->rho = desc->rho;
@@ -349,6 +354,23 @@ extern "C" fse_status_t fse_batch_create(fse_plan_t plan, const fse_block_t* h_b
     return fail(FSE_ERR_HIP, "hipGetDeviceProperties failed");
   }
   b->cus = prop.multiProcessorCount;
+  if (plan->flags & FSE_PLAN_REAL) {
+    if (b->cls[class_of(64)].count != n_blocks) {
+      delete b;
+      return fail(FSE_ERR_UNSUPPORTED, "rFSE is compiled for 64 x 64 transforms");
+    }
+    b->real_lds = fse::real_lds_bytes(std::max(b->cls[class_of(64)].iters_cap, 1));
+    int per_cu = 0;
+    if (hipFuncSetAttribute(fse::real_kernel(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->real_lds) !=
+            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fse::real_kernel(), fse::real_threads(), b->real_lds) !=
+            hipSuccess ||
+        per_cu < 1) {
+      delete b;
+      return fail(FSE_ERR_UNSUPPORTED, "rFSE kernel does not fit on a compute unit (iteration count too large)");
+    }
+    b->real_grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(n_blocks, (int64_t)per_cu * b->cus));
+  }
   for (int ci = 0; ci < 3; ++ci) {
     fse_batch_s::Cls& c = b->cls[ci];
     if (c.count == 0) continue;
@@ -395,6 +417,13 @@ extern "C" fse_status_t fse_batch_launch_info(fse_batch_t batch, int32_t F, int3
   if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
   const int ci = class_of(F);
   if (ci < 0 || batch->cls[ci].count == 0) return fail(FSE_ERR_INVALID_ARG, "no block of this transform size");
+  if (batch->plan->flags & FSE_PLAN_REAL) {
+    if (threads) *threads = fse::real_threads();
+    if (wg_per_cu) *wg_per_cu = (batch->real_grid + batch->cus - 1) / batch->cus;
+    if (grid) *grid = batch->real_grid;
+    if (lds_bytes) *lds_bytes = (int32_t)batch->real_lds;
+    return FSE_OK;
+  }
   const fse_batch_s::Cls& c = batch->cls[ci];
   if (threads) *threads = c.v->threads;
   if (wg_per_cu) *wg_per_cu = c.wg_per_cu;
@@ -470,6 +499,12 @@ static fse_status_t launch_one(fse_batch_t batch, int ci, const uint8_t* d_image
         a.stage_r = batch->d_stage_r;
       }
     }
+    if (!warm && (batch->plan->flags & FSE_PLAN_REAL)) {
+      if (timed(batch, FSE_KERNEL_REAL, 64, s, [&] { return fse::launch_real(a, batch->real_grid, batch->real_lds, s); }) !=
+          hipSuccess)
+        return fail(FSE_ERR_HIP, "kernel launch failed (rFSE)");
+      return FSE_OK;
+    }
     const int kind = !warm ? FSE_KERNEL_PLAIN : batch->warm_split ? FSE_KERNEL_WARM_PREP : FSE_KERNEL_WARM_FUSED;
     if (timed(batch, kind, c.v->F, s, [&] { return fse::launch_class(*c.v, a, c.grid, c.lds, s); }) != hipSuccess)
       return fail(FSE_ERR_HIP, "kernel launch failed");
@@ -517,6 +552,7 @@ extern "C" fse_status_t fse_batch_set_variant(fse_batch_t batch, int32_t F, int3
   if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
   const int ci = class_of(F);
   if (ci < 0 || batch->cls[ci].count == 0) return fail(FSE_ERR_INVALID_ARG, "no block of this transform size");
+  if (batch->plan->flags & FSE_PLAN_REAL) return fail(FSE_ERR_UNSUPPORTED, "the rFSE kernel has one workgroup shape");
   const fse::Variant* vs[16];
   const int nv = std::min(fse::variants_for(F, vs, 16), 16);
   for (int i = 0; i < nv; ++i)
@@ -529,6 +565,7 @@ extern "C" fse_status_t fse_batch_autotune(fse_batch_t batch, const uint8_t* d_i
                                            int32_t reps, void* stream, char* report, size_t report_len) {
   if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
   if (reps < 1) return fail(FSE_ERR_INVALID_ARG, "reps must be >= 1");
+  if (batch->plan->flags & FSE_PLAN_REAL) return fail(FSE_ERR_UNSUPPORTED, "the rFSE kernel has one workgroup shape");
   if (report && report_len) report[0] = 0;
   size_t used = 0;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -580,8 +617,8 @@ extern "C" fse_status_t fse_cnn_patches(fse_batch_t batch, const uint8_t* d_imag
                                         int64_t pitch, uint16_t* d_x, void* stream) {
   if (!batch || !d_image || !d_avail || !d_x) return fail(FSE_ERR_INVALID_ARG, "null argument");
   if (!batch->all_48) return fail(FSE_ERR_UNSUPPORTED, "network inputs need 48x48 areas");
-  if (batch->plan->flags & FSE_PLAN_MASKED_B)
-    return fail(FSE_ERR_UNSUPPORTED, "the warm start needs rectangular loss areas");
+  if (batch->plan->flags & (FSE_PLAN_MASKED_B | FSE_PLAN_REAL))
+    return fail(FSE_ERR_UNSUPPORTED, "the warm start needs a cFSE plan with rectangular loss areas");
   if (pitch < batch->W) return fail(FSE_ERR_INVALID_ARG, "pitch smaller than the width");
   if (fse::cnn::patches(d_image, d_avail, pitch, batch->H, batch->W, batch->d_blocks, batch->d_orig, batch->n, d_x,
                         reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
@@ -594,8 +631,8 @@ extern "C" fse_status_t fse_cnn_forward_blocks(fse_cnn_t net, fse_batch_t batch,
                                                void* stream) {
   if (!batch || !d_image || !d_avail) return fail(FSE_ERR_INVALID_ARG, "null argument");
   if (!batch->all_48) return fail(FSE_ERR_UNSUPPORTED, "network inputs need 48x48 areas");
-  if (batch->plan->flags & FSE_PLAN_MASKED_B)
-    return fail(FSE_ERR_UNSUPPORTED, "the warm start needs rectangular loss areas");
+  if (batch->plan->flags & (FSE_PLAN_MASKED_B | FSE_PLAN_REAL))
+    return fail(FSE_ERR_UNSUPPORTED, "the warm start needs a cFSE plan with rectangular loss areas");
   if (pitch < batch->W) return fail(FSE_ERR_INVALID_ARG, "pitch smaller than the width");
   return fse::cnn::net_forward_blocks(net, d_image, d_avail, pitch, batch->H, batch->W, batch->d_blocks,
                                       batch->d_orig, batch->n, d_logits, reinterpret_cast<hipStream_t>(stream));
@@ -611,8 +648,8 @@ extern "C" fse_status_t fse_warm_extrapolate_batch(fse_batch_t batch, const uint
                                                    const int16_t* d_cand, const int32_t* d_flags, int32_t kc,
                                                    int32_t restricted_iters, int32_t fallback_iters, void* stream) {
   if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
-  if (batch->plan->flags & FSE_PLAN_MASKED_B)
-    return fail(FSE_ERR_UNSUPPORTED, "the warm start needs rectangular loss areas");
+  if (batch->plan->flags & (FSE_PLAN_MASKED_B | FSE_PLAN_REAL))
+    return fail(FSE_ERR_UNSUPPORTED, "the warm start needs a cFSE plan with rectangular loss areas");
   if (batch->n == 0) return FSE_OK;
   if (!d_image || !d_avail || !d_out || !d_status || !d_cand || !d_flags)
     return fail(FSE_ERR_INVALID_ARG, "null device pointer");
@@ -700,7 +737,8 @@ fse_status_t validate_volumes(fse_plan_t plan, const fse_volume_t* v, int32_t n,
                               int32_t W, int32_t* bad) {
   if (bad) *bad = -1;
   if (!plan) return fail(FSE_ERR_INVALID_ARG, "null plan");
-  if (plan->flags & FSE_PLAN_MASKED_B) return fail(FSE_ERR_UNSUPPORTED, "volumes need rectangular loss areas");
+  if (plan->flags & (FSE_PLAN_MASKED_B | FSE_PLAN_REAL))
+    return fail(FSE_ERR_UNSUPPORTED, "volumes need a cFSE plan with rectangular loss areas");
   if (n < 0 || (n > 0 && !v)) return fail(FSE_ERR_INVALID_ARG, "bad volume list");
   if (n_frames <= 0 || H <= 0 || W <= 0) return fail(FSE_ERR_INVALID_ARG, "clip dimensions must be positive");
   for (int32_t i = 0; i < n; ++i) {

@@ -81,6 +81,13 @@ size_t lds_bytes3d(int iters_cap);
 hipError_t launch_fse3d(const Vol3Args& a, int grid, size_t lds, hipStream_t s);
 const void* fse3d_kernel();
 
+// rFSE (real-valued model), F = 64: LDS bytes for a given iteration cap,
+// the kernel (for the occupancy API), its workgroup size, and its launch.
+size_t real_lds_bytes(int iters_cap);
+const void* real_kernel();
+int real_threads();
+hipError_t launch_real(const ClassArgs& a, int grid, size_t lds, hipStream_t s);
+
 // Kernel modes.
 enum Mode : int { kPlain = 0, kWarmFused = 1, kWarmPrep = 2 };
 

@@ -1246,6 +1246,231 @@ __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
     __syncthreads();  // Wl, the list and the scratch are overwritten by the next volume
   }
 }
+
+// ------------------------------------------------------------ rFSE
+// Real-valued FSE (the model of eq. (2): a basis function and its conjugate
+// per iteration) for F = 64, one block per 256-thread workgroup at a time.
+// R_w of real data is Hermitian, so only the bins with l <= 32 are kept:
+// thread (wave w, lane k) owns (k, l = w + 4 c), c < 9 (wave 0 holds the
+// ninth column, l = 32). A pair is represented by its bin with l in 1..31,
+// or with l in {0, 32} and k <= 32. The pair's weighted least-squares fit
+// needs Q = W[2k, 2l]: with D = W0^2 - |Q|^2, A = 2 W0 / D and Bq = 2 Q / D
+// (self-conjugate bins: A = 1 / W0, Bq = 0), the energy decrease is
+// A |P|^2 - Re{Bq* P^2} and the coefficient A P* - Bq* P. These depend on
+// the window only, so the divisions are done once per block, and the
+// decrease is held as a1 x^2 + a2 y^2 + a3 x y (P = x + j y).
+constexpr int kRealNT = 256;
+
+__global__ __launch_bounds__(kRealNT) void fse_real64(ClassArgs a) {
+  constexpr int F = 64, NT = kRealNT, NC = 9;
+  extern __shared__ __align__(16) unsigned char smem[];
+  float2* const Wd = reinterpret_cast<float2*>(smem);          // FFT buffer, then W[l][k] for l <= 32
+  float2* const tw = Wd + F * F;
+  int4* const red = reinterpret_cast<int4*>(tw + F);           // 2 parities x 4 waves x 2 slots
+  float2* const cl_c = reinterpret_cast<float2*>(red + 16);
+  int* const cl_idx = reinterpret_cast<int*>(cl_c + a.iters_cap);
+  const int t0 = threadIdx.x;
+  if (t0 < F) tw[t0] = a.twid[t0];
+  int parity = 0;
+  for (int bi = blockIdx.x; bi < a.n; bi += gridDim.x) {
+    int t = t0;
+    asm volatile("" : "+v"(t));
+    const int kk = t & (F - 1), wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const UBlock bd = uniform_block(a.blocks + bi);
+    const int orig = __builtin_amdgcn_readfirstlane(a.orig[bi]);
+    const int bh = bd.bh, bw = bd.bw, bo = bd.border;
+    const int M = bh + 2 * bo, N = bw + 2 * bo;
+    const int ya = bd.y0 - bo, xa = bd.x0 - bo;
+    const int I = bd.iters;
+    const int64_t fofs = (int64_t)bd.frame * a.H;
+    const uint8_t* img = a.img + fofs * a.pitch;
+    const uint8_t* av = a.avail + fofs * a.pitch;
+    const int pitch = (int)a.pitch;
+
+    // 1. gather and weight (eq. (3)), z = s w + j alpha w, forward transform
+    for (int r = 0; r < F * F / NT; ++r) {
+      const int e = t + r * NT;
+      const int m = e / F, n = e % F;
+      const int y = ya + m, x = xa + n;
+      const bool inB = m >= bo && m < bo + bh && n >= bo && n < bo + bw;
+      float2 z = make_float2(0.f, 0.f);
+      if (m < M && n < N && !inB && y >= 0 && y < a.H && x >= 0 && x < a.W) {
+        const uint32_t p = (uint32_t)(y * pitch + x);
+        if (av[p] != 0) {
+          const int da = min(abs(2 * m - (M - 1)), kWinStride - 1), db = min(abs(2 * n - (N - 1)), kWinStride - 1);
+          const float w = a.wtab[da * kWinStride + db];
+          z = make_float2((float)img[p] * w, kAlpha * w);
+        }
+      }
+      Wd[e] = z;
+    }
+    lds_barrier();
+    fft_lines<F, NT, false>(Wd, tw, t);
+    fft_lines<F, NT, true>(Wd, tw, t);
+
+    // 2. split into R_w (registers) and W (LDS, [l][k] for l <= 32)
+    float Rx[NC], Ry[NC];
+    float2 Wv[NC];
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+      const int l = wv + 4 * cc;
+      Rx[cc] = Ry[cc] = 0.f;
+      Wv[cc] = make_float2(0.f, 0.f);
+      if (l <= F / 2) {
+        const float2 zk = Wd[kk * F + l];
+        const float2 zn = Wd[((F - kk) & (F - 1)) * F + ((F - l) & (F - 1))];
+        Rx[cc] = (zk.x + zn.x) * 0.5f;
+        Ry[cc] = (zk.y - zn.y) * 0.5f;
+        Wv[cc] = make_float2((zk.y + zn.y) * (0.5f / kAlpha), (zn.x - zk.x) * (0.5f / kAlpha));
+      }
+    }
+    const float W0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(Wd[0].y))) * (1.0f / kAlpha);
+    __syncthreads();
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+      const int l = wv + 4 * cc;
+      if (l <= F / 2) Wd[l * F + kk] = Wv[cc];
+    }
+    __syncthreads();
+    if (!(W0 > 0.f)) {
+      if (t == 0) a.status[orig] = FSE_BLOCK_EMPTY_SUPPORT;
+      continue;  // the next block's gather starts after the barrier above
+    }
+
+    // 3. per-bin constants of the pair fit
+    float a1[NC], a2[NC], a3[NC];
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+      const int l = wv + 4 * cc;
+      a1[cc] = a2[cc] = a3[cc] = 0.f;
+      if (l <= F / 2) {
+        const int lq = (2 * l) & (F - 1);  // 0 or 2l <= 62: rows above 32 are read conjugated
+        const bool fq = lq > F / 2;
+        float2 q = Wd[(fq ? F - lq : lq) * F + ((fq ? -2 * kk : 2 * kk) & (F - 1))];
+        q.y = fq ? -q.y : q.y;
+        const bool sc = (kk == 0 || kk == F / 2) && (l == 0 || l == F / 2);
+        const bool rep = (l != 0 && l != F / 2) || kk <= F / 2;
+        const float D = fmaf(W0, W0, -fmaf(q.x, q.x, q.y * q.y));
+        const float iD = 2.0f / D;
+        const float A = sc ? 1.0f / W0 : W0 * iD;
+        const float Br = sc ? 0.f : q.x * iD, Bi = sc ? 0.f : q.y * iD;
+        a1[cc] = rep ? A - Br : 0.f;
+        a2[cc] = rep ? A + Br : 0.f;
+        a3[cc] = rep ? -2.0f * Bi : 0.f;
+      }
+    }
+    auto decrease = [&](int cc) {
+      const float x = Rx[cc], y = Ry[cc];
+      const float tq = fmaf(a3[cc], y, a1[cc] * x);
+      const float d = fmaf(x, tq, (a2[cc] * y) * y);
+      return __float_as_uint(fmaxf(d, 0.f));
+    };
+    uint32_t best = 0;
+    int bj = 0;
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc)
+      if (bits_max_first(decrease(cc), best)) bj = cc;
+
+    bool finite = true;
+    const float hg = 0.5f * a.gamma;
+    // 4. iterations
+    for (int it = 0; it < I; ++it) {
+      const uint32_t wm = wave_max_bits(best);
+      const int wl = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(__ballot(best == wm)));
+      const int jw = __builtin_amdgcn_readlane(bj, wl);
+      const int bin = wl * F + wv + 4 * jw;
+      red[(parity * 4 + wv) * 2] = make_int4((int)wm, bin, __float_as_int(readlane_f(Rx[jw], wl)),
+                                             __float_as_int(readlane_f(Ry[jw], wl)));
+      red[(parity * 4 + wv) * 2 + 1] = make_int4(__float_as_int(readlane_f(a1[jw], wl)),
+                                                 __float_as_int(readlane_f(a2[jw], wl)),
+                                                 __float_as_int(readlane_f(a3[jw], wl)), 0);
+      __syncthreads();
+      int4 s0 = make_int4(0, 0, 0, 0), s1 = make_int4(0, 0, 0, 0);
+      if (kk < 4) {
+        s0 = red[(parity * 4 + kk) * 2];
+        s1 = red[(parity * 4 + kk) * 2 + 1];
+      }
+      parity ^= 1;
+      uint32_t gm = __builtin_amdgcn_readlane(s0.x, 0);
+      int ws = 0;
+#pragma unroll
+      for (int w2 = 1; w2 < 4; ++w2) {
+        const uint32_t m2 = __builtin_amdgcn_readlane(s0.x, w2);
+        ws = m2 > gm ? w2 : ws;  // the first wave wins ties
+        gm = m2 > gm ? m2 : gm;
+      }
+      const int gbin = __builtin_amdgcn_readlane(s0.y, ws);
+      const float x = __int_as_float(__builtin_amdgcn_readlane(s0.z, ws));
+      const float y = __int_as_float(__builtin_amdgcn_readlane(s0.w, ws));
+      const float g1 = __int_as_float(__builtin_amdgcn_readlane(s1.x, ws));
+      const float g2 = __int_as_float(__builtin_amdgcn_readlane(s1.y, ws));
+      const float h = 0.5f * __int_as_float(__builtin_amdgcn_readlane(s1.z, ws));
+      // the pair's coefficient A P* - Bq* P, then the compensation gamma
+      const float cre = fmaf(g1, x, h * y), cim = -fmaf(g2, y, h * x);
+      const int u = gbin >> 6, v = gbin & (F - 1);
+      finite = finite && isfinite(cre) && isfinite(cim);
+      if (wv == 0) {
+        cl_idx[it] = gbin;  // uniform stores; the model is Re{c phi*} = Re{conj(c) phi}
+        cl_c[it] = make_float2(a.gamma * cre, -a.gamma * cim);
+        if (a.trace) {
+          // recorded for the pair's lower-index bin (the conjugate bin has the conjugate coefficient)
+          const bool upper = u > F / 2;
+          fse_trace_t rec;
+          rec.u = (uint16_t)(upper ? F - u : u);
+          rec.v = (uint16_t)(upper ? (F - v) & (F - 1) : v);
+          rec.c_re = a.gamma * cre;
+          rec.c_im = upper ? -a.gamma * cim : a.gamma * cim;
+          rec.r2 = __uint_as_float(gm);
+          a.trace[(int64_t)orig * a.trace_stride + it] = rec;
+        }
+      }
+      // R_w[k,l] -= (gamma / 2) (c W[k+u, l+v] + c* W[k-u, l-v]); rows above
+      // 32 are read as the conjugate of the mirrored entry
+      // uniform factors on the scalar unit: sign flips are integer xors
+      const uint32_t pb = __builtin_amdgcn_readfirstlane(__float_as_uint(hg * cre));
+      const uint32_t qb = __builtin_amdgcn_readfirstlane(__float_as_uint(hg * cim));
+      constexpr uint32_t kSign = 0x80000000u;
+      int o1 = ((kk + u) & (F - 1)) * 8, o1f = ((-kk - u) & (F - 1)) * 8;
+      int o2 = ((kk - u) & (F - 1)) * 8, o2f = ((u - kk) & (F - 1)) * 8;
+      asm volatile("" : "+v"(o1), "+v"(o1f), "+v"(o2), "+v"(o2f));  // computed once, not per bin
+      const unsigned char* Wb = reinterpret_cast<const unsigned char*>(Wd);
+      best = 0;
+      bj = 0;
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) {
+        const int l = wv + 4 * cc;
+        if (cc == NC - 1 && wv != 0) continue;  // wave-uniform: only wave 0 holds l = 32
+        const int l1 = (l + v) & (F - 1), l2 = (l - v) & (F - 1);
+        const bool f1 = l1 > F / 2, f2 = l2 > F / 2;
+        const float2 w1 = *reinterpret_cast<const float2*>(Wb + (f1 ? o1f : o1) + (f1 ? F - l1 : l1) * (F * 8));
+        const float2 w2 = *reinterpret_cast<const float2*>(Wb + (f2 ? o2f : o2) + (f2 ? F - l2 : l2) * (F * 8));
+        const uint32_t s1 = f1 ? kSign : 0u, s2 = f2 ? kSign : 0u;
+        const float mp = __uint_as_float(pb ^ kSign), mq = __uint_as_float(qb ^ kSign), qq = __uint_as_float(qb);
+        float rx = Rx[cc], ry = Ry[cc];
+        rx = fmaf(mp, w1.x, rx);
+        rx = fmaf(__uint_as_float(qb ^ s1), w1.y, rx);          // f1 ? -q : q
+        ry = fmaf(__uint_as_float(pb ^ s1 ^ kSign), w1.y, ry);  // f1 ? p : -p
+        ry = fmaf(mq, w1.x, ry);
+        rx = fmaf(mp, w2.x, rx);
+        rx = fmaf(__uint_as_float(qb ^ s2 ^ kSign), w2.y, rx);  // f2 ? q : -q
+        ry = fmaf(__uint_as_float(pb ^ s2 ^ kSign), w2.y, ry);  // f2 ? p : -p
+        ry = fmaf(qq, w2.x, ry);
+        Rx[cc] = rx;
+        Ry[cc] = ry;
+        if (bits_max_first(decrease(cc), best)) bj = cc;
+      }
+    }
+    __syncthreads();  // the coefficient list is complete
+    if (!finite) {
+      if (t == 0) a.status[orig] = FSE_BLOCK_NONFINITE;
+      continue;
+    }
+    synthesize<F, NT, 1>(cl_idx, cl_c, I, tw, bh, bw, bo, a.out + (fofs + bd.y0) * a.out_pitch + bd.x0,
+                         a.out_pitch, t);
+    if (t == 0) a.status[orig] = FSE_BLOCK_OK;
+    __syncthreads();  // Wd and the list are overwritten by the next block
+  }
+}
 }  // namespace
 
 const Variant* variant_for(int F) {
@@ -1321,6 +1546,17 @@ size_t lds_bytes3d(int iters_cap) {
 }
 
 const void* fse3d_kernel() { return reinterpret_cast<const void*>(&fse3d); }
+
+size_t real_lds_bytes(int iters_cap) { return (size_t)64 * 64 * 8 + 64 * 8 + 16 * 16 + (size_t)iters_cap * 12; }
+
+const void* real_kernel() { return reinterpret_cast<const void*>(&fse_real64); }
+
+int real_threads() { return kRealNT; }
+
+hipError_t launch_real(const ClassArgs& a, int grid, size_t lds, hipStream_t s) {
+  void* args[] = {const_cast<ClassArgs*>(&a)};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&fse_real64), dim3(grid), dim3(kRealNT), args, lds, s);
+}
 
 hipError_t launch_fse3d(const Vol3Args& a, int grid, size_t lds, hipStream_t s) {
   void* args[] = {const_cast<Vol3Args*>(&a)};

@@ -11,7 +11,7 @@ from . import _lib
 
 BLOCK_OK, BLOCK_EMPTY_SUPPORT, BLOCK_NONFINITE = 0, 1, 2
 # FSE_KERNEL_* of include/fse.h, by value
-KERNEL_KINDS = ("plain", "warm_fused", "warm_prep", "restricted")
+KERNEL_KINDS = ("plain", "warm_fused", "warm_prep", "restricted", "real")
 
 BLOCK_DTYPE = np.dtype([("frame", "<i4"), ("y0", "<i4"), ("x0", "<i4"),
                         ("bh", "<i2"), ("bw", "<i2"), ("border", "<i2"),
@@ -50,21 +50,25 @@ def _blocks_array(blocks):
 
 
 PLAN_MASKED_B = 1  # FSE_PLAN_MASKED_B of include/fse.h
+PLAN_REAL = 2      # FSE_PLAN_REAL: real-valued FSE (rFSE)
 
 
 class Plan:
     """fse_plan_t: window decay rho, compensation gamma, iteration limit;
     masked=True makes every block's loss area the lost pixels of its
-    rectangle (arbitrary loss shapes, FSE_PLAN_MASKED_B)."""
+    rectangle (arbitrary loss shapes, FSE_PLAN_MASKED_B); real=True runs
+    real-valued FSE instead of cFSE (FSE_PLAN_REAL, F = 64 blocks only)."""
 
-    def __init__(self, rho=0.8, gamma=0.5, max_iters=4096, masked=False):
+    def __init__(self, rho=0.8, gamma=0.5, max_iters=4096, masked=False, real=False):
         L = _lib.lib()
-        desc = _lib.fse_plan_desc_t(float(rho), float(gamma), int(max_iters), PLAN_MASKED_B if masked else 0)
+        flags = (PLAN_MASKED_B if masked else 0) | (PLAN_REAL if real else 0)
+        desc = _lib.fse_plan_desc_t(float(rho), float(gamma), int(max_iters), flags)
         h = C.c_void_p()
         _check(L.fse_plan_create(C.byref(desc), C.byref(h)), "fse_plan_create")
         self._h = h
         self.rho, self.gamma, self.max_iters = float(rho), float(gamma), int(max_iters)
         self.masked = bool(masked)
+        self.real = bool(real)
 
     @property
     def handle(self):
@@ -284,18 +288,18 @@ def blocks_from_mask(avail, cell=16, border=16, fft=64, iters=100):
     return arr
 
 
-def extrapolate_batch(image, avail, blocks, rho=0.8, gamma=0.5, trace=False, out=None, masked=False):
+def extrapolate_batch(image, avail, blocks, rho=0.8, gamma=0.5, trace=False, out=None, masked=False, real=False):
     """Conceal ``blocks`` in frames ``image`` (uint8 CUDA tensor [F,H,W] or
     [H,W]) with availability ``avail``. Returns (out float32, status int32
     numpy, trace numpy of TRACE_DTYPE [n, max_iters] or None). ``out``
     defaults to the distorted frames as float32. ``masked``: mask-driven
-    loss areas (see Plan)."""
+    loss areas; ``real``: rFSE (see Plan)."""
     import torch
     if image.dim() == 2:
         image, avail = image[None], avail[None]
     arr = _blocks_array(blocks)
     nf, H, W = image.shape
-    plan = Plan(rho, gamma, max(4096, int(arr["iters"].max()) if len(arr) else 0), masked=masked)
+    plan = Plan(rho, gamma, max(4096, int(arr["iters"].max()) if len(arr) else 0), masked=masked, real=real)
     batch = Batch(plan, arr, nf, H, W)
     if out is None:
         out = (image * (avail != 0)).to(torch.float32)

@@ -153,3 +153,26 @@ def volume_slices(vol):
     """(frames, rows, cols) slices of a volume's lost voxels."""
     f, y, x = int(vol["frame"]), int(vol["y0"]), int(vol["x0"])
     return (slice(f, f + int(vol["bt"])), slice(y, y + int(vol["bh"])), slice(x, x + int(vol["bw"])))
+
+
+def replay_real_block(frames, avail, blk, rho, gamma, trace_row):
+    """rFSE counterpart of replay_block: the trace names each selected
+    pair by its lower-index bin and that bin's coefficient, as the oracle
+    does."""
+    from oracle import rfse
+    F, I = int(blk["fft"]), int(blk["iters"])
+    seq, c = gpu_sequence(trace_row, F, I)
+    res = rfse.extrapolate_block(frames, avail, blk, rho, gamma, forced=seq)
+    short = np.array(res["short"]) if I else np.zeros(0)
+    free = np.array(res["free"]) if I else np.zeros(0, dtype=int)
+    div = free != seq
+    ag, ao = accumulate(seq, c), accumulate(seq, np.array(res["chat"]))
+    keys = sorted(ao)
+    vo = np.array([ao[k] for k in keys])
+    vg = np.array([ag.get(k, 0) for k in keys])
+    scale = np.abs(vo).max() if len(vo) else 0.0
+    return dict(ties=int(div.sum()), gap_violations=int((div & (short >= GAP_TOL)).sum()),
+                max_short=float(short[div].max()) if div.any() else 0.0,
+                coef_max=float(np.abs(vg - vo).max() / scale) if scale > 0 else 0.0,
+                coef_l2=float(np.linalg.norm(vg - vo) / np.linalg.norm(vo)) if scale > 0 else 0.0,
+                values=res["values"])

@@ -92,11 +92,12 @@ def test_validation_of_workloads():
 
 
 def test_plan_flags():
-    """FSE_PLAN_MASKED_B is the only accepted plan flag."""
+    """FSE_PLAN_MASKED_B and FSE_PLAN_REAL are the only accepted plan flags."""
     from paper_2204_14193_amd import _lib
     import paper_2204_14193_amd as fse
     fse.Plan(0.8, 0.5, 100, masked=True).close()
-    desc = _lib.fse_plan_desc_t(0.8, 0.5, 100, 2)
+    fse.Plan(0.8, 0.5, 100, real=True).close()
+    desc = _lib.fse_plan_desc_t(0.8, 0.5, 100, 8)
     h = C.c_void_p()
     assert _lib.lib().fse_plan_create(C.byref(desc), C.byref(h)) == -1
 
@@ -160,3 +161,19 @@ def test_volume_layout_and_validation():
     assert status([good, dict(good, y0=40)]) == (-5, 1)        # overlap
     masked = fse.Plan(0.8, 0.5, 300, masked=True)
     assert status([good], masked)[0] == -2
+
+
+def test_real_plan_flags():
+    """FSE_PLAN_REAL is accepted alone and refused together with
+    FSE_PLAN_MASKED_B (host checks, no device work)."""
+    from paper_2204_14193_amd import _lib
+    L = _lib.lib()
+    h = C.c_void_p()
+    d = _lib.fse_plan_desc_t(0.8, 0.5, 100, 2)
+    assert L.fse_plan_create(C.byref(d), C.byref(h)) == 0 and h.value
+    L.fse_plan_destroy(h)
+    h = C.c_void_p()
+    d = _lib.fse_plan_desc_t(0.8, 0.5, 100, 3)
+    assert L.fse_plan_create(C.byref(d), C.byref(h)) == -2 and not h.value
+    d = _lib.fse_plan_desc_t(0.8, 0.5, 100, 4)
+    assert L.fse_plan_create(C.byref(d), C.byref(h)) == -1
