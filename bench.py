@@ -239,6 +239,102 @@ def bench_clip(args):
     print(json.dumps(rec), flush=True)
 
 
+def _oracle_real_block(args):
+    from oracle import rfse
+    frames, avail, blk, rho, gamma = args
+    rfse.extrapolate_block(frames, avail, blk, rho, gamma)
+    return 1
+
+
+def bench_real(args):
+    """rFSE against cFSE at equal numbers of selected basis functions (the
+    paper's runtime comparison, Section IV): the 6432 isolated 16x16 losses
+    of eight 1080p frames, gamma 0.2; cFSE with n iterations, rFSE with n/2
+    (each rFSE iteration adds a basis function and its conjugate), for n in
+    50, 100, 200. One kernel launch per step; the step's HIP event pair
+    brackets it."""
+    import multiprocessing as mp
+    import torch
+    import paper_2204_14193_amd as fse
+    from synth import workloads
+
+    gamma = 0.2
+    wl = workloads.random_1080p_16x16(seeds=tuple(range(99, 99 + args.frames)), iters=100)
+    n = len(wl.blocks)
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(wl.distorted).to(dev)
+    av = torch.from_numpy(wl.avail).to(dev)
+    stream = torch.cuda.current_stream()
+    n_pix = int(wl.blocks["bh"].astype(np.int64) @ wl.blocks["bw"].astype(np.int64))
+
+    def leg(iters, real):
+        blocks = wl.blocks.copy()
+        blocks["iters"] = iters
+        out = img.to(torch.float32)
+        status = torch.zeros(n, dtype=torch.int32, device=dev)
+        plan = fse.Plan(wl.rho, gamma, iters, real=real)
+        batch = fse.Batch(plan, blocks, *wl.frames.shape)
+        run = lambda: batch.run(img, av, out, status)
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        ms, ev_ms = time_steps(run, args.steps, stream)
+        assert (status.cpu().numpy() == fse.BLOCK_OK).all()
+        info = batch.launch_info(64)
+        batch.close()
+        plan.close()
+        return {"iters": iters, "blocks_per_s": n / (ms * 1e-3), "ms_per_step": ms, "kernel_ms": ev_ms,
+                "us_per_block": ms * 1e3 / n, "psnr_db": psnr_lost(wl.frames, out.cpu().numpy(), wl.avail),
+                "grid": info["grid"], "threads": info["threads"], "lds_bytes": info["lds_bytes"]}
+
+    sweep = {}
+    for nbf in (50, 100, 200):
+        c, r = leg(nbf, False), leg(nbf // 2, True)
+        sweep[str(nbf)] = {"cfse": c, "rfse": r, "rfse_over_cfse_time": r["ms_per_step"] / c["ms_per_step"],
+                           "psnr_rfse_minus_cfse_db": r["psnr_db"] - c["psnr_db"]}
+    main_leg = sweep["100"]["rfse"]
+    # 2112 half-plane bins per iteration: the pair update (8 FMA) and the
+    # energy decrease (7 FLOP); 4 FLOP per pixel and iteration for the model
+    flop = n * main_leg["iters"] * (2112 * 23) + n_pix * main_leg["iters"] * FLOP_PER_PIXEL_COEF
+    achieved = flop / (main_leg["kernel_ms"] * 1e-3) / 1e12
+    rec = {
+        "metric": "rFSE blocks/s (16² loss, 64² FFT, 100 basis functions)", "value": main_leg["blocks_per_s"],
+        "unit": "blocks/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": main_leg["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.frames}x 1920x1080 synthetic frames, 804 isolated 16x16 losses per frame, "
+                               "border 16 (48x48 area), 64x64 transform, rho 0.8, gamma 0.2; rFSE with n/2 "
+                               "iterations against cFSE with n, n = 50, 100, 200 basis functions",
+                   "name": "rfse-1080p", "blocks": n},
+        "sweep": sweep,
+        "roofline": {"bound": "alu", "kernel": "fse_real64", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "frac_nonpacked": achieved / NONPACKED_FP32_TFLOPS, "kernel_ms": main_leg["kernel_ms"],
+                     "traffic": measured_traffic("fse_real64", n, "rfse-1080p")},
+    }
+    copy_calibration(args, rec, dev)
+    if not args.no_cpu:
+        cores = len(os.sched_getaffinity(0))
+        m = min(args.cpu_sample, n)
+        idx = np.sort(np.random.default_rng(5).choice(n, m, replace=False))
+        jobs = []
+        for i in idx:
+            b = wl.blocks[i].copy()
+            f = int(b["frame"])
+            b["frame"] = 0
+            b["iters"] = 50
+            jobs.append((wl.distorted[f:f + 1], wl.avail[f:f + 1], b, wl.rho, gamma))
+        with mp.get_context("fork").Pool(cores, initializer=_init_worker) as pool:
+            pool.map(_oracle_real_block, jobs[:cores])
+            t0 = time.perf_counter()
+            pool.map(_oracle_real_block, jobs, chunksize=1)
+            dt = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": m / dt, "unit": "blocks/s", "cores": cores, "kind": "oracle",
+                               "sample": f"{m} seeded blocks of the same workload (FP64 rFSE by direct projection, "
+                                         f"50 iterations each), {dt:.1f} s wall"}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,7 +343,8 @@ def main():
     ap.add_argument("--frames", type=int, default=8)
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--workload", default="random-1080p-16x16",
-                    choices=["random-1080p-16x16", "random-1080p-8x8", "mixed-4k", "strokes-1080p", "clip-1080p"],
+                    choices=["random-1080p-16x16", "random-1080p-8x8", "mixed-4k", "strokes-1080p", "clip-1080p",
+                             "rfse-1080p"],
                     help="the metric's workload (default) or one of the other configurations (plain only)")
     ap.add_argument("--kc", type=int, default=256, help="warm start: candidate bins per block")
     ap.add_argument("--ir", type=int, default=110, help="warm start: restricted iterations")
@@ -264,6 +361,9 @@ def main():
 
     if args.workload == "clip-1080p":
         bench_clip(args)
+        return
+    if args.workload == "rfse-1080p":
+        bench_real(args)
         return
 
     import torch
