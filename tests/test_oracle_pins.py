@@ -13,6 +13,7 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
+import synth
 from oracle import alg1, cfse
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -573,3 +574,114 @@ def test_rfse_pairs_tie_exactly():
     _, dec = rfse.pair_fit(P, float(w.sum()), Q, rfse.self_conjugate(F))
     flip = dec[(-np.arange(F)) % F][:, (-np.arange(F)) % F]
     assert np.array_equal(dec, flip)
+
+
+# ------------------------------------------------------------ fixed point
+
+def _fixed_area(seed=4, M=48, N=48):
+    rng = np.random.default_rng(seed)
+    s = rng.integers(0, 256, size=(M, N)).astype(np.int64)
+    A = rng.random((M, N)) > 0.2
+    A[16:32, 16:32] = False
+    return s, A
+
+
+def test_fixed_transform_rounding_and_scale():
+    """The two integer passes equal the exact sums (Python integers, same
+    integer twiddles) up to the two roundings (|error| <= 0.5 per pass,
+    carried through the second pass), and match the FP64 DFT of the same
+    input at scale 2^6 within the twiddle quantisation."""
+    from oracle import fixed
+    s, A = _fixed_area()
+    M, N = s.shape
+    wq = np.where(A, fixed.window_q(M, N, 0.8), 0)
+    zr, zi = s * wq, wq << fixed.IMAG_SHIFT
+    Zr, Zi = fixed.transform(zr, zi)
+    Tr, Ti = fixed.twiddles_q()
+    # exact sums for a few bins, in Python integers
+    for k, l in [(0, 0), (1, 0), (0, 5), (7, 33), (63, 62), (32, 32)]:
+        ex = 0
+        for m in range(M):
+            row = 0
+            for n in range(N):
+                t = complex(int(Tr[(l * n) % 64]), int(Ti[(l * n) % 64]))
+                row += complex(int(zr[m, n]), int(zi[m, n])) * t
+            ex += row * complex(int(Tr[(k * m) % 64]), int(Ti[(k * m) % 64]))
+        ex /= 2.0 ** (fixed.S_ROW + fixed.S_COL)
+        bound = 0.5 * math.sqrt(2) * (1 + M * 2 ** fixed.Q_T / 2 ** fixed.S_COL)
+        assert abs(complex(int(Zr[k, l]), int(Zi[k, l])) - ex) <= bound, (k, l)
+    # against the FP64 DFT with exact twiddles, at scale 2^6
+    ref = np.fft.fft2(np.pad((zr + 1j * zi).astype(np.complex128), ((0, 64 - M), (0, 64 - N)))) / 2.0 ** 9
+    err = np.abs((Zr + 1j * Zi) - ref)
+    assert err.max() <= 2e-4 * np.abs(ref).max(), err.max() / np.abs(ref).max()
+
+
+def test_fixed_split_and_coefficient_scales():
+    """R2 / 2^7 is the FP64 oracle's R_w and W2 / 2^14 its W (eq. (7) on
+    the same area), and the first coefficient c / 2^16 is gamma R_w / W0,
+    each within the quantisation of the encoding."""
+    from oracle import fixed
+    s, A = _fixed_area(seed=6)
+    M, N = s.shape
+    wq = np.where(A, fixed.window_q(M, N, 0.8), 0)
+    Zr, Zi = fixed.transform(s * wq, wq << fixed.IMAG_SHIFT)
+    Rx, Ry, Wx, Wy = fixed.split(Zr, Zi)
+    w = wq / 2.0 ** fixed.Q_W
+    EM, EN = cfse.analysis_matrix(64, M), cfse.analysis_matrix(64, N)
+    R = cfse.project(w * s + 0j, EM, EN)
+    Wf = cfse.project(w + 0j, EM, EN)
+    assert np.abs((Rx + 1j * Ry) / 2.0 ** 7 - R).max() <= 2e-4 * np.abs(R).max()
+    assert np.abs((Wx + 1j * Wy) / 2.0 ** 14 - Wf).max() <= 2e-4 * np.abs(Wf).max()
+    res = fixed.cfse_fixed(s, wq, 0.5, 1)
+    u, v = divmod(res["seq"][0], 64)
+    c = complex(*res["c"][0]) / 2.0 ** fixed.Q_C
+    assert abs(c - 0.5 * R[u, v] / Wf[0, 0].real) <= 1e-4 * abs(R).max() / Wf[0, 0].real
+
+
+def test_fixed_follows_the_fp64_oracle():
+    """Along the FP64 oracle's selections, the fixed-point coefficients stay
+    within 2e-3 px of the FP64 ones over 300 iterations (no growth of the
+    error: the loop has no division) and the model on B within 0.1 px; free
+    running, the two choose the same bins until a near tie."""
+    from oracle import fixed
+    frames = synth.synthetic_frames(96, 96, (12,))
+    blk = np.zeros(1, dtype=synth.BLOCK_DTYPE)[0]
+    blk["y0"], blk["x0"], blk["bh"], blk["bw"], blk["border"], blk["fft"], blk["iters"] = 40, 40, 16, 16, 16, 64, 300
+    av = np.ones_like(frames)
+    av[0, 40:56, 40:56] = 0
+    dist = frames * av
+    ro = cfse.extrapolate_block(dist, av, blk, 0.8, 0.5)
+    rf = fixed.extrapolate_block(dist, av, blk, 0.8, 0.5, forced=ro["seq"])
+    err = np.abs(np.array([complex(*c) for c in rf["c"]]) / 2.0 ** fixed.Q_C - np.array(ro["chat"]))
+    assert err.max() <= 2e-3, err.max()
+    assert err[200:].max() <= 2 * err[:100].max() + 1e-3
+    assert np.abs(rf["values"] - ro["values"]).max() <= 0.1
+    free = fixed.extrapolate_block(dist, av, blk, 0.8, 0.5, iters=60)
+    gap = np.array(ro["gap"][:60])
+    first_tie = int(np.argmax(gap < 1e-3)) if (gap < 1e-3).any() else 60
+    assert free["seq"][:first_tie] == ro["seq"][:first_tie]
+
+
+def test_fixed_constant_area_and_bounds():
+    """A constant area selects DC every iteration and is reproduced as
+    77 (1 - (1 - gamma)^I) to the output step 2^-8; with all pixels 255 on
+    a full 64 x 64 support every stored value fits int32 and every product
+    int64 (the encoding's range)."""
+    from oracle import fixed
+    M = N = 48
+    A = np.ones((M, N), dtype=bool)
+    A[16:32, 16:32] = False
+    wq = np.where(A, fixed.window_q(M, N, 0.8), 0)
+    res = fixed.cfse_fixed(np.where(A, 77, 0), wq, 0.5, 6)
+    assert res["seq"] == [0] * 6
+    assert np.abs(res["out"][16:32, 16:32] - 77 * (1 - 0.5 ** 6)).max() <= 2.0 ** -7
+    wq = fixed.window_q(64, 64, 1.0)
+    zr, zi = 255 * wq, wq << fixed.IMAG_SHIFT
+    Zr, Zi = fixed.transform(zr, zi)
+    Rx, Ry, Wx, Wy = fixed.split(Zr, Zi)
+    lim = 2 ** 31
+    for a in (Zr, Zi, Rx, Ry, Wx, Wy):
+        assert np.abs(a).max() < lim
+    G = (fixed.gamma_q(1.0) << 33) // int(Wx[0, 0])
+    assert abs(int(np.abs(Rx).max()) * G) < 2 ** 62
+    assert abs(fixed.rshift(int(np.abs(Rx).max()) * G, fixed.S_G)) < 2 ** 24   # coefficients exact in FP32
