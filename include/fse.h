@@ -116,6 +116,23 @@ typedef struct {
  * Re{c phi*}); r2 is the energy decrease. */
 #define FSE_PLAN_REAL 2u
 
+/* Plan flag: fixed-point cFSE (the integer form the paper's conclusion
+ * argues for: the loop has no division). Every value is an integer with a
+ * fixed scale and every sum is exact in int64, so results are reproducible
+ * bit for bit: window round(2^15 rho^d), twiddles round(2^14 e^{-j2pi q/64}),
+ * z = s w + j 2^7 w, a direct separable transform rounded after each pass
+ * (by 2^14, then 2^23), R2 = 2^7 R_w and W2 = 2^14 W by the conjugate
+ * split, one division per block G = floor(round(2^16 gamma) 2^33 / W2[0,0]),
+ * then per iteration the exact argmax of R2x^2 + R2y^2 (lowest index on
+ * ties), c = round(R2[u,v] G / 2^26) (units 2^-16 pixel) and
+ * R2 -= round(c W2[k-u, l-v] / 2^23); B receives
+ * round(sum Re{c e^{j theta}} 2^14 / 2^22) / 2^8, a float32 holding a
+ * multiple of 2^-8. round(x / 2^s) = (x + 2^(s-1)) >> s. Blocks must use
+ * fft = 64 with areas of at most 64 x 64 pixels; the flag excludes
+ * FSE_PLAN_MASKED_B and FSE_PLAN_REAL; the warm start and the 3-D path
+ * refuse it. Trace records carry c / 2^16 (exact in FP32) and the score. */
+#define FSE_PLAN_FIXED 4u
+
 /* One record per block and iteration when tracing: selected bin (u, v),
  * coefficient c of eq. (13) and |R_w[u,v]|^2 as seen by the argmax. For a
  * volume, u = k and v = l * fft_t + s for the selected bin (k, l, s). */
@@ -133,7 +150,8 @@ typedef struct fse_batch_s* fse_batch_t;
  * rounded to FP32. Host-only: no device memory is touched until the first
  * batch is created. Returns FSE_ERR_INVALID_ARG for rho outside (0,1], gamma
  * outside [0,1], max_iters outside [0,4096], unknown flags or null
- * pointers, FSE_ERR_UNSUPPORTED for FSE_PLAN_MASKED_B with FSE_PLAN_REAL. */
+ * pointers, FSE_ERR_UNSUPPORTED when more than one of FSE_PLAN_MASKED_B,
+ * FSE_PLAN_REAL and FSE_PLAN_FIXED is set. */
 fse_status_t fse_plan_create(const fse_plan_desc_t* desc, fse_plan_t* out_plan);
 
 /* Destroy a plan and the device tables it uploaded. Batches created from it
@@ -167,8 +185,8 @@ fse_status_t fse_blocks_from_mask(const uint8_t* h_avail, int32_t n_frames, int3
  * blocks by transform size, orders each group longest-first by F*F*I,
  * uploads descriptors, the schedule and the plan tables to the current
  * device and allocates the work-queue counters. Synchronous. After this
- * call h_blocks may be freed. With an FSE_PLAN_REAL plan every block must
- * have fft = 64 (FSE_ERR_UNSUPPORTED otherwise). */
+ * call h_blocks may be freed. With an FSE_PLAN_REAL or FSE_PLAN_FIXED plan
+ * every block must have fft = 64 (FSE_ERR_UNSUPPORTED otherwise). */
 fse_status_t fse_batch_create(fse_plan_t plan, const fse_block_t* h_blocks, int32_t n_blocks,
                               int32_t n_frames, int32_t H, int32_t W, fse_batch_t* out_batch);
 
@@ -178,7 +196,8 @@ void fse_batch_destroy(fse_batch_t batch);
 /* Largest iteration count among the batch's blocks (the trace stride). */
 int32_t fse_batch_max_iters(fse_batch_t batch);
 
-/* Run cFSE (rFSE with an FSE_PLAN_REAL plan) on every block of the batch:
+/* Run cFSE (rFSE with an FSE_PLAN_REAL plan, fixed-point cFSE with an
+ * FSE_PLAN_FIXED plan) on every block of the batch:
  * kernel launches only, on `stream`
  * (a hipStream_t; null = default stream), asynchronous, no allocation and no
  * host-device copies, so the call may be captured into a HIP graph.
@@ -197,7 +216,7 @@ fse_status_t fse_extrapolate_batch(fse_batch_t batch, const uint8_t* d_image, co
  * per workgroup, workgroups resident per CU, persistent grid size and
  * dynamic LDS bytes per workgroup. Any output pointer may be null. Returns
  * FSE_ERR_INVALID_ARG if the batch has no block of that size. With an
- * FSE_PLAN_REAL plan it describes the rFSE kernel. */
+ * FSE_PLAN_REAL or FSE_PLAN_FIXED plan it describes that kernel. */
 fse_status_t fse_batch_launch_info(fse_batch_t batch, int32_t F, int32_t* threads, int32_t* wg_per_cu,
                                    int32_t* grid, int32_t* lds_bytes);
 
@@ -207,7 +226,8 @@ fse_status_t fse_batch_launch_info(fse_batch_t batch, int32_t F, int32_t* thread
  * they differ in speed only. Returns FSE_ERR_UNSUPPORTED if no such variant
  * is compiled or it does not fit a compute unit, FSE_ERR_INVALID_ARG if the
  * batch has no block of that size, FSE_ERR_UNSUPPORTED for an FSE_PLAN_REAL
- * plan. Host-side; affects later fse_extrapolate_batch calls. */
+ * or FSE_PLAN_FIXED plan. Host-side; affects later fse_extrapolate_batch
+ * calls. */
 fse_status_t fse_batch_set_variant(fse_batch_t batch, int32_t F, int32_t threads);
 
 /* Autotuner: for every transform size present in the batch, launch every
@@ -216,7 +236,8 @@ fse_status_t fse_batch_set_variant(fse_batch_t batch, int32_t F, int32_t threads
  * Arguments as for fse_extrapolate_batch (d_out and d_status receive the
  * results of the last launch). If `report` is not null, up to report_len
  * bytes of text are written to it, one line "F threads microseconds" per
- * variant timed. FSE_ERR_UNSUPPORTED for an FSE_PLAN_REAL plan. */
+ * variant timed. FSE_ERR_UNSUPPORTED for an FSE_PLAN_REAL or FSE_PLAN_FIXED
+ * plan. */
 fse_status_t fse_batch_autotune(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail, int64_t pitch,
                                 float* d_out, int64_t out_pitch, int32_t* d_status, int32_t reps, void* stream,
                                 char* report, size_t report_len);
@@ -236,7 +257,8 @@ enum {
   FSE_KERNEL_WARM_FUSED = 1,  /* warm start, restricted and full phases in one    */
   FSE_KERNEL_WARM_PREP = 2,   /* warm start, transform and staging (split form)   */
   FSE_KERNEL_RESTRICTED = 3,  /* warm start, restricted iterations (split form)   */
-  FSE_KERNEL_REAL = 4         /* rFSE (plan flag FSE_PLAN_REAL)                   */
+  FSE_KERNEL_REAL = 4,        /* rFSE (plan flag FSE_PLAN_REAL)                   */
+  FSE_KERNEL_FIXED = 5        /* fixed-point cFSE (plan flag FSE_PLAN_FIXED)      */
 };
 fse_status_t fse_batch_set_timing(fse_batch_t batch, int32_t max_records);
 int32_t fse_batch_kernel_times(fse_batch_t batch, float* ms, int32_t* kind, int32_t* fft, int32_t cap);
@@ -353,8 +375,8 @@ int32_t fse_warm_trace_stride(fse_batch_t batch, int32_t restricted_iters, int32
  *
  * fse_batch3d_create validates h_volumes (fft = 64, fft_t = 8, area within
  * the transform, B inside the clip, 0 <= iters <= the plan's max_iters, no
- * two B overlapping; the plan must not have FSE_PLAN_MASKED_B or
- * FSE_PLAN_REAL), uploads
+ * two B overlapping; the plan must not have FSE_PLAN_MASKED_B,
+ * FSE_PLAN_REAL or FSE_PLAN_FIXED), uploads
  * them, the 3-D window table and the scratch buffers (256 KB per resident
  * workgroup) to the current device. Synchronous. *bad_index (if not null)
  * receives the first offending volume or -1. */

@@ -87,8 +87,10 @@ struct fse_batch_s {
   bool all_48 = false;                     // every area is 48 x 48 (network input size)
   bool all_small_b = false;                // every B has at most 256 pixels (restricted kernel
                                            // synthesises in its loop, no coefficient list)
-  int32_t real_grid = 0;                   // rFSE launch (plan flag FSE_PLAN_REAL)
-  size_t real_lds = 0;
+  int32_t alt_grid = 0;                    // rFSE or fixed-point launch (FSE_PLAN_REAL, FSE_PLAN_FIXED)
+  size_t alt_lds = 0;
+  int32_t* d_wtab_q = nullptr;             // fixed point: integer window table
+  int2* d_twid_q = nullptr;                // fixed point: integer twiddles
 };
 
 extern "C" const char* fse_last_error(void) { return g_error; }
@@ -100,10 +102,10 @@ extern "C" fse_status_t fse_plan_create(const fse_plan_desc_t* desc, fse_plan_t*
   if (!(desc->gamma >= 0.f && desc->gamma <= 1.f)) return fail(FSE_ERR_INVALID_ARG, "gamma must lie in [0, 1]");
   if (desc->max_iters < 0 || desc->max_iters > fse::kMaxIters)
     return fail(FSE_ERR_INVALID_ARG, "max_iters must lie in [0, 4096]");
-  if ((desc->flags & ~(uint32_t)(FSE_PLAN_MASKED_B | FSE_PLAN_REAL)) != 0)
+  if ((desc->flags & ~(uint32_t)(FSE_PLAN_MASKED_B | FSE_PLAN_REAL | FSE_PLAN_FIXED)) != 0)
     return fail(FSE_ERR_INVALID_ARG, "unknown plan flag");
-  if ((desc->flags & FSE_PLAN_MASKED_B) && (desc->flags & FSE_PLAN_REAL))
-    return fail(FSE_ERR_UNSUPPORTED, "rFSE plans take rectangular loss areas");
+  if (__builtin_popcount(desc->flags) > 1)
+    return fail(FSE_ERR_UNSUPPORTED, "FSE_PLAN_MASKED_B, FSE_PLAN_REAL and FSE_PLAN_FIXED exclude each other");
   fse_plan_s* p = new (std::nothrow) fse_plan_s;
   if (!p) return fail(FSE_ERR_OOM, "host allocation failed");
   p->rho = desc->rho;
@@ -299,6 +301,8 @@ void free_batch(fse_batch_s* b) {
   free_timing(b);
   (void)hipFree(b->d_stage_w);
   (void)hipFree(b->d_stage_r);
+  (void)hipFree(b->d_wtab_q);
+  (void)hipFree(b->d_twid_q);
   (void)hipFree(b->d_blocks);
   (void)hipFree(b->d_orig);
   (void)hipFree(b->d_queue);
@@ -354,22 +358,25 @@ extern "C" fse_status_t fse_batch_create(fse_plan_t plan, const fse_block_t* h_b
     return fail(FSE_ERR_HIP, "hipGetDeviceProperties failed");
   }
   b->cus = prop.multiProcessorCount;
-  if (plan->flags & FSE_PLAN_REAL) {
+  if (plan->flags & (FSE_PLAN_REAL | FSE_PLAN_FIXED)) {
+    const bool real = plan->flags & FSE_PLAN_REAL;
     if (b->cls[class_of(64)].count != n_blocks) {
       delete b;
-      return fail(FSE_ERR_UNSUPPORTED, "rFSE is compiled for 64 x 64 transforms");
+      return fail(FSE_ERR_UNSUPPORTED, real ? "rFSE is compiled for 64 x 64 transforms"
+                                            : "fixed-point cFSE is compiled for 64 x 64 transforms");
     }
-    b->real_lds = fse::real_lds_bytes(std::max(b->cls[class_of(64)].iters_cap, 1));
+    const int cap = std::max(b->cls[class_of(64)].iters_cap, 1);
+    const void* fn = real ? fse::real_kernel() : fse::fixed_kernel();
+    b->alt_lds = real ? fse::real_lds_bytes(cap) : fse::fixed_lds_bytes(cap);
     int per_cu = 0;
-    if (hipFuncSetAttribute(fse::real_kernel(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->real_lds) !=
-            hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fse::real_kernel(), fse::real_threads(), b->real_lds) !=
-            hipSuccess ||
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->alt_lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, real ? fse::real_threads() : fse::fixed_threads(),
+                                                     b->alt_lds) != hipSuccess ||
         per_cu < 1) {
       delete b;
-      return fail(FSE_ERR_UNSUPPORTED, "rFSE kernel does not fit on a compute unit (iteration count too large)");
+      return fail(FSE_ERR_UNSUPPORTED, "kernel does not fit on a compute unit (iteration count too large)");
     }
-    b->real_grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(n_blocks, (int64_t)per_cu * b->cus));
+    b->alt_grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(n_blocks, (int64_t)per_cu * b->cus));
   }
   for (int ci = 0; ci < 3; ++ci) {
     fse_batch_s::Cls& c = b->cls[ci];
@@ -400,6 +407,32 @@ extern "C" fse_status_t fse_batch_create(fse_plan_t plan, const fse_block_t* h_b
     free_batch(b);
     return fail(FSE_ERR_HIP, "upload of the batch failed");
   }
+  if (plan->flags & FSE_PLAN_FIXED) {
+    // integer tables of the fixed-point encoding, FP64 on the host, rounded
+    // once: window round(2^15 rho^(sqrt(a^2 + b^2) / 2)) for doubled
+    // offsets, twiddles round(2^14 exp(-j 2 pi q / 64))
+    const int S = fse::kWinStride;
+    std::vector<int32_t> wq((size_t)S * S);
+    for (int x = 0; x < S; ++x)
+      for (int y = 0; y < S; ++y)
+        wq[(size_t)x * S + y] = (int32_t)std::floor(
+            std::pow((double)plan->rho, std::sqrt((double)x * x + (double)y * y) / 2.0) * 32768.0 + 0.5);
+    std::vector<int2> tq(64);
+    for (int q = 0; q < 64; ++q) {
+      const double th = 2.0 * M_PI * q / 64.0;
+      tq[q] = make_int2((int)std::floor(std::cos(th) * 16384.0 + 0.5), (int)std::floor(-std::sin(th) * 16384.0 + 0.5));
+    }
+    if (hipMalloc(&b->d_wtab_q, wq.size() * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&b->d_twid_q, tq.size() * sizeof(int2)) != hipSuccess) {
+      free_batch(b);
+      return fail(FSE_ERR_OOM, "hipMalloc failed (fixed-point tables)");
+    }
+    if (hipMemcpy(b->d_wtab_q, wq.data(), wq.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_twid_q, tq.data(), tq.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess) {
+      free_batch(b);
+      return fail(FSE_ERR_HIP, "upload of the fixed-point tables failed");
+    }
+  }
   *out_batch = b;
   return FSE_OK;
 }
@@ -417,11 +450,11 @@ extern "C" fse_status_t fse_batch_launch_info(fse_batch_t batch, int32_t F, int3
   if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
   const int ci = class_of(F);
   if (ci < 0 || batch->cls[ci].count == 0) return fail(FSE_ERR_INVALID_ARG, "no block of this transform size");
-  if (batch->plan->flags & FSE_PLAN_REAL) {
-    if (threads) *threads = fse::real_threads();
-    if (wg_per_cu) *wg_per_cu = (batch->real_grid + batch->cus - 1) / batch->cus;
-    if (grid) *grid = batch->real_grid;
-    if (lds_bytes) *lds_bytes = (int32_t)batch->real_lds;
+  if (batch->plan->flags & (FSE_PLAN_REAL | FSE_PLAN_FIXED)) {
+    if (threads) *threads = (batch->plan->flags & FSE_PLAN_REAL) ? fse::real_threads() : fse::fixed_threads();
+    if (wg_per_cu) *wg_per_cu = (batch->alt_grid + batch->cus - 1) / batch->cus;
+    if (grid) *grid = batch->alt_grid;
+    if (lds_bytes) *lds_bytes = (int32_t)batch->alt_lds;
     return FSE_OK;
   }
   const fse_batch_s::Cls& c = batch->cls[ci];
@@ -491,6 +524,9 @@ static fse_status_t launch_one(fse_batch_t batch, int ci, const uint8_t* d_image
     a.fb_iters = warm ? batch->warm_fb : 0;
     a.stage_w = nullptr;
     a.stage_r = nullptr;
+    a.wtab_q = nullptr;
+    a.twid_q = nullptr;
+    a.gamma_q = 0;
     if (warm) {
       a.iters_cap = c.iters_cap;
       a.trace_stride = batch->warm_ir + std::max(batch->max_iters, batch->warm_fb);
@@ -500,9 +536,18 @@ static fse_status_t launch_one(fse_batch_t batch, int ci, const uint8_t* d_image
       }
     }
     if (!warm && (batch->plan->flags & FSE_PLAN_REAL)) {
-      if (timed(batch, FSE_KERNEL_REAL, 64, s, [&] { return fse::launch_real(a, batch->real_grid, batch->real_lds, s); }) !=
+      if (timed(batch, FSE_KERNEL_REAL, 64, s, [&] { return fse::launch_real(a, batch->alt_grid, batch->alt_lds, s); }) !=
           hipSuccess)
         return fail(FSE_ERR_HIP, "kernel launch failed (rFSE)");
+      return FSE_OK;
+    }
+    if (!warm && (batch->plan->flags & FSE_PLAN_FIXED)) {
+      a.wtab_q = batch->d_wtab_q;
+      a.twid_q = batch->d_twid_q;
+      a.gamma_q = (int32_t)std::floor((double)batch->plan->gamma * 65536.0 + 0.5);
+      if (timed(batch, FSE_KERNEL_FIXED, 64, s,
+                [&] { return fse::launch_fixed(a, batch->alt_grid, batch->alt_lds, s); }) != hipSuccess)
+        return fail(FSE_ERR_HIP, "kernel launch failed (fixed point)");
       return FSE_OK;
     }
     const int kind = !warm ? FSE_KERNEL_PLAIN : batch->warm_split ? FSE_KERNEL_WARM_PREP : FSE_KERNEL_WARM_FUSED;
@@ -552,7 +597,8 @@ extern "C" fse_status_t fse_batch_set_variant(fse_batch_t batch, int32_t F, int3
   if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
   const int ci = class_of(F);
   if (ci < 0 || batch->cls[ci].count == 0) return fail(FSE_ERR_INVALID_ARG, "no block of this transform size");
-  if (batch->plan->flags & FSE_PLAN_REAL) return fail(FSE_ERR_UNSUPPORTED, "the rFSE kernel has one workgroup shape");
+  if (batch->plan->flags & (FSE_PLAN_REAL | FSE_PLAN_FIXED))
+    return fail(FSE_ERR_UNSUPPORTED, "the rFSE and fixed-point kernels have one workgroup shape");
   const fse::Variant* vs[16];
   const int nv = std::min(fse::variants_for(F, vs, 16), 16);
   for (int i = 0; i < nv; ++i)
@@ -565,7 +611,8 @@ extern "C" fse_status_t fse_batch_autotune(fse_batch_t batch, const uint8_t* d_i
                                            int32_t reps, void* stream, char* report, size_t report_len) {
   if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
   if (reps < 1) return fail(FSE_ERR_INVALID_ARG, "reps must be >= 1");
-  if (batch->plan->flags & FSE_PLAN_REAL) return fail(FSE_ERR_UNSUPPORTED, "the rFSE kernel has one workgroup shape");
+  if (batch->plan->flags & (FSE_PLAN_REAL | FSE_PLAN_FIXED))
+    return fail(FSE_ERR_UNSUPPORTED, "the rFSE and fixed-point kernels have one workgroup shape");
   if (report && report_len) report[0] = 0;
   size_t used = 0;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -617,7 +664,7 @@ extern "C" fse_status_t fse_cnn_patches(fse_batch_t batch, const uint8_t* d_imag
                                         int64_t pitch, uint16_t* d_x, void* stream) {
   if (!batch || !d_image || !d_avail || !d_x) return fail(FSE_ERR_INVALID_ARG, "null argument");
   if (!batch->all_48) return fail(FSE_ERR_UNSUPPORTED, "network inputs need 48x48 areas");
-  if (batch->plan->flags & (FSE_PLAN_MASKED_B | FSE_PLAN_REAL))
+  if (batch->plan->flags & (FSE_PLAN_MASKED_B | FSE_PLAN_REAL | FSE_PLAN_FIXED))
     return fail(FSE_ERR_UNSUPPORTED, "the warm start needs a cFSE plan with rectangular loss areas");
   if (pitch < batch->W) return fail(FSE_ERR_INVALID_ARG, "pitch smaller than the width");
   if (fse::cnn::patches(d_image, d_avail, pitch, batch->H, batch->W, batch->d_blocks, batch->d_orig, batch->n, d_x,
@@ -631,7 +678,7 @@ extern "C" fse_status_t fse_cnn_forward_blocks(fse_cnn_t net, fse_batch_t batch,
                                                void* stream) {
   if (!batch || !d_image || !d_avail) return fail(FSE_ERR_INVALID_ARG, "null argument");
   if (!batch->all_48) return fail(FSE_ERR_UNSUPPORTED, "network inputs need 48x48 areas");
-  if (batch->plan->flags & (FSE_PLAN_MASKED_B | FSE_PLAN_REAL))
+  if (batch->plan->flags & (FSE_PLAN_MASKED_B | FSE_PLAN_REAL | FSE_PLAN_FIXED))
     return fail(FSE_ERR_UNSUPPORTED, "the warm start needs a cFSE plan with rectangular loss areas");
   if (pitch < batch->W) return fail(FSE_ERR_INVALID_ARG, "pitch smaller than the width");
   return fse::cnn::net_forward_blocks(net, d_image, d_avail, pitch, batch->H, batch->W, batch->d_blocks,
@@ -648,7 +695,7 @@ extern "C" fse_status_t fse_warm_extrapolate_batch(fse_batch_t batch, const uint
                                                    const int16_t* d_cand, const int32_t* d_flags, int32_t kc,
                                                    int32_t restricted_iters, int32_t fallback_iters, void* stream) {
   if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
-  if (batch->plan->flags & (FSE_PLAN_MASKED_B | FSE_PLAN_REAL))
+  if (batch->plan->flags & (FSE_PLAN_MASKED_B | FSE_PLAN_REAL | FSE_PLAN_FIXED))
     return fail(FSE_ERR_UNSUPPORTED, "the warm start needs a cFSE plan with rectangular loss areas");
   if (batch->n == 0) return FSE_OK;
   if (!d_image || !d_avail || !d_out || !d_status || !d_cand || !d_flags)
@@ -737,7 +784,7 @@ fse_status_t validate_volumes(fse_plan_t plan, const fse_volume_t* v, int32_t n,
                               int32_t W, int32_t* bad) {
   if (bad) *bad = -1;
   if (!plan) return fail(FSE_ERR_INVALID_ARG, "null plan");
-  if (plan->flags & (FSE_PLAN_MASKED_B | FSE_PLAN_REAL))
+  if (plan->flags & (FSE_PLAN_MASKED_B | FSE_PLAN_REAL | FSE_PLAN_FIXED))
     return fail(FSE_ERR_UNSUPPORTED, "volumes need a cFSE plan with rectangular loss areas");
   if (n < 0 || (n > 0 && !v)) return fail(FSE_ERR_INVALID_ARG, "bad volume list");
   if (n_frames <= 0 || H <= 0 || W <= 0) return fail(FSE_ERR_INVALID_ARG, "clip dimensions must be positive");

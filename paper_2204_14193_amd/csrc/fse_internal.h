@@ -44,6 +44,10 @@ struct ClassArgs {
   // read by the restricted kernel, indexed by the caller's block index
   float2* stage_w;            // [caller's n_blocks][kHalfRows * 64]: W rows 0..32
   float2* stage_r;            // [caller's n_blocks][kc]: R_w at the candidates
+  // fixed-point form only (plan flag FSE_PLAN_FIXED)
+  const int32_t* wtab_q;      // round(2^15 rho^(sqrt(a^2 + b^2) / 2)), [kWinStride][kWinStride]
+  const int2* twid_q;         // round(2^14 exp(-j 2 pi q / 64)), 64 entries
+  int32_t gamma_q;            // round(2^16 gamma)
 };
 
 // Rows of W kept by the split warm start for F = 64: W[k, l] for k <= 32;
@@ -87,6 +91,12 @@ size_t real_lds_bytes(int iters_cap);
 const void* real_kernel();
 int real_threads();
 hipError_t launch_real(const ClassArgs& a, int grid, size_t lds, hipStream_t s);
+
+// Fixed-point cFSE, F = 64: the same four helpers.
+size_t fixed_lds_bytes(int iters_cap);
+const void* fixed_kernel();
+int fixed_threads();
+hipError_t launch_fixed(const ClassArgs& a, int grid, size_t lds, hipStream_t s);
 
 // Kernel modes.
 enum Mode : int { kPlain = 0, kWarmFused = 1, kWarmPrep = 2 };

@@ -1471,6 +1471,217 @@ __global__ __launch_bounds__(kRealNT) void fse_real64(ClassArgs a) {
     __syncthreads();  // Wd and the list are overwritten by the next block
   }
 }
+
+// ------------------------------------------------------------ fixed point
+// cFSE in integer arithmetic (F = 64): every value is an integer with a
+// fixed scale and every sum is exact in int64, so the result is one
+// deterministic function of the input, reproducible bit for bit:
+//   z = s wq + j 2^7 wq (wq = window, scale 2^15; twiddles T scale 2^14)
+//   Y[m,l] = round(sum_n z[m,n] T[l n] / 2^14),  Z[k,l] = round(sum_m Y[m,l] T[k m] / 2^23)
+//   R2 = Z + conj(Z[-k,-l]) (2^7 R_w),  W2 = -j (Z - conj(Z[-k,-l])) (2^14 W)
+//   G = floor(gamma_q 2^33 / W2[0,0]): the only division, once per block
+//   iterations: argmax R2x^2 + R2y^2 (exact, lowest index on ties),
+//   c = round(R2[u,v] G / 2^26), R2 -= round(c W2[k-u, l-v] / 2^23)
+//   model on B: round(sum Re{c conj(T[u m + v n])} / 2^22) / 2^8
+// round(x / 2^s) is (x + 2^(s-1)) >> s. The transform is computed as two
+// direct passes (an FFT would round between its stages).
+constexpr int kFixedNT = 256;
+
+__device__ __forceinline__ int32_t rshift_lo(int64_t x, int s) {
+  // round(x / 2^s) when the result fits 32 bits
+  return (int32_t)((x + ((int64_t)1 << (s - 1))) >> s);
+}
+
+__global__ __launch_bounds__(kFixedNT) void fse_fixed64(ClassArgs a) {
+  constexpr int F = 64, NT = kFixedNT, NW = NT / 64, BPL = F * F / NT;  // 16 bins per lane
+  extern __shared__ __align__(16) unsigned char smem[];
+  int2* const zb = reinterpret_cast<int2*>(smem);    // z, then Z            [64][64]
+  int2* const yb = zb + F * F;                        // Y [m][l], then W2    [64][64]
+  int2* const tq = yb + F * F;                        // twiddles
+  int4* const red = reinterpret_cast<int4*>(tq + F);  // 2 parities x NW x 2 slots
+  int2* const cl_c = reinterpret_cast<int2*>(red + 4 * NW);
+  int* const cl_idx = reinterpret_cast<int*>(cl_c + a.iters_cap);
+  const int t0 = threadIdx.x;
+  if (t0 < F) tq[t0] = a.twid_q[t0];
+  int parity = 0;
+  for (int bi = blockIdx.x; bi < a.n; bi += gridDim.x) {
+    int t = t0;
+    asm volatile("" : "+v"(t));
+    const int lane = t & (F - 1), wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const UBlock bd = uniform_block(a.blocks + bi);
+    const int orig = __builtin_amdgcn_readfirstlane(a.orig[bi]);
+    const int bh = bd.bh, bw = bd.bw, bo = bd.border;
+    const int M = bh + 2 * bo, N = bw + 2 * bo;
+    const int ya = bd.y0 - bo, xa = bd.x0 - bo;
+    const int I = bd.iters;
+    const int64_t fofs = (int64_t)bd.frame * a.H;
+    const uint8_t* img = a.img + fofs * a.pitch;
+    const uint8_t* av = a.avail + fofs * a.pitch;
+    const int pitch = (int)a.pitch;
+
+    // 1. z on the area (rows and columns beyond M, N are never read)
+    for (int e = t; e < F * F; e += NT) {
+      const int m = e / F, n = e % F;
+      const int y = ya + m, x = xa + n;
+      const bool inB = m >= bo && m < bo + bh && n >= bo && n < bo + bw;
+      int2 z = make_int2(0, 0);
+      if (m < M && n < N && !inB && y >= 0 && y < a.H && x >= 0 && x < a.W) {
+        const uint32_t p = (uint32_t)(y * pitch + x);
+        if (av[p] != 0) {
+          const int da = min(abs(2 * m - (M - 1)), kWinStride - 1), db = min(abs(2 * n - (N - 1)), kWinStride - 1);
+          const int w = a.wtab_q[da * kWinStride + db];
+          z = make_int2((int)img[p] * w, w << 7);
+        }
+      }
+      zb[e] = z;
+    }
+    __syncthreads();
+    // 2. row pass: lane l, rows m = wave, wave + NW, ...
+    {
+      const int l = lane;
+      for (int m = wave; m < M; m += NW) {
+        int64_t ar = 0, ai = 0;
+        for (int n = 0; n < N; ++n) {
+          const int2 z = zb[m * F + n];        // broadcast
+          const int2 tw = tq[(l * n) & (F - 1)];
+          ar += (int64_t)z.x * tw.x - (int64_t)z.y * tw.y;
+          ai += (int64_t)z.x * tw.y + (int64_t)z.y * tw.x;
+        }
+        yb[m * F + l] = make_int2(rshift_lo(ar, 14), rshift_lo(ai, 14));
+      }
+    }
+    __syncthreads();
+    // 3. column pass: lane l, frequencies k = wave, wave + NW, ...; Z into zb
+    {
+      const int l = lane;
+      for (int k = wave; k < F; k += NW) {
+        int64_t ar = 0, ai = 0;
+        for (int m = 0; m < M; ++m) {
+          const int2 y = yb[m * F + l];
+          const int2 tw = tq[(k * m) & (F - 1)];  // uniform
+          ar += (int64_t)y.x * tw.x - (int64_t)y.y * tw.y;
+          ai += (int64_t)y.x * tw.y + (int64_t)y.y * tw.x;
+        }
+        zb[k * F + l] = make_int2(rshift_lo(ar, 23), rshift_lo(ai, 23));
+      }
+    }
+    __syncthreads();
+    // 4. split: R2 into registers (bin wave*1024 + j*64 + lane), W2 into yb
+    int Rx[BPL], Ry[BPL];
+#pragma unroll
+    for (int j = 0; j < BPL; ++j) {
+      const int k = wave * BPL + j, l = lane;
+      const int2 zk = zb[k * F + l];
+      const int2 zn = zb[((F - k) & (F - 1)) * F + ((F - l) & (F - 1))];
+      Rx[j] = zk.x + zn.x;
+      Ry[j] = zk.y - zn.y;
+      yb[k * F + l] = make_int2(zk.y + zn.y, zn.x - zk.x);
+    }
+    __syncthreads();
+    const int W0 = __builtin_amdgcn_readfirstlane(yb[0].x);
+    if (W0 <= 0) {
+      if (t == 0) a.status[orig] = FSE_BLOCK_EMPTY_SUPPORT;
+      __syncthreads();
+      continue;
+    }
+    const int64_t G = ((int64_t)a.gamma_q << 33) / W0;
+    // per-thread first maximum of the exact score
+    uint64_t best = 0;
+    int bj = 0;
+#pragma unroll
+    for (int j = 0; j < BPL; ++j) {
+      const uint64_t sc = (uint64_t)((int64_t)Rx[j] * Rx[j] + (int64_t)Ry[j] * Ry[j]);
+      bj = sc > best ? j : bj;
+      best = sc > best ? sc : best;
+    }
+    for (int it = 0; it < I; ++it) {
+      // wave: largest score (high word, then low word), then the lowest bin
+      const uint32_t bh32 = (uint32_t)(best >> 32), bl32 = (uint32_t)best;
+      const uint32_t mh = wave_max_bits(bh32);
+      const uint32_t ml = wave_max_bits(bh32 == mh ? bl32 : 0u);
+      const bool top = bh32 == mh && bl32 == ml;
+      const uint32_t key = wave_min_u32(top ? (uint32_t)(bj * 64 + lane) : 0xffffffffu);
+      const int wl = (int)(key & 63), jw = (int)(key >> 6);
+      const int widx = wave * (BPL * 64) + (int)key;
+      const int wrx = __builtin_amdgcn_readlane(Rx[jw], wl), wry = __builtin_amdgcn_readlane(Ry[jw], wl);
+      red[(parity * NW + wave) * 2] = make_int4((int)mh, (int)ml, widx, 0);
+      red[(parity * NW + wave) * 2 + 1] = make_int4(wrx, wry, 0, 0);
+      __syncthreads();
+      uint32_t gh = 0, gl = 0;
+      int gidx = 0, gx = 0, gy = 0;
+#pragma unroll
+      for (int w2 = 0; w2 < NW; ++w2) {
+        const int4 v0 = red[(parity * NW + w2) * 2];
+        const int4 v1 = red[(parity * NW + w2) * 2 + 1];
+        const uint32_t h2 = (uint32_t)__builtin_amdgcn_readfirstlane(v0.x);
+        const uint32_t l2 = (uint32_t)__builtin_amdgcn_readfirstlane(v0.y);
+        const bool take = w2 == 0 || h2 > gh || (h2 == gh && l2 > gl);  // the first wave wins ties
+        gh = take ? h2 : gh;
+        gl = take ? l2 : gl;
+        gidx = take ? __builtin_amdgcn_readfirstlane(v0.z) : gidx;
+        gx = take ? __builtin_amdgcn_readfirstlane(v1.x) : gx;
+        gy = take ? __builtin_amdgcn_readfirstlane(v1.y) : gy;
+      }
+      parity ^= 1;
+      const int u = gidx >> 6, v = gidx & (F - 1);
+      const int cr = (int)(((int64_t)gx * G + ((int64_t)1 << 25)) >> 26);  // eq. (13)
+      const int ci = (int)(((int64_t)gy * G + ((int64_t)1 << 25)) >> 26);
+      if (wave == 0) {
+        cl_idx[it] = gidx;  // uniform stores
+        cl_c[it] = make_int2(cr, ci);
+        if (a.trace) {
+          fse_trace_t rec;
+          rec.u = (uint16_t)u;
+          rec.v = (uint16_t)v;
+          rec.c_re = (float)cr * (1.0f / 65536.0f);
+          rec.c_im = (float)ci * (1.0f / 65536.0f);
+          rec.r2 = (float)(((uint64_t)gh << 32) | gl);
+          a.trace[(int64_t)orig * a.trace_stride + it] = rec;
+        }
+      }
+      // eq. (18): R2[k,l] -= round(c W2[k-u, l-v] / 2^23); the row k - u is
+      // uniform per register, the column per lane
+      int col = ((lane - v) & (F - 1)) * 8;
+      asm volatile("" : "+v"(col));
+      const unsigned char* Wb = reinterpret_cast<const unsigned char*>(yb);
+      constexpr int64_t kHalf = (int64_t)1 << 22;
+      best = 0;
+      bj = 0;
+#pragma unroll
+      for (int j = 0; j < BPL; ++j) {
+        const int row = ((wave * BPL + j - u) & (F - 1)) * (F * 8);
+        const int2 w = *reinterpret_cast<const int2*>(Wb + row + col);
+        const int64_t dx = (int64_t)cr * w.x - (int64_t)ci * w.y + kHalf;
+        const int64_t dy = (int64_t)cr * w.y + (int64_t)ci * w.x + kHalf;
+        const int rx = Rx[j] - (int)(dx >> 23), ry = Ry[j] - (int)(dy >> 23);
+        Rx[j] = rx;
+        Ry[j] = ry;
+        const uint64_t sc = (uint64_t)((int64_t)rx * rx + (int64_t)ry * ry);
+        bj = sc > best ? j : bj;
+        best = sc > best ? sc : best;
+      }
+    }
+    __syncthreads();  // the coefficient list is complete
+    // 5. model on B, exact int64 sums
+    {
+      const int np = bh * bw;
+      float* ob = a.out + (fofs + bd.y0) * a.out_pitch + bd.x0;
+      for (int p = t; p < np; p += NT) {
+        const int m = bo + p / bw, n = bo + p % bw;
+        int64_t acc = 0;
+        for (int it = 0; it < I; ++it) {
+          const int gidx = __builtin_amdgcn_readfirstlane(cl_idx[it]);
+          const int2 c = cl_c[it];
+          const int2 tw = tq[((gidx >> 6) * m + (gidx & (F - 1)) * n) & (F - 1)];
+          acc += (int64_t)c.x * tw.x + (int64_t)c.y * tw.y;
+        }
+        ob[(int64_t)(p / bw) * a.out_pitch + p % bw] = (float)rshift_lo(acc, 22) * (1.0f / 256.0f);
+      }
+    }
+    if (t == 0) a.status[orig] = FSE_BLOCK_OK;
+    __syncthreads();  // the buffers and the list are overwritten by the next block
+  }
+}
 }  // namespace
 
 const Variant* variant_for(int F) {
@@ -1552,6 +1763,19 @@ size_t real_lds_bytes(int iters_cap) { return (size_t)64 * 64 * 8 + 64 * 8 + 16 
 const void* real_kernel() { return reinterpret_cast<const void*>(&fse_real64); }
 
 int real_threads() { return kRealNT; }
+
+size_t fixed_lds_bytes(int iters_cap) {
+  return (size_t)2 * 64 * 64 * 8 + 64 * 8 + 4 * (kFixedNT / 64) * 16 + (size_t)iters_cap * 12;
+}
+
+const void* fixed_kernel() { return reinterpret_cast<const void*>(&fse_fixed64); }
+
+int fixed_threads() { return kFixedNT; }
+
+hipError_t launch_fixed(const ClassArgs& a, int grid, size_t lds, hipStream_t s) {
+  void* args[] = {const_cast<ClassArgs*>(&a)};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&fse_fixed64), dim3(grid), dim3(kFixedNT), args, lds, s);
+}
 
 hipError_t launch_real(const ClassArgs& a, int grid, size_t lds, hipStream_t s) {
   void* args[] = {const_cast<ClassArgs*>(&a)};

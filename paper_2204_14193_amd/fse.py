@@ -11,7 +11,7 @@ from . import _lib
 
 BLOCK_OK, BLOCK_EMPTY_SUPPORT, BLOCK_NONFINITE = 0, 1, 2
 # FSE_KERNEL_* of include/fse.h, by value
-KERNEL_KINDS = ("plain", "warm_fused", "warm_prep", "restricted", "real")
+KERNEL_KINDS = ("plain", "warm_fused", "warm_prep", "restricted", "real", "fixed")
 
 BLOCK_DTYPE = np.dtype([("frame", "<i4"), ("y0", "<i4"), ("x0", "<i4"),
                         ("bh", "<i2"), ("bw", "<i2"), ("border", "<i2"),
@@ -51,17 +51,19 @@ def _blocks_array(blocks):
 
 PLAN_MASKED_B = 1  # FSE_PLAN_MASKED_B of include/fse.h
 PLAN_REAL = 2      # FSE_PLAN_REAL: real-valued FSE (rFSE)
+PLAN_FIXED = 4     # FSE_PLAN_FIXED: fixed-point cFSE
 
 
 class Plan:
     """fse_plan_t: window decay rho, compensation gamma, iteration limit;
     masked=True makes every block's loss area the lost pixels of its
     rectangle (arbitrary loss shapes, FSE_PLAN_MASKED_B); real=True runs
-    real-valued FSE instead of cFSE (FSE_PLAN_REAL, F = 64 blocks only)."""
+    real-valued FSE instead of cFSE (FSE_PLAN_REAL, F = 64 blocks only);
+    fixed=True runs the fixed-point cFSE encoding (FSE_PLAN_FIXED, F = 64)."""
 
-    def __init__(self, rho=0.8, gamma=0.5, max_iters=4096, masked=False, real=False):
+    def __init__(self, rho=0.8, gamma=0.5, max_iters=4096, masked=False, real=False, fixed=False):
         L = _lib.lib()
-        flags = (PLAN_MASKED_B if masked else 0) | (PLAN_REAL if real else 0)
+        flags = (PLAN_MASKED_B if masked else 0) | (PLAN_REAL if real else 0) | (PLAN_FIXED if fixed else 0)
         desc = _lib.fse_plan_desc_t(float(rho), float(gamma), int(max_iters), flags)
         h = C.c_void_p()
         _check(L.fse_plan_create(C.byref(desc), C.byref(h)), "fse_plan_create")
@@ -69,6 +71,7 @@ class Plan:
         self.rho, self.gamma, self.max_iters = float(rho), float(gamma), int(max_iters)
         self.masked = bool(masked)
         self.real = bool(real)
+        self.fixed = bool(fixed)
 
     @property
     def handle(self):
@@ -288,18 +291,20 @@ def blocks_from_mask(avail, cell=16, border=16, fft=64, iters=100):
     return arr
 
 
-def extrapolate_batch(image, avail, blocks, rho=0.8, gamma=0.5, trace=False, out=None, masked=False, real=False):
+def extrapolate_batch(image, avail, blocks, rho=0.8, gamma=0.5, trace=False, out=None, masked=False, real=False,
+                      fixed=False):
     """Conceal ``blocks`` in frames ``image`` (uint8 CUDA tensor [F,H,W] or
     [H,W]) with availability ``avail``. Returns (out float32, status int32
     numpy, trace numpy of TRACE_DTYPE [n, max_iters] or None). ``out``
     defaults to the distorted frames as float32. ``masked``: mask-driven
-    loss areas; ``real``: rFSE (see Plan)."""
+    loss areas; ``real``: rFSE; ``fixed``: fixed-point cFSE (see Plan)."""
     import torch
     if image.dim() == 2:
         image, avail = image[None], avail[None]
     arr = _blocks_array(blocks)
     nf, H, W = image.shape
-    plan = Plan(rho, gamma, max(4096, int(arr["iters"].max()) if len(arr) else 0), masked=masked, real=real)
+    plan = Plan(rho, gamma, max(4096, int(arr["iters"].max()) if len(arr) else 0), masked=masked, real=real,
+                fixed=fixed)
     batch = Batch(plan, arr, nf, H, W)
     if out is None:
         out = (image * (avail != 0)).to(torch.float32)

@@ -164,8 +164,9 @@ def test_volume_layout_and_validation():
 
 
 def test_real_plan_flags():
-    """FSE_PLAN_REAL is accepted alone and refused together with
-    FSE_PLAN_MASKED_B (host checks, no device work)."""
+    """FSE_PLAN_REAL and FSE_PLAN_FIXED are accepted alone and refused in
+    any combination with each other or FSE_PLAN_MASKED_B; unknown bits are
+    invalid (host checks, no device work)."""
     from paper_2204_14193_amd import _lib
     L = _lib.lib()
     h = C.c_void_p()
@@ -175,5 +176,13 @@ def test_real_plan_flags():
     h = C.c_void_p()
     d = _lib.fse_plan_desc_t(0.8, 0.5, 100, 3)
     assert L.fse_plan_create(C.byref(d), C.byref(h)) == -2 and not h.value
+    h = C.c_void_p()
     d = _lib.fse_plan_desc_t(0.8, 0.5, 100, 4)
+    assert L.fse_plan_create(C.byref(d), C.byref(h)) == 0 and h.value
+    L.fse_plan_destroy(h)
+    for flags in (5, 6, 7):
+        h = C.c_void_p()
+        d = _lib.fse_plan_desc_t(0.8, 0.5, 100, flags)
+        assert L.fse_plan_create(C.byref(d), C.byref(h)) == -2 and not h.value
+    d = _lib.fse_plan_desc_t(0.8, 0.5, 100, 8)
     assert L.fse_plan_create(C.byref(d), C.byref(h)) == -1
