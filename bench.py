@@ -335,6 +335,94 @@ def bench_real(args):
     print(json.dumps(rec), flush=True)
 
 
+def _oracle_fixed_block(args):
+    from oracle import fixed
+    frames, avail, blk, rho, gamma = args
+    fixed.extrapolate_block(frames, avail, blk, rho, gamma)
+    return 1
+
+
+INT64_MAD_PEAK = 256 * 4 * 16 * 2.4e9 / 4   # 64-bit multiply-add, quarter rate (assumed)
+
+
+def bench_fixed(args):
+    """Fixed-point cFSE against the FP32 kernel on the 6432 isolated 16x16
+    losses of eight 1080p frames (100 iterations, gamma 0.5). One kernel
+    launch per step; the step's HIP event pair brackets it."""
+    import multiprocessing as mp
+    import torch
+    import paper_2204_14193_amd as fse
+    from synth import workloads
+
+    wl = workloads.random_1080p_16x16(seeds=tuple(range(99, 99 + args.frames)), iters=args.iters)
+    n = len(wl.blocks)
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(wl.distorted).to(dev)
+    av = torch.from_numpy(wl.avail).to(dev)
+    stream = torch.cuda.current_stream()
+
+    def leg(fixed_point):
+        out = img.to(torch.float32)
+        status = torch.zeros(n, dtype=torch.int32, device=dev)
+        plan = fse.Plan(wl.rho, wl.gamma, args.iters, fixed=fixed_point)
+        batch = fse.Batch(plan, wl.blocks, *wl.frames.shape)
+        run = lambda: batch.run(img, av, out, status)
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        ms, ev_ms = time_steps(run, args.steps, stream)
+        assert (status.cpu().numpy() == fse.BLOCK_OK).all()
+        info = batch.launch_info(64)
+        batch.close()
+        plan.close()
+        return {"blocks_per_s": n / (ms * 1e-3), "ms_per_step": ms, "kernel_ms": ev_ms,
+                "psnr_db": psnr_lost(wl.frames, out.cpu().numpy(), wl.avail), **info}
+
+    legs = {"float": leg(False), "fixed": leg(True)}
+    fx = legs["fixed"]
+    # 64-bit multiply-adds per launch: the two transform passes (4 per
+    # complex term), 6 per bin and iteration (score 2, update 4), 2 per
+    # pixel and iteration for the model
+    M = N = 48
+    mads = n * (4 * (M * N * 64 + 64 * 64 * M) + args.iters * 64 * 64 * 6 + args.iters * 256 * 2)
+    achieved = mads / (fx["kernel_ms"] * 1e-3)
+    rec = {
+        "metric": "fixed-point cFSE blocks/s (16² loss, 64² FFT, 100 iterations)", "value": fx["blocks_per_s"],
+        "unit": "blocks/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": fx["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32/int64", "data": "synthetic",
+        "config": {"workload": f"{args.frames}x 1920x1080 synthetic frames, 804 isolated 16x16 losses per frame, "
+                               f"border 16 (48x48 area), 64x64 transform, rho 0.8, gamma 0.5, {args.iters} "
+                               "iterations; fixed-point encoding against the FP32 kernel",
+                   "name": "fixed-1080p", "blocks": n},
+        "legs": legs, "psnr_fixed_minus_float_db": fx["psnr_db"] - legs["float"]["psnr_db"],
+        "time_fixed_over_float": fx["ms_per_step"] / legs["float"]["ms_per_step"],
+        "roofline": {"bound": "alu", "kernel": "fse_fixed64", "achieved": achieved / 1e12, "peak": INT64_MAD_PEAK / 1e12,
+                     "unit": "T int64-MAD/s", "frac": achieved / INT64_MAD_PEAK, "kernel_ms": fx["kernel_ms"],
+                     "traffic": measured_traffic("fse_fixed64", n, "fixed-1080p")},
+    }
+    copy_calibration(args, rec, dev)
+    if not args.no_cpu:
+        cores = len(os.sched_getaffinity(0))
+        m = min(args.cpu_sample, n)
+        idx = np.sort(np.random.default_rng(5).choice(n, m, replace=False))
+        jobs = []
+        for i in idx:
+            b = wl.blocks[i].copy()
+            f = int(b["frame"])
+            b["frame"] = 0
+            jobs.append((wl.distorted[f:f + 1], wl.avail[f:f + 1], b, float(np.float32(wl.rho)),
+                         float(np.float32(wl.gamma))))
+        with mp.get_context("fork").Pool(cores, initializer=_init_worker) as pool:
+            pool.map(_oracle_fixed_block, jobs[:cores])
+            t0 = time.perf_counter()
+            pool.map(_oracle_fixed_block, jobs, chunksize=1)
+            dt = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": m / dt, "unit": "blocks/s", "cores": cores, "kind": "oracle",
+                               "sample": f"{m} seeded blocks of the same workload (integer oracle, "
+                                         f"{args.iters} iterations each), {dt:.1f} s wall"}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -344,7 +432,7 @@ def main():
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--workload", default="random-1080p-16x16",
                     choices=["random-1080p-16x16", "random-1080p-8x8", "mixed-4k", "strokes-1080p", "clip-1080p",
-                             "rfse-1080p"],
+                             "rfse-1080p", "fixed-1080p"],
                     help="the metric's workload (default) or one of the other configurations (plain only)")
     ap.add_argument("--kc", type=int, default=256, help="warm start: candidate bins per block")
     ap.add_argument("--ir", type=int, default=110, help="warm start: restricted iterations")
@@ -364,6 +452,9 @@ def main():
         return
     if args.workload == "rfse-1080p":
         bench_real(args)
+        return
+    if args.workload == "fixed-1080p":
+        bench_fixed(args)
         return
 
     import torch
