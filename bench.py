@@ -289,8 +289,10 @@ def bench_real(args):
 
     sweep = {}
     for nbf in (50, 100, 200):
-        c, r = leg(nbf, False), leg(nbf // 2, True)
-        sweep[str(nbf)] = {"cfse": c, "rfse": r, "rfse_over_cfse_time": r["ms_per_step"] / c["ms_per_step"],
+        c, r, ri = leg(nbf, False), leg(nbf // 2, True), leg(nbf // 2, "inloop")
+        sweep[str(nbf)] = {"cfse": c, "rfse": r, "rfse_inloop": ri,
+                           "rfse_over_cfse_time": r["ms_per_step"] / c["ms_per_step"],
+                           "rfse_inloop_over_cfse_time": ri["ms_per_step"] / c["ms_per_step"],
                            "psnr_rfse_minus_cfse_db": r["psnr_db"] - c["psnr_db"]}
     main_leg = sweep["100"]["rfse"]
     # 2112 half-plane bins per iteration: the pair update (8 FMA) and the

@@ -116,6 +116,13 @@ typedef struct {
  * Re{c phi*}); r2 is the energy decrease. */
 #define FSE_PLAN_REAL 2u
 
+/* Modifier of FSE_PLAN_REAL (invalid without it): the pair constants,
+ * divisions by W0^2 - |W[2k,2l]|^2 included, are recomputed for every bin in
+ * every iteration instead of once per block, the formulation whose cost
+ * the paper's runtime comparison describes (Section II). Same results up
+ * to FP32 rounding. */
+#define FSE_PLAN_REAL_INLOOP 8u
+
 /* Plan flag: fixed-point cFSE (the integer form the paper's conclusion
  * argues for: the loop has no division). Every value is an integer with a
  * fixed scale and every sum is exact in int64, so results are reproducible
@@ -150,8 +157,9 @@ typedef struct fse_batch_s* fse_batch_t;
  * rounded to FP32. Host-only: no device memory is touched until the first
  * batch is created. Returns FSE_ERR_INVALID_ARG for rho outside (0,1], gamma
  * outside [0,1], max_iters outside [0,4096], unknown flags or null
- * pointers, FSE_ERR_UNSUPPORTED when more than one of FSE_PLAN_MASKED_B,
- * FSE_PLAN_REAL and FSE_PLAN_FIXED is set. */
+ * pointers or FSE_PLAN_REAL_INLOOP without FSE_PLAN_REAL,
+ * FSE_ERR_UNSUPPORTED when more than one of FSE_PLAN_MASKED_B, FSE_PLAN_REAL
+ * and FSE_PLAN_FIXED is set. */
 fse_status_t fse_plan_create(const fse_plan_desc_t* desc, fse_plan_t* out_plan);
 
 /* Destroy a plan and the device tables it uploaded. Batches created from it

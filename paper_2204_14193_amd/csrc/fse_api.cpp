@@ -102,9 +102,11 @@ extern "C" fse_status_t fse_plan_create(const fse_plan_desc_t* desc, fse_plan_t*
   if (!(desc->gamma >= 0.f && desc->gamma <= 1.f)) return fail(FSE_ERR_INVALID_ARG, "gamma must lie in [0, 1]");
   if (desc->max_iters < 0 || desc->max_iters > fse::kMaxIters)
     return fail(FSE_ERR_INVALID_ARG, "max_iters must lie in [0, 4096]");
-  if ((desc->flags & ~(uint32_t)(FSE_PLAN_MASKED_B | FSE_PLAN_REAL | FSE_PLAN_FIXED)) != 0)
+  if ((desc->flags & ~(uint32_t)(FSE_PLAN_MASKED_B | FSE_PLAN_REAL | FSE_PLAN_FIXED | FSE_PLAN_REAL_INLOOP)) != 0)
     return fail(FSE_ERR_INVALID_ARG, "unknown plan flag");
-  if (__builtin_popcount(desc->flags) > 1)
+  if ((desc->flags & FSE_PLAN_REAL_INLOOP) && !(desc->flags & FSE_PLAN_REAL))
+    return fail(FSE_ERR_INVALID_ARG, "FSE_PLAN_REAL_INLOOP modifies FSE_PLAN_REAL");
+  if (__builtin_popcount(desc->flags & ~(uint32_t)FSE_PLAN_REAL_INLOOP) > 1)
     return fail(FSE_ERR_UNSUPPORTED, "FSE_PLAN_MASKED_B, FSE_PLAN_REAL and FSE_PLAN_FIXED exclude each other");
   fse_plan_s* p = new (std::nothrow) fse_plan_s;
   if (!p) return fail(FSE_ERR_OOM, "host allocation failed");
@@ -366,7 +368,7 @@ extern "C" fse_status_t fse_batch_create(fse_plan_t plan, const fse_block_t* h_b
                                             : "fixed-point cFSE is compiled for 64 x 64 transforms");
     }
     const int cap = std::max(b->cls[class_of(64)].iters_cap, 1);
-    const void* fn = real ? fse::real_kernel() : fse::fixed_kernel();
+    const void* fn = real ? fse::real_kernel(plan->flags & FSE_PLAN_REAL_INLOOP) : fse::fixed_kernel();
     b->alt_lds = real ? fse::real_lds_bytes(cap) : fse::fixed_lds_bytes(cap);
     int per_cu = 0;
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->alt_lds) != hipSuccess ||
@@ -536,7 +538,9 @@ static fse_status_t launch_one(fse_batch_t batch, int ci, const uint8_t* d_image
       }
     }
     if (!warm && (batch->plan->flags & FSE_PLAN_REAL)) {
-      if (timed(batch, FSE_KERNEL_REAL, 64, s, [&] { return fse::launch_real(a, batch->alt_grid, batch->alt_lds, s); }) !=
+      if (timed(batch, FSE_KERNEL_REAL, 64, s, [&] {
+            return fse::launch_real(a, batch->plan->flags & FSE_PLAN_REAL_INLOOP, batch->alt_grid, batch->alt_lds, s);
+          }) !=
           hipSuccess)
         return fail(FSE_ERR_HIP, "kernel launch failed (rFSE)");
       return FSE_OK;

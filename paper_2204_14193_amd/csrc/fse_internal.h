@@ -86,11 +86,13 @@ hipError_t launch_fse3d(const Vol3Args& a, int grid, size_t lds, hipStream_t s);
 const void* fse3d_kernel();
 
 // rFSE (real-valued model), F = 64: LDS bytes for a given iteration cap,
-// the kernel (for the occupancy API), its workgroup size, and its launch.
+// the kernel (for the occupancy API), its workgroup size, and its launch;
+// inloop selects the form that recomputes the pair constants in every
+// iteration.
 size_t real_lds_bytes(int iters_cap);
-const void* real_kernel();
+const void* real_kernel(bool inloop);
 int real_threads();
-hipError_t launch_real(const ClassArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t launch_real(const ClassArgs& a, bool inloop, int grid, size_t lds, hipStream_t s);
 
 // Fixed-point cFSE, F = 64: the same four helpers.
 size_t fixed_lds_bytes(int iters_cap);

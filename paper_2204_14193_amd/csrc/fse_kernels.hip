@@ -1259,8 +1259,12 @@ __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
 // A |P|^2 - Re{Bq* P^2} and the coefficient A P* - Bq* P. These depend on
 // the window only, so the divisions are done once per block, and the
 // decrease is held as a1 x^2 + a2 y^2 + a3 x y (P = x + j y).
+// INLOOP recomputes the constants, divisions included, in every iteration
+// (the formulation whose cost the paper's runtime comparison describes);
+// the results agree with the hoisted form up to FP32 rounding.
 constexpr int kRealNT = 256;
 
+template <bool INLOOP>
 __global__ __launch_bounds__(kRealNT) void fse_real64(ClassArgs a) {
   constexpr int F = 64, NT = kRealNT, NC = 9;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1339,8 +1343,7 @@ __global__ __launch_bounds__(kRealNT) void fse_real64(ClassArgs a) {
 
     // 3. per-bin constants of the pair fit
     float a1[NC], a2[NC], a3[NC];
-#pragma unroll
-    for (int cc = 0; cc < NC; ++cc) {
+    auto constants = [&](int cc) {
       const int l = wv + 4 * cc;
       a1[cc] = a2[cc] = a3[cc] = 0.f;
       if (l <= F / 2) {
@@ -1358,7 +1361,9 @@ __global__ __launch_bounds__(kRealNT) void fse_real64(ClassArgs a) {
         a2[cc] = rep ? A + Br : 0.f;
         a3[cc] = rep ? -2.0f * Bi : 0.f;
       }
-    }
+    };
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) constants(cc);
     auto decrease = [&](int cc) {
       const float x = Rx[cc], y = Ry[cc];
       const float tq = fmaf(a3[cc], y, a1[cc] * x);
@@ -1457,6 +1462,7 @@ __global__ __launch_bounds__(kRealNT) void fse_real64(ClassArgs a) {
         ry = fmaf(qq, w2.x, ry);
         Rx[cc] = rx;
         Ry[cc] = ry;
+        if constexpr (INLOOP) constants(cc);
         if (bits_max_first(decrease(cc), best)) bj = cc;
       }
     }
@@ -1760,7 +1766,9 @@ const void* fse3d_kernel() { return reinterpret_cast<const void*>(&fse3d); }
 
 size_t real_lds_bytes(int iters_cap) { return (size_t)64 * 64 * 8 + 64 * 8 + 16 * 16 + (size_t)iters_cap * 12; }
 
-const void* real_kernel() { return reinterpret_cast<const void*>(&fse_real64); }
+const void* real_kernel(bool inloop) {
+  return inloop ? reinterpret_cast<const void*>(&fse_real64<true>) : reinterpret_cast<const void*>(&fse_real64<false>);
+}
 
 int real_threads() { return kRealNT; }
 
@@ -1777,9 +1785,9 @@ hipError_t launch_fixed(const ClassArgs& a, int grid, size_t lds, hipStream_t s)
   return hipLaunchKernel(reinterpret_cast<const void*>(&fse_fixed64), dim3(grid), dim3(kFixedNT), args, lds, s);
 }
 
-hipError_t launch_real(const ClassArgs& a, int grid, size_t lds, hipStream_t s) {
+hipError_t launch_real(const ClassArgs& a, bool inloop, int grid, size_t lds, hipStream_t s) {
   void* args[] = {const_cast<ClassArgs*>(&a)};
-  return hipLaunchKernel(reinterpret_cast<const void*>(&fse_real64), dim3(grid), dim3(kRealNT), args, lds, s);
+  return hipLaunchKernel(real_kernel(inloop), dim3(grid), dim3(kRealNT), args, lds, s);
 }
 
 hipError_t launch_fse3d(const Vol3Args& a, int grid, size_t lds, hipStream_t s) {

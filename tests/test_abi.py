@@ -184,5 +184,11 @@ def test_real_plan_flags():
         h = C.c_void_p()
         d = _lib.fse_plan_desc_t(0.8, 0.5, 100, flags)
         assert L.fse_plan_create(C.byref(d), C.byref(h)) == -2 and not h.value
-    d = _lib.fse_plan_desc_t(0.8, 0.5, 100, 8)
+    d = _lib.fse_plan_desc_t(0.8, 0.5, 100, 8)       # the in-loop modifier alone
+    assert L.fse_plan_create(C.byref(d), C.byref(h)) == -1
+    h = C.c_void_p()
+    d = _lib.fse_plan_desc_t(0.8, 0.5, 100, 2 | 8)
+    assert L.fse_plan_create(C.byref(d), C.byref(h)) == 0 and h.value
+    L.fse_plan_destroy(h)
+    d = _lib.fse_plan_desc_t(0.8, 0.5, 100, 16)
     assert L.fse_plan_create(C.byref(d), C.byref(h)) == -1

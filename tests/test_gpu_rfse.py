@@ -18,13 +18,13 @@ def _say(msg):
     print(msg, flush=True)
 
 
-def _run(distorted, avail, blocks, rho, gamma, trace=True):
+def _run(distorted, avail, blocks, rho, gamma, trace=True, real=True):
     import torch
     import paper_2204_14193_amd as fse
     dev = torch.device("cuda:0")
     img = torch.from_numpy(distorted).to(dev)
     av = torch.from_numpy(avail).to(dev)
-    out, st, tr = fse.extrapolate_batch(img, av, blocks, rho, gamma, trace=trace, real=True)
+    out, st, tr = fse.extrapolate_batch(img, av, blocks, rho, gamma, trace=trace, real=real)
     return out.cpu().numpy(), st, tr
 
 
@@ -73,6 +73,23 @@ def test_rfse_isolated_256_full_parity():
     assert d <= parity.PSNR_TOL
     lost = wl.avail == 0
     assert np.array_equal(out[~lost], wl.distorted[~lost].astype(np.float32))
+
+
+def test_rfse_inloop_variant_parity():
+    """The form that recomputes the pair constants in every iteration
+    (FSE_PLAN_REAL_INLOOP) meets the same bars on the 256x256 case."""
+    wl = workloads.isolated_256()
+    blocks = wl.blocks.copy()
+    blocks["iters"] = 50
+    _say(f"case rfse-inloop isolated-256: {len(blocks)} blocks F=64 I=50")
+    out, st, tr = _run(wl.distorted, wl.avail, blocks, wl.rho, wl.gamma, real="inloop")
+    assert (st == 0).all(), st
+    idx = range(len(blocks))
+    rows = _check(wl.frames, wl.avail, blocks, wl.rho, wl.gamma, out, tr, idx)
+    d, pg, po = _psnr(wl.frames, wl.avail, blocks, wl.rho, wl.gamma, out, idx)
+    _say(f"ties={sum(r['ties'] for r in rows)} coef_max={max(r['coef_max'] for r in rows):.2e} "
+         f"psnr gpu={pg:.4f} oracle={po:.4f}")
+    assert d <= parity.PSNR_TOL
 
 
 def test_rfse_1080p_sampled_parity():
