@@ -600,7 +600,9 @@ def main():
         lds_bytes = LDS_BYTES_PER_BIN_ITER * bin_iters
         rec["lds_roofline"] = {"achieved": lds_bytes / (roof["ms"] * 1e-3) / 1e12, "peak": NOMINAL_LDS_TBPS,
                                "unit": "TB/s", "frac": lds_bytes / (roof["ms"] * 1e-3) / 1e12 / NOMINAL_LDS_TBPS,
-                               "note": "algorithmic 24 B/bin/iteration against the nominal LDS bandwidth"}
+                               "note": "algorithmic 24 B/bin/iteration (R_w read and written, shifted W read) "
+                                       "against the nominal LDS bandwidth; only the 8-B W read touches LDS, "
+                                       "R_w stays in registers"}
     copy_calibration(args, rec, dev)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, n), masked=masked)
