@@ -136,3 +136,18 @@ def test_rfse_edge_cases():
     bad[1]["border"] = 8
     with pytest.raises(fse.FseError):
         _run(dist, av, bad, 0.8, 0.5)
+
+
+def test_rfse_mixed_block_sizes():
+    """8x8 (border 16), 32x32 (border 16: a 64x64 area, the largest) and
+    16x16 (border 8) blocks in one launch, every block replayed."""
+    frames = workloads.synthetic_image(192, 192, 77)[None]
+    blist = [losses.Block(0, 24, 24, 8, 8, 16, 64, 30), losses.Block(0, 96, 16, 32, 32, 16, 64, 30),
+             losses.Block(0, 40, 120, 16, 16, 8, 64, 30)]
+    blocks = losses.blocks_to_array(blist)
+    av = losses.availability_mask(frames.shape, blist)
+    dist = (frames * av).astype(np.uint8)
+    _say("case rfse mixed sizes: 8x8/b16, 32x32/b16, 16x16/b8")
+    out, st, tr = _run(dist, av, blocks, 0.8, 0.5)
+    assert (st == 0).all(), st
+    _check(frames, av, blocks, 0.8, 0.5, out, tr, range(3))

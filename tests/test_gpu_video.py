@@ -121,3 +121,25 @@ def test_clip_edge_cases():
     _check(sub, out, tr, [2, 3])
     out2, st2, tr2 = _run(dist, av, np.zeros(0, dtype=losses.VOLUME_DTYPE), 0.8, 0.5)
     assert len(st2) == 0 and np.array_equal(out2, dist.astype(np.float32))
+
+
+def test_clip_mixed_volume_sizes():
+    """Volumes of other shapes in one launch: 8x8x1 (border 8, 1 frame),
+    24x24x4 (border 12 and 2: a 48x48x8 area, 2304 voxels, more than one
+    per thread), 16x16x2 with border 24 (a 64x64x6 area, the largest that
+    fits), each replayed against the oracle."""
+    wl = workloads.clip_small()
+    vols = np.zeros(3, dtype=losses.VOLUME_DTYPE)
+    spec = [(1, 8, 8, 8, 0, 3, 40), (4, 24, 24, 12, 2, 2, 100), (2, 16, 16, 24, 2, 4, 180)]
+    for v, (bt, bh, bw, bd, td, f, pos) in zip(vols, spec):
+        v["frame"], v["y0"], v["x0"] = f, pos, pos
+        v["bt"], v["bh"], v["bw"], v["border"], v["tborder"] = bt, bh, bw, bd, td
+        v["fft"], v["fft_t"], v["iters"] = 64, 8, 30
+    av = losses.volume_availability(wl.frames.shape, vols)
+    dist = (wl.frames * av).astype(np.uint8)
+    _say("case clip-mixed: 8x8x1, 24x24x4, 16x16x2 border 24")
+    out, st, tr = _run(dist, av, vols, 0.8, 0.5)
+    assert (st == 0).all(), st
+    sub = workloads.Workload("mixed", wl.frames, av, vols, 0.8, 0.5)
+    rows = _check(sub, out, tr, range(3))
+    _say(f"coef_max={max(r['coef_max'] for r in rows):.2e} pix={max(r['pix_maxabs'] for r in rows):.2e}")
