@@ -26,7 +26,9 @@ Closed forms (P = R_w[k,l] = sum w r phi*, W0 = sum w, Q = W[2k, 2l] =
 sum w phi*^2, D = W0^2 - |Q|^2):
   c = 2 (W0 P* - Q* P) / D,  decrease = Re{c P} = 2 (W0 |P|^2 - Re{Q* P^2}) / D;
   self-conjugate bins: c = P / W0 (real), decrease = P^2 / W0.
-They are pinned against a brute-force weighted least-squares fit.
+They are pinned against a brute-force weighted least-squares fit. Whether
+they are [Kaup2005]'s rules cannot be checked here: parity unpinned
+against the paper's rFSE (no numbers of it are available).
 """
 import numpy as np
 
