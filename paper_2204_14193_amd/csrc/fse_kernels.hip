@@ -1081,41 +1081,38 @@ __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
         __syncthreads();  // the buffers are reused; the scratch is read by other threads
       }
     }
-    // 2. Ft-point DFT along time of every column (k, l), in place in the
-    // scratch (a thread reads and writes only its own columns)
-    for (int c = t; c < F * F; c += NT) {
-      float2 zt[FT];
-#pragma unroll
-      for (int q = 0; q < FT; ++q) zt[q] = q < T ? Z[q * (F * F) + c] : make_float2(0.f, 0.f);
-#pragma unroll
-      for (int sq = 0; sq < FT; ++sq) {
-        float2 acc = zt[0];
-#pragma unroll
-        for (int q = 1; q < FT; ++q) acc = cadd(acc, cmul(zt[q], tw[(sq * q * (F / FT)) & (F - 1)]));
-        Z[sq * (F * F) + c] = acc;
-      }
-    }
-    __syncthreads();
-    // 3. split Z = R_w + j alpha W by conjugate symmetry: R_w of the
-    // thread's bins into registers, W for l <= 32 into LDS as [l][s][k]
+    // 2+3. temporal DFT fused with the conjugate-symmetric split. For the
+    // thread's column (k, l) and its mirror (-k, -l), over the area's frames
+    // t: a_t = Z_t[k,l] + conj(Z_t[-k,-l]), b_t = Z_t[k,l] - conj(Z_t[-k,-l]);
+    // then R_w[k,l,s] = (1/2) sum_t a_t e^{-j 2 pi s t / Ft} into registers
+    // and, for l <= 32, W[k,l,s] = -j / (2 alpha) sum_t b_t e^{-j 2 pi s t / Ft}
+    // into LDS as [l][s][k] (over the dead FFT buffers)
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6), kk = t & (F - 1);
     float Rx[BPT], Ry[BPT];
 #pragma unroll
     for (int cc = 0; cc < BPT / FT; ++cc) {
       const int l = (BPT / FT) * wv + cc;
+      const bool needW = l <= F / 2;  // uniform
+      float2 A[FT], B[FT];
+#pragma unroll
+      for (int s3 = 0; s3 < FT; ++s3) A[s3] = B[s3] = make_float2(0.f, 0.f);
+      for (int q = 0; q < T; ++q) {
+        const float2 zk = Z[(q * F + l) * F + kk];
+        const float2 zn = Z[(q * F + ((F - l) & (F - 1))) * F + ((F - kk) & (F - 1))];
+        const float2 av = make_float2(zk.x + zn.x, zk.y - zn.y), bv = make_float2(zk.x - zn.x, zk.y + zn.y);
+#pragma unroll
+        for (int s3 = 0; s3 < FT; ++s3) {
+          const float2 e = tw[(s3 * q * (F / FT)) & (F - 1)];
+          A[s3] = cadd(A[s3], cmul(av, e));
+          if (needW) B[s3] = cadd(B[s3], cmul(bv, e));
+        }
+      }
 #pragma unroll
       for (int s3 = 0; s3 < FT; ++s3) {
-        const float2 zk = Z[(s3 * F + l) * F + kk];
-        const float2 zn = Z[(((FT - s3) & (FT - 1)) * F + ((F - l) & (F - 1))) * F + ((F - kk) & (F - 1))];
-        Rx[cc * FT + s3] = (zk.x + zn.x) * 0.5f;
-        Ry[cc * FT + s3] = (zk.y - zn.y) * 0.5f;
+        Rx[cc * FT + s3] = A[s3].x * 0.5f;
+        Ry[cc * FT + s3] = A[s3].y * 0.5f;
+        if (needW) Wl[(l * FT + s3) * F + kk] = make_float2(B[s3].y * (0.5f / kAlpha), -B[s3].x * (0.5f / kAlpha));
       }
-    }
-    for (int e = t; e < WH; e += NT) {
-      const int l = e / (F * FT), s3 = (e / F) % FT, k = e % F;
-      const float2 zk = Z[(s3 * F + l) * F + k];
-      const float2 zn = Z[(((FT - s3) & (FT - 1)) * F + ((F - l) & (F - 1))) * F + ((F - k) & (F - 1))];
-      Wl[e] = make_float2((zk.y + zn.y) * (0.5f / kAlpha), (zn.x - zk.x) * (0.5f / kAlpha));
     }
     __syncthreads();
     const float W0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(Wl[0].x)));
