@@ -6,8 +6,9 @@ is no CPU fallback: if the library is not built, importing the binding
 raises.
 """
 from .fse import (Plan, Batch, Batch3d, extrapolate_batch, extrapolate3d, blocks_from_mask, BLOCK_DTYPE,
-                  VOLUME_DTYPE, TRACE_DTYPE, BLOCK_OK, BLOCK_EMPTY_SUPPORT, BLOCK_NONFINITE, FseError)
+                  VOLUME_DTYPE, TRACE_DTYPE, BLOCK_OK, BLOCK_EMPTY_SUPPORT, BLOCK_NONFINITE, FseError,
+                  measure_lds_bandwidth)
 
 __all__ = ["Plan", "Batch", "Batch3d", "extrapolate_batch", "extrapolate3d", "blocks_from_mask", "BLOCK_DTYPE",
            "VOLUME_DTYPE", "TRACE_DTYPE",
-           "BLOCK_OK", "BLOCK_EMPTY_SUPPORT", "BLOCK_NONFINITE", "FseError"]
+           "BLOCK_OK", "BLOCK_EMPTY_SUPPORT", "BLOCK_NONFINITE", "FseError", "measure_lds_bandwidth"]

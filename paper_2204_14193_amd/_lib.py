@@ -52,6 +52,7 @@ SIGNATURES = {
     "fse_batch_set_timing": (I32, [P, I32]),
     "fse_batch_kernel_times": (I32, [P, P, P, P, I32]),
     "fse_last_error": (C.c_char_p, []),
+    "fse_measure_lds_bandwidth": (I32, [I32, P, C.POINTER(C.c_double)]),
     "fse_cnn_num_params": (I64, []),
     "fse_cnn_create": (I32, [I32, C.c_uint64, C.POINTER(P)]),
     "fse_cnn_destroy": (None, [P]),

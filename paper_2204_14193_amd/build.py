@@ -13,7 +13,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfse.so")
 
-SOURCES = ["fse_kernels.hip", "fse_api.cpp", "cnn_kernels.hip", "cnn_api.cpp"]
+SOURCES = ["fse_kernels.hip", "fse_api.cpp", "cnn_kernels.hip", "cnn_api.cpp", "lds_probe.hip"]
 
 # Packed FP32 instructions are switched off for all device code on this
 # platform; the host pass warns that it does not know the feature.

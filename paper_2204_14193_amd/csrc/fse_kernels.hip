@@ -1035,7 +1035,6 @@ __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
     // opaque thread index: keeps index-derived addresses out of the volume loop
     int t = t0;
     asm volatile("" : "+v"(t));
-    const int wave = t >> 6;
     const fse_volume_t* vp = a.vols + vi;
     const int f0 = __builtin_amdgcn_readfirstlane(vp->frame);
     const int y0 = __builtin_amdgcn_readfirstlane(vp->y0), x0 = __builtin_amdgcn_readfirstlane(vp->x0);

@@ -325,3 +325,13 @@ def extrapolate_batch(image, avail, blocks, rho=0.8, gamma=0.5, trace=False, out
     batch.close()
     plan.close()
     return out, st, tr
+
+
+def measure_lds_bandwidth(iters=2000):
+    """Aggregate LDS read bandwidth of the current device in bytes/s
+    (fse_measure_lds_bandwidth), for roofline accounting."""
+    import torch
+    out = C.c_double(0.0)
+    _check(_lib.lib().fse_measure_lds_bandwidth(int(iters), C.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                                C.byref(out)), "fse_measure_lds_bandwidth")
+    return out.value

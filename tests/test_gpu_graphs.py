@@ -81,3 +81,13 @@ def test_3d_graph_capture():
     _replays_match(lambda s: batch.run(img, av, out, status, stream=s), out, status, base, len(wl.blocks))
     batch.close()
     plan.close()
+
+
+def test_lds_bandwidth_probe():
+    """The LDS bandwidth measurement returns a plausible aggregate figure
+    (between 20 and 120 TB/s on 256 compute units; nominal 78.6)."""
+    import paper_2204_14193_amd as fse
+    _say("case lds bandwidth probe")
+    bw = fse.measure_lds_bandwidth(500) / 1e12
+    _say(f"lds {bw:.1f} TB/s")
+    assert 20.0 < bw < 120.0
