@@ -35,7 +35,7 @@ METRIC = "FSE blocks/s (16² loss, 64² FFT) plain vs warm-start at ≤0.1 dB PS
 PSNR_BAR_DB = 0.1
 PEAK_FP32_TFLOPS = 157.3        # MI355X FP32 vector, published (counts packed FMA)
 NONPACKED_FP32_TFLOPS = 78.6    # 256 CU x 64 lanes x 2 FLOP x 2.4 GHz, without packed FP32
-NOMINAL_LDS_TBPS = 78.6         # 256 CU x 128 B/clk x 2.4 GHz
+NOMINAL_LDS_TBPS = 78.6         # 256 CU x 128 B/clk x 2.4 GHz (gfx950 measures about twice that)
 PEAK_HBM_TBPS = 8.0
 FLOP_PER_BIN_ITER = 11          # complex multiply-subtract (8) + |R|^2 (3), eq. (18) + eq. (12)
 FLOP_PER_PIXEL_COEF = 4         # Re{c e^{j theta}}: two FMAs, the model on B

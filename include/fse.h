@@ -404,10 +404,10 @@ fse_status_t fse_extrapolate3d_batch(fse_batch3d_t batch, const uint8_t* d_frame
                                      fse_trace_t* d_trace, void* stream);
 
 /* Measurement (roofline accounting): the LDS read bandwidth of the current
- * device, measured by a kernel in which every workgroup (4 per compute
- * unit, 64 KiB of LDS each) streams `iters` x 8 conflict-free 16-byte reads
+ * device, measured by a kernel in which every workgroup (5 per compute
+ * unit, 32 KiB of LDS each) streams `iters` x 8 conflict-free 16-byte reads
  * per thread (64 consecutive lanes read 1 KiB of consecutive entries).
- * Launches once to warm up, then times five launches with HIP events on
+ * Launches three times to warm up, then times five launches with HIP events on
  * `stream`; writes the aggregate bytes/s of the median to *bytes_per_s. Synchronous;
  * allocates and frees a small device buffer. FSE_ERR_INVALID_ARG for a null
  * pointer or iters outside [1, 2^20]. */
