@@ -84,10 +84,11 @@ def test_3d_graph_capture():
 
 
 def test_lds_bandwidth_probe():
-    """The LDS bandwidth measurement returns a plausible aggregate figure
-    (between 20 and 120 TB/s on 256 compute units; nominal 78.6)."""
+    """The LDS bandwidth measurement returns a plausible aggregate figure:
+    above the 128 B/clk per CU long assumed (78.6 TB/s on 256 CUs at
+    2.4 GHz; about 240 B/clk is measured) and below 256 B/clk at 2.6 GHz."""
     import paper_2204_14193_amd as fse
     _say("case lds bandwidth probe")
-    bw = fse.measure_lds_bandwidth(500) / 1e12
+    bw = fse.measure_lds_bandwidth(1000) / 1e12
     _say(f"lds {bw:.1f} TB/s")
-    assert 20.0 < bw < 120.0
+    assert 60.0 < bw < 171.0
