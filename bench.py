@@ -239,7 +239,7 @@ def bench_clip(args):
     plan.close()
     copy_calibration(args, rec, dev)
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_baseline_volumes(wl, min(args.cpu_sample, 384, n))
+        rec["cpu_baseline"] = cpu_baseline_volumes(wl, min(args.cpu_sample, 48, n))
     print(json.dumps(rec), flush=True)
 
 
@@ -443,7 +443,8 @@ def main():
     ap.add_argument("--kc", type=int, default=256, help="warm start: candidate bins per block")
     ap.add_argument("--ir", type=int, default=110, help="warm start: restricted iterations")
     ap.add_argument("--no-warm", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--cpu-sample", type=int, default=1024,
+                    help="blocks timed on the FP64 oracle (about 20-30 s of CPU work; 3-D: at most 48 volumes)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the (untimed) autotuner")
     ap.add_argument("--copy-bytes", type=int, default=0,
