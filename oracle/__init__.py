@@ -10,6 +10,12 @@ Modules:
           (8)-(10), (13), (14), (17)); the reference the GPU results are checked against.
   alg1    the frequency-domain formulation of Algorithm 1 in FP64 (eqs. (11),
           (12), (15), (18)); a pin for the oracle and a CPU speed reference.
+  cfse3   the same in three dimensions (video; Section II and the
+          Conclusion), by direct spatio-temporal projection.
+  rfse    real-valued FSE, the model of eq. (2), with selection and
+          estimation derived as a weighted least-squares fit of each pair.
+  fixed   a fixed-point integer encoding of Algorithm 1 with one division
+          per block (the Conclusion's argument), defined bit for bit.
   cnn     FP64 forward/backward of the warm-start network (not in the paper).
   metrics PSNR over lost pixels.
 """
