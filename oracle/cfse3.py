@@ -82,10 +82,12 @@ def basis(F, Ft, M, N, T, k, l, s):
     return np.conj(tF[(k * m) % F]) * np.conj(tF[(l * n) % F]) * np.conj(tT[(s * t) % Ft])
 
 
-def cfse3(s, w, F, Ft, gamma, iters, forced=None):
+def cfse3(s, w, F, Ft, gamma, iters, forced=None, cand=None):
     """cFSE on one M x N x T area by direct projection (the 3-D counterpart
     of ``oracle.cfse.cfse``; same return dict, bins as linear indices
-    (k F + l) Ft + s and coefficients keyed (k, l, s))."""
+    (k F + l) Ft + s and coefficients keyed (k, l, s)). ``cand`` optionally
+    restricts the argmax to a boolean F x F x Ft mask of candidate bins (a
+    restriction of the dictionary; every equation unchanged)."""
     M, N, T = s.shape
     if F < M or F < N or Ft < T:
         raise ValueError("transform smaller than the area")
@@ -101,13 +103,13 @@ def cfse3(s, w, F, Ft, gamma, iters, forced=None):
     for nu in range(iters):
         p = project(r * w, EM, EN, ET) / den                    # eq. (9)
         crit = np.abs(p) ** 2 * den                              # eq. (10)
-        free = c2.select(crit)
+        free = c2.select(crit, cand)
         idx = free if forced is None else int(forced[nu])
         mag = np.sqrt(crit)
         ref = mag.ravel()[free]
         out["free"].append(free)
         out["short"].append(float((ref - mag.ravel()[idx]) / ref) if ref > 0 else 0.0)
-        out["gap"].append(c2.top2_gap(mag))
+        out["gap"].append(c2.top2_gap(mag if cand is None else mag[cand]))
         kl, sv = divmod(idx, Ft)
         u, v = divmod(kl, F)
         c = gamma * p[u, v, sv]                                  # eq. (13)
@@ -122,7 +124,7 @@ def cfse3(s, w, F, Ft, gamma, iters, forced=None):
     return out
 
 
-def extrapolate_volume(frames, avail, vol, rho, gamma, forced=None, iters=None):
+def extrapolate_volume(frames, avail, vol, rho, gamma, forced=None, iters=None, cand=None):
     """cFSE for one volume descriptor; the run dict plus 'values' = Re{g} on
     B as a bh x bw x bt array, or None when the volume has no support."""
     s, A, B = area_of_volume(frames, avail, vol)
@@ -131,7 +133,7 @@ def extrapolate_volume(frames, avail, vol, rho, gamma, forced=None, iters=None):
     if w.sum() == 0:
         return None
     I = int(vol["iters"]) if iters is None else iters
-    res = cfse3(s, w, int(vol["fft"]), int(vol["fft_t"]), gamma, I, forced=forced)
+    res = cfse3(s, w, int(vol["fft"]), int(vol["fft_t"]), gamma, I, forced=forced, cand=cand)
     bd, td = int(vol["border"]), int(vol["tborder"])
     res["values"] = res["g"][bd:bd + int(vol["bh"]), bd:bd + int(vol["bw"]), td:td + int(vol["bt"])].real.copy()
     return res

@@ -685,3 +685,29 @@ def test_fixed_constant_area_and_bounds():
     G = (fixed.gamma_q(1.0) << 33) // int(Wx[0, 0])
     assert abs(int(np.abs(Rx).max()) * G) < 2 ** 62
     assert abs(fixed.rshift(int(np.abs(Rx).max()) * G, fixed.S_G)) < 2 ** 24   # coefficients exact in FP32
+
+
+def test_3d_candidate_restriction():
+    """The 3-D candidate mask restricts the dictionary only: all-true equals
+    the unrestricted run; a mask of (k, l) columns keeps every selection in
+    it with monotone energy; a single candidate is selected every time."""
+    from oracle import cfse3
+    rng = np.random.default_rng(14)
+    M, N, T, F, Ft = 10, 10, 4, 16, 8
+    s = rng.normal(size=(M, N, T)) * 20 + 100
+    A = rng.random((M, N, T)) > 0.2
+    w = np.where(A, cfse3.window(M, N, T, 0.8), 0.0)
+    sA = np.where(A, s, 0)
+    full = cfse3.cfse3(sA, w, F, Ft, 0.5, 10)
+    allc = cfse3.cfse3(sA, w, F, Ft, 0.5, 10, cand=np.ones((F, F, Ft), bool))
+    assert full["seq"] == allc["seq"] and np.allclose(full["chat"], allc["chat"], rtol=0, atol=0)
+    cols = np.zeros((F, F), bool)
+    cols[rng.choice(F, 6), rng.choice(F, 6)] = True
+    cand = np.repeat(cols[:, :, None], Ft, axis=2)
+    r = cfse3.cfse3(sA, w, F, Ft, 0.5, 12, cand=cand)
+    assert all(cand.ravel()[i] for i in r["seq"])
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(r["energy"], r["energy"][1:]))
+    one = np.zeros((F, F, Ft), bool)
+    one[3, 5, 2] = True
+    r1 = cfse3.cfse3(sA, w, F, Ft, 0.5, 4, cand=one)
+    assert r1["seq"] == [(3 * F + 5) * Ft + 2] * 4
