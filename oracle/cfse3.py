@@ -109,7 +109,8 @@ def cfse3(s, w, F, Ft, gamma, iters, forced=None, cand=None):
         ref = mag.ravel()[free]
         out["free"].append(free)
         out["short"].append(float((ref - mag.ravel()[idx]) / ref) if ref > 0 else 0.0)
-        out["gap"].append(c2.top2_gap(mag if cand is None else mag[cand]))
+        live = mag if cand is None else mag[cand]
+        out["gap"].append(c2.top2_gap(live) if live.size >= 2 else 1.0)
         kl, sv = divmod(idx, Ft)
         u, v = divmod(kl, F)
         c = gamma * p[u, v, sv]                                  # eq. (13)
