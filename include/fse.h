@@ -403,6 +403,22 @@ fse_status_t fse_extrapolate3d_batch(fse_batch3d_t batch, const uint8_t* d_frame
                                      int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
                                      fse_trace_t* d_trace, void* stream);
 
+/* Warm-started 3-D cFSE: the iterations of fse_extrapolate3d_batch with the
+ * argmax and the update restricted to candidate bins (a restriction of the
+ * dictionary; every equation unchanged). d_cand2 is int16 [n_volumes][k2]:
+ * for each volume k2 = 128 distinct columns k * 64 + l in ascending order
+ * (for instance the top-128 bins of the 2-D warm-start network run on the
+ * volume's first lost frame, fse_cnn_forward_blocks + fse_cnn_topk); the
+ * candidates are those columns with every s, 1024 bins. d_flags int32
+ * [n_volumes] as written by fse_cnn_topk: a volume whose flag is nonzero is
+ * not concealed (status FSE_BLOCK_NONFINITE, B untouched; run it with
+ * fse_extrapolate3d_batch). Other arguments, results and errors as for
+ * fse_extrapolate3d_batch; FSE_ERR_UNSUPPORTED for k2 != 128. */
+fse_status_t fse_warm3d_extrapolate_batch(fse_batch3d_t batch, const uint8_t* d_frames, const uint8_t* d_avail,
+                                          int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
+                                          fse_trace_t* d_trace, const int16_t* d_cand2, const int32_t* d_flags,
+                                          int32_t k2, void* stream);
+
 /* Measurement (roofline accounting): the LDS read bandwidth of the current
  * device, measured by a kernel in which every workgroup (5 per compute
  * unit, 32 KiB of LDS each) streams `iters` x 8 conflict-free 16-byte reads

@@ -42,6 +42,7 @@ SIGNATURES = {
     "fse_batch3d_create": (I32, [P, P, I32, I32, I32, I32, C.POINTER(P), PI32]),
     "fse_batch3d_destroy": (None, [P]),
     "fse_extrapolate3d_batch": (I32, [P, P, P, I64, P, I64, P, P, P]),
+    "fse_warm3d_extrapolate_batch": (I32, [P, P, P, I64, P, I64, P, P, P, P, I32, P]),
     "fse_batch_create": (I32, [P, P, I32, I32, I32, I32, C.POINTER(P)]),
     "fse_batch_destroy": (None, [P]),
     "fse_batch_max_iters": (I32, [P]),

@@ -848,9 +848,11 @@ extern "C" fse_status_t fse_batch3d_create(fse_plan_t plan, const fse_volume_t* 
     return fail(FSE_ERR_HIP, "hipGetDevice failed");
   }
   b->lds = fse::lds_bytes3d(std::max(b->max_iters, 1));
-  const void* fn = fse::fse3d_kernel();
+  const void* fn = fse::fse3d_kernel(false);
   int per_cu = 0;
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds) != hipSuccess ||
+      hipFuncSetAttribute(fse::fse3d_kernel(true), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds) !=
+          hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, fse::kNT3, b->lds) != hipSuccess || per_cu < 1) {
     delete b;
     return fail(FSE_ERR_UNSUPPORTED, "3-D kernel does not fit on a compute unit (iteration count too large)");
@@ -892,9 +894,9 @@ extern "C" void fse_batch3d_destroy(fse_batch3d_t batch) {
   free_batch3d(batch);
 }
 
-extern "C" fse_status_t fse_extrapolate3d_batch(fse_batch3d_t batch, const uint8_t* d_frames, const uint8_t* d_avail,
-                                                int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
-                                                fse_trace_t* d_trace, void* stream) {
+static fse_status_t launch3d(fse_batch3d_t batch, const uint8_t* d_frames, const uint8_t* d_avail, int64_t pitch,
+                             float* d_out, int64_t out_pitch, int32_t* d_status, fse_trace_t* d_trace,
+                             const int16_t* d_cand2, const int32_t* d_flags, void* stream) {
   if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
   if (batch->n == 0) return FSE_OK;
   if (!d_frames || !d_avail || !d_out || !d_status) return fail(FSE_ERR_INVALID_ARG, "null device pointer");
@@ -923,7 +925,26 @@ extern "C" fse_status_t fse_extrapolate3d_batch(fse_batch3d_t batch, const uint8
   a.twid = batch->tables->twid[class_of(fse::kF3)];
   a.gamma = batch->plan->gamma;
   a.scratch = batch->d_scratch;
-  if (fse::launch_fse3d(a, batch->grid, batch->lds, reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+  a.cand2 = d_cand2;
+  a.flags = d_flags;
+  const bool warm = d_cand2 != nullptr;
+  if (fse::launch_fse3d(a, warm, batch->grid, batch->lds, reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
     return fail(FSE_ERR_HIP, "kernel launch failed (3-D)");
   return FSE_OK;
+}
+
+extern "C" fse_status_t fse_extrapolate3d_batch(fse_batch3d_t batch, const uint8_t* d_frames, const uint8_t* d_avail,
+                                                int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
+                                                fse_trace_t* d_trace, void* stream) {
+  return launch3d(batch, d_frames, d_avail, pitch, d_out, out_pitch, d_status, d_trace, nullptr, nullptr, stream);
+}
+
+extern "C" fse_status_t fse_warm3d_extrapolate_batch(fse_batch3d_t batch, const uint8_t* d_frames,
+                                                     const uint8_t* d_avail, int64_t pitch, float* d_out,
+                                                     int64_t out_pitch, int32_t* d_status, fse_trace_t* d_trace,
+                                                     const int16_t* d_cand2, const int32_t* d_flags, int32_t k2,
+                                                     void* stream) {
+  if (!d_cand2 || !d_flags) return fail(FSE_ERR_INVALID_ARG, "null candidate list");
+  if (k2 != fse::kCand3) return fail(FSE_ERR_UNSUPPORTED, "the 3-D warm start takes 128 candidate columns per volume");
+  return launch3d(batch, d_frames, d_avail, pitch, d_out, out_pitch, d_status, d_trace, d_cand2, d_flags, stream);
 }

@@ -79,11 +79,19 @@ struct Vol3Args {
   const float2* twid;    // 64 entries exp(-j 2 pi q / 64)
   float gamma;
   float2* scratch;       // [grid][kFt3][kF3][kF3]
+  // warm start only: candidate columns k * 64 + l per volume (ascending)
+  // and the network's per-volume flags (nonzero: no usable candidates)
+  const int16_t* cand2;  // [n][kCand3]
+  const int32_t* flags;  // [n]
 };
 
+// Warm-started 3-D: candidate columns per volume; with all kFt3 values of s
+// they give one candidate bin per thread.
+constexpr int kCand3 = kNT3 / kFt3;
+
 size_t lds_bytes3d(int iters_cap);
-hipError_t launch_fse3d(const Vol3Args& a, int grid, size_t lds, hipStream_t s);
-const void* fse3d_kernel();
+hipError_t launch_fse3d(const Vol3Args& a, bool warm, int grid, size_t lds, hipStream_t s);
+const void* fse3d_kernel(bool warm);
 
 // rFSE (real-valued model), F = 64: LDS bytes for a given iteration cap,
 // the kernel (for the occupancy API), its workgroup size, and its launch;

@@ -1017,6 +1017,10 @@ __device__ __forceinline__ uint32_t bits_max_first(uint32_t bits, uint32_t& best
   return bits > best ? (best = bits, 1u) : 0u;
 }
 
+// WARM restricts the argmax to candidate bins: for each volume, kCand3
+// columns (k, l) (a row of cand2, ascending) with all Ft values of s, one
+// bin per thread in index order; the update runs over the candidates only.
+template <bool WARM>
 __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
   constexpr int F = kF3, FT = kFt3, NT = kNT3, BPT = F * F * FT / NT;  // 32 bins per thread
   constexpr int WH = kHalfCols3 * F * FT;                              // 16896 entries of W
@@ -1043,6 +1047,13 @@ __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
     const int td = __builtin_amdgcn_readfirstlane(vp->tborder), I = __builtin_amdgcn_readfirstlane(vp->iters);
     const int M = bh + 2 * bd, N = bw + 2 * bd, T = bt + 2 * td;
     const int ya = y0 - bd, xa = x0 - bd, ta = f0 - td;
+    if constexpr (WARM) {
+      // a candidate row the network could not provide: left to the caller
+      if (__builtin_amdgcn_readfirstlane(a.flags[vi]) != 0) {
+        if (t == 0) a.status[vi] = FSE_BLOCK_NONFINITE;
+        continue;
+      }
+    }
 
     // 1. gather, window (eq. (3)), z = s w + j alpha w, and the 2-D FFT of
     // every frame of the area; four frames at a time, one per 256 threads
@@ -1087,11 +1098,12 @@ __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
     // and, for l <= 32, W[k,l,s] = -j / (2 alpha) sum_t b_t e^{-j 2 pi s t / Ft}
     // into LDS as [l][s][k] (over the dead FFT buffers)
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6), kk = t & (F - 1);
-    float Rx[BPT], Ry[BPT];
+    float Rx[WARM ? 1 : BPT], Ry[WARM ? 1 : BPT];
 #pragma unroll
     for (int cc = 0; cc < BPT / FT; ++cc) {
       const int l = (BPT / FT) * wv + cc;
       const bool needW = l <= F / 2;  // uniform
+      if (WARM && !needW) continue;
       float2 A[FT], B[FT];
 #pragma unroll
       for (int s3 = 0; s3 < FT; ++s3) A[s3] = B[s3] = make_float2(0.f, 0.f);
@@ -1102,16 +1114,35 @@ __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
 #pragma unroll
         for (int s3 = 0; s3 < FT; ++s3) {
           const float2 e = tw[(s3 * q * (F / FT)) & (F - 1)];
-          A[s3] = cadd(A[s3], cmul(av, e));
+          if (!WARM) A[s3] = cadd(A[s3], cmul(av, e));
           if (needW) B[s3] = cadd(B[s3], cmul(bv, e));
         }
       }
 #pragma unroll
       for (int s3 = 0; s3 < FT; ++s3) {
-        Rx[cc * FT + s3] = A[s3].x * 0.5f;
-        Ry[cc * FT + s3] = A[s3].y * 0.5f;
+        if constexpr (!WARM) {
+          Rx[cc * FT + s3] = A[s3].x * 0.5f;
+          Ry[cc * FT + s3] = A[s3].y * 0.5f;
+        }
         if (needW) Wl[(l * FT + s3) * F + kk] = make_float2(B[s3].y * (0.5f / kAlpha), -B[s3].x * (0.5f / kAlpha));
       }
+    }
+    // warm start: R_w at the thread's candidate (k, l, s), the same sums
+    float rx1 = 0.f, ry1 = 0.f;
+    int ck = 0, cl = 0, cs = 0;
+    if constexpr (WARM) {
+      const int c2 = a.cand2[(int64_t)vi * kCand3 + (t >> 3)];
+      ck = c2 >> 6;
+      cl = c2 & (F - 1);
+      cs = t & (FT - 1);
+      float2 acc = make_float2(0.f, 0.f);
+      for (int q = 0; q < T; ++q) {
+        const float2 zk = Z[(q * F + cl) * F + ck];
+        const float2 zn = Z[(q * F + ((F - cl) & (F - 1))) * F + ((F - ck) & (F - 1))];
+        acc = cadd(acc, cmul(make_float2(zk.x + zn.x, zk.y - zn.y), tw[(cs * q * (F / FT)) & (F - 1)]));
+      }
+      rx1 = acc.x * 0.5f;
+      ry1 = acc.y * 0.5f;
     }
     __syncthreads();
     const float W0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(Wl[0].x)));
@@ -1121,99 +1152,155 @@ __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
       continue;
     }
     const float gW = a.gamma * (1.0f / W0);
-    // per-thread first maximum of |R_w|^2 (bits) and where it is
-    uint32_t best = 0;
-    int bj = 0;
-#pragma unroll
-    for (int j = 0; j < BPT; ++j) {
-      const uint32_t b2 = __float_as_uint(fmaf(Ry[j], Ry[j], Rx[j] * Rx[j]));
-      if (bits_max_first(b2, best)) bj = j;
-    }
     bool finite = true;
-    // 4. iterations (eqs. (12), (13), (18))
-    for (int it = 0; it < I; ++it) {
-      // the thread's candidate, then the wave's (first lane: lowest k), then
-      // the workgroup's (largest value, lowest bin index among equals)
-      const uint32_t wm = wave_max_bits(best);
-      const unsigned long long hits = __ballot(best == wm);
-      const int wl = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(hits));
-      const int jw = __builtin_amdgcn_readlane(bj, wl);  // uniform: one indexed register read
-      const int widx = wl * (F * FT) + wv * BPT + jw;
-      const float wre = readlane_f(Rx[jw], wl), wim = readlane_f(Ry[jw], wl);
-      xch[parity * (NT / 64) + wv] = make_int4((int)wm, widx, __float_as_int(wre), __float_as_int(wim));  // uniform
-      __syncthreads();
-      int4 sv = make_int4(0, 0x7fffffff, 0, 0);
-      if (kk < NT / 64) sv = xch[parity * (NT / 64) + kk];
-      parity ^= 1;
-      unsigned hi = (unsigned)sv.x, lo = ~(unsigned)sv.y;
-      dpp_max64<kQuadXor1>(hi, lo);
-      dpp_max64<kQuadXor2>(hi, lo);
-      dpp_max64<kRowHalfMirror>(hi, lo);
-      dpp_max64<kRowMirror>(hi, lo);  // lanes 0-15: the maximum over the 16 slots
-      const uint32_t gm = (uint32_t)__builtin_amdgcn_readlane((int)hi, 0);
-      const int gidx = (int)~(unsigned)__builtin_amdgcn_readlane((int)lo, 0);
-      const int ws = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(__ballot(kk < NT / 64 && sv.y == gidx)));
-      const float gre = __int_as_float(__builtin_amdgcn_readlane(sv.z, ws));
-      const float gim = __int_as_float(__builtin_amdgcn_readlane(sv.w, ws));
-      const int s0 = gidx & (FT - 1), v0 = (gidx >> 3) & (F - 1), u0 = gidx >> 9;
-      const float cre = gW * gre, cim = gW * gim;  // eq. (13)
-      finite = finite && isfinite(cre) && isfinite(cim);
-      if (wv == 0) {
-        cl_idx[it] = gidx;  // uniform stores
-        cl_c[it] = make_float2(cre, cim);
-        if (a.trace) {
-          fse_trace_t rec;
-          rec.u = (uint16_t)u0;
-          rec.v = (uint16_t)(v0 * FT + s0);
-          rec.c_re = cre;
-          rec.c_im = cim;
-          rec.r2 = __uint_as_float(gm);
-          a.trace[(int64_t)vi * a.trace_stride + it] = rec;
+    if constexpr (!WARM) {
+      // per-thread first maximum of |R_w|^2 (bits) and where it is
+      uint32_t best = 0;
+      int bj = 0;
+  #pragma unroll
+      for (int j = 0; j < BPT; ++j) {
+        const uint32_t b2 = __float_as_uint(fmaf(Ry[j], Ry[j], Rx[j] * Rx[j]));
+        if (bits_max_first(b2, best)) bj = j;
+      }
+      // 4. iterations (eqs. (12), (13), (18))
+      for (int it = 0; it < I; ++it) {
+        // the thread's candidate, then the wave's (first lane: lowest k), then
+        // the workgroup's (largest value, lowest bin index among equals)
+        const uint32_t wm = wave_max_bits(best);
+        const unsigned long long hits = __ballot(best == wm);
+        const int wl = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(hits));
+        const int jw = __builtin_amdgcn_readlane(bj, wl);  // uniform: one indexed register read
+        const int widx = wl * (F * FT) + wv * BPT + jw;
+        const float wre = readlane_f(Rx[jw], wl), wim = readlane_f(Ry[jw], wl);
+        xch[parity * (NT / 64) + wv] = make_int4((int)wm, widx, __float_as_int(wre), __float_as_int(wim));  // uniform
+        __syncthreads();
+        int4 sv = make_int4(0, 0x7fffffff, 0, 0);
+        if (kk < NT / 64) sv = xch[parity * (NT / 64) + kk];
+        parity ^= 1;
+        unsigned hi = (unsigned)sv.x, lo = ~(unsigned)sv.y;
+        dpp_max64<kQuadXor1>(hi, lo);
+        dpp_max64<kQuadXor2>(hi, lo);
+        dpp_max64<kRowHalfMirror>(hi, lo);
+        dpp_max64<kRowMirror>(hi, lo);  // lanes 0-15: the maximum over the 16 slots
+        const uint32_t gm = (uint32_t)__builtin_amdgcn_readlane((int)hi, 0);
+        const int gidx = (int)~(unsigned)__builtin_amdgcn_readlane((int)lo, 0);
+        const int ws = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(__ballot(kk < NT / 64 && sv.y == gidx)));
+        const float gre = __int_as_float(__builtin_amdgcn_readlane(sv.z, ws));
+        const float gim = __int_as_float(__builtin_amdgcn_readlane(sv.w, ws));
+        const int s0 = gidx & (FT - 1), v0 = (gidx >> 3) & (F - 1), u0 = gidx >> 9;
+        const float cre = gW * gre, cim = gW * gim;  // eq. (13)
+        finite = finite && isfinite(cre) && isfinite(cim);
+        if (wv == 0) {
+          cl_idx[it] = gidx;  // uniform stores
+          cl_c[it] = make_float2(cre, cim);
+          if (a.trace) {
+            fse_trace_t rec;
+            rec.u = (uint16_t)u0;
+            rec.v = (uint16_t)(v0 * FT + s0);
+            rec.c_re = cre;
+            rec.c_im = cim;
+            rec.r2 = __uint_as_float(gm);
+            a.trace[(int64_t)vi * a.trace_stride + it] = rec;
+          }
+        }
+        // eq. (18): R_w[k,l,s] -= c W[k-u, l-v, s-s0]. The row l' = (l - v)
+        // mod 64 is uniform per column; for l' > 32 the stored value is
+        // W[u-k, v-l, s0-s] and its conjugate is used, which swaps the sign of
+        // two of the four products.
+        const int kq = ((kk - u0) & (F - 1)) * 8, kqf = ((u0 - kk) & (F - 1)) * 8;  // byte offsets
+        const unsigned creb = __float_as_uint(cre), cimb = __float_as_uint(cim);
+        const float* const Wb = reinterpret_cast<const float*>(Wl);
+        best = 0;
+        bj = 0;
+  #pragma unroll
+        for (int cc = 0; cc < BPT / FT; ++cc) {
+          const int lp = ((BPT / FT) * wv + cc - v0) & (F - 1);
+          const bool flip = lp > F / 2;
+          const int lrow = flip ? (F - lp) & (F - 1) : lp;
+          const int base = (flip ? kqf : kq) + lrow * (FT * F * 8);
+          const float A = __uint_as_float(flip ? cimb ^ 0x80000000u : cimb);
+          const float Bc = __uint_as_float(flip ? creb : creb ^ 0x80000000u);
+          // the column's eight W values first, so that their loads overlap
+          float2 wc[FT];
+  #pragma unroll
+          for (int s3 = 0; s3 < FT; ++s3) {
+            const int srot = (flip ? s0 - s3 : s3 - s0) & (FT - 1);
+            wc[s3] = *reinterpret_cast<const float2*>(reinterpret_cast<const unsigned char*>(Wb) + base +
+                                                      srot * (F * 8));
+          }
+          // keeps the eight loads ahead of the arithmetic (the scheduler would
+          // otherwise wait for each load before issuing the next)
+          asm volatile("" : "+v"(wc[0].x), "+v"(wc[0].y), "+v"(wc[1].x), "+v"(wc[1].y), "+v"(wc[2].x), "+v"(wc[2].y),
+                       "+v"(wc[3].x), "+v"(wc[3].y), "+v"(wc[4].x), "+v"(wc[4].y), "+v"(wc[5].x), "+v"(wc[5].y),
+                       "+v"(wc[6].x), "+v"(wc[6].y), "+v"(wc[7].x), "+v"(wc[7].y));
+  #pragma unroll
+          for (int s3 = 0; s3 < FT; ++s3) {
+            const int j = cc * FT + s3;
+            const float2 w = wc[s3];
+            float rx = Rx[j], ry = Ry[j];
+            rx = fmaf(-cre, w.x, rx);
+            rx = fmaf(A, w.y, rx);
+            ry = fmaf(Bc, w.y, ry);
+            ry = fmaf(-cim, w.x, ry);
+            Rx[j] = rx;
+            Ry[j] = ry;
+            if (bits_max_first(__float_as_uint(fmaf(ry, ry, rx * rx)), best)) bj = j;
+          }
         }
       }
-      // eq. (18): R_w[k,l,s] -= c W[k-u, l-v, s-s0]. The row l' = (l - v)
-      // mod 64 is uniform per column; for l' > 32 the stored value is
-      // W[u-k, v-l, s0-s] and its conjugate is used, which swaps the sign of
-      // two of the four products.
-      const int kq = ((kk - u0) & (F - 1)) * 8, kqf = ((u0 - kk) & (F - 1)) * 8;  // byte offsets
-      const unsigned creb = __float_as_uint(cre), cimb = __float_as_uint(cim);
-      const float* const Wb = reinterpret_cast<const float*>(Wl);
-      best = 0;
-      bj = 0;
-#pragma unroll
-      for (int cc = 0; cc < BPT / FT; ++cc) {
-        const int lp = ((BPT / FT) * wv + cc - v0) & (F - 1);
+    } else {
+      // warm start: one candidate bin per thread, in index order
+      const int myidx = ((ck << 6) | cl) * FT + cs;
+      uint32_t best = __float_as_uint(fmaf(ry1, ry1, rx1 * rx1));
+      for (int it = 0; it < I; ++it) {
+        const uint32_t wm = wave_max_bits(best);
+        const int wl = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(__ballot(best == wm)));
+        const int widx = __builtin_amdgcn_readlane(myidx, wl);
+        const float wre = readlane_f(rx1, wl), wim = readlane_f(ry1, wl);
+        xch[parity * (NT / 64) + wv] = make_int4((int)wm, widx, __float_as_int(wre), __float_as_int(wim));  // uniform
+        __syncthreads();
+        int4 sv = make_int4(0, 0x7fffffff, 0, 0);
+        if (kk < NT / 64) sv = xch[parity * (NT / 64) + kk];
+        parity ^= 1;
+        unsigned hi = (unsigned)sv.x, lo = ~(unsigned)sv.y;
+        dpp_max64<kQuadXor1>(hi, lo);
+        dpp_max64<kQuadXor2>(hi, lo);
+        dpp_max64<kRowHalfMirror>(hi, lo);
+        dpp_max64<kRowMirror>(hi, lo);
+        const uint32_t gm = (uint32_t)__builtin_amdgcn_readlane((int)hi, 0);
+        const int gidx = (int)~(unsigned)__builtin_amdgcn_readlane((int)lo, 0);
+        const int ws = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(__ballot(kk < NT / 64 && sv.y == gidx)));
+        const float gre = __int_as_float(__builtin_amdgcn_readlane(sv.z, ws));
+        const float gim = __int_as_float(__builtin_amdgcn_readlane(sv.w, ws));
+        const int s0 = gidx & (FT - 1), v0 = (gidx >> 3) & (F - 1), u0 = gidx >> 9;
+        const float cre = gW * gre, cim = gW * gim;  // eq. (13)
+        finite = finite && isfinite(cre) && isfinite(cim);
+        if (wv == 0) {
+          cl_idx[it] = gidx;  // uniform stores
+          cl_c[it] = make_float2(cre, cim);
+          if (a.trace) {
+            fse_trace_t rec;
+            rec.u = (uint16_t)u0;
+            rec.v = (uint16_t)(v0 * FT + s0);
+            rec.c_re = cre;
+            rec.c_im = cim;
+            rec.r2 = __uint_as_float(gm);
+            a.trace[(int64_t)vi * a.trace_stride + it] = rec;
+          }
+        }
+        // eq. (18) at the candidate: W[k-u, l-v, s-s0], from the mirrored
+        // entry conjugated when (l - v) mod 64 > 32
+        const int lp = (cl - v0) & (F - 1);
         const bool flip = lp > F / 2;
-        const int lrow = flip ? (F - lp) & (F - 1) : lp;
-        const int base = (flip ? kqf : kq) + lrow * (FT * F * 8);
-        const float A = __uint_as_float(flip ? cimb ^ 0x80000000u : cimb);
-        const float Bc = __uint_as_float(flip ? creb : creb ^ 0x80000000u);
-        // the column's eight W values first, so that their loads overlap
-        float2 wc[FT];
-#pragma unroll
-        for (int s3 = 0; s3 < FT; ++s3) {
-          const int srot = (flip ? s0 - s3 : s3 - s0) & (FT - 1);
-          wc[s3] = *reinterpret_cast<const float2*>(reinterpret_cast<const unsigned char*>(Wb) + base +
-                                                    srot * (F * 8));
-        }
-        // keeps the eight loads ahead of the arithmetic (the scheduler would
-        // otherwise wait for each load before issuing the next)
-        asm volatile("" : "+v"(wc[0].x), "+v"(wc[0].y), "+v"(wc[1].x), "+v"(wc[1].y), "+v"(wc[2].x), "+v"(wc[2].y),
-                     "+v"(wc[3].x), "+v"(wc[3].y), "+v"(wc[4].x), "+v"(wc[4].y), "+v"(wc[5].x), "+v"(wc[5].y),
-                     "+v"(wc[6].x), "+v"(wc[6].y), "+v"(wc[7].x), "+v"(wc[7].y));
-#pragma unroll
-        for (int s3 = 0; s3 < FT; ++s3) {
-          const int j = cc * FT + s3;
-          const float2 w = wc[s3];
-          float rx = Rx[j], ry = Ry[j];
-          rx = fmaf(-cre, w.x, rx);
-          rx = fmaf(A, w.y, rx);
-          ry = fmaf(Bc, w.y, ry);
-          ry = fmaf(-cim, w.x, ry);
-          Rx[j] = rx;
-          Ry[j] = ry;
-          if (bits_max_first(__float_as_uint(fmaf(ry, ry, rx * rx)), best)) bj = j;
-        }
+        const int row = flip ? (F - lp) & (F - 1) : lp;
+        const int kx = (flip ? u0 - ck : ck - u0) & (F - 1), sx = (flip ? s0 - cs : cs - s0) & (FT - 1);
+        float2 w = Wl[(row * FT + sx) * F + kx];
+        w.y = flip ? -w.y : w.y;
+        rx1 = fmaf(-cre, w.x, rx1);
+        rx1 = fmaf(cim, w.y, rx1);
+        ry1 = fmaf(-cre, w.y, ry1);
+        ry1 = fmaf(-cim, w.x, ry1);
+        best = __float_as_uint(fmaf(ry1, ry1, rx1 * rx1));
       }
     }
     __syncthreads();  // the coefficient list is complete
@@ -1758,7 +1845,9 @@ size_t lds_bytes3d(int iters_cap) {
   return (size_t)kHalfCols3 * kF3 * kFt3 * 8 + kF3 * 8 + 2 * (kNT3 / 64) * 16 + (size_t)iters_cap * 12;
 }
 
-const void* fse3d_kernel() { return reinterpret_cast<const void*>(&fse3d); }
+const void* fse3d_kernel(bool warm) {
+  return warm ? reinterpret_cast<const void*>(&fse3d<true>) : reinterpret_cast<const void*>(&fse3d<false>);
+}
 
 size_t real_lds_bytes(int iters_cap) { return (size_t)64 * 64 * 8 + 64 * 8 + 16 * 16 + (size_t)iters_cap * 12; }
 
@@ -1786,8 +1875,8 @@ hipError_t launch_real(const ClassArgs& a, bool inloop, int grid, size_t lds, hi
   return hipLaunchKernel(real_kernel(inloop), dim3(grid), dim3(kRealNT), args, lds, s);
 }
 
-hipError_t launch_fse3d(const Vol3Args& a, int grid, size_t lds, hipStream_t s) {
+hipError_t launch_fse3d(const Vol3Args& a, bool warm, int grid, size_t lds, hipStream_t s) {
   void* args[] = {const_cast<Vol3Args*>(&a)};
-  return hipLaunchKernel(reinterpret_cast<const void*>(&fse3d), dim3(grid), dim3(kNT3), args, lds, s);
+  return hipLaunchKernel(fse3d_kernel(warm), dim3(grid), dim3(kNT3), args, lds, s);
 }
 }  // namespace fse

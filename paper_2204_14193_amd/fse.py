@@ -240,6 +240,29 @@ class Batch3d:
             C.c_void_p(out.data_ptr()), out.stride(1), C.c_void_p(status.data_ptr()), tptr,
             C.c_void_p(s.cuda_stream)), "fse_extrapolate3d_batch")
 
+    def run_warm(self, frames, avail, out, status, cand2, flags, trace=None, stream=None):
+        """Warm-started form (fse_warm3d_extrapolate_batch): cand2 int16
+        [n, 128] candidate columns k*64+l per volume (ascending), flags
+        int32 [n] (nonzero: volume skipped with status BLOCK_NONFINITE)."""
+        import torch
+        Batch._check_tensors(self, frames, avail, out, status)
+        if not cand2.is_cuda or cand2.dtype != torch.int16 or tuple(cand2.shape) != (self.n, 128) \
+                or not cand2.is_contiguous():
+            raise ValueError("cand2 must be a contiguous CUDA int16 tensor [n, 128]")
+        if not flags.is_cuda or flags.dtype != torch.int32 or flags.numel() < self.n:
+            raise ValueError("flags must be a CUDA int32 tensor with one entry per volume")
+        tptr = None
+        if trace is not None:
+            if not trace.is_cuda or trace.numel() * trace.element_size() < self.n * self.max_iters * 16:
+                raise ValueError("trace buffer too small")
+            tptr = C.c_void_p(trace.data_ptr())
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(_lib.lib().fse_warm3d_extrapolate_batch(
+            self._h, C.c_void_p(frames.data_ptr()), C.c_void_p(avail.data_ptr()), frames.stride(1),
+            C.c_void_p(out.data_ptr()), out.stride(1), C.c_void_p(status.data_ptr()), tptr,
+            C.c_void_p(cand2.data_ptr()), C.c_void_p(flags.data_ptr()), 128, C.c_void_p(s.cuda_stream)),
+            "fse_warm3d_extrapolate_batch")
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.lib().fse_batch3d_destroy(self._h)

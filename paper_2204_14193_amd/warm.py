@@ -136,3 +136,37 @@ class WarmStart:
         topk(self.logits, self.kc, self.cand, self.flags, stream)
         warm_extrapolate(self.batch, image, avail, out, status, self.cand, self.flags, self.kc, self.ir, self.fb,
                          trace, stream)
+
+
+class WarmStart3d:
+    """Warm-started 3-D concealment. The 2-D network runs on each volume's
+    first lost frame (its 48x48 area around the 16x16 hole, the input it was
+    trained on) and its top-128 bins (k, l) become the volume's candidate
+    columns; the 3-D iterations then run over those columns with every s
+    (fse_warm3d_extrapolate_batch). Volumes must be 16x16 with a 16-pixel
+    border. Buffers are allocated once; run() only launches kernels."""
+
+    def __init__(self, net, batch3d, volumes, plan):
+        import torch
+        from .fse import Batch, BLOCK_DTYPE
+        vols = np.ascontiguousarray(volumes)
+        blocks = np.zeros(len(vols), dtype=BLOCK_DTYPE)
+        for f in ("frame", "y0", "x0", "bh", "bw", "border"):
+            blocks[f] = vols[f]
+        blocks["fft"] = 64
+        blocks["iters"] = 0
+        self.net, self.batch3d = net, batch3d
+        self.batch2d = Batch(plan, blocks, *batch3d.shape)
+        n = len(vols)
+        dev = torch.device("cuda")
+        self.logits = torch.empty((n, N_BINS), dtype=torch.float32, device=dev)
+        self.cand = torch.empty((n, 128), dtype=torch.int16, device=dev)
+        self.flags = torch.empty((n,), dtype=torch.int32, device=dev)
+
+    def run(self, frames, avail, out, status, trace=None, stream=None):
+        self.net.forward_blocks(self.batch2d, frames, avail, self.logits, stream)
+        topk(self.logits, 128, self.cand, self.flags, stream)
+        self.batch3d.run_warm(frames, avail, out, status, self.cand, self.flags, trace, stream)
+
+    def close(self):
+        self.batch2d.close()

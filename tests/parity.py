@@ -125,15 +125,24 @@ def replay_warm_block(frames, avail, blk, rho, gamma, trace_row, cand_bins, ir, 
     return out
 
 
-def replay_volume(frames, avail, vol, rho, gamma, trace_row):
+def volume_candidates(cand_row, F=64, Ft=8):
+    """The warm-started 3-D candidate mask: the given columns k F + l with
+    every s."""
+    cols = np.zeros(F * F, dtype=bool)
+    cols[np.asarray(cand_row, dtype=np.int64)] = True
+    return np.repeat(cols.reshape(F, F)[:, :, None], Ft, axis=2)
+
+
+def replay_volume(frames, avail, vol, rho, gamma, trace_row, cand=None):
     """3-D counterpart of replay_block: the trace's (u, v) are (k, l Ft + s),
-    so the linear bin (k F + l) Ft + s is u F Ft + v."""
+    so the linear bin (k F + l) Ft + s is u F Ft + v. ``cand``: the
+    candidate mask of a warm-started volume."""
     from oracle import cfse3
     F, Ft, I = int(vol["fft"]), int(vol["fft_t"]), int(vol["iters"])
     rec = trace_row[:I]
     seq = rec["u"].astype(np.int64) * (F * Ft) + rec["v"].astype(np.int64)
     c = rec["c_re"].astype(np.float64) + 1j * rec["c_im"].astype(np.float64)
-    res = cfse3.extrapolate_volume(frames, avail, vol, rho, gamma, forced=seq)
+    res = cfse3.extrapolate_volume(frames, avail, vol, rho, gamma, forced=seq, cand=cand)
     short = np.array(res["short"]) if I else np.zeros(0)
     free = np.array(res["free"]) if I else np.zeros(0, dtype=int)
     div = free != seq
