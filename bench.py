@@ -186,9 +186,10 @@ def cpu_baseline_volumes(wl, n_sample, seed=5):
 
 
 def bench_clip(args):
-    """3-D (video) cFSE: lost 16x16x2 volumes of a 1920x1080x16 clip, one
-    kernel launch per step; reported in volumes/s (not the blocks/s
-    metric of the 2-D path)."""
+    """3-D (video) cFSE: lost 16x16x2 volumes of a 1920x1080x16 clip,
+    plain (one kernel launch per step) and warm-started (network, top-K,
+    restricted 3-D kernel); reported in volumes/s (not the blocks/s metric
+    of the 2-D path): the warm leg's if it loses at most 0.1 dB."""
     import torch
     import paper_2204_14193_amd as fse
     from synth import workloads
@@ -211,29 +212,65 @@ def bench_clip(args):
     # one launch per step: the step's HIP event pair brackets the kernel alone
     ms, ev_ms = time_steps(run, args.steps, stream)
     assert (status.cpu().numpy() == fse.BLOCK_OK).all()
+    p_plain = psnr_lost(wl.frames, out.cpu().numpy(), wl.avail)
+    legs = {"plain": {"volumes_per_s": n / (ms * 1e-3), "ms_per_step": ms, "kernel_ms": ev_ms, "psnr_db": p_plain}}
+
+    # learned warm start: the 2-D network's top-128 columns per volume, then
+    # the 3-D iterations over those columns with every s
+    from paper_2204_14193_amd import warm
+    net = warm.Net(n, seed=0)
+    net.load()
+    ws = warm.WarmStart3d(net, batch, wl.blocks, plan)
+    out_w = img.to(torch.float32)
+    status_w = torch.zeros(n, dtype=torch.int32, device=dev)
+    run_w = lambda: ws.run(img, av, out_w, status_w)
+    for _ in range(args.warmup):
+        run_w()
+    torch.cuda.synchronize()
+    ms_w, ev_w = time_steps(run_w, args.steps, stream)
+    assert (status_w.cpu().numpy() == fse.BLOCK_OK).all() and int(ws.flags.sum().item()) == 0
+    p_w = psnr_lost(wl.frames, out_w.cpu().numpy(), wl.avail)
+    # the 3-D kernel alone (same candidates), for its roofline
+    _, ev_k = time_steps(lambda: batch.run_warm(img, av, out_w, status_w, ws.cand, ws.flags), args.steps, stream)
+    legs["warm"] = {"volumes_per_s": n / (ms_w * 1e-3), "ms_per_step": ms_w, "event_ms": ev_w,
+                    "kernel_ms": ev_k, "psnr_db": p_w, "psnr_loss_db": p_plain - p_w,
+                    "meets_bar": p_plain - p_w <= PSNR_BAR_DB, "speedup_vs_plain": ms / ms_w,
+                    "candidates": "top-128 (k, l) of the 2-D network on the first lost frame, x 8 s"}
+    ws.close()
+    net.close()
+    use_warm = legs["warm"]["meets_bar"]
     bins = 64 * 64 * 8
     lds_peak = fse.measure_lds_bandwidth() / 1e12
     vox = int(np.sum(wl.blocks["bt"].astype(np.int64) * wl.blocks["bh"] * wl.blocks["bw"]))
-    flop = n * iters * bins * FLOP_PER_BIN_ITER + vox * iters * FLOP_PER_PIXEL_COEF
-    achieved = flop / (ev_ms * 1e-3) / 1e12
-    lds = n * iters * bins * 8 / (ev_ms * 1e-3) / 1e12      # the shifted W read; R_w stays in registers
+    if use_warm:
+        kern, k_ms, rep_ms = "fse3d<warm>", ev_k, ms_w
+        flop = n * iters * 1024 * FLOP_PER_BIN_ITER + vox * iters * FLOP_PER_PIXEL_COEF
+    else:
+        kern, k_ms, rep_ms = "fse3d", ev_ms, ms
+        flop = n * iters * bins * FLOP_PER_BIN_ITER + vox * iters * FLOP_PER_PIXEL_COEF
+    achieved = flop / (k_ms * 1e-3) / 1e12
+    lds = n * iters * bins * 8 / (ev_ms * 1e-3) / 1e12      # plain kernel: the shifted W read, R_w in registers
     rec = {
-        "metric": "3-D FSE volumes/s (16x16x2 loss, 64x64x8 FFT)", "value": n / (ms * 1e-3), "unit": "volumes/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "metric": "3-D FSE volumes/s (16x16x2 loss, 64x64x8 FFT) plain vs warm-start at <=0.1 dB PSNR loss",
+        "value": n / (rep_ms * 1e-3), "unit": "volumes/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": rep_ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "16x 1920x1080 synthetic frames (one image moving up to 3 px per frame), "
                                f"{n} lost 16x16x2 volumes (5% of the volume grid), border 16 px and 2 frames "
                                f"(48x48x6 area), 64x64x8 transform, rho 0.8, gamma 0.5, {iters} iterations",
-                   "name": "clip-1080p", "volumes": n, "iters": iters},
-        "mvoxel_per_s": vox / (ms * 1e-3) / 1e6,
-        "psnr_db": psnr_lost(wl.frames, out.cpu().numpy(), wl.avail),
-        "roofline": {"bound": "alu", "kernel": "fse3d", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                   "name": "clip-1080p", "volumes": n, "iters": iters,
+                   "reported_leg": "warm" if use_warm else "plain"},
+        "legs": legs,
+        "mvoxel_per_s": vox / (rep_ms * 1e-3) / 1e6,
+        "psnr_db": p_w if use_warm else p_plain,
+        "roofline": {"bound": "alu", "kernel": kern, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "frac_nonpacked": achieved / NONPACKED_FP32_TFLOPS, "kernel_ms": ev_ms,
-                     "traffic": measured_traffic("fse3d", n, "clip-1080p")},
-        "lds_roofline": {"achieved": lds, "peak": lds_peak, "peak_nominal": NOMINAL_LDS_TBPS, "unit": "TB/s",
-                         "frac": lds / lds_peak,
-                         "note": "algorithmic 8 B/bin/iteration (shifted W) against the measured LDS bandwidth"},
+                     "frac_nonpacked": achieved / NONPACKED_FP32_TFLOPS, "kernel_ms": k_ms,
+                     "traffic": measured_traffic(kern, n, "clip-1080p")},
+        "lds_roofline": {"kernel": "fse3d", "achieved": lds, "peak": lds_peak, "peak_nominal": NOMINAL_LDS_TBPS,
+                         "unit": "TB/s", "frac": lds / lds_peak,
+                         "note": "plain kernel: algorithmic 8 B/bin/iteration (shifted W) against the measured LDS "
+                                 "bandwidth"},
     }
     batch.close()
     plan.close()

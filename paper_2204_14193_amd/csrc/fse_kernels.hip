@@ -1019,7 +1019,7 @@ __device__ __forceinline__ uint32_t bits_max_first(uint32_t bits, uint32_t& best
 
 // WARM restricts the argmax to candidate bins: for each volume, kCand3
 // columns (k, l) (a row of cand2, ascending) with all Ft values of s, one
-// bin per thread in index order; the update runs over the candidates only.
+// bin per thread; the update runs over the candidates only.
 template <bool WARM>
 __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
   constexpr int F = kF3, FT = kFt3, NT = kNT3, BPT = F * F * FT / NT;  // 32 bins per thread
@@ -1127,14 +1127,17 @@ __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
         if (needW) Wl[(l * FT + s3) * F + kk] = make_float2(B[s3].y * (0.5f / kAlpha), -B[s3].x * (0.5f / kAlpha));
       }
     }
-    // warm start: R_w at the thread's candidate (k, l, s), the same sums
+    // warm start: R_w at the thread's candidate (k, l, s), the same sums.
+    // Thread t takes column t mod 128 and s = t / 128: s is uniform in a
+    // wave, so the lanes' W reads in the update fall on different columns
+    // (no systematic bank conflicts), and lane order is still index order.
     float rx1 = 0.f, ry1 = 0.f;
     int ck = 0, cl = 0, cs = 0;
     if constexpr (WARM) {
-      const int c2 = a.cand2[(int64_t)vi * kCand3 + (t >> 3)];
+      const int c2 = a.cand2[(int64_t)vi * kCand3 + (t & (kCand3 - 1))];
       ck = c2 >> 6;
       cl = c2 & (F - 1);
-      cs = t & (FT - 1);
+      cs = t / kCand3;
       float2 acc = make_float2(0.f, 0.f);
       for (int q = 0; q < T; ++q) {
         const float2 zk = Z[(q * F + cl) * F + ck];
@@ -1249,7 +1252,7 @@ __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
         }
       }
     } else {
-      // warm start: one candidate bin per thread, in index order
+      // warm start: one candidate bin per thread (index order within a wave)
       const int myidx = ((ck << 6) | cl) * FT + cs;
       uint32_t best = __float_as_uint(fmaf(ry1, ry1, rx1 * rx1));
       for (int it = 0; it < I; ++it) {
