@@ -92,3 +92,31 @@ def test_lds_bandwidth_probe():
     bw = fse.measure_lds_bandwidth(1000) / 1e12
     _say(f"lds {bw:.1f} TB/s")
     assert 60.0 < bw < 171.0
+
+
+def test_3d_warm_start_graph_capture():
+    """The warm-started 3-D step (network on the first lost frames, top-128,
+    restricted 3-D kernel) is capture-safe after its first eager run."""
+    import torch
+    import paper_2204_14193_amd as fse
+    from paper_2204_14193_amd import warm
+    wl = workloads.clip_small(iters=20)
+    _say(f"case graph capture 3-D warm: {len(wl.blocks)} volumes")
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(wl.distorted).to(dev)
+    av = torch.from_numpy(wl.avail).to(dev)
+    plan = fse.Plan(wl.rho, wl.gamma, 20)
+    batch = fse.Batch3d(plan, wl.blocks, *wl.frames.shape)
+    net = warm.Net(len(wl.blocks), seed=0)
+    net.load()
+    ws = warm.WarmStart3d(net, batch, wl.blocks, plan)
+    base = (img * (av != 0)).to(torch.float32)
+    out = base.clone()
+    status = torch.zeros(len(wl.blocks), dtype=torch.int32, device=dev)
+    ws.run(img, av, out, status)                     # first eager run (one-time network set-up)
+    torch.cuda.synchronize()
+    _replays_match(lambda s: ws.run(img, av, out, status, stream=s), out, status, base, len(wl.blocks))
+    ws.close()
+    net.close()
+    batch.close()
+    plan.close()
