@@ -17,6 +17,12 @@
  * on an F x F zero-padded transform grid (F in {32, 64, 128}; the paper uses
  * a 48x48 area in a 64x64 transform, Section IV).
  *
+ * Beside plain cFSE the library offers a learned warm start (fse_cnn_*,
+ * fse_warm_*), mask-driven loss areas (FSE_PLAN_MASKED_B), real-valued FSE
+ * (FSE_PLAN_REAL), a bit-exact fixed-point encoding (FSE_PLAN_FIXED), 3-D
+ * video concealment of lost volumes (fse_batch3d_*, plain and warm-started)
+ * and an LDS bandwidth probe for roofline accounting.
+ *
  * Conventions used by every entry point:
  *  - Pointers prefixed d_ are device memory on the current HIP device and
  *    are owned by the caller; h_ pointers are host memory owned by the
