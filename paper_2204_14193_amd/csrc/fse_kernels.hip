@@ -796,6 +796,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MODE == kWar
 }
 
 // ------------------------------------------------------------ restricted
+template <bool B>
+struct BoolC {
+  static constexpr bool value = B;
+};
+
 // Second kernel of the split warm start (F = 64): the restricted iterations
 // of one block per workgroup of NWB waves, with W rows 0..32 in LDS (17 KB,
 // so that many blocks share a compute unit and hide each other's latency)
@@ -880,6 +885,11 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
 
   bool finite = true;
   int parity = 0;
+  // The iteration loop, compiled once per combination of the two
+  // block-uniform options (in-loop synthesis, trace), so that neither is
+  // tested inside it.
+  auto iterate = [&](auto inloop_c, auto trace_c) __attribute__((always_inline)) {
+  constexpr bool kInloop = decltype(inloop_c)::value, kTrace = decltype(trace_c)::value;
   for (int it = 0; it < a.ir; ++it) {
     unsigned lm = mb[0];
 #pragma unroll
@@ -921,8 +931,8 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
     }
     const int u = x >> 12, v = (x >> 3) & 511;
     const float cre = gW * re, cim = gW * im;  // eq. (13)
-    finite = finite && isfinite(cre) && isfinite(cim);
-    if (inloop) {
+    finite = finite & isfinite(cre) & isfinite(cim);  // no short circuit: no branch
+    if constexpr (kInloop) {
 #pragma unroll
       for (int q = 0; q < QI; ++q) {
         const float2 e = tw[phase_index<F>(u, v, mq[q], nq[q])];  // as in synthesize: Re{c e^{j theta}} = c.x e.x + c.y e.y
@@ -930,12 +940,12 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
         acc[q] = fmaf(cim, e.y, acc[q]);
       }
     }
-    if (wave == 0) {
-      if (!inloop) {
+    if (NWB == 1 || wave == 0) {
+      if constexpr (!kInloop) {
         cl_idx[it] = u * F + v;  // uniform stores
         cl_c[it] = make_float2(cre, cim);
       }
-      if (a.trace) {
+      if constexpr (kTrace) {
         fse_trace_t rec;
         rec.u = (uint16_t)u;
         rec.v = (uint16_t)v;
@@ -966,6 +976,14 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
       Ry[j] = ry;
       mb[j] = __float_as_uint(fmaf(ry, ry, rx * rx));
     }
+  }
+  };
+  if (inloop) {
+    if (a.trace) iterate(BoolC<true>{}, BoolC<true>{});
+    else iterate(BoolC<true>{}, BoolC<false>{});
+  } else {
+    if (a.trace) iterate(BoolC<false>{}, BoolC<true>{});
+    else iterate(BoolC<false>{}, BoolC<false>{});
   }
   // every coefficient must be finite (all waves computed the same ones)
   if (!finite) {
