@@ -8,7 +8,7 @@ It shares no code with the GPU path; both take their inputs from ``synth``.
 Modules:
   cfse    plain cFSE by direct spatial projection (Section III, eqs. (3),
           (8)-(10), (13), (14), (17)); the reference the GPU results are checked against.
-  alg1    the frequency-domain formulation of Algorithm 1 in FP64 (eqs. (11),
+  spectral the frequency-domain form of Section III in FP64 (eqs. (11),
           (12), (15), (18)); a pin for the oracle and a CPU speed reference.
   cfse3   the same in three dimensions (video; Section II and the
           Conclusion), by direct spatio-temporal projection.

@@ -12,6 +12,10 @@ from . import _lib
 from .fse import _check
 
 N_BINS = 4096
+# Operating point of the packaged network: candidate bins per block and
+# restricted iterations (chosen on validation frames, see the training report)
+KC = 256
+RESTRICTED_ITERS = 110
 PATCH = (48, 48, 2)
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "warm_cnn.npz")
 

@@ -69,6 +69,34 @@ def _oracle_forward_bf16(params, x):
     return feat @ p["head.w"].T + p["head.b"]
 
 
+def _oracle_backward_bf16(p, x, target, pos_weight):
+    """The oracle's gradients with the GPU's storage precision: activations
+    stored in BF16 after each ReLU, and the operands of every backward
+    product (dL/dlogits, dL/dz of each layer) rounded to BF16 as the GPU
+    rounds them before its MFMA products; bias gradients from the unrounded
+    values. Returns (logits, flat gradient)."""
+    acts, pre = [x], []
+    h = x
+    for i in range(4):
+        z = cnn.conv_forward(h, p[f"conv{i + 1}.w"], p[f"conv{i + 1}.b"])
+        pre.append(z)
+        h = bf16(np.maximum(z, 0.0)).astype(np.float64)
+        acts.append(h)
+    feat = h.reshape(h.shape[0], -1)
+    logits = feat @ p["head.w"].T + p["head.b"]
+    _, dl = cnn.bce_loss(logits, target, pos_weight)
+    dlb = bf16(dl).astype(np.float64)
+    g = {"head.w": dlb.T @ feat, "head.b": dl.sum(axis=0)}
+    dh = (dlb @ p["head.w"]).reshape(acts[4].shape)
+    for i in reversed(range(4)):
+        dz = dh * (pre[i] > 0)
+        dzb = bf16(dz).astype(np.float64)
+        dx, dw, _ = cnn.conv_backward(acts[i], p[f"conv{i + 1}.w"], dzb)
+        g[f"conv{i + 1}.w"], g[f"conv{i + 1}.b"] = dw, dz.sum(axis=(0, 1, 2))
+        dh = dx
+    return logits, cnn.flatten_grads(g)
+
+
 def test_forward_matches_oracle():
     import torch
     from paper_2204_14193_amd import warm
@@ -138,9 +166,8 @@ def test_backward_matches_oracle_and_adam_step():
     _, g = net.get_params(grads=True)
     xin = x.float().cpu().numpy().astype(np.float64)
     pq = cnn.unflatten(bf16(params).astype(np.float64))
-    lo, cache = cnn.forward(pq, xin)
-    l_ref, dl = cnn.bce_loss(lo, tgt.astype(float), 4.0)
-    gref = cnn.flatten_grads(cnn.backward(pq, cache, dl))
+    lo, gref = _oracle_backward_bf16(pq, xin, tgt.astype(float), 4.0)
+    l_ref, _ = cnn.bce_loss(lo, tgt.astype(float), 4.0)
     _say(f"  loss gpu={loss.item():.6f} oracle={l_ref:.6f}")
     assert abs(loss.item() - l_ref) <= 2e-3 * abs(l_ref)
     o = 0
@@ -148,7 +175,7 @@ def test_backward_matches_oracle_and_adam_step():
         n = int(np.prod(shp))
         a, b = g[o:o + n], gref[o:o + n]
         _say(f"  {name:8s} relfro={_relfro(a, b):.2e} cos={_cos(a, b):.6f}")
-        assert _relfro(a, b) <= 3e-2 and _cos(a, b) >= 0.9995, name
+        assert _relfro(a, b) <= 1e-2 and _cos(a, b) >= 0.9999, name
         o += n
     # one Adam step from zero moments: w -= lr * g / (|g| + eps)
     lr, eps = 1e-3, 1e-8
@@ -392,6 +419,60 @@ def test_warm_start_quality_bar_and_timing_hook():
     _say(f"  plain-100 {p_plain:.3f} dB, warm {p_warm:.3f} dB, plain-50 {p_50:.3f} dB")
     assert p_plain - p_warm <= 0.1
     assert p_warm - p_50 >= 0.5
+
+
+def test_warm_leg_as_benchmarked_replays_against_oracle():
+    """The benchmark's warm leg exactly as timed: the eight 1080p frames
+    (6432 blocks), network candidates from the packaged weights at the
+    package's operating point (top-KC bins, RESTRICTED_ITERS restricted
+    iterations, in-loop model on B), one call of WarmStart.run with a trace.
+    A seeded sample of 32 blocks is replayed against the oracle restricted
+    to the same candidates: selections (near ties aside), coefficients,
+    pixels, and the sample's PSNR against the free-running oracle."""
+    import torch
+    import paper_2204_14193_amd as fse
+    from paper_2204_14193_amd import warm
+    kc, ir = warm.KC, warm.RESTRICTED_ITERS
+    wl = workloads.random_1080p_16x16(seeds=tuple(range(99, 107)), iters=100)
+    n = len(wl.blocks)
+    _say(f"case warm leg as benchmarked: {n} blocks, kc={kc}, ir={ir}")
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(wl.distorted).to(dev)
+    av = torch.from_numpy(wl.avail).to(dev)
+    wb = wl.blocks.copy()
+    wb["iters"] = 0
+    plan = fse.Plan(wl.rho, wl.gamma, ir + 100)
+    bw = fse.Batch(plan, wb, *wl.frames.shape)
+    net = warm.Net(n)
+    net.load()
+    ws = warm.WarmStart(net, bw, kc, ir, 100)
+    out = img.to(torch.float32)
+    st = torch.full((n,), -1, dtype=torch.int32, device=dev)
+    stride = warm.trace_stride(bw, ir, 100)
+    tr = torch.zeros((n, stride * 16), dtype=torch.uint8, device=dev)
+    ws.run(img, av, out, st, trace=tr)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == fse.BLOCK_OK).all() and int(ws.flags.sum().item()) == 0
+    trace = tr.cpu().numpy().view(fse.TRACE_DTYPE).reshape(n, stride)
+    cand = ws.cand.cpu().numpy()
+    o = out.cpu().numpy()
+    idx = np.sort(np.random.default_rng(21).choice(n, 32, replace=False))
+    worst = 0.0
+    for i in idx:
+        blk = wl.blocks[i]
+        r = parity.replay_warm_block(wl.frames, wl.avail, blk, wl.rho, wl.gamma, trace[i], cand[i], ir, 0)
+        rr = r["restricted"]
+        assert rr["gap_violations"] == 0, (i, rr)
+        assert rr["coef_max"] <= parity.COEF_TOL and rr["coef_l2"] <= parity.COEF_TOL, (i, rr)
+        f, y0, x0 = int(blk["frame"]), int(blk["y0"]), int(blk["x0"])
+        pix = float(np.abs(o[f, y0:y0 + 16, x0:x0 + 16] - r["values"]).max())
+        assert pix < parity.PIX_TOL, (i, pix)
+        worst = max(worst, pix)
+    d, pg, po = parity.warm_psnr_delta(wl.frames, wl.avail, wl.blocks[idx], cand[idx], wl.rho, wl.gamma, ir, o,
+                                       processes=8)
+    _say(f"  pix={worst:.2e} sample psnr gpu={pg:.4f} oracle={po:.4f}")
+    assert d <= parity.PSNR_TOL
+    net.close()
 
 
 def test_split_warm_large_blocks_use_the_list_synthesis():

@@ -69,7 +69,11 @@ def test_random_1080p_16x16_sampled_parity_8_frames():
     lost = wl.avail == 0
     assert np.isfinite(out[lost]).all() and np.abs(out[lost]).max() < 1e4
     idx = np.random.default_rng(11).choice(len(wl.blocks), 48, replace=False)
-    parity.check_blocks(wl.frames, wl.avail, wl.blocks, wl.rho, wl.gamma, tr, out, idx)
+    rows = parity.check_blocks(wl.frames, wl.avail, wl.blocks, wl.rho, wl.gamma, tr, out, idx)
+    sub = wl.blocks[np.sort(idx)]
+    d, pg, po, _ = parity.psnr_delta(wl.frames, wl.avail, sub, wl.rho, wl.gamma, out, processes=8)
+    _say(f"sample pix={max(r['pix_maxabs'] for r in rows):.2e} psnr gpu={pg:.4f} oracle={po:.4f}")
+    assert d <= parity.PSNR_TOL
 
 
 def _ragged_workload():
@@ -103,7 +107,15 @@ def test_ragged_edges_and_degenerate_blocks():
     # zero iterations: model is zero on B
     assert (out[0, 20:24, 30:34] == 0).all()
     idx = [0, 1, 2, 3, 4]
-    parity.check_blocks(wl.frames, wl.avail, wl.blocks, wl.rho, wl.gamma, tr, out, idx)
+    rows = parity.check_blocks(wl.frames, wl.avail, wl.blocks, wl.rho, wl.gamma, tr, out, idx)
+    for r in rows:
+        _say(f"  block {r['index']} F={wl.blocks['fft'][r['index']]}: coef_max={r['coef_max']:.2e} "
+             f"pix_maxabs={r['pix_maxabs']:.2e}")
+    # frame PSNR per transform size (F = 32: blocks 0, 1; 64: 2, 3; 128: 4)
+    for sel in ([0, 1], [2, 3], [4]):
+        d, pg, po, _ = parity.psnr_delta(wl.frames, wl.avail, wl.blocks[sel], wl.rho, wl.gamma, out)
+        _say(f"  blocks {sel}: psnr gpu={pg:.4f} oracle={po:.4f}")
+        assert d <= parity.PSNR_TOL, sel
 
 
 def test_gamma_zero_gives_zero_model():
@@ -223,6 +235,13 @@ def test_mixed_4k_uneven_batch_parity():
         b = wl.blocks[r["index"]]
         _say(f"  size {b['bh']:2d} F={b['fft']:3d} I={b['iters']:3d}: coef_max={r['coef_max']:.2e} "
              f"coef_l2={r['coef_l2']:.2e} pix_maxabs={r['pix_maxabs']:.2e} ties={r['ties']}")
+    # PSNR of the sample per transform size against the free-running oracle
+    idx = np.array(sorted(idx))
+    for F in (32, 64, 128):
+        sel = idx[wl.blocks["fft"][idx] == F]
+        d, pg, po, _ = parity.psnr_delta(wl.frames, wl.avail, wl.blocks[sel], wl.rho, wl.gamma, out, processes=8)
+        _say(f"  F={F}: {len(sel)} blocks, psnr gpu={pg:.4f} oracle={po:.4f}")
+        assert d <= parity.PSNR_TOL, F
 
 
 def test_graph_capture_replays_match_eager():

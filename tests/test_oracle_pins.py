@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import alg1, cfse
+from oracle import cfse, spectral
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -313,26 +313,185 @@ def test_independence_from_outside_area():
     np.testing.assert_array_equal(other["values"], base["values"])
 
 
+# ------------------------------------------ warm start and restricted bins
+
+def test_init_continues_an_interrupted_run():
+    """Initial coefficients (eq. (8) with a non-zero starting model): I1
+    iterations, then I2 more started from the first run's accumulated
+    coefficients, equal one uninterrupted run of I1 + I2 iterations (the
+    residual is s minus the model either way)."""
+    s, w, F = _patch(seed=8)
+    first = cfse.cfse(s, w, F, 0.5, 15)
+    rest = cfse.cfse(s, w, F, 0.5, 20, init=dict(first["coefs"]))
+    whole = cfse.cfse(s, w, F, 0.5, 35)
+    assert rest["seq"] == whole["seq"][15:]
+    np.testing.assert_allclose(rest["chat"], whole["chat"][15:], rtol=1e-10, atol=1e-10 * abs(whole["chat"][0]))
+    np.testing.assert_allclose(rest["g"], whole["g"], atol=1e-9)
+    assert abs(rest["energy"][0] - whole["energy"][15]) <= 1e-10 * whole["energy"][0]
+
+
+def test_init_single_basis_function():
+    """Starting from c0 on the basis function the signal is made of: with no
+    iteration the model is c0*phi; with iterations the remaining amplitude
+    a - c0 shrinks by (1 - gamma) per step, so the accumulated coefficient is
+    a - (a - c0)(1 - gamma)^nu."""
+    F, M, N = 16, 12, 12
+    k0, l0, a, c0 = 5, 11, 40.0 + 9.0j, 30.0 - 2.0j
+    A = np.ones((M, N), dtype=bool)
+    A[4:8, 4:8] = False
+    w = cfse.weighting(M, N, 0.8, A)
+    phi = np.exp(2j * np.pi * (k0 * np.arange(M)[:, None] + l0 * np.arange(N)[None, :]) / F)
+    s = a * phi
+    res = cfse.cfse(s, w, F, 0.5, 0, init={(k0, l0): c0})
+    np.testing.assert_allclose(res["g"], c0 * phi, atol=1e-12 * abs(c0))
+    res = cfse.cfse(s, w, F, 0.5, 6, init={(k0, l0): c0})
+    assert res["seq"] == [k0 * F + l0] * 6
+    acc = c0 + np.cumsum(res["chat"])
+    for nu in range(6):
+        assert abs(acc[nu] - (a - (a - c0) * 0.5 ** (nu + 1))) < 1e-12 * abs(a)
+    assert abs(res["coefs"][(k0, l0)] - acc[-1]) < 1e-12 * abs(a)
+
+
+def test_candidate_mask_all_true_is_unrestricted():
+    """An all-true candidate mask restricts nothing: identical selections
+    and coefficients, bit for bit."""
+    s, w, F = _patch(seed=9)
+    free = cfse.cfse(s, w, F, 0.5, 30)
+    allc = cfse.cfse(s, w, F, 0.5, 30, cand=np.ones((F, F), dtype=bool))
+    assert free["seq"] == allc["seq"] and free["chat"] == allc["chat"]
+
+
+def test_single_candidate_converges_to_its_fixed_point():
+    """Input a*phi_0 + b*phi_1 with the stronger b, restricted to the single
+    candidate phi_0: every step selects phi_0, and its accumulated
+    coefficient is C*(1 - (1 - gamma)^nu) with C* = a + b*Wd/W0, where
+    W0 = sum(w) and Wd is the window's DFT at the difference of the two
+    bins (brute-force double sum), the weighted least-squares fit of phi_0
+    alone."""
+    F, M, N = 8, 6, 7
+    k0, l0, k1, l1 = 1, 2, 3, 6
+    a, b = 10.0 - 4.0j, 25.0 + 15.0j
+    A = np.ones((M, N), dtype=bool)
+    A[2:4, 3:5] = False
+    w = cfse.weighting(M, N, 0.7, A)
+    m, n = np.arange(M)[:, None], np.arange(N)[None, :]
+    phi = lambda k, l: np.exp(2j * np.pi * (k * m + l * n) / F)
+    s = a * phi(k0, l0) + b * phi(k1, l1)
+    free = cfse.cfse(s, w, F, 0.5, 1)
+    assert free["seq"] == [k1 * F + l1]
+    cand = np.zeros((F, F), dtype=bool)
+    cand[k0, l0] = True
+    Wd = _brute_dft(w, F)[(k0 - k1) % F, (l0 - l1) % F]
+    cstar = a + b * Wd / w.sum()
+    for gamma in (0.5, 0.9):
+        res = cfse.cfse(s, w, F, gamma, 8, cand=cand)
+        assert res["seq"] == [k0 * F + l0] * 8
+        acc = np.cumsum(res["chat"])
+        for nu in range(8):
+            assert abs(acc[nu] - cstar * (1 - (1 - gamma) ** (nu + 1))) < 1e-11 * abs(cstar)
+
+
+def test_candidate_mask_keeps_selections_inside_and_energy_identity():
+    """A random candidate mask: every selection lies in it, is the largest
+    criterion among the candidates (checked against a brute-force
+    projection of the spatial residual), and the weighted residual energy
+    falls by gamma(2 - gamma)|R_w[u,v]|^2/W0 per step."""
+    s, w, F = _patch(seed=10)
+    M, N = s.shape
+    rng = _rng(10)
+    cand = rng.random((F, F)) < 0.2
+    gamma = 0.5
+    res = cfse.cfse(s, w, F, gamma, 25, cand=cand)
+    W0 = w.sum()
+    r = s.astype(complex)
+    for nu, (idx, c) in enumerate(zip(res["seq"], res["chat"])):
+        assert cand.ravel()[idx]
+        R = _brute_dft(r * w, F).ravel()
+        mags = np.where(cand.ravel(), np.abs(R), -1.0)
+        assert mags[idx] >= mags.max() * (1 - 1e-9)
+        assert abs(c - gamma * R[idx] / W0) < 1e-9 * abs(R).max() / W0
+        E0, E1 = res["energy"][nu], res["energy"][nu + 1]
+        assert abs(E1 - (E0 - gamma * (2 - gamma) * abs(R[idx]) ** 2 / W0)) <= 1e-10 * res["energy"][0]
+        u, v = divmod(idx, F)
+        r = r - c * np.exp(2j * np.pi * (u * np.arange(M)[:, None] + v * np.arange(N)[None, :]) / F)
+
+
+def test_shortfall_and_gap_of_a_forced_selection():
+    """Near-tie bookkeeping of the replay protocol: on the full F x F grid
+    with w = 1 the basis functions are orthogonal and |R_w| at a bin is
+    F^2 |amplitude|. With amplitudes 12 and 9 on two bins, forcing the
+    weaker one first gives shortfall (|R|max - |R|followed)/|R|max =
+    (12 - 9)/12 = 0.25 (not the 0.4375 of squared magnitudes), the free
+    choice is the stronger bin, and the top-two gap is also 0.25."""
+    F = 8
+    w = np.ones((F, F))
+    m, n = np.arange(F)[:, None], np.arange(F)[None, :]
+    b1, b2 = (2, 3), (5, 1)
+    s = 12.0 * np.exp(2j * np.pi * (b1[0] * m + b1[1] * n) / F) \
+        + 9.0j * np.exp(2j * np.pi * (b2[0] * m + b2[1] * n) / F)
+    i1, i2 = b1[0] * F + b1[1], b2[0] * F + b2[1]
+    res = cfse.cfse(s, w, F, 0.5, 2, forced=[i2, i1])
+    assert res["free"][0] == i1
+    assert abs(res["short"][0] - 0.25) < 1e-12
+    assert abs(res["gap"][0] - 0.25) < 1e-12
+    # after half of the weaker amplitude is removed: 12 against 4.5, and the
+    # followed bin is now the free choice
+    assert res["free"][1] == i1 and res["short"][1] == 0.0
+    assert abs(res["gap"][1] - 7.5 / 12) < 1e-12
+
+
+def test_psnr_over_lost_pixels_hand_value():
+    """PSNR over the lost pixels, reconstruction clipped to [0, 255] first.
+    Lost pixels (avail == 0) with reference 20, 30, 40 and reconstruction
+    22, 300 (clipped to 255), 35: errors 2, 225, -5, MSE = 50654/3, PSNR =
+    10 log10(255^2 * 3 / 50654) = 5.855879 dB. The received pixel (error
+    1000) does not count; a perfect reconstruction gives infinity."""
+    from oracle import metrics
+    ref = np.array([[10.0, 20.0], [30.0, 40.0]])
+    rec = np.array([[1010.0, 22.0], [300.0, 35.0]])
+    avail = np.array([[1, 0], [0, 0]], dtype=np.uint8)
+    assert abs(metrics.psnr_lost(ref, rec, avail) - 5.8558787) < 1e-6
+    assert metrics.psnr_lost(ref, np.where(avail == 0, ref, -5.0), avail) == float("inf")
+    # negative values clip to 0: error -20 on one lost pixel only
+    rec2 = ref.copy()
+    rec2[0, 1] = -7.0
+    assert abs(metrics.psnr_lost(ref, rec2, avail) - 10 * math.log10(65025 * 3 / 400)) < 1e-9
+
+
 # --------------------------------------------------------------- eq. (18)
 
 def test_frequency_domain_update_matches_projection():
-    """eq. (18) is eq. (17) followed by eq. (7): Algorithm 1 in the Fourier
-    domain, forced along the oracle's selections, reproduces the oracle's
-    coefficients and model (FP64, relative 1e-10)."""
+    """eq. (18) is eq. (17) followed by eq. (7): after every step, the
+    spectral state (residual spectrum updated by the shifted window
+    spectrum) equals the projection of the spatial residual s - sum c*phi
+    onto every basis function, formed directly from the direct oracle's
+    selections and coefficients; the free-running spectral form makes the
+    same selections and its model matches (FP64, relative 1e-10)."""
     from synth import workloads
     wl = workloads.isolated_256()
+    F = 64
     for bi in (0, 9, 36, 63):
         blk = wl.blocks[bi]
         s, A, B = cfse.area_of_block(wl.frames, wl.avail, blk)
-        w = cfse.weighting(*s.shape, 0.8, A)
-        res = cfse.cfse(s, w, 64, 0.5, 100)
-        seq, chat, g = alg1.cfse_fft(s, w, 64, 0.5, 100, forced=res["seq"])
-        d = np.array(chat) - np.array(res["chat"])
-        assert np.linalg.norm(d) <= 1e-10 * np.linalg.norm(res["chat"])
+        M, N = s.shape
+        w = cfse.weighting(M, N, 0.8, A)
+        res = cfse.cfse(s, w, F, 0.5, 100)
+        EM, EN = cfse.analysis_matrix(F, M), cfse.analysis_matrix(F, N)
+        st = spectral.SpectralState(s, w, F, 0.5)
+        r = s.astype(complex)
+        scale = np.abs(st.residual).max()
+        for nu in range(100):
+            if nu % 9 == 0:   # every ninth state against the spatial residual
+                direct = cfse.project(r * w, EM, EN)
+                assert np.abs(st.residual - direct).max() <= 1e-10 * scale, (bi, nu)
+            idx, c = st.advance(res["seq"][nu])
+            assert abs(c - res["chat"][nu]) <= 1e-10 * abs(res["chat"][0]), (bi, nu)
+            u, v = divmod(res["seq"][nu], F)
+            r = r - res["chat"][nu] * cfse.basis(F, M, N, u, v)
+        np.testing.assert_allclose(st.model(), res["g"], atol=1e-9)
+        bins, coefs, g = spectral.run(s, w, F, 0.5, 100)
+        assert bins == res["seq"]
         np.testing.assert_allclose(g, res["g"], atol=1e-9)
-        # free-running: the same tie rule gives the same selections
-        seq_free, _, _ = alg1.cfse_fft(s, w, 64, 0.5, 100)
-        assert seq_free == res["seq"]
 
 
 # ------------------------------------------------- arbitrary loss shapes
