@@ -477,8 +477,9 @@ def main():
                     choices=["random-1080p-16x16", "random-1080p-8x8", "mixed-4k", "strokes-1080p", "clip-1080p",
                              "rfse-1080p", "fixed-1080p"],
                     help="the metric's workload (default) or one of the other configurations (plain only)")
-    ap.add_argument("--kc", type=int, default=256, help="warm start: candidate bins per block")
-    ap.add_argument("--ir", type=int, default=110, help="warm start: restricted iterations")
+    ap.add_argument("--kc", type=int, default=None, help="warm start: candidate bins per block "
+                                                           "(default: the packaged network's operating point)")
+    ap.add_argument("--ir", type=int, default=None, help="warm start: restricted iterations (default: as --kc)")
     ap.add_argument("--no-warm", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1024,
                     help="blocks timed on the FP64 oracle (about 20-30 s of CPU work; 3-D: at most 48 volumes)")
@@ -487,6 +488,9 @@ def main():
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run 3 plain device copies of this many bytes (counter calibration)")
     args = ap.parse_args()
+    from paper_2204_14193_amd import warm as _warm
+    args.kc = _warm.KC if args.kc is None else args.kc
+    args.ir = _warm.RESTRICTED_ITERS if args.ir is None else args.ir
     if args.gpus != 1:
         print("this benchmark runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)

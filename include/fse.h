@@ -368,13 +368,27 @@ fse_status_t fse_cnn_topk(const float* d_logits, int32_t B, int32_t K, int16_t* 
  * same results. Output, status and threading as fse_extrapolate_batch;
  * d_trace (optional) rows have fse_warm_trace_stride(...) entries: the
  * restricted selections first. The staging buffer of the two-kernel form
- * (n_blocks x (16896 + 8*kc) bytes) is allocated on the first call and kept
- * by the batch. */
+ * (n_blocks x (16896 + 4096) bytes, room for any compiled kc) is allocated
+ * by fse_warm_prepare, or by the first call here if that was not called,
+ * and kept by the batch until fse_batch_destroy. After fse_warm_prepare
+ * with the same (kc, restricted_iters, fallback_iters) this call allocates
+ * nothing and may be captured into a HIP graph; a call with other counts
+ * reconfigures the batch (host state only), which a graph captured before
+ * does not see. */
 fse_status_t fse_warm_extrapolate_batch(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail,
                                         int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
                                         fse_trace_t* d_trace, const int16_t* d_cand, const int32_t* d_flags,
                                         int32_t kc, int32_t restricted_iters, int32_t fallback_iters,
                                         void* stream);
+
+/* Set-up of the warm start (Algorithm 1 started from a candidate set; same
+ * arguments as fse_warm_extrapolate_batch): chooses the kernels and their
+ * launch shape for (kc, restricted_iters, fallback_iters) and allocates the
+ * batch's staging buffer if the two-kernel form needs one. Synchronous, host
+ * side plus one allocation; call it before capturing warm-started launches
+ * into a graph or in a loop that must not allocate. Errors as
+ * fse_warm_extrapolate_batch. */
+fse_status_t fse_warm_prepare(fse_batch_t batch, int32_t kc, int32_t restricted_iters, int32_t fallback_iters);
 
 /* restricted_iters + max(largest block iteration count, fallback_iters). */
 int32_t fse_warm_trace_stride(fse_batch_t batch, int32_t restricted_iters, int32_t fallback_iters);

@@ -67,6 +67,7 @@ SIGNATURES = {
     "fse_cnn_topk": (I32, [P, I32, I32, P, P, P]),
     "fse_warm_extrapolate_batch": (I32, [P, P, P, I64, P, I64, P, P, P, P, I32, I32, I32, P]),
     "fse_warm_trace_stride": (I32, [P, I32, I32]),
+    "fse_warm_prepare": (I32, [P, I32, I32, I32]),
 }
 
 _lib = None

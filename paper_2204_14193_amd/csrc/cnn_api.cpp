@@ -41,7 +41,7 @@ struct fse_cnn_s {
   // inference head: features and head weights in fragment layout
   uint16_t* feats_frag = nullptr;  // [ceil(max_batch / 32) * 32][288]
   uint16_t* head_frag = nullptr;   // [4096][288]
-  bool head_stale = true;          // `work` changed since head_frag was made
+  bool head_stale = false;         // `work` changed since head_frag was made (after Adam)
   // training scratch, allocated on the first backward call
   uint16_t* acts = nullptr;   // [max_batch][kActElems]
   float* dlog = nullptr;      // [B][4096]
@@ -130,7 +130,7 @@ extern "C" fse_status_t fse_cnn_create(int32_t max_batch, uint64_t seed, fse_cnn
   if (hipMemcpy(n->master, h.data(), P * 4, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(n->grad, 0, P * 4) != hipSuccess || hipMemset(n->m, 0, P * 4) != hipSuccess ||
       hipMemset(n->v, 0, P * 4) != hipSuccess || f32_to_bf16(n->master, (int64_t)P, n->work, nullptr) != hipSuccess ||
-      hipDeviceSynchronize() != hipSuccess) {
+      permute_head(n->work + kOffHeadW, n->head_frag, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     free_net(n);
     return cfail(FSE_ERR_HIP, "parameter upload failed");
   }
@@ -148,11 +148,14 @@ extern "C" fse_status_t fse_cnn_set_params(fse_cnn_t net, const float* h_params)
   if (!net || !h_params) return cfail(FSE_ERR_INVALID_ARG, "null argument");
   if (!check_device(net)) return cfail(FSE_ERR_INVALID_ARG, "network was created on another device");
   const size_t P = (size_t)kNumParams;
+  // the inference layout of the head is made here too, so that the first
+  // forward pass after a parameter upload launches no set-up kernel
   if (hipMemcpy(net->master, h_params, P * 4, hipMemcpyHostToDevice) != hipSuccess ||
       f32_to_bf16(net->master, (int64_t)P, net->work, nullptr) != hipSuccess ||
+      permute_head(net->work + kOffHeadW, net->head_frag, nullptr) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess)
     return cfail(FSE_ERR_HIP, "parameter upload failed");
-  net->head_stale = true;
+  net->head_stale = false;
   return FSE_OK;
 }
 

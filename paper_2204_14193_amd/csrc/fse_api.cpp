@@ -467,10 +467,18 @@ extern "C" fse_status_t fse_batch_launch_info(fse_batch_t batch, int32_t F, int3
   return FSE_OK;
 }
 
+// Warm-started launches run the blocks [start, start + count) of the warm
+// class with the given staging (split form); count < 0 means all of them.
+struct WarmRange {
+  int32_t start = 0, count = -1;
+  float2* stage_w = nullptr;
+  float2* stage_r = nullptr;
+};
+
 static fse_status_t launch_one(fse_batch_t batch, int ci, const uint8_t* d_image, const uint8_t* d_avail,
                                int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
                                fse_trace_t* d_trace, hipStream_t s, const int16_t* cand = nullptr,
-                               const int32_t* flags = nullptr);
+                               const int32_t* flags = nullptr, const WarmRange& wr = WarmRange());
 
 extern "C" fse_status_t fse_extrapolate_batch(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail,
                                               int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
@@ -493,7 +501,8 @@ extern "C" fse_status_t fse_extrapolate_batch(fse_batch_t batch, const uint8_t* 
 
 static fse_status_t launch_one(fse_batch_t batch, int ci, const uint8_t* d_image, const uint8_t* d_avail,
                                int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
-                               fse_trace_t* d_trace, hipStream_t s, const int16_t* cand, const int32_t* flags) {
+                               fse_trace_t* d_trace, hipStream_t s, const int16_t* cand, const int32_t* flags,
+                               const WarmRange& wr) {
   // the kernels address a frame's pixels with 32-bit offsets
   if ((int64_t)batch->H * pitch >= ((int64_t)1 << 31))
     return fail(FSE_ERR_INVALID_ARG, "a frame (H x pitch bytes) must be smaller than 2 GiB");
@@ -529,12 +538,21 @@ static fse_status_t launch_one(fse_batch_t batch, int ci, const uint8_t* d_image
     a.wtab_q = nullptr;
     a.twid_q = nullptr;
     a.gamma_q = 0;
+    int grid = c.grid;
     if (warm) {
       a.iters_cap = c.iters_cap;
       a.trace_stride = batch->warm_ir + std::max(batch->max_iters, batch->warm_fb);
+      const int32_t count = wr.count < 0 ? c.count - wr.start : wr.count;
+      if (wr.start < 0 || count < 0 || wr.start + count > c.count) return fail(FSE_ERR_INVALID_ARG, "bad block range");
+      if (count == 0) return FSE_OK;
+      a.blocks += wr.start;
+      a.orig += wr.start;
+      a.n = count;
+      grid = (int32_t)std::min<int64_t>(count, (int64_t)c.wg_per_cu * batch->cus);
       if (batch->warm_split) {
-        a.stage_w = batch->d_stage_w;
-        a.stage_r = batch->d_stage_r;
+        a.stage_w = wr.stage_w;
+        a.stage_r = wr.stage_r;
+        if (!a.stage_w || !a.stage_r) return fail(FSE_ERR_INVALID_ARG, "no staging for the split warm start");
       }
     }
     if (!warm && (batch->plan->flags & FSE_PLAN_REAL)) {
@@ -555,7 +573,7 @@ static fse_status_t launch_one(fse_batch_t batch, int ci, const uint8_t* d_image
       return FSE_OK;
     }
     const int kind = !warm ? FSE_KERNEL_PLAIN : batch->warm_split ? FSE_KERNEL_WARM_PREP : FSE_KERNEL_WARM_FUSED;
-    if (timed(batch, kind, c.v->F, s, [&] { return fse::launch_class(*c.v, a, c.grid, c.lds, s); }) != hipSuccess)
+    if (timed(batch, kind, c.v->F, s, [&] { return fse::launch_class(*c.v, a, grid, c.lds, s); }) != hipSuccess)
       return fail(FSE_ERR_HIP, "kernel launch failed");
     if (warm && batch->warm_split &&
         timed(batch, FSE_KERNEL_RESTRICTED, 64, s,
@@ -693,11 +711,15 @@ extern "C" int32_t fse_warm_trace_stride(fse_batch_t batch, int32_t restricted_i
   return batch ? restricted_iters + std::max(batch->max_iters, fallback_iters) : 0;
 }
 
-extern "C" fse_status_t fse_warm_extrapolate_batch(fse_batch_t batch, const uint8_t* d_image,
-                                                   const uint8_t* d_avail, int64_t pitch, float* d_out,
-                                                   int64_t out_pitch, int32_t* d_status, fse_trace_t* d_trace,
-                                                   const int16_t* d_cand, const int32_t* d_flags, int32_t kc,
-                                                   int32_t restricted_iters, int32_t fallback_iters, void* stream) {
+namespace {
+
+// Candidate counts the staging is sized for: the largest compiled one, so
+// that a later change of kc never reallocates it.
+constexpr int kStageKcMax = 512;
+
+fse_status_t warm_check(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail, int64_t pitch,
+                        float* d_out, int64_t out_pitch, int32_t* d_status, const int16_t* d_cand,
+                        const int32_t* d_flags, int32_t restricted_iters, int32_t fallback_iters) {
   if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
   if (batch->plan->flags & (FSE_PLAN_MASKED_B | FSE_PLAN_REAL | FSE_PLAN_FIXED))
     return fail(FSE_ERR_UNSUPPORTED, "the warm start needs a cFSE plan with rectangular loss areas");
@@ -705,61 +727,105 @@ extern "C" fse_status_t fse_warm_extrapolate_batch(fse_batch_t batch, const uint
   if (!d_image || !d_avail || !d_out || !d_status || !d_cand || !d_flags)
     return fail(FSE_ERR_INVALID_ARG, "null device pointer");
   if (pitch < batch->W || out_pitch < batch->W) return fail(FSE_ERR_INVALID_ARG, "pitch smaller than the width");
-  const int ci = class_of(64);
-  if (batch->cls[ci].count != batch->n) return fail(FSE_ERR_UNSUPPORTED, "the warm start needs F = 64 blocks only");
+  if (batch->cls[class_of(64)].count != batch->n) return fail(FSE_ERR_UNSUPPORTED, "the warm start needs F = 64 blocks only");
   if (restricted_iters < 0 || fallback_iters < 0 ||
       restricted_iters + std::max(batch->max_iters, fallback_iters) > batch->plan->max_iters)
     return fail(FSE_ERR_INVALID_ARG, "iteration counts outside the plan's limit");
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != batch->device)
     return fail(FSE_ERR_INVALID_ARG, "batch was created on another device");
-  if (kc != batch->warm_kc || restricted_iters != batch->warm_ir || fallback_iters != batch->warm_fb) {
-    // With no full iteration after the restricted ones, the transform and
-    // the restricted iterations run as two kernels (split form); otherwise
-    // one kernel does both phases.
-    const bool split = batch->max_iters == 0;
-    const fse::Variant* v = fse::warm_variant_for(64, kc, split ? fse::kWarmPrep : fse::kWarmFused);
-    if (!v) return fail(FSE_ERR_UNSUPPORTED, "no warm-start kernel for this candidate count");
-    fse_batch_s::Cls c = batch->cls[ci];
-    c.iters_cap = split ? std::max(c.iters_cap, fallback_iters)
-                        : restricted_iters + std::max(c.iters_cap, fallback_iters);
-    fse_status_t st = configure(batch, c, v);
-    if (st != FSE_OK) return st;
-    if (split) {
-      const void* rk = fse::restricted_kernel(kc);
-      // without coefficient lists (and, with one wave, without the
-      // cross-wave slots) a block needs 17 KB of LDS: nine per compute unit
-      const size_t lds = fse::restricted_lds_bytes(kc, restricted_iters, !batch->all_small_b);
-      if (!rk) return fail(FSE_ERR_UNSUPPORTED, "no restricted kernel for this candidate count");
-      if (hipFuncSetAttribute(rk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return fail(FSE_ERR_HIP, "hipFuncSetAttribute failed (LDS size)");
-      int per_cu = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rk, fse::restricted_threads(kc), lds) != hipSuccess ||
-          per_cu < 1)
-        return fail(FSE_ERR_UNSUPPORTED, "restricted kernel does not fit on a compute unit");
-      if (kc != batch->stage_kc) {
-        (void)hipFree(batch->d_stage_r);
-        batch->d_stage_r = nullptr;
-        batch->stage_kc = 0;
-        if (hipMalloc(&batch->d_stage_r, (size_t)batch->n * kc * sizeof(float2)) != hipSuccess)
-          return fail(FSE_ERR_OOM, "hipMalloc failed (warm staging)");
-        batch->stage_kc = kc;
-      }
-      if (!batch->d_stage_w &&
-          hipMalloc(&batch->d_stage_w, (size_t)batch->n * fse::kHalfRows * 64 * sizeof(float2)) != hipSuccess) {
-        batch->d_stage_w = nullptr;
-        return fail(FSE_ERR_OOM, "hipMalloc failed (warm staging)");
-      }
-      batch->restricted_lds = lds;
-    }
-    batch->warm = c;
-    batch->warm_split = split;
-    batch->warm_kc = kc;
-    batch->warm_ir = restricted_iters;
-    batch->warm_fb = fallback_iters;
+  return FSE_OK;
+}
+
+// Launch configuration of the warm-started form for (kc, ir, fb); host
+// state and kernel attributes only, no device memory.
+fse_status_t warm_configure(fse_batch_t batch, int32_t kc, int32_t restricted_iters, int32_t fallback_iters) {
+  if (kc == batch->warm_kc && restricted_iters == batch->warm_ir && fallback_iters == batch->warm_fb)
+    return FSE_OK;
+  const int ci = class_of(64);
+  // With no full iteration after the restricted ones, the transform and the
+  // restricted iterations run as two kernels (split form); otherwise one
+  // kernel does both phases.
+  const bool split = batch->max_iters == 0;
+  const fse::Variant* v = fse::warm_variant_for(64, kc, split ? fse::kWarmPrep : fse::kWarmFused);
+  if (!v) return fail(FSE_ERR_UNSUPPORTED, "no warm-start kernel for this candidate count");
+  fse_batch_s::Cls c = batch->cls[ci];
+  c.iters_cap = split ? std::max(c.iters_cap, fallback_iters) : restricted_iters + std::max(c.iters_cap, fallback_iters);
+  fse_status_t st = configure(batch, c, v);
+  if (st != FSE_OK) return st;
+  size_t lds = 0;
+  if (split) {
+    const void* rk = fse::restricted_kernel(kc);
+    // without coefficient lists (and, with one wave, without the
+    // cross-wave slots) a block needs 17 KB of LDS: nine per compute unit
+    lds = fse::restricted_lds_bytes(kc, restricted_iters, !batch->all_small_b);
+    if (!rk) return fail(FSE_ERR_UNSUPPORTED, "no restricted kernel for this candidate count");
+    if (hipFuncSetAttribute(rk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+      return fail(FSE_ERR_HIP, "hipFuncSetAttribute failed (LDS size)");
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rk, fse::restricted_threads(kc), lds) != hipSuccess ||
+        per_cu < 1)
+      return fail(FSE_ERR_UNSUPPORTED, "restricted kernel does not fit on a compute unit");
   }
-  return launch_one(batch, ci, d_image, d_avail, pitch, d_out, out_pitch, d_status, d_trace,
-                    reinterpret_cast<hipStream_t>(stream), d_cand, d_flags);
+  batch->restricted_lds = lds;
+  batch->warm = c;
+  batch->warm_split = split;
+  batch->warm_kc = kc;
+  batch->warm_ir = restricted_iters;
+  batch->warm_fb = fallback_iters;
+  return FSE_OK;
+}
+
+// Library-owned staging of the split form for every block of the batch,
+// sized for kStageKcMax candidates; allocated once.
+fse_status_t warm_staging(fse_batch_t batch) {
+  if (!batch->warm_split || (batch->d_stage_w && batch->d_stage_r)) return FSE_OK;
+  if (hipMalloc(&batch->d_stage_r, (size_t)batch->n * kStageKcMax * sizeof(float2)) != hipSuccess) {
+    batch->d_stage_r = nullptr;
+    return fail(FSE_ERR_OOM, "hipMalloc failed (warm staging)");
+  }
+  if (hipMalloc(&batch->d_stage_w, (size_t)batch->n * fse::kHalfRows * 64 * sizeof(float2)) != hipSuccess) {
+    batch->d_stage_w = nullptr;
+    return fail(FSE_ERR_OOM, "hipMalloc failed (warm staging)");
+  }
+  batch->stage_kc = kStageKcMax;
+  return FSE_OK;
+}
+
+}  // namespace
+
+extern "C" fse_status_t fse_warm_prepare(fse_batch_t batch, int32_t kc, int32_t restricted_iters,
+                                         int32_t fallback_iters) {
+  if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
+  if (batch->plan->flags & (FSE_PLAN_MASKED_B | FSE_PLAN_REAL | FSE_PLAN_FIXED))
+    return fail(FSE_ERR_UNSUPPORTED, "the warm start needs a cFSE plan with rectangular loss areas");
+  if (batch->n == 0) return FSE_OK;
+  if (batch->cls[class_of(64)].count != batch->n) return fail(FSE_ERR_UNSUPPORTED, "the warm start needs F = 64 blocks only");
+  if (restricted_iters < 0 || fallback_iters < 0 ||
+      restricted_iters + std::max(batch->max_iters, fallback_iters) > batch->plan->max_iters)
+    return fail(FSE_ERR_INVALID_ARG, "iteration counts outside the plan's limit");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != batch->device)
+    return fail(FSE_ERR_INVALID_ARG, "batch was created on another device");
+  fse_status_t st = warm_configure(batch, kc, restricted_iters, fallback_iters);
+  return st != FSE_OK ? st : warm_staging(batch);
+}
+
+extern "C" fse_status_t fse_warm_extrapolate_batch(fse_batch_t batch, const uint8_t* d_image,
+                                                   const uint8_t* d_avail, int64_t pitch, float* d_out,
+                                                   int64_t out_pitch, int32_t* d_status, fse_trace_t* d_trace,
+                                                   const int16_t* d_cand, const int32_t* d_flags, int32_t kc,
+                                                   int32_t restricted_iters, int32_t fallback_iters, void* stream) {
+  fse_status_t st = warm_check(batch, d_image, d_avail, pitch, d_out, out_pitch, d_status, d_cand, d_flags,
+                               restricted_iters, fallback_iters);
+  if (st != FSE_OK || batch->n == 0) return st;
+  if ((st = warm_configure(batch, kc, restricted_iters, fallback_iters)) != FSE_OK) return st;
+  if ((st = warm_staging(batch)) != FSE_OK) return st;  // allocates only if fse_warm_prepare was not called
+  WarmRange wr;
+  wr.stage_w = batch->d_stage_w;
+  wr.stage_r = batch->d_stage_r;
+  return launch_one(batch, class_of(64), d_image, d_avail, pitch, d_out, out_pitch, d_status, d_trace,
+                    reinterpret_cast<hipStream_t>(stream), d_cand, d_flags, wr);
 }
 
 // ------------------------------------------------------------ 3-D (video)

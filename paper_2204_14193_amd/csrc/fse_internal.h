@@ -41,9 +41,10 @@ struct ClassArgs {
   int32_t ir;                 // restricted iterations
   int32_t fb_iters;           // full iterations of a block that falls back
   // split warm-started form: staging written by the transform kernel and
-  // read by the restricted kernel, indexed by the caller's block index
-  float2* stage_w;            // [caller's n_blocks][kHalfRows * 64]: W rows 0..32
-  float2* stage_r;            // [caller's n_blocks][kc]: R_w at the candidates
+  // read by the restricted kernel, indexed by the block's position in this
+  // launch's list (blocks[0 .. n))
+  float2* stage_w;            // [n][kHalfRows * 64]: W rows 0..32
+  float2* stage_r;            // [n][kc]: R_w at the candidates
   // fixed-point form only (plan flag FSE_PLAN_FIXED)
   const int32_t* wtab_q;      // round(2^15 rho^(sqrt(a^2 + b^2) / 2)), [kWinStride][kWinStride]
   const int2* twid_q;         // round(2^14 exp(-j 2 pi q / 64)), 64 entries

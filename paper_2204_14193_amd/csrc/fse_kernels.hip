@@ -405,14 +405,14 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
   if constexpr (MODE == kWarmPrep) {
     if (warm) {
       // stage W[k, l] for k <= F/2 (split as below) and R_w at the candidates
-      float2* ws = a.stage_w + (int64_t)orig * (kHalfRows * F);
+      float2* ws = a.stage_w + (int64_t)bi * (kHalfRows * F);
       for (int e = t; e < kHalfRows * F; e += NT) {
         const int k = e / F, l = e % F;
         const float2 zk = Wd[e];
         const float2 zn = Wd[((F - k) & (F - 1)) * F + ((F - l) & (F - 1))];
         ws[e] = make_float2((zk.y + zn.y) * (0.5f / kAlpha), (zn.x - zk.x) * (0.5f / kAlpha));
       }
-      float2* rs = a.stage_r + (int64_t)orig * KC;
+      float2* rs = a.stage_r + (int64_t)bi * KC;
       for (int c = t; c < KC; c += NT) {
         const int ci = a.cand[(int64_t)orig * KC + c];
         const int k = ci / F, l = ci % F;
@@ -830,7 +830,7 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
   if (__builtin_amdgcn_readfirstlane(a.flags[orig]) != 0) return;  // concealed by the transform kernel
 
   {
-    const float4* src = reinterpret_cast<const float4*>(a.stage_w + (int64_t)orig * (kHalfRows * F));
+    const float4* src = reinterpret_cast<const float4*>(a.stage_w + (int64_t)bi * (kHalfRows * F));
     float4* dst = reinterpret_cast<float4*>(Wh);
     for (int e = t; e < kHalfRows * F / 2; e += NT) dst[e] = src[e];
     if (t < F) tw[t] = a.twid[t];
@@ -849,7 +849,7 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
     const int c = wave * (KC / NWB) + lane * CPL + j;
     const int bin = a.cand[(int64_t)orig * KC + c];
     const int k = bin / F, l = bin % F;
-    const float2 r = a.stage_r[(int64_t)orig * KC + c];
+    const float2 r = a.stage_r[(int64_t)bi * KC + c];
     Rx[j] = r.x;
     Ry[j] = r.y;
     xa[j] = k * 4096 + l * 8;

@@ -111,6 +111,13 @@ def trace_stride(batch, restricted_iters, fallback_iters):
     return int(_lib.lib().fse_warm_trace_stride(batch._h, int(restricted_iters), int(fallback_iters)))
 
 
+def warm_prepare(batch, kc, restricted_iters, fallback_iters):
+    """Kernel choice and staging of the warm start for these counts (the one
+    allocating step; later warm launches with the same counts allocate nothing)."""
+    _check(_lib.lib().fse_warm_prepare(batch._h, int(kc), int(restricted_iters), int(fallback_iters)),
+           "fse_warm_prepare")
+
+
 def warm_extrapolate(batch, image, avail, out, status, cand, flags, kc, restricted_iters, fallback_iters,
                      trace=None, stream=None):
     batch._check_tensors(image, avail, out, status)
@@ -122,10 +129,11 @@ def warm_extrapolate(batch, image, avail, out, status, cand, flags, kc, restrict
 
 class WarmStart:
     """The whole warm-started concealment of one batch: forward pass (inputs
-    built from the frames), candidate sets, warm-started FSE. Buffers are allocated
-    once per batch size; run() only launches kernels."""
+    built from the frames), candidate sets, warm-started FSE. Buffers and the
+    warm start's staging are allocated here; run() only launches kernels (it
+    may be captured into a HIP graph from its first call on)."""
 
-    def __init__(self, net, batch, kc=256, restricted_iters=75, fallback_iters=100):
+    def __init__(self, net, batch, kc=KC, restricted_iters=RESTRICTED_ITERS, fallback_iters=100):
         import torch
         self.net, self.batch = net, batch
         self.kc, self.ir, self.fb = int(kc), int(restricted_iters), int(fallback_iters)
@@ -134,6 +142,7 @@ class WarmStart:
         self.logits = torch.empty((n, N_BINS), dtype=torch.float32, device=dev)
         self.cand = torch.empty((n, self.kc), dtype=torch.int16, device=dev)
         self.flags = torch.empty((n,), dtype=torch.int32, device=dev)
+        warm_prepare(batch, self.kc, self.ir, self.fb)
 
     def run(self, image, avail, out, status, trace=None, stream=None):
         self.net.forward_blocks(self.batch, image, avail, self.logits, stream)

@@ -120,3 +120,56 @@ def test_3d_warm_start_graph_capture():
     net.close()
     batch.close()
     plan.close()
+
+
+def test_2d_warm_start_graph_capture_on_first_use():
+    """The benchmark's warm-started step (network inputs and forward pass,
+    top-K, transform kernel, restricted kernel) captured into a graph on its
+    very first call, before any eager run: three replays, with eager work
+    between them, match an eager run bit for bit."""
+    import torch
+    import paper_2204_14193_amd as fse
+    from paper_2204_14193_amd import warm
+    wl = workloads.random_1080p_16x16(seeds=(99,), iters=100)
+    blocks = wl.blocks.copy()
+    blocks["iters"] = 0
+    n = len(blocks)
+    _say(f"case graph capture 2-D warm on first use: {n} blocks")
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(wl.distorted).to(dev)
+    av = torch.from_numpy(wl.avail).to(dev)
+    plan = fse.Plan(wl.rho, wl.gamma, warm.RESTRICTED_ITERS + 100)
+    batch = fse.Batch(plan, blocks, *wl.frames.shape)
+    net = warm.Net(n, seed=0)
+    net.load()
+    ws = warm.WarmStart(net, batch)
+    base = (img * (av != 0)).to(torch.float32)
+    out = base.clone()
+    status = torch.full((n,), -1, dtype=torch.int32, device=dev)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        ws.run(img, av, out, status, stream=s)
+    out.copy_(base)
+    status.fill_(-1)
+    ws.run(img, av, out, status)
+    torch.cuda.synchronize()
+    assert (status == 0).all()
+    eager, cand = out.clone(), ws.cand.clone()
+    for rep in range(3):
+        out.copy_(base)
+        status.fill_(-1)
+        ws.cand.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert (status == 0).all(), rep
+        assert torch.equal(ws.cand, cand), rep
+        assert torch.equal(out, eager), rep
+        _ = (base * 2).sum().item()                 # unrelated eager work between replays
+    del g
+    net.close()
+    batch.close()
+    plan.close()
