@@ -390,6 +390,29 @@ fse_status_t fse_warm_extrapolate_batch(fse_batch_t batch, const uint8_t* d_imag
  * fse_warm_extrapolate_batch. */
 fse_status_t fse_warm_prepare(fse_batch_t batch, int32_t kc, int32_t restricted_iters, int32_t fallback_iters);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * warm-started cFSE of fse_warm_extrapolate_batch, same arguments, same
+ * kernels and the same bits, but it allocates nothing. The two-kernel
+ * form's staging lives in a static array of 48 MiB that the library holds
+ * on every device it runs on until the process ends; the batch's blocks run
+ * in consecutive ranges of at most fse_warm_noalloc_max_blocks(kc) blocks
+ * that reuse it in stream order. Every call on a device shares that
+ * device's array: calls that overlap on one device (other streams, other
+ * threads) race and give undefined results. kc beyond the array
+ * (fse_warm_noalloc_max_blocks(kc) == 0) is FSE_ERR_UNSUPPORTED. A change of
+ * (kc, restricted_iters, fallback_iters) reconfigures the batch's host
+ * state only (no allocation). Other errors as fse_warm_extrapolate_batch. */
+fse_status_t fse_warm_extrapolate_batch_noalloc(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail,
+                                                int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
+                                                fse_trace_t* d_trace, const int16_t* d_cand, const int32_t* d_flags,
+                                                int32_t kc, int32_t restricted_iters, int32_t fallback_iters,
+                                                void* stream);
+
+/* Blocks per staging range of fse_warm_extrapolate_batch_noalloc for kc
+ * candidates (0 when kc < 1 or kc > 512). Host only. */
+size_t fse_warm_noalloc_max_blocks(int32_t kc);
+
 /* restricted_iters + max(largest block iteration count, fallback_iters). */
 int32_t fse_warm_trace_stride(fse_batch_t batch, int32_t restricted_iters, int32_t fallback_iters);
 

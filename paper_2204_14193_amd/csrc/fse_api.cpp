@@ -828,6 +828,49 @@ extern "C" fse_status_t fse_warm_extrapolate_batch(fse_batch_t batch, const uint
                     reinterpret_cast<hipStream_t>(stream), d_cand, d_flags, wr);
 }
 
+extern "C" size_t fse_warm_noalloc_max_blocks(int32_t kc) {
+  if (kc < 1 || kc > kStageKcMax) return 0;
+  const size_t per_block = (size_t)fse::kHalfRows * 64 * sizeof(float2) + (size_t)kc * sizeof(float2);
+  return (fse::kScratchBytes - 256) / per_block;
+}
+
+extern "C" fse_status_t fse_warm_extrapolate_batch_noalloc(fse_batch_t batch, const uint8_t* d_image,
+                                                           const uint8_t* d_avail, int64_t pitch, float* d_out,
+                                                           int64_t out_pitch, int32_t* d_status,
+                                                           fse_trace_t* d_trace, const int16_t* d_cand,
+                                                           const int32_t* d_flags, int32_t kc,
+                                                           int32_t restricted_iters, int32_t fallback_iters,
+                                                           void* stream) {
+  fse_status_t st = warm_check(batch, d_image, d_avail, pitch, d_out, out_pitch, d_status, d_cand, d_flags,
+                               restricted_iters, fallback_iters);
+  if (st != FSE_OK || batch->n == 0) return st;
+  if ((st = warm_configure(batch, kc, restricted_iters, fallback_iters)) != FSE_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int ci = class_of(64);
+  if (!batch->warm_split)  // one kernel, no staging
+    return launch_one(batch, ci, d_image, d_avail, pitch, d_out, out_pitch, d_status, d_trace, s, d_cand, d_flags);
+  const size_t chunk = fse_warm_noalloc_max_blocks(kc);
+  if (chunk == 0) return fail(FSE_ERR_UNSUPPORTED, "candidate count beyond the static staging");
+  void* base = nullptr;
+  if (fse::scratch_address(batch->device, &base) != hipSuccess)
+    return fail(FSE_ERR_HIP, "hipGetSymbolAddress failed (static staging)");
+  // W rows of each block first, then its candidates' R_w; 256-byte aligned
+  WarmRange wr;
+  wr.stage_w = reinterpret_cast<float2*>(base);
+  const size_t wbytes = chunk * fse::kHalfRows * 64 * sizeof(float2);
+  wr.stage_r = reinterpret_cast<float2*>(reinterpret_cast<char*>(base) + ((wbytes + 255) & ~(size_t)255));
+  // consecutive ranges reuse the staging: each range's two kernels are
+  // ordered on the stream before the next range's transform kernel
+  for (int32_t start = 0; start < batch->n; start += (int32_t)chunk) {
+    wr.start = start;
+    wr.count = (int32_t)std::min<int64_t>((int64_t)chunk, batch->n - start);
+    if ((st = launch_one(batch, ci, d_image, d_avail, pitch, d_out, out_pitch, d_status, d_trace, s, d_cand, d_flags,
+                         wr)) != FSE_OK)
+      return st;
+  }
+  return FSE_OK;
+}
+
 // ------------------------------------------------------------ 3-D (video)
 
 struct fse_batch3d_s {

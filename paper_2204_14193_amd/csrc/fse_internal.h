@@ -157,4 +157,11 @@ hipError_t launch_class(const Variant& v, const ClassArgs& a, int grid, size_t l
 // Launch the restricted kernel over the n blocks of a class.
 hipError_t launch_restricted(int kc, const ClassArgs& a, size_t lds, hipStream_t s);
 
+// Device memory of the allocation-free warm start: a file-scope array of
+// kScratchBytes on every device the library runs on, held until the
+// process ends. scratch_address returns its address on `device` (which must
+// be current), looked up on the first call per device and kept.
+constexpr size_t kScratchBytes = (size_t)48 << 20;
+hipError_t scratch_address(int device, void** out);
+
 }  // namespace fse

@@ -24,6 +24,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+
 #include "fse_internal.h"
 
 namespace fse {
@@ -1843,6 +1846,28 @@ hipError_t launch_restricted(int kc, const ClassArgs& a, size_t lds, hipStream_t
   if (!fn || a.n <= 0) return hipErrorInvalidValue;
   void* args[] = {const_cast<ClassArgs*>(&a)};
   return hipLaunchKernel(fn, dim3(a.n), dim3(restricted_threads(kc)), args, lds, s);
+}
+
+// Staging of the allocation-free warm start (fse_warm_extrapolate_batch_noalloc).
+// In host code `scratch` names a host-side stand-in: only the address from
+// hipGetSymbolAddress may reach a kernel or a copy.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(int device, void** out) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(device);
+  if (it != addr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || p == nullptr) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+  addr.emplace(device, p);
+  *out = p;
+  return hipSuccess;
 }
 
 size_t lds_bytes(const Variant& v, int iters_cap) {

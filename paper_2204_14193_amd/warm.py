@@ -127,6 +127,23 @@ def warm_extrapolate(batch, image, avail, out, status, cand, flags, kc, restrict
         int(fallback_iters), _stream(stream)), "fse_warm_extrapolate_batch")
 
 
+def warm_extrapolate_noalloc(batch, image, avail, out, status, cand, flags, kc, restricted_iters, fallback_iters,
+                             trace=None, stream=None):
+    """warm_extrapolate without any device allocation: the staging lives in
+    the library's static per-device array (calls on one device must not
+    overlap)."""
+    batch._check_tensors(image, avail, out, status)
+    _check(_lib.lib().fse_warm_extrapolate_batch_noalloc(
+        batch._h, _ptr(image), _ptr(avail), image.stride(1), _ptr(out), out.stride(1), _ptr(status),
+        None if trace is None else _ptr(trace), _ptr(cand), _ptr(flags), int(kc), int(restricted_iters),
+        int(fallback_iters), _stream(stream)), "fse_warm_extrapolate_batch_noalloc")
+
+
+def noalloc_max_blocks(kc):
+    """Blocks per launch range of the allocation-free warm start."""
+    return int(_lib.lib().fse_warm_noalloc_max_blocks(int(kc)))
+
+
 class WarmStart:
     """The whole warm-started concealment of one batch: forward pass (inputs
     built from the frames), candidate sets, warm-started FSE. Buffers and the
