@@ -13,12 +13,15 @@
 //   4. the model is evaluated on B only, Re{sum c*phi_(u,v)} (the inverse
 //      transform of G restricted to B), and written to HBM.
 //
-// Data placement: R_w lives in VGPRs. Wave w of the workgroup owns the RPW
-// consecutive spectrum rows [w*RPW, (w+1)*RPW); its slot j holds the 64
-// consecutive bins w*RPW*F + 64*j + lane. W lives in LDS as its F rows plus
-// copies of its first RPW-1 rows, so the rows a wave reads for a shift
-// (k-u) mod F are always consecutive and every load of the update uses a
-// compile-time offset from one per-iteration base address. The argmax is a
+// Data placement: R_w lives in VGPRs. Wave w of the workgroup owns GR groups
+// of RPG consecutive spectrum rows, group g being rows
+// [g*F/GR + w*RPG, g*F/GR + (w+1)*RPG); its slots hold those rows' bins in
+// ascending order, 64 consecutive bins per slot. W lives in LDS as its F
+// rows plus copies of its first RPG-1 rows, so the rows a group reads for a
+// shift (k-u) mod F are always consecutive and every load of the update
+// uses a compile-time offset from one per-iteration base address per group.
+// At F = 64 a group is 8 rows whatever the workgroup size, so W with its
+// wrapped rows takes 71 rows (36 KB) and four workgroups fit a CU. The argmax is a
 // DPP reduction inside the wave and one LDS exchange and barrier across
 // waves.
 #include <hip/hip_runtime.h>
@@ -97,6 +100,18 @@ __device__ __forceinline__ void dpp_max64(unsigned& hi, unsigned& lo) {
   const bool take = b > a;
   hi = take ? ohi : hi;
   lo = take ? olo : lo;
+}
+
+// Maximum (MAX) or minimum over each group of N consecutive lanes (N a power
+// of two up to 16), left in every lane of the group.
+template <int N, bool MAX>
+__device__ __forceinline__ unsigned group_reduce(unsigned x) {
+  auto step = [&](unsigned y) { return MAX ? max(x, y) : min(x, y); };
+  if constexpr (N >= 2) x = step((unsigned)__builtin_amdgcn_update_dpp(0, (int)x, kQuadXor1, 0xf, 0xf, false));
+  if constexpr (N >= 4) x = step((unsigned)__builtin_amdgcn_update_dpp(0, (int)x, kQuadXor2, 0xf, 0xf, false));
+  if constexpr (N >= 8) x = step((unsigned)__builtin_amdgcn_update_dpp(0, (int)x, kRowHalfMirror, 0xf, 0xf, false));
+  if constexpr (N >= 16) x = step((unsigned)__builtin_amdgcn_update_dpp(0, (int)x, kRowMirror, 0xf, 0xf, false));
+  return x;
 }
 
 __device__ __forceinline__ float readlane_f(float x, int lane) {
@@ -279,11 +294,18 @@ struct Shape {
   static constexpr int NW = NT / 64;          // waves per workgroup
   static constexpr int BPL = F * F / NT;      // bins per lane
   static constexpr int RPW = F / NW;          // spectrum rows owned by one wave
-  static constexpr int WROWS = F + RPW - 1;   // W rows in LDS: F plus RPW-1 wrapped copies
+  static constexpr int GR = (F == 64 && RPW > 8) ? RPW / 8 : 1;  // row groups of a wave
+  static constexpr int RPG = RPW / GR;        // rows per group
+  static constexpr int SPG = BPL / GR;        // slots per group
+  static constexpr int WROWS = F + RPG - 1;   // W rows in LDS: F plus RPG-1 wrapped copies
   static constexpr int PH = F > 64 ? F / 64 : 1;  // column phases of a lane
   static_assert(NT % 64 == 0 && NW <= 16 && F % NW == 0 && BPL * NT == F * F && BPL * 64 == RPW * F,
                 "bad tiling");
   static_assert(F <= 64 || (F % 64 == 0 && BPL % PH == 0), "bad tiling");
+  static_assert(GR == 1 || (F == 64 && SPG * 64 == RPG * F), "bad row groups");
+  // first row of group g of wave w, and the wave owning row k
+  static __device__ __forceinline__ int group_row(int w, int g) { return g * (F / GR) + w * RPG; }
+  static __device__ __forceinline__ int wave_of_row(int k) { return (int)(((unsigned)k % (F / GR)) / RPG); }
 };
 
 // LDS carve-up of one workgroup (dynamic shared memory).
@@ -334,7 +356,7 @@ template <int F, int NT, int KC, int MODE>
 __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, const Lds& s, const int t,
                                              int& parity) {
   using S = Shape<F, NT>;
-  constexpr int BPL = S::BPL, NW = S::NW, RPW = S::RPW, PH = S::PH;
+  constexpr int BPL = S::BPL, NW = S::NW, RPG = S::RPG, SPG = S::SPG, GR = S::GR, PH = S::PH;
   constexpr int CPL = KC > 0 ? KC / 64 : 1;  // candidates per lane of wave 0
   constexpr bool FUSED = MODE == kWarmFused;
   static_assert(KC % 64 == 0 && KC <= 1024, "candidate count must be a multiple of 64");
@@ -342,7 +364,24 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
   static_assert(MODE != kWarmPrep || F == 64, "the split warm start is compiled for F = 64");
   const int lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
-  const int wbase = wave * RPW * F;  // linear index of this wave's first bin
+  // linear index of the first bin of slot j is gbase[j / SPG] + (j % SPG) * 64
+  int gbase[GR];
+#pragma unroll
+  for (int g = 0; g < GR; ++g) gbase[g] = S::group_row(wave, g) * F;
+  // LDS element index of W[(k-u) mod F, (l-v) mod F] for the first bin of
+  // each row group and column phase of this lane
+  auto shifted_bases = [&](int u, int v, int (&wb)[GR][PH]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int g = 0; g < GR; ++g) {
+      const int r0 = (S::group_row(wave, g) - u) & (F - 1);
+#pragma unroll
+      for (int p = 0; p < PH; ++p) {
+        const int lr = F <= 64 ? lane / F : 0;
+        const int lc = F <= 64 ? lane % F : p * 64 + lane;
+        wb[g][p] = (r0 + lr) * F + ((lc - v) & (F - 1));
+      }
+    }
+  };
   float2* const Wd = s.Wd;
 
   const UBlock bd = uniform_block(a.blocks + bi);
@@ -444,12 +483,12 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
 
   // split Z = R_w + j*alpha*W by conjugate symmetry; R_w goes to VGPRs, W
   // is held until every thread has read Z, then written over it (rows
-  // 0..RPW-2 also into their wrapped copies F..F+RPW-2).
+  // 0..RPG-2 also into their wrapped copies F..F+RPG-2).
   fvec<BPL> Rx, Ry;
   float2 Wv[BPL];
 #pragma unroll
   for (int j = 0; j < BPL; ++j) {
-    const int idx = wbase + j * 64 + lane;
+    const int idx = gbase[j / SPG] + (j % SPG) * 64 + lane;
     const int k = idx / F, l = idx % F;
     const float2 zk = Wd[k * F + l];
     const float2 zn = Wd[((F - k) & (F - 1)) * F + ((F - l) & (F - 1))];
@@ -461,9 +500,9 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < BPL; ++j) {
-    const int idx = wbase + j * 64 + lane;
+    const int idx = gbase[j / SPG] + (j % SPG) * 64 + lane;
     Wd[idx] = Wv[j];
-    if (idx < (RPW - 1) * F) Wd[idx + F * F] = Wv[j];
+    if (idx < (RPG - 1) * F) Wd[idx + F * F] = Wv[j];
   }
   __syncthreads();
 
@@ -570,17 +609,11 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
         const float cre = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(c.x)));
         const float cim = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(c.y)));
         const int u = bin / F, v = bin % F;
-        const int r0 = (wave * RPW - u) & (F - 1);
-        int wb[PH];
-#pragma unroll
-        for (int p = 0; p < PH; ++p) {
-          const int lr = F <= 64 ? lane / F : 0;
-          const int lc = F <= 64 ? lane % F : p * 64 + lane;
-          wb[p] = (r0 + lr) * F + ((lc - v) & (F - 1));
-        }
+        int wb[GR][PH];
+        shifted_bases(u, v, wb);
 #pragma unroll
         for (int j = 0; j < BPL; ++j) {
-          const float2 w = Wd[wb[j % PH] + (j / PH) * 64 * PH];
+          const float2 w = Wd[wb[j / SPG][j % PH] + ((j % SPG) / PH) * 64 * PH];
           float rx = Rx[j], ry = Ry[j];
           rx = fmaf(-cre, w.x, rx);
           rx = fmaf(cim, w.y, rx);
@@ -627,7 +660,7 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
     wj = __builtin_amdgcn_readfirstlane(wj);
     const float re = readlane_f(Rx[wj], wl);
     const float im = readlane_f(Ry[wj], wl);
-    const int widx = wbase + wj * 64 + wl;
+    const int widx = __builtin_amdgcn_readfirstlane(gbase[wj / SPG]) + (wj % SPG) * 64 + wl;
     if constexpr (NW == 1) {
       sel = widx; sre = re; sim = im; smag = __uint_as_float(wm);
     } else {
@@ -636,26 +669,24 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
       __syncthreads();
       // lane i < NW holds wave i's candidate; key = (|R|^2 bits, ~index) so
       // the largest key is the largest value with the lowest index
+      // Every group of NW lanes holds the NW entries: the largest value over
+      // the group, then the lowest index among the entries holding it.
       const int4 o = slot[lane & (NW - 1)];
-      unsigned hi = (unsigned)o.x, lo = ~(unsigned)o.y;
-      if constexpr (NW >= 2) dpp_max64<kQuadXor1>(hi, lo);
-      if constexpr (NW >= 4) dpp_max64<kQuadXor2>(hi, lo);
-      if constexpr (NW >= 8) dpp_max64<kRowHalfMirror>(hi, lo);
-      if constexpr (NW >= 16) dpp_max64<kRowMirror>(hi, lo);
-      sel = (int)~(unsigned)__builtin_amdgcn_readfirstlane((int)lo);
-      smag = __uint_as_float((unsigned)__builtin_amdgcn_readfirstlane((int)hi));
-      const int4 win = slot[sel / (RPW * F)];
-      sre = __int_as_float(__builtin_amdgcn_readfirstlane(win.z));
-      sim = __int_as_float(__builtin_amdgcn_readfirstlane(win.w));
+      const unsigned gm = group_reduce<NW, true>((unsigned)o.x);
+      const unsigned key = group_reduce<NW, false>((unsigned)o.x == gm ? (unsigned)o.y : 0xffffffffu);
+      sel = __builtin_amdgcn_readfirstlane((int)key);
+      smag = __uint_as_float((unsigned)__builtin_amdgcn_readfirstlane((int)gm));
+      // lane i holds wave i's entry: the winner's value without another LDS read
+      const int ww = S::wave_of_row((int)((unsigned)sel / F));
+      sre = __int_as_float(__builtin_amdgcn_readlane(o.z, ww));
+      sim = __int_as_float(__builtin_amdgcn_readlane(o.w, ww));
       parity ^= 1;
     }
   };
   if (I_full > 0) select();
 
-  bool finite = true;
   for (int it = 0; it < I_full; ++it) {
     const float cre = gW * sre, cim = gW * sim;          // eq. (13)
-    finite = finite && isfinite(cre) && isfinite(cim);
     // All lanes of wave 0 store the same uniform values: no lane-divergent
     // region inside the loops (see the persistent loop below).
     if (wave == 0) {
@@ -674,19 +705,13 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
     if (it + 1 == I_full) break;
     const int u = sel / F, v = sel % F;
     // eq. (18): R_w[k,l] -= c * W[k-u, l-v] over the wave's bins, fused with
-    // |R_w|^2. Row (k-u) mod F of the wave's first bin is r0; the rows of its
-    // later bins follow consecutively (wrapped copies cover the overflow).
-    const int r0 = (wave * RPW - u) & (F - 1);
-    int wb[PH];
-#pragma unroll
-    for (int p = 0; p < PH; ++p) {
-      const int lr = F <= 64 ? lane / F : 0;
-      const int lc = F <= 64 ? lane % F : p * 64 + lane;
-      wb[p] = (r0 + lr) * F + ((lc - v) & (F - 1));
-    }
+    // |R_w|^2. Within a row group the rows of later slots follow the first
+    // one's row (k-u) mod F consecutively (wrapped copies cover the overflow).
+    int wb[GR][PH];
+    shifted_bases(u, v, wb);
 #pragma unroll
     for (int j = 0; j < BPL; ++j) {
-      const float2 w = Wd[wb[j % PH] + (j / PH) * 64 * PH];
+      const float2 w = Wd[wb[j / SPG][j % PH] + ((j % SPG) / PH) * 64 * PH];
       float rx = Rx[j], ry = Ry[j];
       rx = fmaf(-cre, w.x, rx);
       rx = fmaf(cim, w.y, rx);
@@ -698,15 +723,15 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
     }
     select();
   }
-  __syncthreads();
-  if (FUSED && warm) {
-    // the restricted phase's coefficients must be finite as well
-    for (int it = 0; it < a.ir; ++it) {
-      const float2 c = s.cl_c[it];
-      finite = finite && isfinite(c.x) && isfinite(c.y);
-    }
+  // every coefficient (restricted phase included) must be finite; checked
+  // once over the list instead of in every iteration (a NaN |R_w|^2 sorts
+  // above every finite value, so it is selected and its coefficient listed)
+  bool bad = false;
+  for (int it = t; it < tbase + I_full; it += NT) {
+    const float2 c = s.cl_c[it];
+    bad = bad || !isfinite(c.x) || !isfinite(c.y);
   }
-  if (!finite) return FSE_BLOCK_NONFINITE;
+  if (__syncthreads_or(bad)) return FSE_BLOCK_NONFINITE;
 
   // 4. model on B
   synthesize<F, NT, 1>(s.cl_idx, s.cl_c, tbase + I_full, s.tw, bh, bw, bo,
@@ -1873,7 +1898,9 @@ hipError_t scratch_address(int device, void** out) {
 size_t lds_bytes(const Variant& v, int iters_cap) {
   const size_t F = (size_t)v.F;
   const size_t nw = (size_t)v.threads / 64;
-  const size_t rows = F + F / nw - 1;
+  const size_t rpw = F / nw;
+  const size_t rpg = (F == 64 && rpw > 8) ? 8 : rpw;  // rows per group, as Shape<F, NT>::RPG
+  const size_t rows = F + rpg - 1;
   const size_t cap = (size_t)iters_cap;
   const size_t kc = v.mode == kWarmFused ? (size_t)v.kc : 0;  // as KCL in the kernel
   return rows * F * 8 + F * 8 + 2 * nw * 16 + (cap + kc) * 8 + (cap + kc) * 4 + 16;
