@@ -118,16 +118,17 @@ __device__ __forceinline__ float readlane_f(float x, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
 }
 
-// (u m + v n) mod F for the phase factor of pixel (m, n) and bin (u, v),
-// all below 2^8: two full-rate 24-bit multiplies (the compiler, seeing that
-// only the low bits are kept, would otherwise pick the quarter-rate 32-bit
-// multiply and a 64-bit multiply-add).
+// Byte offset 8 * ((u m + v n) mod F) of the phase factor of pixel (m, n)
+// and a wave-uniform bin (u, v) in a table of F float2, from m8 = 8 m and
+// n8 = 8 n: two full-rate 24-bit multiplies with u, v read from SGPRs (the
+// compiler, seeing that only the low bits are kept, would otherwise pick
+// the quarter-rate 32-bit multiply and a 64-bit multiply-add).
 template <int F>
-__device__ __forceinline__ uint32_t phase_index(uint32_t u, uint32_t v, uint32_t m, uint32_t n) {
+__device__ __forceinline__ uint32_t phase_byte(uint32_t u, uint32_t v, uint32_t m8, uint32_t n8) {
   uint32_t vn, r;
-  asm("v_mul_u32_u24 %0, %1, %2" : "=v"(vn) : "v"(v), "v"(n));
-  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(u), "v"(m), "v"(vn));
-  return r & (F - 1);
+  asm("v_mul_u32_u24 %0, %1, %2" : "=v"(vn) : "s"(v), "v"(n8));
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "s"(u), "v"(m8), "v"(vn));
+  return r & (8 * F - 1);
 }
 
 // Workgroup barrier that orders LDS accesses only: global loads issued
@@ -869,8 +870,8 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
   // the byte offset of W[(k-u) mod 64, (l-v) mod 64] (row pitch 512 B) is
   // ((y >> 3) & 0x7e00) | (y & 0x1f8); subtracting xa from
   // (64+u)*4096 + (64+v)*8 gives the mirrored bin the same way.
-  float Rx[CPL], Ry[CPL];
-  int xa[CPL];
+  fvec<CPL> Rx, Ry;
+  int __attribute__((ext_vector_type(CPL))) xa;
   unsigned mb[CPL];
 #pragma unroll
   for (int j = 0; j < CPL; ++j) {
@@ -901,15 +902,16 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
   const UBlock bd = uniform_block(a.blocks + bi);
   const int np = bd.bh * bd.bw;
   const bool inloop = np <= NT * QI;
-  int mq[QI], nq[QI];
+  int mq[QI], nq[QI];  // area position of the thread's pixels, times 8 (byte scale of the twiddle table)
   float acc[QI];
 #pragma unroll
   for (int q = 0; q < QI; ++q) {
     const int p = min(t + q * NT, np - 1);
-    mq[q] = bd.border + p / bd.bw;
-    nq[q] = bd.border + p % bd.bw;
+    mq[q] = 8 * (bd.border + p / bd.bw);
+    nq[q] = 8 * (bd.border + p % bd.bw);
     acc[q] = 0.f;
   }
+  const char* const twb = reinterpret_cast<const char*>(tw);
 
   bool finite = true;
   int parity = 0;
@@ -924,21 +926,20 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
     for (int j = 1; j < CPL; ++j) lm = max(lm, mb[j]);
     unsigned wm = wave_max_bits(lm);
     // the wave's lowest candidate holding its maximum: lowest lane, then j
-    float hre = 0.f, him = 0.f;
-    int hx = 0;
-    bool hit = false;
+    // (one lane mask per slot on the scalar unit)
+    unsigned long long hm[CPL], hits = 0;
 #pragma unroll
-    for (int j = CPL - 1; j >= 0; --j) {
-      const bool h = mb[j] == wm;
-      hre = h ? Rx[j] : hre;
-      him = h ? Ry[j] : him;
-      hx = h ? xa[j] : hx;
-      hit = hit || h;
+    for (int j = 0; j < CPL; ++j) {
+      hm[j] = __ballot(mb[j] == wm);
+      hits |= hm[j];
     }
-    const unsigned long long hits = __ballot(hit);
-    const int wl = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(hits));
-    float re = readlane_f(hre, wl), im = readlane_f(him, wl);
-    int x = __builtin_amdgcn_readlane(hx, wl);
+    const int wl = (int)__builtin_ctzll(hits);
+    int wj = CPL - 1;
+#pragma unroll
+    for (int j = CPL - 2; j >= 0; --j) wj = ((hm[j] >> wl) & 1) ? j : wj;
+    // wj is uniform: the slot is picked by relative register addressing
+    float re = readlane_f(Rx[wj], wl), im = readlane_f(Ry[wj], wl);
+    int x = __builtin_amdgcn_readlane(xa[wj], wl);
     if constexpr (NWB == 2) {
       // across the two waves: the larger value, wave 0 (the lower
       // candidates) on a tie; every component made uniform before selecting
@@ -963,7 +964,7 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
     if constexpr (kInloop) {
 #pragma unroll
       for (int q = 0; q < QI; ++q) {
-        const float2 e = tw[phase_index<F>(u, v, mq[q], nq[q])];  // as in synthesize: Re{c e^{j theta}} = c.x e.x + c.y e.y
+        const float2 e = *reinterpret_cast<const float2*>(twb + phase_byte<F>(u, v, mq[q], nq[q]));  // as in synthesize: Re{c e^{j theta}} = c.x e.x + c.y e.y
         acc[q] = fmaf(cre, e.x, acc[q]);
         acc[q] = fmaf(cim, e.y, acc[q]);
       }
@@ -1023,7 +1024,7 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
   if (inloop) {
 #pragma unroll
     for (int q = 0; q < QI; ++q)
-      if (t + q * NT < np) ob[(int64_t)(mq[q] - bd.border) * a.out_pitch + (nq[q] - bd.border)] = acc[q];
+      if (t + q * NT < np) ob[(int64_t)(mq[q] / 8 - bd.border) * a.out_pitch + (nq[q] / 8 - bd.border)] = acc[q];
   } else {
     __syncthreads();
     synthesize<F, NT, 4 / NWB>(cl_idx, cl_c, a.ir, tw, bd.bh, bd.bw, bd.border, ob, a.out_pitch, t);
