@@ -7,7 +7,11 @@ inputs resident in HBM. Two legs are timed, each over the same number of
 steps:
   plain  FSE with 100 iterations per block (persistent kernel);
   warm   the learned warm start: network inputs, forward pass, top-K
-         candidate bins, transform kernel, restricted iterations.
+         candidate bins, transform kernel, restricted iterations (K, their
+         count and step as chosen on validation frames);
+and, with the same K, count and step, two warm starts whose candidates are
+not learned (the initial spectrum's top K; the K lowest frequencies), which
+show what the network adds.
 PSNR over the lost pixels (against the undistorted frames) decides: the
 reported value is the warm start's blocks/s if it loses at most 0.1 dB
 against plain FSE, otherwise plain FSE's.
@@ -480,6 +484,9 @@ def main():
     ap.add_argument("--kc", type=int, default=None, help="warm start: candidate bins per block "
                                                            "(default: the packaged network's operating point)")
     ap.add_argument("--ir", type=int, default=None, help="warm start: restricted iterations (default: as --kc)")
+    ap.add_argument("--gamma-r", type=float, default=None, help="warm start: step of the restricted iterations "
+                                                               "(default: as --kc; <= 0: the plan's gamma)")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the warm start's non-learned candidate legs")
     ap.add_argument("--no-warm", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1024,
                     help="blocks timed on the FP64 oracle (about 20-30 s of CPU work; 3-D: at most 48 volumes)")
@@ -491,6 +498,10 @@ def main():
     from paper_2204_14193_amd import warm as _warm
     args.kc = _warm.KC if args.kc is None else args.kc
     args.ir = _warm.RESTRICTED_ITERS if args.ir is None else args.ir
+    if args.gamma_r is None:
+        args.gamma_r = _warm.RESTRICTED_GAMMA
+    elif args.gamma_r <= 0:
+        args.gamma_r = None
     if args.gpus != 1:
         print("this benchmark runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
@@ -514,7 +525,8 @@ def main():
         wl = workloads.random_1080p_16x16(seeds=tuple(range(99, 99 + args.frames)), iters=args.iters)
         desc = (f"{args.frames}x 1920x1080 synthetic frames, 804 isolated 16x16 losses per frame (10%), "
                 f"border 16 (48x48 area), 64x64 transform, rho 0.8, gamma 0.5; plain FSE {args.iters} iterations "
-                f"vs learned warm start (top-{args.kc} candidates, {args.ir} restricted iterations)")
+                f"vs learned warm start (top-{args.kc} candidates, {args.ir} restricted iterations, step "
+                f"{0.5 if args.gamma_r is None else args.gamma_r})")
     elif args.workload == "random-1080p-8x8":
         wl = workloads.random_1080p_8x8(iters=200)
         desc = ("1920x1080 synthetic frame, 3240 isolated 8x8 losses (10%), border 16 (40x40 area), "
@@ -582,7 +594,7 @@ def main():
         batch_w = fse.Batch(plan_w, wblocks, *wl.frames.shape)
         net = warm.Net(n, seed=0)
         net.load()
-        ws = warm.WarmStart(net, batch_w, args.kc, args.ir, args.iters)
+        ws = warm.WarmStart(net, batch_w, args.kc, args.ir, args.iters, args.gamma_r)
         run_warm = lambda: ws.run(img, av, out_w, status_w)
         for _ in range(args.warmup):
             run_warm()
@@ -602,10 +614,48 @@ def main():
                         "psnr_loss_db": legs["plain"]["psnr_db"] - p_w,
                         "meets_bar": legs["plain"]["psnr_db"] - p_w <= PSNR_BAR_DB,
                         "speedup_vs_plain": legs["plain"]["ms_per_step"] / ms_w, "fallbacks": fallbacks,
-                        "kc": args.kc, "restricted_iters": args.ir, "weights_sha": wsha,
+                        "kc": args.kc, "restricted_iters": args.ir,
+                        "restricted_step": wl.gamma if args.gamma_r is None else args.gamma_r, "weights_sha": wsha,
                         "kernels": {("fse_restricted<%d>" % args.kc if k == "restricted" else
                                      "fse_persistent<64,512,%d,prep>" % args.kc): {"ms": v[1], "launches": v[0]}
                                     for k, v in kw.items()}}
+        if not args.no_ablation:
+            # what the network adds: the same warm start (K, restricted
+            # iterations and step) with candidate sets that are not learned
+            from paper_2204_14193_amd import operating_point as op
+            cand = torch.empty_like(ws.cand)
+            flg = torch.zeros_like(ws.flags)
+            power = torch.empty((n, 4096), dtype=torch.float32, device=dev)
+            low = torch.from_numpy(np.tile(op.lowfreq_bins(args.kc), (n, 1))).to(dev)
+            props = {"spectrum": lambda: (warm.initial_power(batch_w, img, av, power),
+                                          warm.topk(power, args.kc, cand, flg)),
+                     "lowfreq": lambda: cand.copy_(low)}
+            for name, propose in props.items():
+                out_a = img.to(torch.float32)
+                run_a = lambda: (propose(), warm.warm_extrapolate(batch_w, img, av, out_a, status_w, cand, flg,
+                                                                  args.kc, args.ir, args.iters))
+                for _ in range(args.warmup):
+                    run_a()
+                ms_a, _ = time_steps(run_a, args.steps, stream)
+                assert (status_w.cpu().numpy() == fse.BLOCK_OK).all()
+                p_a = psnr_lost(wl.frames, out_a.cpu().numpy(), wl.avail)
+                legs["warm_" + name] = {
+                    "candidates": {"spectrum": "top-K of |DFT(s w)|^2 (the first selection's criterion)",
+                                   "lowfreq": "the K lowest frequencies, the same for every block"}[name],
+                    "blocks_per_s": n / (ms_a * 1e-3), "ms_per_step": ms_a, "psnr_db": p_a,
+                    "psnr_loss_db": legs["plain"]["psnr_db"] - p_a,
+                    "meets_bar": legs["plain"]["psnr_db"] - p_a <= PSNR_BAR_DB,
+                    "kc": args.kc, "restricted_iters": args.ir}
+        try:
+            with open(os.path.join(ROOT, "paper_2204_14193_amd", "weights", "operating_point.json")) as fh:
+                opj = json.load(fh)
+            legs["warm"]["operating_point"] = {
+                "chosen": opj["chosen"], "rule": opj["rule"], "loss_target_db": opj["loss_target_db"],
+                "validation_seeds": opj["validation_seeds"],
+                "validation_loss_db": opj["validation_best"]["loss_db"],
+                "is_default": (args.kc, args.ir) == (warm.KC, warm.RESTRICTED_ITERS)}
+        except (OSError, ValueError, KeyError):
+            pass
         n_pix = int(wl.blocks["bh"].astype(np.int64) @ wl.blocks["bw"].astype(np.int64))
         warm_roof = {"kernel": "fse_restricted<%d>" % args.kc,
                      "flop": n * args.ir * args.kc * FLOP_PER_BIN_ITER + n_pix * args.ir * FLOP_PER_PIXEL_COEF,

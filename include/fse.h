@@ -413,6 +413,25 @@ fse_status_t fse_warm_extrapolate_batch_noalloc(fse_batch_t batch, const uint8_t
  * candidates (0 when kc < 1 or kc > 512). Host only. */
 size_t fse_warm_noalloc_max_blocks(int32_t kc);
 
+/* Step of the warm start's restricted iterations: the gamma of eq. (13)
+ * used while the argmax and update run over the candidates (the full
+ * iterations after them and every fallback keep the plan's gamma). A value
+ * in (0, 1]; a negative value restores the plan's gamma (the default). Host
+ * state of the batch, read by later warm-started launches (a graph captured
+ * before the change keeps the old step). */
+fse_status_t fse_warm_set_restricted_gamma(fse_batch_t batch, float gamma_r);
+
+/* Squared magnitudes of the first transform, |R_w[k, l]|^2 = |DFT(s w)|^2
+ * (eq. (11), the criterion of eq. (12) before the first selection), for
+ * every block of a batch whose blocks all use F = 64: d_power [n_blocks][4096]
+ * FP32 in the caller's block order, bin k*64 + l; the same FP32 values the
+ * iterations compare. Candidate sets that do not come from the network (the
+ * top-K of this spectrum, fse_cnn_topk on d_power) serve as the comparison
+ * for the learned ones. Asynchronous on `stream`; errors as
+ * fse_warm_extrapolate_batch. */
+fse_status_t fse_initial_power(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail, int64_t pitch,
+                               float* d_power, void* stream);
+
 /* restricted_iters + max(largest block iteration count, fallback_iters). */
 int32_t fse_warm_trace_stride(fse_batch_t batch, int32_t restricted_iters, int32_t fallback_iters);
 

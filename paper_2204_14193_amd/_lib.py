@@ -68,6 +68,8 @@ SIGNATURES = {
     "fse_warm_extrapolate_batch": (I32, [P, P, P, I64, P, I64, P, P, P, P, I32, I32, I32, P]),
     "fse_warm_trace_stride": (I32, [P, I32, I32]),
     "fse_warm_prepare": (I32, [P, I32, I32, I32]),
+    "fse_initial_power": (I32, [P, P, P, I64, P, P]),
+    "fse_warm_set_restricted_gamma": (I32, [P, C.c_float]),
     "fse_warm_extrapolate_batch_noalloc": (I32, [P, P, P, I64, P, I64, P, P, P, P, I32, I32, I32, P]),
     "fse_warm_noalloc_max_blocks": (C.c_size_t, [I32]),
 }

@@ -75,6 +75,7 @@ struct fse_batch_s {
   } cls[3];
   Cls warm;                                // warm-started launch of the F = 64 class
   int32_t warm_kc = 0, warm_ir = -1, warm_fb = -1;
+  float warm_gamma = -1.f;                 // step of the restricted iterations; < 0: the plan's gamma
   bool warm_split = false;                 // transform kernel + restricted kernel
   size_t restricted_lds = 0;
   float2* d_stage_w = nullptr;             // split form's staging (caller's block order)
@@ -532,9 +533,11 @@ static fse_status_t launch_one(fse_batch_t batch, int ci, const uint8_t* d_image
     a.cand = cand;
     a.flags = flags;
     a.ir = warm ? batch->warm_ir : 0;
+    a.gamma_r = warm && batch->warm_gamma >= 0.f ? batch->warm_gamma : batch->plan->gamma;
     a.fb_iters = warm ? batch->warm_fb : 0;
     a.stage_w = nullptr;
     a.stage_r = nullptr;
+    a.power = nullptr;
     a.wtab_q = nullptr;
     a.twid_q = nullptr;
     a.gamma_q = 0;
@@ -811,6 +814,14 @@ extern "C" fse_status_t fse_warm_prepare(fse_batch_t batch, int32_t kc, int32_t 
   return st != FSE_OK ? st : warm_staging(batch);
 }
 
+extern "C" fse_status_t fse_warm_set_restricted_gamma(fse_batch_t batch, float gamma_r) {
+  if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
+  if (!(gamma_r < 0.f || (gamma_r > 0.f && gamma_r <= 1.f)))
+    return fail(FSE_ERR_INVALID_ARG, "the restricted step must lie in (0, 1], or be negative for the plan's gamma");
+  batch->warm_gamma = gamma_r < 0.f ? -1.f : gamma_r;
+  return FSE_OK;
+}
+
 extern "C" fse_status_t fse_warm_extrapolate_batch(fse_batch_t batch, const uint8_t* d_image,
                                                    const uint8_t* d_avail, int64_t pitch, float* d_out,
                                                    int64_t out_pitch, int32_t* d_status, fse_trace_t* d_trace,
@@ -826,6 +837,46 @@ extern "C" fse_status_t fse_warm_extrapolate_batch(fse_batch_t batch, const uint
   wr.stage_r = batch->d_stage_r;
   return launch_one(batch, class_of(64), d_image, d_avail, pitch, d_out, out_pitch, d_status, d_trace,
                     reinterpret_cast<hipStream_t>(stream), d_cand, d_flags, wr);
+}
+
+extern "C" fse_status_t fse_initial_power(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail,
+                                          int64_t pitch, float* d_power, void* stream) {
+  if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
+  if (batch->plan->flags & (FSE_PLAN_MASKED_B | FSE_PLAN_REAL | FSE_PLAN_FIXED))
+    return fail(FSE_ERR_UNSUPPORTED, "the initial spectrum needs a cFSE plan with rectangular loss areas");
+  if (batch->n == 0) return FSE_OK;
+  if (!d_image || !d_avail || !d_power) return fail(FSE_ERR_INVALID_ARG, "null device pointer");
+  if (pitch < batch->W) return fail(FSE_ERR_INVALID_ARG, "pitch smaller than the width");
+  const int ci = class_of(64);
+  if (batch->cls[ci].count != batch->n) return fail(FSE_ERR_UNSUPPORTED, "the initial spectrum needs F = 64 blocks only");
+  if ((int64_t)batch->H * pitch >= ((int64_t)1 << 31))
+    return fail(FSE_ERR_INVALID_ARG, "a frame (H x pitch bytes) must be smaller than 2 GiB");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != batch->device)
+    return fail(FSE_ERR_INVALID_ARG, "batch was created on another device");
+  const fse::Variant* v = fse::power_variant_for(64);
+  if (!v) return fail(FSE_ERR_UNSUPPORTED, "no power-spectrum kernel");
+  fse_batch_s::Cls c = batch->cls[ci];
+  c.iters_cap = 0;
+  fse_status_t st = configure(batch, c, v);
+  if (st != FSE_OK) return st;
+  fse::ClassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.img = d_image;
+  a.avail = d_avail;
+  a.pitch = pitch;
+  a.H = batch->H;
+  a.W = batch->W;
+  a.blocks = batch->d_blocks + c.offset;
+  a.orig = batch->d_orig + c.offset;
+  a.n = c.count;
+  a.wtab = batch->tables->wtab;
+  a.twid = batch->tables->twid[ci];
+  a.gamma = batch->plan->gamma;
+  a.power = d_power;
+  if (fse::launch_class(*v, a, c.grid, c.lds, reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+    return fail(FSE_ERR_HIP, "kernel launch failed (initial spectrum)");
+  return FSE_OK;
 }
 
 extern "C" size_t fse_warm_noalloc_max_blocks(int32_t kc) {

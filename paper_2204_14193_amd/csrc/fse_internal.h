@@ -39,12 +39,14 @@ struct ClassArgs {
   const int16_t* cand;        // [caller's n_blocks][kc] candidate bins, ascending
   const int32_t* flags;       // [caller's n_blocks]: nonzero = run plain FSE
   int32_t ir;                 // restricted iterations
+  float gamma_r;              // step of the restricted iterations (gamma of eq. (13) there)
   int32_t fb_iters;           // full iterations of a block that falls back
   // split warm-started form: staging written by the transform kernel and
   // read by the restricted kernel, indexed by the block's position in this
   // launch's list (blocks[0 .. n))
   float2* stage_w;            // [n][kHalfRows * 64]: W rows 0..32
   float2* stage_r;            // [n][kc]: R_w at the candidates
+  float* power;               // kPower mode: [caller's n_blocks][F * F] |R_w|^2 of the first transform
   // fixed-point form only (plan flag FSE_PLAN_FIXED)
   const int32_t* wtab_q;      // round(2^15 rho^(sqrt(a^2 + b^2) / 2)), [kWinStride][kWinStride]
   const int2* twid_q;         // round(2^14 exp(-j 2 pi q / 64)), 64 entries
@@ -110,7 +112,9 @@ int fixed_threads();
 hipError_t launch_fixed(const ClassArgs& a, int grid, size_t lds, hipStream_t s);
 
 // Kernel modes.
-enum Mode : int { kPlain = 0, kWarmFused = 1, kWarmPrep = 2 };
+// kPower: transform only, |R_w|^2 of every bin written out (candidate sets
+// taken from the initial spectrum).
+enum Mode : int { kPlain = 0, kWarmFused = 1, kWarmPrep = 2, kPower = 3 };
 
 // One compiled kernel variant for transform size F.
 struct Variant {
@@ -127,6 +131,9 @@ const Variant* variant_for(int F);
 // Warm-started variant for F with kc candidates per block in the given mode
 // (kWarmFused or kWarmPrep), or null.
 const Variant* warm_variant_for(int F, int kc, int mode);
+
+// Transform-only variant writing |R_w|^2 (mode kPower), or null.
+const Variant* power_variant_for(int F);
 
 // Restricted kernel of the split warm start (F = 64, one workgroup per
 // block of the class, grid = class size): null if kc is not compiled.

@@ -361,7 +361,8 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
   constexpr int CPL = KC > 0 ? KC / 64 : 1;  // candidates per lane of wave 0
   constexpr bool FUSED = MODE == kWarmFused;
   static_assert(KC % 64 == 0 && KC <= 1024, "candidate count must be a multiple of 64");
-  static_assert((MODE == kPlain) == (KC == 0), "warm modes need candidates");
+  static_assert((MODE == kPlain || MODE == kPower) == (KC == 0), "warm modes need candidates");
+  static_assert(MODE != kPower || F == 64, "the power spectrum is compiled for F = 64");
   static_assert(MODE != kWarmPrep || F == 64, "the split warm start is compiled for F = 64");
   const int lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -439,6 +440,20 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
   fft_lines<F, NT, false>(Wd, s.tw, t);
   fft_lines<F, NT, true>(Wd, s.tw, t);
 
+  if constexpr (MODE == kPower) {
+    // |R_w|^2 of every bin, split and squared as the iterations below do
+    float* pw = a.power + (int64_t)orig * (F * F);
+    for (int e = t; e < F * F; e += NT) {
+      const int k = e / F, l = e % F;
+      const float2 zk = Wd[e];
+      const float2 zn = Wd[((F - k) & (F - 1)) * F + ((F - l) & (F - 1))];
+      const float rx = (zk.x + zn.x) * 0.5f, ry = (zk.y - zn.y) * 0.5f;
+      pw[e] = fmaf(ry, ry, rx * rx);
+    }
+    lds_barrier();  // Wd is overwritten by the next block
+    return kPending;
+  }
+
   // Warm start: wave 0 takes R_w at its candidate bins straight from the
   // transform (same arithmetic as the split below, so the values are the
   // bits the split produces for those bins). A block whose network output
@@ -509,6 +524,7 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
 
   if (!(W0 > 0.f)) return FSE_BLOCK_EMPTY_SUPPORT;  // no received pixel in the area
   const float gW = a.gamma * (1.0f / W0);
+  const float gWr = a.gamma_r * (1.0f / W0);
 
   // 3. iterations. |R_w|^2 is kept as its bit pattern: for values >= 0 the
   // unsigned order of the bits is the order of the values, so the argmax
@@ -554,7 +570,7 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
               im = readlane_f(cRy[j], wl);
             }
           }
-          const float cre = gW * re, cim = gW * im;      // eq. (13)
+          const float cre = gWr * re, cim = gWr * im;    // eq. (13) with the restricted step
           s.cl_idx[it] = bin;                             // uniform stores
           s.cl_c[it] = make_float2(cre, cim);
           if (a.trace) {
@@ -745,7 +761,7 @@ template <int F, int NT, int KC, int MODE>
 // The transform kernel of the split warm start is held to 64 registers: with
 // its LDS (38 KB without the fused form's lists) four 512-thread workgroups
 // then share a compute unit.
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MODE == kWarmPrep ? 8 : 1))) void fse_persistent(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MODE >= kWarmPrep ? 8 : 1))) void fse_persistent(
     ClassArgs a) {
   using S = Shape<F, NT>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -774,7 +790,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MODE == kWar
   // let the other lanes run ahead into the next pass.)
   const int lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
-  if constexpr (MODE == kWarmPrep) {
+  if constexpr (MODE == kWarmPrep || MODE == kPower) {
     // The transform kernel of the split warm start costs the same for every
     // block: workgroup g takes blocks g, g + grid, ... without the queue,
     // whose single counter, contended by every workgroup, cost more per
@@ -891,7 +907,7 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
     if (wave == 0) a.status[orig] = FSE_BLOCK_EMPTY_SUPPORT;
     return;
   }
-  const float gW = a.gamma * (1.0f / W0);
+  const float gW = a.gamma_r * (1.0f / W0);  // the restricted step
 
   // The model on B (as in the persistent kernel) is accumulated inside the
   // loop when the block has at most NT*QI pixels (QI per thread), in the
@@ -1048,6 +1064,7 @@ const Variant kVariants[] = {
     make_variant<64, 256, 512, kWarmFused>(),
     make_variant<64, 512, 256, kWarmPrep>(), make_variant<64, 512, 128, kWarmPrep>(),
     make_variant<64, 512, 512, kWarmPrep>(), make_variant<64, 512, 384, kWarmPrep>(),
+    make_variant<64, 512, 0, kPower>(),
 };
 
 
@@ -1825,7 +1842,13 @@ __global__ __launch_bounds__(kFixedNT) void fse_fixed64(ClassArgs a) {
 
 const Variant* variant_for(int F) {
   for (const Variant& v : kVariants)
-    if (v.F == F && v.kc == 0) return &v;
+    if (v.F == F && v.kc == 0 && v.mode == kPlain) return &v;
+  return nullptr;
+}
+
+const Variant* power_variant_for(int F) {
+  for (const Variant& v : kVariants)
+    if (v.F == F && v.mode == kPower) return &v;
   return nullptr;
 }
 
@@ -1838,7 +1861,7 @@ const Variant* warm_variant_for(int F, int kc, int mode) {
 int variants_for(int F, const Variant** out, int cap) {
   int n = 0;
   for (const Variant& v : kVariants)
-    if (v.F == F && v.kc == 0) {
+    if (v.F == F && v.kc == 0 && v.mode == kPlain) {
       if (n < cap) out[n] = &v;
       ++n;
     }

@@ -12,10 +12,13 @@ from . import _lib
 from .fse import _check
 
 N_BINS = 4096
-# Operating point of the packaged network: candidate bins per block and
-# restricted iterations (chosen on validation frames, see the training report)
+# Operating point of the packaged network: candidate bins per block,
+# restricted iterations and their step, the fastest setting within 0.05 dB
+# of plain FSE-100 on validation frames (seeds 5000-5007; the sweep is in
+# weights/operating_point.json, written by paper_2204_14193_amd.operating_point)
 KC = 256
-RESTRICTED_ITERS = 110
+RESTRICTED_ITERS = 60
+RESTRICTED_GAMMA = 1.0       # None: the plan's gamma
 PATCH = (48, 48, 2)
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "warm_cnn.npz")
 
@@ -102,6 +105,13 @@ def patches(batch, image, avail, x, stream=None):
                                       _stream(stream)), "fse_cnn_patches")
 
 
+def initial_power(batch, image, avail, power, stream=None):
+    """|DFT(s w)|^2 of every bin of every block of `batch` into power
+    (CUDA float32 [n, 4096]): candidate sets from the initial spectrum."""
+    _check(_lib.lib().fse_initial_power(batch._h, _ptr(image), _ptr(avail), image.stride(1), _ptr(power),
+                                        _stream(stream)), "fse_initial_power")
+
+
 def topk(logits, K, cand, flags, stream=None):
     _check(_lib.lib().fse_cnn_topk(_ptr(logits), int(logits.shape[0]), int(K), _ptr(cand), _ptr(flags),
                                    _stream(stream)), "fse_cnn_topk")
@@ -116,6 +126,12 @@ def warm_prepare(batch, kc, restricted_iters, fallback_iters):
     allocating step; later warm launches with the same counts allocate nothing)."""
     _check(_lib.lib().fse_warm_prepare(batch._h, int(kc), int(restricted_iters), int(fallback_iters)),
            "fse_warm_prepare")
+
+
+def set_restricted_gamma(batch, gamma_r):
+    """Step of the restricted iterations (None: the plan's gamma)."""
+    _check(_lib.lib().fse_warm_set_restricted_gamma(batch._h, -1.0 if gamma_r is None else float(gamma_r)),
+           "fse_warm_set_restricted_gamma")
 
 
 def warm_extrapolate(batch, image, avail, out, status, cand, flags, kc, restricted_iters, fallback_iters,
@@ -150,9 +166,11 @@ class WarmStart:
     warm start's staging are allocated here; run() only launches kernels (it
     may be captured into a HIP graph from its first call on)."""
 
-    def __init__(self, net, batch, kc=KC, restricted_iters=RESTRICTED_ITERS, fallback_iters=100):
+    def __init__(self, net, batch, kc=KC, restricted_iters=RESTRICTED_ITERS, fallback_iters=100,
+                 restricted_gamma=RESTRICTED_GAMMA):
         import torch
         self.net, self.batch = net, batch
+        self.gamma_r = restricted_gamma
         self.kc, self.ir, self.fb = int(kc), int(restricted_iters), int(fallback_iters)
         n = batch.n
         dev = torch.device("cuda")
@@ -160,6 +178,7 @@ class WarmStart:
         self.cand = torch.empty((n, self.kc), dtype=torch.int16, device=dev)
         self.flags = torch.empty((n,), dtype=torch.int32, device=dev)
         warm_prepare(batch, self.kc, self.ir, self.fb)
+        set_restricted_gamma(batch, restricted_gamma)
 
     def run(self, image, avail, out, status, trace=None, stream=None):
         self.net.forward_blocks(self.batch, image, avail, self.logits, stream)

@@ -135,10 +135,11 @@ def warm_psnr_delta(frames, avail, blocks, cands, rho, gamma, ir, out_gpu, proce
     return abs(p_gpu - p_orc), p_gpu, p_orc
 
 
-def replay_warm_block(frames, avail, blk, rho, gamma, trace_row, cand_bins, ir, iters):
-    """Warm-started block: the restricted phase is replayed with the argmax
-    limited to the candidate bins, then the full phase from the oracle's own
-    restricted model. Returns the same figures as replay_block, per phase."""
+def replay_warm_block(frames, avail, blk, rho, gamma, trace_row, cand_bins, ir, iters, gamma_r=None):
+    """Warm-started block: the restricted phase (step gamma_r, default gamma)
+    is replayed with the argmax limited to the candidate bins, then the full
+    phase from the oracle's own restricted model. Returns the same figures as
+    replay_block, per phase."""
     F = int(blk["fft"])
     s, A, B = cfse.area_of_block(frames, avail, blk)
     w = cfse.weighting(*s.shape, rho, A)
@@ -147,7 +148,7 @@ def replay_warm_block(frames, avail, blk, rho, gamma, trace_row, cand_bins, ir, 
     cand = cand.reshape(F, F)
     out = {}
     seq_r, c_r = gpu_sequence(trace_row, F, ir)
-    r1 = cfse.cfse(s, w, F, gamma, ir, forced=seq_r, cand=cand)
+    r1 = cfse.cfse(s, w, F, gamma if gamma_r is None else gamma_r, ir, forced=seq_r, cand=cand)
     seq_f, c_f = gpu_sequence(trace_row[ir:], F, iters)
     r2 = cfse.cfse(s, w, F, gamma, iters, forced=seq_f, init=dict(r1["coefs"]))
     for name, seq, c, res in (("restricted", seq_r, c_r, r1), ("full", seq_f, c_f, r2)):
