@@ -652,6 +652,10 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
   // linear index grows with (slot j, lane), so the wave's winner is the
   // lowest slot, then the lowest lane, holding the wave maximum.
   auto select = [&]() {
+    // The argmax is the serial part of an iteration, and the other waves of
+    // the block wait for it at the barrier below: its instructions go ahead
+    // of the update streams of the compute unit's other blocks.
+    __builtin_amdgcn_s_setprio(3);
     unsigned lm = mb[0];
 #pragma unroll
     for (int j = 1; j < BPL; ++j) lm = max(lm, mb[j]);
@@ -699,6 +703,7 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
       sim = __int_as_float(__builtin_amdgcn_readlane(o.w, ww));
       parity ^= 1;
     }
+    __builtin_amdgcn_s_setprio(0);
   };
   if (I_full > 0) select();
 
