@@ -114,9 +114,57 @@ def _init_worker():
 
 def _oracle_block(args):
     from oracle import cfse
-    frames, avail, blk, rho, gamma, masked = args
-    cfse.extrapolate_block(frames, avail, blk, rho, gamma, masked=masked)
-    return 1
+    frames, avail, blk, rho, gamma, masked = args[:6]
+    cand = args[6] if len(args) > 6 else None
+    iters = args[7] if len(args) > 7 else None
+    if cand is not None:
+        F = int(blk["fft"])
+        mask = np.zeros(F * F, dtype=bool)
+        mask[np.asarray(cand, dtype=np.int64)] = True
+        cand = mask.reshape(F, F)
+    res = cfse.extrapolate_block(frames, avail, blk, rho, gamma, masked=masked, cand=cand, iters=iters)
+    return None if res is None else (res["values"], res["lost"])
+
+
+def fp32_error(wl, blocks, vals, out_gpu):
+    """The GPU's FP32 result against the FP64 oracle's on the given blocks:
+    largest pixel difference on B and PSNR over the blocks' lost pixels
+    (each against the undistorted frames)."""
+    ref, g, o, worst = [], [], [], 0.0
+    for b, v in zip(blocks, vals):
+        if v is None:
+            continue
+        f, y0, x0 = int(b["frame"]), int(b["y0"]), int(b["x0"])
+        sl = (f, slice(y0, y0 + int(b["bh"])), slice(x0, x0 + int(b["bw"])))
+        lost = v[1]
+        gv = out_gpu[sl].astype(np.float64)[lost]
+        ref.append(wl.frames[sl].astype(np.float64)[lost])
+        g.append(gv)
+        o.append(v[0][lost])
+        worst = max(worst, float(np.abs(gv - v[0][lost]).max()))
+    ref, g, o = np.concatenate(ref), np.concatenate(g), np.concatenate(o)
+    lost = np.zeros(ref.shape, dtype=np.uint8)
+    pg, po = psnr_lost(ref, g, lost), psnr_lost(ref, o, lost)
+    return {"blocks": len(blocks), "max_abs_pixel_diff": worst, "psnr_gpu_db": pg, "psnr_oracle_db": po,
+            "psnr_delta_db": pg - po}
+
+
+def warm_error(wl, out_gpu, cand, args, n_sample=256, seed=6):
+    """The warm leg's FP32 result against the FP64 oracle running the same
+    restricted iterations (the GPU's candidates, count and step) on a
+    seeded sample of blocks."""
+    import multiprocessing as mp
+    idx = np.sort(np.random.default_rng(seed).choice(len(wl.blocks), min(n_sample, len(wl.blocks)), replace=False))
+    g = wl.gamma if args.gamma_r is None else args.gamma_r
+    jobs = []
+    for i in idx:
+        b = wl.blocks[i].copy()
+        f = int(b["frame"])
+        b["frame"] = 0
+        jobs.append((wl.frames[f:f + 1], wl.avail[f:f + 1], b, wl.rho, g, False, cand[i], args.ir))
+    with mp.get_context("fork").Pool(len(os.sched_getaffinity(0)), initializer=_init_worker) as pool:
+        vals = pool.map(_oracle_block, jobs, chunksize=1)
+    return fp32_error(wl, wl.blocks[idx], vals, out_gpu)
 
 
 def _spectral_block(args):
@@ -129,9 +177,10 @@ def _spectral_block(args):
     return 1
 
 
-def cpu_baseline(wl, n_sample, seed=5, masked=False):
+def cpu_baseline(wl, n_sample, seed=5, masked=False, out_gpu=None):
     """FP64 oracle, as it stands, over a seeded sample of the workload's
-    blocks, one process per host core."""
+    blocks, one process per host core; with the GPU's output, the FP32
+    error against the oracle on the same blocks."""
     import multiprocessing as mp
     cores = len(os.sched_getaffinity(0))
     idx = np.sort(np.random.default_rng(seed).choice(len(wl.blocks), n_sample, replace=False))
@@ -145,7 +194,7 @@ def cpu_baseline(wl, n_sample, seed=5, masked=False):
     with mp.get_context("fork").Pool(cores, initializer=_init_worker) as pool:
         pool.map(_oracle_block, jobs[:cores])            # warm the workers
         t0 = time.perf_counter()
-        pool.map(_oracle_block, jobs, chunksize=1)
+        vals = pool.map(_oracle_block, jobs, chunksize=1)
         dt = time.perf_counter() - t0
         # the method in its frequency-domain form (FFTs and the spectral
         # update, FP64): the fair CPU speed reference, timed the same way
@@ -159,9 +208,10 @@ def cpu_baseline(wl, n_sample, seed=5, masked=False):
             cpu = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
     except Exception:
         pass
+    err = {} if out_gpu is None else {"fp32_error": fp32_error(wl, wl.blocks[idx], vals, out_gpu)}
     return {"value": n_sample / dt, "unit": "blocks/s", "cores": cores, "kind": "oracle",
             "sample": f"{n_sample} seeded blocks of the same workload (FP64 direct projection, "
-                      f"{int(wl.blocks[idx[0]]['iters'])} iterations each), {dt:.1f} s wall on {cpu}",
+                      f"{int(wl.blocks[idx[0]]['iters'])} iterations each), {dt:.1f} s wall on {cpu}", **err,
             "fft_form": {"value": n_sample / dt_fft, "unit": "blocks/s", "cores": cores,
                          "kind": "FP64 frequency-domain form (oracle.spectral: FFTs, eq. (18) update)",
                          "seconds": dt_fft}}
@@ -592,9 +642,10 @@ def main():
     ms, ev_ms = time_steps(run_plain, args.steps, stream)
     assert (status.cpu().numpy() == fse.BLOCK_OK).all()
     bin_iters = int(np.sum(wl.blocks["fft"].astype(np.int64) ** 2 * wl.blocks["iters"].astype(np.int64)))
+    out_plain = out.cpu().numpy()
     legs["plain"] = {"blocks_per_s": n / (ms * 1e-3), "ms_per_step": ms, "event_ms": ev_ms,
                      "instrumented_ms_per_step": ms_ins,
-                     "psnr_db": psnr_lost(wl.frames, out.cpu().numpy(), wl.avail),
+                     "psnr_db": psnr_lost(wl.frames, out_plain, wl.avail),
                      "kernels": {f"fse_persistent<{F},{info[F]['threads']}>": {"ms": kern[("plain", F)][1], **info[F]}
                                  for F in classes},
                      "autotune_us": {f"{F}/{t}": round(us, 1) for F, t, us in tuning}}
@@ -629,7 +680,9 @@ def main():
         ms_w, ev_w = time_steps(run_warm, args.steps, stream)
         assert (status_w.cpu().numpy() == fse.BLOCK_OK).all()
         fallbacks = int(ws.flags.sum().item())
-        p_w = psnr_lost(wl.frames, out_w.cpu().numpy(), wl.avail)
+        out_warm = out_w.cpu().numpy()
+        warm_cand = ws.cand.cpu().numpy()
+        p_w = psnr_lost(wl.frames, out_warm, wl.avail)
         with open(warm.WEIGHTS, "rb") as fh:
             wsha = hashlib.sha256(fh.read()).hexdigest()[:16]
         legs["warm"] = {"blocks_per_s": n / (ms_w * 1e-3), "ms_per_step": ms_w, "event_ms": ev_w,
@@ -726,7 +779,9 @@ def main():
                                        "R_w stays in registers"}
     copy_calibration(args, rec, dev)
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, n), masked=masked)
+        rec["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, n), masked=masked, out_gpu=out_plain)
+        if use_warm:
+            rec["cpu_baseline"]["warm_fp32_error"] = warm_error(wl, out_warm, warm_cand, args)
     print(json.dumps(rec), flush=True)
 
 
