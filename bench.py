@@ -405,11 +405,12 @@ def bench_real(args):
 
     sweep = {}
     for nbf in (50, 100, 200):
-        c, r, ri = leg(nbf, False), leg(nbf // 2, True), leg(nbf // 2, "inloop")
-        sweep[str(nbf)] = {"cfse": c, "rfse": r, "rfse_inloop": ri,
+        c, r, ri, rp = leg(nbf, False), leg(nbf // 2, True), leg(nbf // 2, "inloop"), leg(nbf // 2, "power")
+        sweep[str(nbf)] = {"cfse": c, "rfse": r, "rfse_inloop": ri, "rfse_power": rp,
                            "rfse_over_cfse_time": r["ms_per_step"] / c["ms_per_step"],
                            "rfse_inloop_over_cfse_time": ri["ms_per_step"] / c["ms_per_step"],
-                           "psnr_rfse_minus_cfse_db": r["psnr_db"] - c["psnr_db"]}
+                           "psnr_rfse_minus_cfse_db": r["psnr_db"] - c["psnr_db"],
+                           "psnr_rfse_power_minus_cfse_db": rp["psnr_db"] - c["psnr_db"]}
     main_leg = sweep["100"]["rfse"]
     # 2112 half-plane bins per iteration: the pair update (8 FMA) and the
     # energy decrease (7 FLOP); 4 FLOP per pixel and iteration for the model

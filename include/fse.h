@@ -113,13 +113,14 @@ typedef struct {
 
 /* Plan flag: real-valued FSE (rFSE, the model of eq. (2), Section II)
  * instead of cFSE. Every iteration adds a basis function and its complex
- * conjugate; the pair is the weighted least-squares fit of the residual on
+ * conjugate: the pair is the weighted least-squares fit of the residual on
  * the real span of phi_(k,l) and phi_(-k,-l), selected by the largest
  * decrease of the weighted residual energy and scaled by gamma. Blocks
  * must use fft = 64; the plan cannot be combined with FSE_PLAN_MASKED_B;
  * the warm start and the 3-D path refuse it. Trace records name the
  * pair's lower-index bin and its coefficient c (model increment
- * Re{c phi*}); r2 is the energy decrease. */
+ * Re{c phi*}); r2 is the selection criterion (the decrease, or |R_w|^2
+ * with FSE_PLAN_REAL_POWER). */
 #define FSE_PLAN_REAL 2u
 
 /* Modifier of FSE_PLAN_REAL (invalid without it): the pair constants,
@@ -128,6 +129,12 @@ typedef struct {
  * the paper's runtime comparison describes (Section II). Same results up
  * to FP32 rounding. */
 #define FSE_PLAN_REAL_INLOOP 8u
+
+/* Modifier of FSE_PLAN_REAL (invalid without it, exclusive with
+ * FSE_PLAN_REAL_INLOOP): the other reading of rFSE's selection, the pair
+ * holding the bin of largest |R_w|^2 (the criterion of eq. (12)), with the
+ * same least-squares estimate. */
+#define FSE_PLAN_REAL_POWER 16u
 
 /* Plan flag: fixed-point cFSE (the integer form the paper's conclusion
  * argues for: the loop has no division). Every value is an integer with a

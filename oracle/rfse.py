@@ -22,6 +22,17 @@ which is not available. This module derives them from eq. (2) alone
 * its coefficient is scaled by gamma (the compensation of eq. (13)) and
   the real model is subtracted from the residual in the spatial domain.
 
+Two selection rules are implemented (``selection``):
+* "decrease" (the kept reading): the pair with the largest decrease of the
+  weighted residual energy under its least-squares fit (per-bin divisions,
+  the cost Section II attributes to rFSE's selection);
+* "power" (the other reading): the pair holding the bin of largest
+  |R_w[k,l]|^2, the criterion of eq. (12), with the same least-squares
+  estimate. Neither reproduces Section IV's "rFSE slightly above cFSE" on
+  the synthetic frames at the paper's gamma = 0.2 (both are 0.1-0.7 dB
+  below cFSE at equal numbers of basis functions); "decrease" is closer
+  there.
+
 Closed forms (P = R_w[k,l] = sum w r phi*, W0 = sum w, Q = W[2k, 2l] =
 sum w phi*^2, D = W0^2 - |Q|^2):
   c = 2 (W0 P* - Q* P) / D,  decrease = Re{c P} = 2 (W0 |P|^2 - Re{Q* P^2}) / D;
@@ -68,11 +79,16 @@ def pair_fit(P, W0, Q, sc):
     return c, dec
 
 
-def rfse(s, w, F, gamma, iters, offset=(0, 0), forced=None):
+def rfse(s, w, F, gamma, iters, offset=(0, 0), forced=None, selection="decrease"):
     """rFSE on one M x N area (s: signal, 0 where unknown; w: eq. (3)
     weights). Returns dict(seq, chat, free, short, gap, energy, coefs, g):
     seq the selected lower-index bins, chat their coefficients c (model
-    increment Re{c phi*}), g the real model on the area."""
+    increment Re{c phi*}), g the real model on the area. ``selection``:
+    "power" (largest |R_w|^2) or "decrease" (largest least-squares energy
+    decrease, the default); short and gap are in |R_w| or in decrease
+    accordingly."""
+    if selection not in ("power", "decrease"):
+        raise ValueError("selection must be 'power' or 'decrease'")
     M, N = s.shape
     if F < M or F < N:
         raise ValueError("transform smaller than the area")
@@ -91,14 +107,19 @@ def rfse(s, w, F, gamma, iters, offset=(0, 0), forced=None):
         P = c2.project((w * r).astype(np.complex128), EM, EN)     # R_w, eq. (7)
         c, dec = pair_fit(P, W0, Q, sc)
         dec = np.maximum(dec.real, 0.0)
-        free = c2.select(dec)
+        if selection == "power":
+            free = c2.select(np.abs(P) ** 2)
+            crit = np.abs(P)
+        else:
+            free = c2.select(dec)
+            crit = dec
         idx = free if forced is None else int(forced[nu])
-        ref = dec.ravel()[free]
+        ref = crit.ravel()[free]
         out["free"].append(free)
-        out["short"].append(float((ref - dec.ravel()[idx]) / ref) if ref > 0 else 0.0)
-        # the partner of the best bin has the same decrease: the gap is to
+        out["short"].append(float((ref - crit.ravel()[idx]) / ref) if ref > 0 else 0.0)
+        # the partner of the best bin has the same criterion: the gap is to
         # the best bin of another pair
-        others = dec.ravel().copy()
+        others = crit.ravel().copy()
         others[[free, pair_index(F, free)]] = -1.0
         out["gap"].append(float((ref - others.max()) / ref) if ref > 0 else 0.0)
         u, vv = divmod(idx, F)
@@ -114,7 +135,7 @@ def rfse(s, w, F, gamma, iters, offset=(0, 0), forced=None):
     return out
 
 
-def extrapolate_block(frames, avail, blk, rho, gamma, forced=None, iters=None):
+def extrapolate_block(frames, avail, blk, rho, gamma, forced=None, iters=None, selection="decrease"):
     """rFSE for one block descriptor; the run dict plus 'values' = g on
     the block's rectangle, or None when the block has no support."""
     s, A, B = c2.area_of_block(frames, avail, blk)
@@ -123,7 +144,7 @@ def extrapolate_block(frames, avail, blk, rho, gamma, forced=None, iters=None):
     if w.sum() == 0:
         return None
     I = int(blk["iters"]) if iters is None else iters
-    res = rfse(s, w, int(blk["fft"]), gamma, I, forced=forced)
+    res = rfse(s, w, int(blk["fft"]), gamma, I, forced=forced, selection=selection)
     bd, bh, bw = int(blk["border"]), int(blk["bh"]), int(blk["bw"])
     res["values"] = res["g"][bd:bd + bh, bd:bd + bw].copy()
     return res

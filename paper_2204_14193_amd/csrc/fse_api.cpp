@@ -35,6 +35,11 @@ namespace {
 
 constexpr int kSizes[3] = {128, 64, 32};  // class order: longest blocks first
 
+int real_sel(uint32_t flags) {
+  return (flags & FSE_PLAN_REAL_INLOOP) ? fse::kRealInloop : (flags & FSE_PLAN_REAL_POWER) ? fse::kRealPower
+                                                                                        : fse::kRealDecrease;
+}
+
 int class_of(int F) {
   for (int c = 0; c < 3; ++c)
     if (kSizes[c] == F) return c;
@@ -103,11 +108,14 @@ extern "C" fse_status_t fse_plan_create(const fse_plan_desc_t* desc, fse_plan_t*
   if (!(desc->gamma >= 0.f && desc->gamma <= 1.f)) return fail(FSE_ERR_INVALID_ARG, "gamma must lie in [0, 1]");
   if (desc->max_iters < 0 || desc->max_iters > fse::kMaxIters)
     return fail(FSE_ERR_INVALID_ARG, "max_iters must lie in [0, 4096]");
-  if ((desc->flags & ~(uint32_t)(FSE_PLAN_MASKED_B | FSE_PLAN_REAL | FSE_PLAN_FIXED | FSE_PLAN_REAL_INLOOP)) != 0)
+  if ((desc->flags & ~(uint32_t)(FSE_PLAN_MASKED_B | FSE_PLAN_REAL | FSE_PLAN_FIXED | FSE_PLAN_REAL_INLOOP |
+                                  FSE_PLAN_REAL_POWER)) != 0)
     return fail(FSE_ERR_INVALID_ARG, "unknown plan flag");
-  if ((desc->flags & FSE_PLAN_REAL_INLOOP) && !(desc->flags & FSE_PLAN_REAL))
-    return fail(FSE_ERR_INVALID_ARG, "FSE_PLAN_REAL_INLOOP modifies FSE_PLAN_REAL");
-  if (__builtin_popcount(desc->flags & ~(uint32_t)FSE_PLAN_REAL_INLOOP) > 1)
+  if ((desc->flags & (FSE_PLAN_REAL_INLOOP | FSE_PLAN_REAL_POWER)) && !(desc->flags & FSE_PLAN_REAL))
+    return fail(FSE_ERR_INVALID_ARG, "FSE_PLAN_REAL_INLOOP and FSE_PLAN_REAL_POWER modify FSE_PLAN_REAL");
+  if ((desc->flags & FSE_PLAN_REAL_INLOOP) && (desc->flags & FSE_PLAN_REAL_POWER))
+    return fail(FSE_ERR_INVALID_ARG, "FSE_PLAN_REAL_INLOOP and FSE_PLAN_REAL_POWER exclude each other");
+  if (__builtin_popcount(desc->flags & ~(uint32_t)(FSE_PLAN_REAL_INLOOP | FSE_PLAN_REAL_POWER)) > 1)
     return fail(FSE_ERR_UNSUPPORTED, "FSE_PLAN_MASKED_B, FSE_PLAN_REAL and FSE_PLAN_FIXED exclude each other");
   fse_plan_s* p = new (std::nothrow) fse_plan_s;
   if (!p) return fail(FSE_ERR_OOM, "host allocation failed");
@@ -369,7 +377,7 @@ extern "C" fse_status_t fse_batch_create(fse_plan_t plan, const fse_block_t* h_b
                                             : "fixed-point cFSE is compiled for 64 x 64 transforms");
     }
     const int cap = std::max(b->cls[class_of(64)].iters_cap, 1);
-    const void* fn = real ? fse::real_kernel(plan->flags & FSE_PLAN_REAL_INLOOP) : fse::fixed_kernel();
+    const void* fn = real ? fse::real_kernel(real_sel(plan->flags)) : fse::fixed_kernel();
     b->alt_lds = real ? fse::real_lds_bytes(cap) : fse::fixed_lds_bytes(cap);
     int per_cu = 0;
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->alt_lds) != hipSuccess ||
@@ -560,7 +568,7 @@ static fse_status_t launch_one(fse_batch_t batch, int ci, const uint8_t* d_image
     }
     if (!warm && (batch->plan->flags & FSE_PLAN_REAL)) {
       if (timed(batch, FSE_KERNEL_REAL, 64, s, [&] {
-            return fse::launch_real(a, batch->plan->flags & FSE_PLAN_REAL_INLOOP, batch->alt_grid, batch->alt_lds, s);
+            return fse::launch_real(a, real_sel(batch->plan->flags), batch->alt_grid, batch->alt_lds, s);
           }) !=
           hipSuccess)
         return fail(FSE_ERR_HIP, "kernel launch failed (rFSE)");

@@ -101,9 +101,12 @@ const void* fse3d_kernel(bool warm);
 // inloop selects the form that recomputes the pair constants in every
 // iteration.
 size_t real_lds_bytes(int iters_cap);
-const void* real_kernel(bool inloop);
+// rFSE forms: selection by the least-squares decrease (constants per block
+// or per iteration) or by |R_w|^2.
+enum RealSel : int { kRealDecrease = 0, kRealInloop = 1, kRealPower = 2 };
+const void* real_kernel(int sel);
 int real_threads();
-hipError_t launch_real(const ClassArgs& a, bool inloop, int grid, size_t lds, hipStream_t s);
+hipError_t launch_real(const ClassArgs& a, int sel, int grid, size_t lds, hipStream_t s);
 
 // Fixed-point cFSE, F = 64: the same four helpers.
 size_t fixed_lds_bytes(int iters_cap);

@@ -1411,16 +1411,23 @@ __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
 // or with l in {0, 32} and k <= 32. The pair's weighted least-squares fit
 // needs Q = W[2k, 2l]: with D = W0^2 - |Q|^2, A = 2 W0 / D and Bq = 2 Q / D
 // (self-conjugate bins: A = 1 / W0, Bq = 0), the energy decrease is
-// A |P|^2 - Re{Bq* P^2} and the coefficient A P* - Bq* P. These depend on
-// the window only, so the divisions are done once per block, and the
-// decrease is held as a1 x^2 + a2 y^2 + a3 x y (P = x + j y).
-// INLOOP recomputes the constants, divisions included, in every iteration
-// (the formulation whose cost the paper's runtime comparison describes);
-// the results agree with the hoisted form up to FP32 rounding.
+// A |P|^2 - Re{Bq* P^2} and the coefficient A P* - Bq* P, held as
+// a1 x^2 + a2 y^2 + a3 x y and (a1 x + a3 y / 2, -a2 y - a3 x / 2) for
+// P = x + j y. SEL picks the form:
+//   kRealDecrease  the pair of largest decrease; the constants depend on the
+//                  window only, so the divisions are done once per block;
+//   kRealInloop    the same selection with the constants, divisions
+//                  included, recomputed for every bin in every iteration
+//                  (the formulation whose cost the paper's runtime
+//                  comparison describes);
+//   kRealPower     the other reading of the selection: the pair holding the
+//                  largest |P|^2 (the criterion of eq. (12)); the constants
+//                  serve the winner's coefficient only.
 constexpr int kRealNT = 256;
 
-template <bool INLOOP>
+template <int SEL>
 __global__ __launch_bounds__(kRealNT) void fse_real64(ClassArgs a) {
+  constexpr bool INLOOP = SEL == kRealInloop;
   constexpr int F = 64, NT = kRealNT, NC = 9;
   extern __shared__ __align__(16) unsigned char smem[];
   float2* const Wd = reinterpret_cast<float2*>(smem);          // FFT buffer, then W[l][k] for l <= 32
@@ -1519,11 +1526,19 @@ __global__ __launch_bounds__(kRealNT) void fse_real64(ClassArgs a) {
     };
 #pragma unroll
     for (int cc = 0; cc < NC; ++cc) constants(cc);
+    // 1 for the bins that represent a pair, 0 for the others
+    float rp[NC];
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) rp[cc] = a1[cc] > 0.f ? 1.f : 0.f;
     auto decrease = [&](int cc) {
       const float x = Rx[cc], y = Ry[cc];
-      const float tq = fmaf(a3[cc], y, a1[cc] * x);
-      const float d = fmaf(x, tq, (a2[cc] * y) * y);
-      return __float_as_uint(fmaxf(d, 0.f));
+      if constexpr (SEL != kRealPower) {
+        const float tq = fmaf(a3[cc], y, a1[cc] * x);
+        const float d = fmaf(x, tq, (a2[cc] * y) * y);
+        return __float_as_uint(fmaxf(d, 0.f));
+      } else {
+        return __float_as_uint(rp[cc] * fmaf(y, y, x * x));
+      }
     };
     uint32_t best = 0;
     int bj = 0;
@@ -1953,8 +1968,12 @@ const void* fse3d_kernel(bool warm) {
 
 size_t real_lds_bytes(int iters_cap) { return (size_t)64 * 64 * 8 + 64 * 8 + 16 * 16 + (size_t)iters_cap * 12; }
 
-const void* real_kernel(bool inloop) {
-  return inloop ? reinterpret_cast<const void*>(&fse_real64<true>) : reinterpret_cast<const void*>(&fse_real64<false>);
+const void* real_kernel(int sel) {
+  switch (sel) {
+    case kRealInloop: return reinterpret_cast<const void*>(&fse_real64<kRealInloop>);
+    case kRealPower: return reinterpret_cast<const void*>(&fse_real64<kRealPower>);
+    default: return reinterpret_cast<const void*>(&fse_real64<kRealDecrease>);
+  }
 }
 
 int real_threads() { return kRealNT; }
@@ -1972,9 +1991,9 @@ hipError_t launch_fixed(const ClassArgs& a, int grid, size_t lds, hipStream_t s)
   return hipLaunchKernel(reinterpret_cast<const void*>(&fse_fixed64), dim3(grid), dim3(kFixedNT), args, lds, s);
 }
 
-hipError_t launch_real(const ClassArgs& a, bool inloop, int grid, size_t lds, hipStream_t s) {
+hipError_t launch_real(const ClassArgs& a, int sel, int grid, size_t lds, hipStream_t s) {
   void* args[] = {const_cast<ClassArgs*>(&a)};
-  return hipLaunchKernel(real_kernel(inloop), dim3(grid), dim3(kRealNT), args, lds, s);
+  return hipLaunchKernel(real_kernel(sel), dim3(grid), dim3(kRealNT), args, lds, s);
 }
 
 hipError_t launch_fse3d(const Vol3Args& a, bool warm, int grid, size_t lds, hipStream_t s) {

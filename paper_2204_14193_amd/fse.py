@@ -53,6 +53,7 @@ PLAN_MASKED_B = 1  # FSE_PLAN_MASKED_B of include/fse.h
 PLAN_REAL = 2      # FSE_PLAN_REAL: real-valued FSE (rFSE)
 PLAN_FIXED = 4     # FSE_PLAN_FIXED: fixed-point cFSE
 PLAN_REAL_INLOOP = 8  # FSE_PLAN_REAL_INLOOP: rFSE with the pair constants recomputed per iteration
+PLAN_REAL_POWER = 16  # FSE_PLAN_REAL_POWER: rFSE selecting the pair of largest |R_w|^2
 
 
 class Plan:
@@ -61,13 +62,16 @@ class Plan:
     rectangle (arbitrary loss shapes, FSE_PLAN_MASKED_B); real=True runs
     real-valued FSE instead of cFSE (FSE_PLAN_REAL, F = 64 blocks only);
     fixed=True runs the fixed-point cFSE encoding (FSE_PLAN_FIXED, F = 64);
-    real="inloop" runs rFSE with its constants recomputed in every iteration."""
+    real="inloop" runs rFSE with its constants recomputed in every iteration;
+    real="power" runs rFSE selecting the pair of largest |R_w|^2."""
 
     def __init__(self, rho=0.8, gamma=0.5, max_iters=4096, masked=False, real=False, fixed=False):
         L = _lib.lib()
         flags = (PLAN_MASKED_B if masked else 0) | (PLAN_REAL if real else 0) | (PLAN_FIXED if fixed else 0)
         if real == "inloop":
             flags |= PLAN_REAL_INLOOP
+        elif real == "power":
+            flags |= PLAN_REAL_POWER
         desc = _lib.fse_plan_desc_t(float(rho), float(gamma), int(max_iters), flags)
         h = C.c_void_p()
         _check(L.fse_plan_create(C.byref(desc), C.byref(h)), "fse_plan_create")

@@ -208,14 +208,14 @@ def volume_slices(vol):
     return (slice(f, f + int(vol["bt"])), slice(y, y + int(vol["bh"])), slice(x, x + int(vol["bw"])))
 
 
-def replay_real_block(frames, avail, blk, rho, gamma, trace_row):
+def replay_real_block(frames, avail, blk, rho, gamma, trace_row, selection="decrease"):
     """rFSE counterpart of replay_block: the trace names each selected
     pair by its lower-index bin and that bin's coefficient, as the oracle
-    does."""
+    does; ``selection`` is the oracle's selection reading."""
     from oracle import rfse
     F, I = int(blk["fft"]), int(blk["iters"])
     seq, c = gpu_sequence(trace_row, F, I)
-    res = rfse.extrapolate_block(frames, avail, blk, rho, gamma, forced=seq)
+    res = rfse.extrapolate_block(frames, avail, blk, rho, gamma, forced=seq, selection=selection)
     short = np.array(res["short"]) if I else np.zeros(0)
     free = np.array(res["free"]) if I else np.zeros(0, dtype=int)
     div = free != seq

@@ -190,5 +190,13 @@ def test_real_plan_flags():
     d = _lib.fse_plan_desc_t(0.8, 0.5, 100, 2 | 8)
     assert L.fse_plan_create(C.byref(d), C.byref(h)) == 0 and h.value
     L.fse_plan_destroy(h)
-    d = _lib.fse_plan_desc_t(0.8, 0.5, 100, 16)
+    d = _lib.fse_plan_desc_t(0.8, 0.5, 100, 16)     # the power-selection modifier alone
+    assert L.fse_plan_create(C.byref(d), C.byref(h)) == -1
+    h = C.c_void_p()
+    d = _lib.fse_plan_desc_t(0.8, 0.5, 100, 2 | 16)
+    assert L.fse_plan_create(C.byref(d), C.byref(h)) == 0 and h.value
+    L.fse_plan_destroy(h)
+    d = _lib.fse_plan_desc_t(0.8, 0.5, 100, 2 | 8 | 16)  # the two modifiers exclude each other
+    assert L.fse_plan_create(C.byref(d), C.byref(h)) == -1
+    d = _lib.fse_plan_desc_t(0.8, 0.5, 100, 32)
     assert L.fse_plan_create(C.byref(d), C.byref(h)) == -1

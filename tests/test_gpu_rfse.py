@@ -28,28 +28,29 @@ def _run(distorted, avail, blocks, rho, gamma, trace=True, real=True):
     return out.cpu().numpy(), st, tr
 
 
-def _check(frames, avail, blocks, rho, gamma, out, tr, idx):
+def _check(frames, avail, blocks, rho, gamma, out, tr, idx, selection="decrease"):
     rows = []
     for i in idx:
         b = blocks[i]
-        r = parity.replay_real_block(frames * avail, avail, b, rho, gamma, tr[i])
+        r = parity.replay_real_block(frames * avail, avail, b, rho, gamma, tr[i], selection)
         f, y0, x0 = int(b["frame"]), int(b["y0"]), int(b["x0"])
         g = out[f, y0:y0 + int(b["bh"]), x0:x0 + int(b["bw"])].astype(np.float64)
         r["pix_maxabs"] = float(np.abs(g - r["values"]).max())
         rows.append(r)
         assert r["gap_violations"] == 0, (i, r)
         assert r["coef_max"] <= parity.COEF_TOL and r["coef_l2"] <= parity.COEF_TOL, (i, r)
+        assert r["pix_maxabs"] < parity.PIX_TOL, (i, r["pix_maxabs"])
     return rows
 
 
-def _psnr(frames, avail, blocks, rho, gamma, out, idx):
+def _psnr(frames, avail, blocks, rho, gamma, out, idx, selection="decrease"):
     ref = (frames * avail).astype(np.float64)
     mask = np.ones_like(avail)
     for i in idx:
         b = blocks[i]
         f, y0, x0 = int(b["frame"]), int(b["y0"]), int(b["x0"])
         sl = (f, slice(y0, y0 + int(b["bh"])), slice(x0, x0 + int(b["bw"])))
-        ref[sl] = rfse.extrapolate_block(frames * avail, avail, b, rho, gamma)["values"]
+        ref[sl] = rfse.extrapolate_block(frames * avail, avail, b, rho, gamma, selection=selection)["values"]
         mask[sl] = 0
     pg, po = metrics.psnr_lost(frames, out, mask), metrics.psnr_lost(frames, ref, mask)
     return abs(pg - po), pg, po
@@ -87,6 +88,25 @@ def test_rfse_inloop_variant_parity():
     idx = range(len(blocks))
     rows = _check(wl.frames, wl.avail, blocks, wl.rho, wl.gamma, out, tr, idx)
     d, pg, po = _psnr(wl.frames, wl.avail, blocks, wl.rho, wl.gamma, out, idx)
+    _say(f"ties={sum(r['ties'] for r in rows)} coef_max={max(r['coef_max'] for r in rows):.2e} "
+         f"psnr gpu={pg:.4f} oracle={po:.4f}")
+    assert d <= parity.PSNR_TOL
+
+
+@pytest.mark.parametrize("gamma", [0.2, 0.5])
+def test_rfse_power_selection_parity(gamma):
+    """The other selection reading (FSE_PLAN_REAL_POWER: the pair holding
+    the largest |R_w|^2) against the oracle with that reading: every block
+    of the 256x256 case, 50 iterations."""
+    wl = workloads.isolated_256()
+    blocks = wl.blocks.copy()
+    blocks["iters"] = 50
+    _say(f"case rfse-power isolated-256: {len(blocks)} blocks F=64 I=50 gamma={gamma}")
+    out, st, tr = _run(wl.distorted, wl.avail, blocks, wl.rho, gamma, real="power")
+    assert (st == 0).all(), st
+    idx = range(len(blocks))
+    rows = _check(wl.frames, wl.avail, blocks, wl.rho, gamma, out, tr, idx, "power")
+    d, pg, po = _psnr(wl.frames, wl.avail, blocks, wl.rho, gamma, out, idx, "power")
     _say(f"ties={sum(r['ties'] for r in rows)} coef_max={max(r['coef_max'] for r in rows):.2e} "
          f"psnr gpu={pg:.4f} oracle={po:.4f}")
     assert d <= parity.PSNR_TOL

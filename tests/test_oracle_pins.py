@@ -675,19 +675,26 @@ def test_rfse_pair_fit_is_weighted_least_squares():
             assert abs(dec[k, l] - db) <= 1e-9 * max(1.0, abs(db)), (k, l, dec[k, l], db)
 
 
-def test_rfse_selection_and_energy_identity():
+@pytest.mark.parametrize("selection", ["power", "decrease"])
+def test_rfse_selection_and_energy_identity(selection):
     """Each iteration selects the lower-index bin of the pair with the
-    largest brute-force decrease, the weighted energy falls by exactly
-    gamma (2 - gamma) times that decrease, and the model stays real."""
+    largest brute-force criterion (the weighted residual's |projection|^2
+    by eq. (7), or the least-squares decrease), the weighted energy falls by
+    exactly gamma (2 - gamma) times the selected pair's decrease, and the
+    model stays real."""
     from oracle import rfse
     r, w, A, F = _rfse_case(seed=5)
     s = np.where(A, r, 0.0)
     gamma = 0.6
-    res = rfse.rfse(s, w, F, gamma, 6)
+    res = rfse.rfse(s, w, F, gamma, 6, selection=selection)
     resid = s.copy()
     for it, idx in enumerate(res["seq"]):
         decs = np.array([[_pair_lstsq(resid, w, F, k, l)[1] for l in range(F)] for k in range(F)])
-        assert idx == int(np.flatnonzero(decs.ravel() >= decs.max() * (1 - 1e-9))[0])
+        if selection == "power":
+            crit = np.abs(_brute_dft(resid * w, F)) ** 2
+        else:
+            crit = decs
+        assert idx == int(np.flatnonzero(crit.ravel() >= crit.max() * (1 - 1e-9))[0])
         e0, e1 = res["energy"][it], res["energy"][it + 1]
         assert abs((e0 - e1) - gamma * (2 - gamma) * decs.ravel()[idx]) <= 1e-9 * e0
         u, v = divmod(idx, F)
@@ -700,8 +707,9 @@ def test_rfse_selection_and_energy_identity():
     np.testing.assert_allclose(res["g"], s - resid, atol=1e-9)
 
 
+@pytest.mark.parametrize("selection", ["power", "decrease"])
 @pytest.mark.parametrize("k0,l0", [(3, 5), (13, 2), (0, 0), (8, 0), (0, 8), (8, 8)])
-def test_rfse_recovers_a_real_sinusoid(k0, l0):
+def test_rfse_recovers_a_real_sinusoid(k0, l0, selection):
     """A real sinusoid a cos(theta + p) on the support (a constant or an
     alternating pattern for the self-conjugate bins) is the whole model
     after one iteration at gamma = 1, also on the loss area, and the
@@ -716,7 +724,7 @@ def test_rfse_recovers_a_real_sinusoid(k0, l0):
     A = np.ones((M, N), dtype=bool)
     A[4:8, 4:8] = False
     w = np.where(A, cfse.window(M, N, 0.8), 0.0)
-    res = rfse.rfse(np.where(A, x, 0.0), w, F, 1.0, 1)
+    res = rfse.rfse(np.where(A, x, 0.0), w, F, 1.0, 1, selection=selection)
     assert res["seq"] == [min(k0 * F + l0, rfse.pair_index(F, k0 * F + l0))]
     np.testing.assert_allclose(res["g"], x, atol=1e-9)
 
