@@ -941,14 +941,12 @@ struct fse_batch3d_s {
   const DeviceTables* tables = nullptr;
   fse_volume_t* d_vols = nullptr;
   float* d_wtab3 = nullptr;
-  float2* d_scratch = nullptr;
 };
 
 namespace {
 void free_batch3d(fse_batch3d_s* b) {
   (void)hipFree(b->d_vols);
   (void)hipFree(b->d_wtab3);
-  (void)hipFree(b->d_scratch);
   delete b;
 }
 
@@ -1041,8 +1039,7 @@ extern "C" fse_status_t fse_batch3d_create(fse_plan_t plan, const fse_volume_t* 
             (float)std::pow((double)plan->rho, 0.5 * std::sqrt((double)a * a + (double)d * d + (double)c * c));
   const size_t nv = (size_t)std::max(n_volumes, 1);
   if (hipMalloc(&b->d_vols, nv * sizeof(fse_volume_t)) != hipSuccess ||
-      hipMalloc(&b->d_wtab3, w3.size() * sizeof(float)) != hipSuccess ||
-      hipMalloc(&b->d_scratch, (size_t)b->grid * fse::kFt3 * fse::kF3 * fse::kF3 * sizeof(float2)) != hipSuccess) {
+      hipMalloc(&b->d_wtab3, w3.size() * sizeof(float)) != hipSuccess) {
     free_batch3d(b);
     return fail(FSE_ERR_OOM, "hipMalloc failed (3-D batch)");
   }
@@ -1092,7 +1089,6 @@ static fse_status_t launch3d(fse_batch3d_t batch, const uint8_t* d_frames, const
   a.wtab3 = batch->d_wtab3;
   a.twid = batch->tables->twid[class_of(fse::kF3)];
   a.gamma = batch->plan->gamma;
-  a.scratch = batch->d_scratch;
   a.cand2 = d_cand2;
   a.flags = d_flags;
   const bool warm = d_cand2 != nullptr;

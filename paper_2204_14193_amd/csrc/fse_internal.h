@@ -81,7 +81,6 @@ struct Vol3Args {
   const float* wtab3;
   const float2* twid;    // 64 entries exp(-j 2 pi q / 64)
   float gamma;
-  float2* scratch;       // [grid][kFt3][kF3][kF3]
   // warm start only: candidate columns k * 64 + l per volume (ascending)
   // and the network's per-volume flags (nonzero: no usable candidates)
   const int16_t* cand2;  // [n][kCand3]

@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 
@@ -186,14 +187,21 @@ __device__ __forceinline__ void dft_small(float2 (&a)[R]) {
   }
 }
 
-template <int F, int NT, int R, int NS, bool COLS>
+// TOUT writes the pass's output transposed (element (line, e) of a row pass
+// to Z[e * F + line]); with more threads than butterflies the extra
+// threads only take part in the barriers.
+template <int F, int NT, int R, int NS, bool COLS, bool TOUT = false>
 __device__ __forceinline__ void fft_pass(float2* Z, const float2* tw, int t) {
-  constexpr int L = F / R;           // butterflies per line
-  constexpr int PER = F * F / R / NT;  // butterflies per thread
-  static_assert(PER * R * NT == F * F, "pass does not tile the grid");
+  constexpr int L = F / R;             // butterflies per line
+  constexpr int NB = F * F / R;        // butterflies per pass
+  constexpr int PER = NB >= NT ? NB / NT : 1;  // butterflies per thread
+  static_assert(NB >= NT ? PER * NT == NB : NT % NB == 0, "pass does not tile the grid");
+  static_assert(!TOUT || !COLS, "transposed output is for row passes");
+  const bool active = NB >= NT || t < NB;
   float2 v[PER][R];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
+    if (!active) break;
     const int b = t + i * NT;
     const int line = COLS ? (b % F) : (b / L);
     const int j = COLS ? (b / F) : (b % L);
@@ -212,6 +220,7 @@ __device__ __forceinline__ void fft_pass(float2* Z, const float2* tw, int t) {
   lds_barrier();
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
+    if (!active) break;
     const int b = t + i * NT;
     const int line = COLS ? (b % F) : (b / L);
     const int j = COLS ? (b / F) : (b % L);
@@ -219,7 +228,7 @@ __device__ __forceinline__ void fft_pass(float2* Z, const float2* tw, int t) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int e = o + r * NS;
-      if (COLS) Z[e * F + line] = v[i][r]; else Z[line * F + e] = v[i][r];
+      if (COLS || TOUT) Z[e * F + line] = v[i][r]; else Z[line * F + e] = v[i][r];
     }
   }
   lds_barrier();
@@ -1075,34 +1084,113 @@ const Variant kVariants[] = {
 
 // ------------------------------------------------------------ 3-D (video)
 // cFSE of one lost volume per workgroup of kNT3 = 1024 threads, F = 64,
-// Ft = 8 (the iteration of Section III on a 3-D grid). Thread t owns the 32
-// bins with linear index (k F + l) Ft + s = 32 t + j, i.e. the columns
-// (k, l) = 4 t + j / 8 and s = j % 8, so lane, wave and j order is the
-// bin order and the lowest-index tie-break of the argmax falls out of
-// "first maximum". LDS holds W for l <= 32 as [l][k][s] (the other half is
-// W[-k,-l,-s] conjugated), 132 KB; before that the same bytes hold four
-// 64 x 64 FFT buffers.
+// Ft = 8 (the iteration of Section III on a 3-D grid). Bin (k, l, s) has
+// the linear index (k F + l) Ft + s.
+//
+// Spectra without a round trip through memory: the temporal 8-point DFT of
+// z = s w + j alpha w is taken first, per pixel, straight from the frames;
+// the 64 x 64 spatial FFTs of its eight s-slices then run in LDS in four
+// rounds of slices closed under s -> -s ({1, 7, 2, 6}, {3, 5}, {0}, {4}), so
+// that the conjugate-symmetric split of a bin and of its mirror (-k, -l, -s)
+// finds both slices in the same round. W is kept for l <= 32 (the rest is
+// W[-k, -l, -s] conjugated) as eight s-slots of 33 x 64 values, [l][k]. The
+// rounds fill the slots in the order they produce them, each round's FFT
+// buffers lying over the slots not yet written (the values a round produces
+// wait in registers until its buffers are dead); one permutation then puts
+// slot s at W[., ., s].
+constexpr int kSlot3 = kHalfCols3 * kF3;  // float2 entries per s-slot of W
+// slot each s is produced into, 4 bits per s (the rounds write s = 1, 7, 2, 6, 3, 5, 0, 4)
+constexpr uint32_t kSlotOf3 = 0x13574206u;
+__host__ __device__ constexpr int slot_of3(int s) { return (int)((kSlotOf3 >> (4 * s)) & 7u); }
+static_assert(slot_of3(1) == 0 && slot_of3(7) == 1 && slot_of3(2) == 2 && slot_of3(6) == 3 && slot_of3(3) == 4 &&
+                  slot_of3(5) == 5 && slot_of3(0) == 6 && slot_of3(4) == 7,
+              "slots in the order the rounds write them");
+// LDS: twiddles [0, 512), argmax exchange [512, 1024), then W; the
+// coefficient list follows W (over the last round's FFT buffer, dead by then)
+constexpr int kW3Ofs = 1024;
+constexpr int kW3Bytes = kFt3 * kSlot3 * 8;
+constexpr int kFftBuf3 = kF3 * kF3;  // float2 entries of one FFT buffer
+static_assert(4 * kFftBuf3 <= kFt3 * kSlot3 && 4 * kSlot3 + 2 * kFftBuf3 <= kFt3 * kSlot3 &&
+                  6 * kSlot3 + kFftBuf3 <= kFt3 * kSlot3,
+              "the buffers of rounds 1-3 lie inside W");
+
+// 2-D FFT of a 64 x 64 buffer filled as [m][n]: columns first, then rows,
+// the last pass written transposed, so that buf[l * 64 + k] holds Z(k, l)
+// and a wave reading one l for 64 consecutive k reads consecutive entries.
+template <int NT>
+__device__ __forceinline__ void fft2_lk(float2* buf, const float2* tw, int t) {
+  fft_pass<kF3, NT, 8, 1, true>(buf, tw, t);
+  fft_pass<kF3, NT, 8, 8, true>(buf, tw, t);
+  fft_pass<kF3, NT, 8, 1, false>(buf, tw, t);
+  fft_pass<kF3, NT, 8, 8, false, true>(buf, tw, t);
+}
+
+// The split of slice S (buffer bs) against slice -S (buffer bm): with
+// P = Z(k, l, S) and Q = Z(-k, -l, -S), R_w = (P + conj Q) / 2 and
+// W = (P - conj Q) / (2 j alpha). The thread's columns are (k, l) =
+// (lane, 4 wv + cc): R_w of the plain form goes to its registers, W for
+// l <= 32 to wp. In the warm form waves 0-3 take R_w at their candidates
+// (column (ck, cl), s = 4 h + j) instead.
+template <bool WARM, int S, int NR>
+__device__ __forceinline__ void split3(const float2* bs, const float2* bm, int wv, int kk, float (&Rx)[NR],
+                                       float (&Ry)[NR], float2 (&wp)[4], int ck, int cl, int h) {
+  constexpr int F = kF3;
+  const int km = (F - kk) & (F - 1);
+#pragma unroll
+  for (int cc = 0; cc < 4; ++cc) {
+    const int l = 4 * wv + cc;
+    const bool needW = l <= F / 2;  // uniform
+    wp[cc] = make_float2(0.f, 0.f);  // defined on every path (no value carried across volumes)
+    if (WARM && !needW) continue;
+    const float2 P = bs[l * F + kk], Q = bm[((F - l) & (F - 1)) * F + km];
+    if constexpr (!WARM) {
+      Rx[cc * kFt3 + S] = 0.5f * (P.x + Q.x);
+      Ry[cc * kFt3 + S] = 0.5f * (P.y - Q.y);
+      asm volatile("" : "+v"(Rx[cc * kFt3 + S]), "+v"(Ry[cc * kFt3 + S]));  // held as R_w, not as P and Q
+    }
+    if (needW) wp[cc] = make_float2((P.y + Q.y) * (0.5f / kAlpha), (Q.x - P.x) * (0.5f / kAlpha));
+    asm volatile("" : "+v"(wp[cc].x), "+v"(wp[cc].y));  // held as W, not as P and Q
+  }
+  if constexpr (WARM) {
+    if (wv < 4 && (S >> 2) == h) {
+      const float2 P = bs[cl * F + ck], Q = bm[((F - cl) & (F - 1)) * F + ((F - ck) & (F - 1))];
+      Rx[S & 3] = 0.5f * (P.x + Q.x);
+      Ry[S & 3] = 0.5f * (P.y - Q.y);
+      asm volatile("" : "+v"(Rx[S & 3]), "+v"(Ry[S & 3]));
+    }
+  }
+  asm volatile("" ::: "memory");  // one slice's reads in flight at a time
+}
+
+template <int S>
+__device__ __forceinline__ void store_w3(float2* Wl, const float2 (&wp)[4], int wv, int kk) {
+#pragma unroll
+  for (int cc = 0; cc < 4; ++cc) {
+    const int l = 4 * wv + cc;
+    if (l <= kF3 / 2) Wl[slot_of3(S) * kSlot3 + l * kF3 + kk] = wp[cc];
+  }
+}
+
 __device__ __forceinline__ uint32_t bits_max_first(uint32_t bits, uint32_t& best) {
   return bits > best ? (best = bits, 1u) : 0u;
 }
 
 // WARM restricts the argmax to candidate bins: for each volume, kCand3
-// columns (k, l) (a row of cand2, ascending) with all Ft values of s, one
-// bin per thread; the update runs over the candidates only.
+// columns (k, l) (a row of cand2, ascending) with all Ft values of s. Waves
+// 0-3, one per SIMD, iterate: wave w holds the columns 64 (w & 1) + lane and
+// s = 4 (w >> 1) + j, j < 4, so lane and j order is index order within a
+// wave; the other waves only take part in the barrier of each iteration.
 template <bool WARM>
 __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
   constexpr int F = kF3, FT = kFt3, NT = kNT3, BPT = F * F * FT / NT;  // 32 bins per thread
-  constexpr int WH = kHalfCols3 * F * FT;                              // 16896 entries of W
   extern __shared__ __align__(16) unsigned char smem[];
-  float2* const Wl = reinterpret_cast<float2*>(smem);
-  float2* const tw = Wl + WH;
-  int4* const xch = reinterpret_cast<int4*>(tw + F);                   // 2 x 16 argmax slots
-  float2* const cl_c = reinterpret_cast<float2*>(xch + 2 * (NT / 64));
+  float2* const tw = reinterpret_cast<float2*>(smem);
+  int4* const xch = reinterpret_cast<int4*>(smem + 512);  // 2 x 16 argmax slots
+  float2* const Wl = reinterpret_cast<float2*>(smem + kW3Ofs);
+  float2* const cl_c = reinterpret_cast<float2*>(smem + kW3Ofs + kW3Bytes);
   int* const cl_idx = reinterpret_cast<int*>(cl_c + a.iters_cap);
-  static_assert(4 * F * F <= WH, "four FFT buffers fit the W region");
   const int t0 = threadIdx.x;
   if (t0 < F) tw[t0] = a.twid[t0];
-  float2* const Z = a.scratch + (int64_t)blockIdx.x * (FT * F * F);
   int parity = 0;
   for (int vi = blockIdx.x; vi < a.n; vi += gridDim.x) {
     // opaque thread index: keeps index-derived addresses out of the volume loop
@@ -1123,118 +1211,162 @@ __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
         continue;
       }
     }
-
-    // 1. gather, window (eq. (3)), z = s w + j alpha w, and the 2-D FFT of
-    // every frame of the area; four frames at a time, one per 256 threads
-    {
-      const int g = t >> 8, tg = t & 255;
-      float2* const buf = Wl + g * (F * F);
-      for (int r0 = 0; r0 < T; r0 += 4) {
-        const int sl = r0 + g;
-        const int f = ta + sl;
-        const bool frame_ok = sl < T && f >= 0 && f < a.n_frames;
-        const uint8_t* img = a.img + (int64_t)(frame_ok ? f : 0) * a.H * a.pitch;
-        const uint8_t* av = a.avail + (int64_t)(frame_ok ? f : 0) * a.H * a.pitch;
-        const int dc = min(abs(2 * sl - (T - 1)), kWinStrideT - 1);
-        for (int e = tg; e < F * F; e += 256) {
-          const int m = e / F, n = e % F;
-          const int y = ya + m, x = xa + n;
-          const bool inB = m >= bd && m < bd + bh && n >= bd && n < bd + bw && sl >= td && sl < td + bt;
-          bool use = frame_ok && m < M && n < N && !inB && y >= 0 && y < a.H && x >= 0 && x < a.W;
-          float2 z = make_float2(0.f, 0.f);
-          if (use) {
-            const uint32_t p = (uint32_t)(y * (int)a.pitch + x);
-            if (av[p] != 0) {
-              const int da = min(abs(2 * m - (M - 1)), kWinStride - 1), db = min(abs(2 * n - (N - 1)), kWinStride - 1);
-              const float w = a.wtab3[(dc * kWinStride + da) * kWinStride + db];
-              z = make_float2((float)img[p] * w, kAlpha * w);
-            }
-          }
-          buf[e] = z;
-        }
-        __syncthreads();
-        fft_lines<F, 256, false>(buf, tw, tg);
-        fft_lines<F, 256, true>(buf, tw, tg);
-        if (sl < T)
-          for (int e = tg; e < F * F; e += 256) Z[sl * (F * F) + e] = buf[(e & (F - 1)) * F + (e >> 6)];  // [l][k]
-        __syncthreads();  // the buffers are reused; the scratch is read by other threads
-      }
-    }
-    // 2+3. temporal DFT fused with the conjugate-symmetric split. For the
-    // thread's column (k, l) and its mirror (-k, -l), over the area's frames
-    // t: a_t = Z_t[k,l] + conj(Z_t[-k,-l]), b_t = Z_t[k,l] - conj(Z_t[-k,-l]);
-    // then R_w[k,l,s] = (1/2) sum_t a_t e^{-j 2 pi s t / Ft} into registers
-    // and, for l <= 32, W[k,l,s] = -j / (2 alpha) sum_t b_t e^{-j 2 pi s t / Ft}
-    // into LDS as [l][s][k] (over the dead FFT buffers)
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6), kk = t & (F - 1);
-    float Rx[WARM ? 1 : BPT], Ry[WARM ? 1 : BPT];
+
+    // 1. gather, window (eq. (3)), z = s w + j alpha w, and the temporal DFT
+    // of z per pixel; thread t takes the pixels (m, n) = (t / 64 + 16 q, t % 64).
+    // The slices of the first round go to its four FFT buffers, the others
+    // stay in registers for the later rounds.
+    float2 keep[4][4];  // s = 3, 5, 0, 4
 #pragma unroll
-    for (int cc = 0; cc < BPT / FT; ++cc) {
-      const int l = (BPT / FT) * wv + cc;
-      const bool needW = l <= F / 2;  // uniform
-      if (WARM && !needW) continue;
-      float2 A[FT], B[FT];
+    for (int q = 0; q < 4; ++q) {
+      const int m = wv + 16 * q, n = kk;
+      const int y = ya + m, x = xa + n;
+      const bool inA = m < M && n < N && y >= 0 && y < a.H && x >= 0 && x < a.W;
+      const bool inBmn = m >= bd && m < bd + bh && n >= bd && n < bd + bw;
+      const int da = min(abs(2 * m - (M - 1)), kWinStride - 1), db = min(abs(2 * n - (N - 1)), kWinStride - 1);
+      const uint32_t p = inA ? (uint32_t)(y * (int)a.pitch + x) : 0u;
+      const int dab = da * kWinStride + db;
+      // every load reads a valid address (a frame of the clip, pixel 0 when
+      // unused), so that all of them issue before the first wait; the frame
+      // offsets are uniform
+      float2 z[FT];
 #pragma unroll
-      for (int s3 = 0; s3 < FT; ++s3) A[s3] = B[s3] = make_float2(0.f, 0.f);
-      for (int q = 0; q < T; ++q) {
-        const float2 zk = Z[(q * F + l) * F + kk];
-        const float2 zn = Z[(q * F + ((F - l) & (F - 1))) * F + ((F - kk) & (F - 1))];
-        const float2 av = make_float2(zk.x + zn.x, zk.y - zn.y), bv = make_float2(zk.x - zn.x, zk.y + zn.y);
-#pragma unroll
-        for (int s3 = 0; s3 < FT; ++s3) {
-          const float2 e = tw[(s3 * q * (F / FT)) & (F - 1)];
-          if (!WARM) A[s3] = cadd(A[s3], cmul(av, e));
-          if (needW) B[s3] = cadd(B[s3], cmul(bv, e));
-        }
+      for (int sl = 0; sl < FT; ++sl) {
+        const int f = ta + sl;
+        const int64_t fo = (int64_t)min(max(f, 0), a.n_frames - 1) * a.H * a.pitch;
+        const bool use = inA && sl < T && f >= 0 && f < a.n_frames && !(inBmn && sl >= td && sl < td + bt);
+        const uint32_t o = use ? p : 0u;
+        const uint8_t av = (a.avail + fo)[o], px = (a.img + fo)[o];
+        const int dc = min(abs(2 * sl - (T - 1)), kWinStrideT - 1);
+        const float w = (a.wtab3 + dc * kWinStride * kWinStride)[dab];
+        // the window where the pixel counts, else +0 (a mask, not a branch)
+        const float wu = __int_as_float(__float_as_int(w) & -(int)(use && av != 0));
+        z[sl] = make_float2((float)px * wu, kAlpha * wu);
       }
+      dft_small<FT>(z);  // z[s] = sum_t z_t exp(-j 2 pi s t / Ft)
+      const int e = m * F + n;
+      Wl[0 * kFftBuf3 + e] = z[1];
+      Wl[1 * kFftBuf3 + e] = z[7];
+      Wl[2 * kFftBuf3 + e] = z[2];
+      Wl[3 * kFftBuf3 + e] = z[6];
+      keep[q][0] = z[3];
+      keep[q][1] = z[5];
+      keep[q][2] = z[0];
+      keep[q][3] = z[4];
+      // the kept slices as values now (not their inputs), and one pixel's
+      // loads in flight at a time
+      asm volatile("" : "+v"(keep[q][0].x), "+v"(keep[q][0].y), "+v"(keep[q][1].x), "+v"(keep[q][1].y),
+                   "+v"(keep[q][2].x), "+v"(keep[q][2].y), "+v"(keep[q][3].x), "+v"(keep[q][3].y)::"memory");
+    }
+
+    // 2. the spatial FFTs and the conjugate-symmetric split, round by round:
+    // R_w into registers, W into its s-slots
+    float Rx[WARM ? 4 : BPT], Ry[WARM ? 4 : BPT];
+    if constexpr (WARM) {
 #pragma unroll
-      for (int s3 = 0; s3 < FT; ++s3) {
-        if constexpr (!WARM) {
-          Rx[cc * FT + s3] = A[s3].x * 0.5f;
-          Ry[cc * FT + s3] = A[s3].y * 0.5f;
-        }
-        if (needW) Wl[(l * FT + s3) * F + kk] = make_float2(B[s3].y * (0.5f / kAlpha), -B[s3].x * (0.5f / kAlpha));
+      for (int j = 0; j < 4; ++j) Rx[j] = Ry[j] = 0.f;
+    }
+    int ck = 0, cl = 0, c2 = 0;
+    const int h = wv >> 1;
+    if constexpr (WARM) {
+      if (wv < 4) {
+        c2 = a.cand2[(int64_t)vi * kCand3 + (wv & 1) * 64 + kk];
+        ck = c2 >> 6;
+        cl = c2 & (F - 1);
       }
     }
-    // warm start: R_w at the thread's candidate (k, l, s), the same sums.
-    // Thread t takes column t mod 128 and s = t / 128: s is uniform in a
-    // wave, so the lanes' W reads in the update fall on different columns
-    // (no systematic bank conflicts), and lane order is still index order.
-    float rx1 = 0.f, ry1 = 0.f;
-    int ck = 0, cl = 0, cs = 0;
-    if constexpr (WARM) {
-      const int c2 = a.cand2[(int64_t)vi * kCand3 + (t & (kCand3 - 1))];
-      ck = c2 >> 6;
-      cl = c2 & (F - 1);
-      cs = t / kCand3;
-      float2 acc = make_float2(0.f, 0.f);
-      for (int q = 0; q < T; ++q) {
-        const float2 zk = Z[(q * F + cl) * F + ck];
-        const float2 zn = Z[(q * F + ((F - cl) & (F - 1))) * F + ((F - ck) & (F - 1))];
-        acc = cadd(acc, cmul(make_float2(zk.x + zn.x, zk.y - zn.y), tw[(cs * q * (F / FT)) & (F - 1)]));
+    {  // round 1: s = 1, 7, 2, 6
+      __syncthreads();
+      fft2_lk<256>(Wl + (t >> 8) * kFftBuf3, tw, t & 255);
+      float2 wp[4][4];
+      split3<WARM, 1>(Wl + 0 * kFftBuf3, Wl + 1 * kFftBuf3, wv, kk, Rx, Ry, wp[0], ck, cl, h);
+      split3<WARM, 7>(Wl + 1 * kFftBuf3, Wl + 0 * kFftBuf3, wv, kk, Rx, Ry, wp[1], ck, cl, h);
+      split3<WARM, 2>(Wl + 2 * kFftBuf3, Wl + 3 * kFftBuf3, wv, kk, Rx, Ry, wp[2], ck, cl, h);
+      split3<WARM, 6>(Wl + 3 * kFftBuf3, Wl + 2 * kFftBuf3, wv, kk, Rx, Ry, wp[3], ck, cl, h);
+      lds_barrier();  // the buffers are dead
+      store_w3<1>(Wl, wp[0], wv, kk);
+      store_w3<7>(Wl, wp[1], wv, kk);
+      store_w3<2>(Wl, wp[2], wv, kk);
+      store_w3<6>(Wl, wp[3], wv, kk);
+    }
+    {  // round 2: s = 3, 5, over slots 4-7
+      float2* const b3 = Wl + 4 * kSlot3;
+      float2* const b5 = b3 + kFftBuf3;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        b3[(wv + 16 * q) * F + kk] = keep[q][0];
+        b5[(wv + 16 * q) * F + kk] = keep[q][1];
       }
-      rx1 = acc.x * 0.5f;
-      ry1 = acc.y * 0.5f;
+      lds_barrier();
+      fft2_lk<512>(b3 + (t >> 9) * kFftBuf3, tw, t & 511);
+      float2 wp[2][4];
+      split3<WARM, 3>(b3, b5, wv, kk, Rx, Ry, wp[0], ck, cl, h);
+      split3<WARM, 5>(b5, b3, wv, kk, Rx, Ry, wp[1], ck, cl, h);
+      lds_barrier();
+      store_w3<3>(Wl, wp[0], wv, kk);
+      store_w3<5>(Wl, wp[1], wv, kk);
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {  // rounds 3 and 4: s = 0 over slots 6-7, s = 4 over slot 7 and beyond
+      float2* const b = Wl + (6 + r) * kSlot3;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) b[(wv + 16 * q) * F + kk] = keep[q][2 + r];
+      lds_barrier();
+      fft2_lk<1024>(b, tw, t);
+      float2 wp[4];
+      if (r == 0) split3<WARM, 0>(b, b, wv, kk, Rx, Ry, wp, ck, cl, h);
+      else split3<WARM, 4>(b, b, wv, kk, Rx, Ry, wp, ck, cl, h);
+      lds_barrier();
+      if (r == 0) store_w3<0>(Wl, wp, wv, kk);
+      else store_w3<4>(Wl, wp, wv, kk);
+    }
+    // the slots into s order (slot s holds W[., ., s]): the six that move
+    // form one cycle; each thread reads its entries of all six, then writes
+    // them to their places
+    {
+      constexpr uint32_t kFrom = 0x764310u;   // the six moving slots, 4 bits each
+      constexpr uint32_t kOrder = 0x40536271u;  // s held by each slot before the move, 4 bits per slot
+      constexpr int kTail = kSlot3 - 2 * NT;    // 64 entries per slot past 2 NT
+      static_assert(kTail > 0 && 6 * kTail <= NT, "slot tails fit one pass");
+      float2 mv[6][2], mt = make_float2(0.f, 0.f);
+      const int ti = (t / kTail) % 6;           // the slot whose tail entry t % kTail this thread moves
+      const int tfrom = (int)((kFrom >> (4 * ti)) & 15u);
+      lds_barrier();
+#pragma unroll
+      for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int r = 0; r < 2; ++r) mv[i][r] = Wl[(int)((kFrom >> (4 * i)) & 15u) * kSlot3 + t + r * NT];
+      if (t < 6 * kTail) mt = Wl[tfrom * kSlot3 + 2 * NT + t % kTail];
+      lds_barrier();
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        const int to = (int)((kOrder >> (4 * ((kFrom >> (4 * i)) & 15u))) & 7u);
+#pragma unroll
+        for (int r = 0; r < 2; ++r) Wl[to * kSlot3 + t + r * NT] = mv[i][r];
+      }
+      if (t < 6 * kTail) Wl[(int)((kOrder >> (4 * tfrom)) & 7u) * kSlot3 + 2 * NT + t % kTail] = mt;
     }
     __syncthreads();
     const float W0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(Wl[0].x)));
     if (!(W0 > 0.f)) {
       if (t == 0) a.status[vi] = FSE_BLOCK_EMPTY_SUPPORT;
-      __syncthreads();  // Wl and the scratch are overwritten by the next volume
+      __syncthreads();  // LDS is overwritten by the next volume
       continue;
     }
     const float gW = a.gamma * (1.0f / W0);
+    const unsigned char* const Wb = reinterpret_cast<const unsigned char*>(Wl);
     bool finite = true;
     if constexpr (!WARM) {
       // per-thread first maximum of |R_w|^2 (bits) and where it is
       uint32_t best = 0;
       int bj = 0;
-  #pragma unroll
+#pragma unroll
       for (int j = 0; j < BPT; ++j) {
         const uint32_t b2 = __float_as_uint(fmaf(Ry[j], Ry[j], Rx[j] * Rx[j]));
         if (bits_max_first(b2, best)) bj = j;
       }
-      // 4. iterations (eqs. (12), (13), (18))
+      // 3. iterations (eqs. (12), (13), (18))
       for (int it = 0; it < I; ++it) {
         // the thread's candidate, then the wave's (first lane: lowest k), then
         // the workgroup's (largest value, lowest bin index among equals)
@@ -1278,34 +1410,32 @@ __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
         // eq. (18): R_w[k,l,s] -= c W[k-u, l-v, s-s0]. The row l' = (l - v)
         // mod 64 is uniform per column; for l' > 32 the stored value is
         // W[u-k, v-l, s0-s] and its conjugate is used, which swaps the sign of
-        // two of the four products.
+        // two of the four products. The s-slot offsets are uniform.
         const int kq = ((kk - u0) & (F - 1)) * 8, kqf = ((u0 - kk) & (F - 1)) * 8;  // byte offsets
         const unsigned creb = __float_as_uint(cre), cimb = __float_as_uint(cim);
-        const float* const Wb = reinterpret_cast<const float*>(Wl);
         best = 0;
         bj = 0;
-  #pragma unroll
+#pragma unroll
         for (int cc = 0; cc < BPT / FT; ++cc) {
           const int lp = ((BPT / FT) * wv + cc - v0) & (F - 1);
           const bool flip = lp > F / 2;
           const int lrow = flip ? (F - lp) & (F - 1) : lp;
-          const int base = (flip ? kqf : kq) + lrow * (FT * F * 8);
+          const int base = (flip ? kqf : kq) + lrow * (F * 8);
           const float A = __uint_as_float(flip ? cimb ^ 0x80000000u : cimb);
           const float Bc = __uint_as_float(flip ? creb : creb ^ 0x80000000u);
           // the column's eight W values first, so that their loads overlap
           float2 wc[FT];
-  #pragma unroll
+#pragma unroll
           for (int s3 = 0; s3 < FT; ++s3) {
             const int srot = (flip ? s0 - s3 : s3 - s0) & (FT - 1);
-            wc[s3] = *reinterpret_cast<const float2*>(reinterpret_cast<const unsigned char*>(Wb) + base +
-                                                      srot * (F * 8));
+            wc[s3] = *reinterpret_cast<const float2*>(Wb + base + srot * (kSlot3 * 8));
           }
           // keeps the eight loads ahead of the arithmetic (the scheduler would
           // otherwise wait for each load before issuing the next)
           asm volatile("" : "+v"(wc[0].x), "+v"(wc[0].y), "+v"(wc[1].x), "+v"(wc[1].y), "+v"(wc[2].x), "+v"(wc[2].y),
                        "+v"(wc[3].x), "+v"(wc[3].y), "+v"(wc[4].x), "+v"(wc[4].y), "+v"(wc[5].x), "+v"(wc[5].y),
                        "+v"(wc[6].x), "+v"(wc[6].y), "+v"(wc[7].x), "+v"(wc[7].y));
-  #pragma unroll
+#pragma unroll
           for (int s3 = 0; s3 < FT; ++s3) {
             const int j = cc * FT + s3;
             const float2 w = wc[s3];
@@ -1320,35 +1450,37 @@ __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
           }
         }
       }
-    } else {
-      // warm start: one candidate bin per thread (index order within a wave)
-      const int myidx = ((ck << 6) | cl) * FT + cs;
-      uint32_t best = __float_as_uint(fmaf(ry1, ry1, rx1 * rx1));
+    } else if (wv < 4) {
+      // warm start: four candidate bins per lane of waves 0-3
+      uint32_t best = 0;
+      int bj = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (bits_max_first(__float_as_uint(fmaf(Ry[j], Ry[j], Rx[j] * Rx[j])), best)) bj = j;
       for (int it = 0; it < I; ++it) {
         const uint32_t wm = wave_max_bits(best);
         const int wl = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(__ballot(best == wm)));
-        const int widx = __builtin_amdgcn_readlane(myidx, wl);
-        const float wre = readlane_f(rx1, wl), wim = readlane_f(ry1, wl);
-        xch[parity * (NT / 64) + wv] = make_int4((int)wm, widx, __float_as_int(wre), __float_as_int(wim));  // uniform
+        const int jw = __builtin_amdgcn_readlane(bj, wl);
+        const int widx = __builtin_amdgcn_readlane(c2, wl) * FT + 4 * h + jw;
+        const float wre = readlane_f(Rx[jw], wl), wim = readlane_f(Ry[jw], wl);
+        if (kk == 0) xch[parity * 4 + wv] = make_int4((int)wm, widx, __float_as_int(wre), __float_as_int(wim));
         __syncthreads();
         int4 sv = make_int4(0, 0x7fffffff, 0, 0);
-        if (kk < NT / 64) sv = xch[parity * (NT / 64) + kk];
+        if (kk < 4) sv = xch[parity * 4 + kk];
         parity ^= 1;
         unsigned hi = (unsigned)sv.x, lo = ~(unsigned)sv.y;
         dpp_max64<kQuadXor1>(hi, lo);
-        dpp_max64<kQuadXor2>(hi, lo);
-        dpp_max64<kRowHalfMirror>(hi, lo);
-        dpp_max64<kRowMirror>(hi, lo);
+        dpp_max64<kQuadXor2>(hi, lo);  // lanes 0-3: the maximum over the 4 slots
         const uint32_t gm = (uint32_t)__builtin_amdgcn_readlane((int)hi, 0);
         const int gidx = (int)~(unsigned)__builtin_amdgcn_readlane((int)lo, 0);
-        const int ws = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(__ballot(kk < NT / 64 && sv.y == gidx)));
+        const int ws = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(__ballot(kk < 4 && sv.y == gidx)));
         const float gre = __int_as_float(__builtin_amdgcn_readlane(sv.z, ws));
         const float gim = __int_as_float(__builtin_amdgcn_readlane(sv.w, ws));
         const int s0 = gidx & (FT - 1), v0 = (gidx >> 3) & (F - 1), u0 = gidx >> 9;
         const float cre = gW * gre, cim = gW * gim;  // eq. (13)
         finite = finite && isfinite(cre) && isfinite(cim);
-        if (wv == 0) {
-          cl_idx[it] = gidx;  // uniform stores
+        if (wv == 0 && kk == 0) {  // one lane
+          cl_idx[it] = gidx;
           cl_c[it] = make_float2(cre, cim);
           if (a.trace) {
             fse_trace_t rec;
@@ -1360,28 +1492,45 @@ __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
             a.trace[(int64_t)vi * a.trace_stride + it] = rec;
           }
         }
-        // eq. (18) at the candidate: W[k-u, l-v, s-s0], from the mirrored
-        // entry conjugated when (l - v) mod 64 > 32
+        // eq. (18) at the candidates: W[k-u, l-v, s-s0], from the mirrored
+        // entry conjugated when (l - v) mod 64 > 32. The lane's column fixes
+        // the row and k offset; the s-slot offsets of both cases are uniform
+        // and the lane's case picks one with a mask.
         const int lp = (cl - v0) & (F - 1);
         const bool flip = lp > F / 2;
         const int row = flip ? (F - lp) & (F - 1) : lp;
-        const int kx = (flip ? u0 - ck : ck - u0) & (F - 1), sx = (flip ? s0 - cs : cs - s0) & (FT - 1);
-        float2 w = Wl[(row * FT + sx) * F + kx];
-        w.y = flip ? -w.y : w.y;
-        rx1 = fmaf(-cre, w.x, rx1);
-        rx1 = fmaf(cim, w.y, rx1);
-        ry1 = fmaf(-cre, w.y, ry1);
-        ry1 = fmaf(-cim, w.x, ry1);
-        best = __float_as_uint(fmaf(ry1, ry1, rx1 * rx1));
+        const int kx = (flip ? u0 - ck : ck - u0) & (F - 1);
+        const int base = (row * F + kx) * 8;
+        const int fm = flip ? -1 : 0;
+        const float A = flip ? -cim : cim, Bc = flip ? cre : -cre;
+        best = 0;
+        bj = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int sj = 4 * h + j;
+          const int on = ((sj - s0) & (FT - 1)) * (kSlot3 * 8);
+          const int of = ((s0 - sj) & (FT - 1)) * (kSlot3 * 8);
+          const float2 w = *reinterpret_cast<const float2*>(Wb + base + on + ((of - on) & fm));
+          float rx = Rx[j], ry = Ry[j];
+          rx = fmaf(-cre, w.x, rx);
+          rx = fmaf(A, w.y, rx);
+          ry = fmaf(Bc, w.y, ry);
+          ry = fmaf(-cim, w.x, ry);
+          Rx[j] = rx;
+          Ry[j] = ry;
+          if (bits_max_first(__float_as_uint(fmaf(ry, ry, rx * rx)), best)) bj = j;
+        }
       }
+    } else {
+      for (int it = 0; it < I; ++it) __syncthreads();  // one barrier per iteration of waves 0-3
     }
-    __syncthreads();  // the coefficient list is complete
-    if (!finite) {
+    // the coefficient list is complete; every coefficient must be finite
+    if (__syncthreads_or(!finite)) {
       if (t == 0) a.status[vi] = FSE_BLOCK_NONFINITE;
       __syncthreads();
       continue;
     }
-    // 5. model on B (Algorithm 1, last loop, in 3-D): Re{sum c e^{j theta}}
+    // 4. model on B (Algorithm 1, last loop, in 3-D): Re{sum c e^{j theta}}
     const int np = bh * bw * bt;
     for (int p = t; p < np; p += NT) {
       const int tt = p / (bh * bw), rem = p % (bh * bw), i = rem / bw, jj = rem % bw;
@@ -1398,7 +1547,7 @@ __global__ __launch_bounds__(kNT3) void fse3d(Vol3Args a) {
       a.out[((int64_t)(f0 + tt) * a.H + y0 + i) * a.out_pitch + x0 + jj] = acc;
     }
     if (t == 0) a.status[vi] = FSE_BLOCK_OK;
-    __syncthreads();  // Wl, the list and the scratch are overwritten by the next volume
+    __syncthreads();  // LDS is overwritten by the next volume
   }
 }
 
@@ -1959,7 +2108,9 @@ hipError_t launch_class(const Variant& v, const ClassArgs& a, int grid, size_t l
 
 namespace fse {
 size_t lds_bytes3d(int iters_cap) {
-  return (size_t)kHalfCols3 * kF3 * kFt3 * 8 + kF3 * 8 + 2 * (kNT3 / 64) * 16 + (size_t)iters_cap * 12;
+  // the last round's FFT buffer (from slot 7 on) or W and the coefficient list
+  return std::max((size_t)kW3Ofs + (size_t)(7 * kSlot3 + kFftBuf3) * 8,
+                  (size_t)kW3Ofs + kW3Bytes + (size_t)iters_cap * 12);
 }
 
 const void* fse3d_kernel(bool warm) {
