@@ -665,18 +665,25 @@ __device__ __forceinline__ int conceal_block(const ClassArgs& a, const int bi, c
     // the block wait for it at the barrier below: its instructions go ahead
     // of the update streams of the compute unit's other blocks.
     __builtin_amdgcn_s_setprio(3);
-    unsigned lm = mb[0];
+    // running maxima over slot pairs: pm[i] = max over slots 0 .. 2 i + 1
+    constexpr int NP = (BPL + 1) / 2;
+    unsigned pm[NP];
+    pm[0] = BPL > 1 ? max(mb[0], mb[BPL > 1 ? 1 : 0]) : mb[0];
 #pragma unroll
-    for (int j = 1; j < BPL; ++j) lm = max(lm, mb[j]);
+    for (int i = 1; i < NP; ++i) pm[i] = max(pm[i - 1], 2 * i + 1 < BPL ? max(mb[2 * i], mb[2 * i + 1]) : mb[2 * i]);
+    const unsigned lm = pm[NP - 1];
     const unsigned wm = wave_max_bits(lm);
     const unsigned long long cand = __ballot(lm == wm);
     int wj = 0, wl;
     if (__builtin_popcountll(cand) == 1) {
-      // usual case: one lane holds the maximum; find its slot on the scalar unit
+      // usual case: one lane holds the maximum; on the scalar unit, the first
+      // pair whose running maximum reaches it, then the slot within the pair
       wl = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(cand));
+      int pi = NP - 1;
 #pragma unroll
-      for (int j = BPL - 1; j >= 0; --j)
-        wj = ((unsigned)__builtin_amdgcn_readlane((int)mb[j], wl) == wm) ? j : wj;
+      for (int i = NP - 2; i >= 0; --i) pi = ((unsigned)__builtin_amdgcn_readlane((int)pm[i], wl) == wm) ? i : pi;
+      const int j0 = __builtin_amdgcn_readfirstlane(2 * pi);
+      wj = (j0 + 1 < BPL && (unsigned)__builtin_amdgcn_readlane((int)mb[j0], wl) != wm) ? j0 + 1 : j0;
     } else {
       // several lanes hold it (exact ties, e.g. conjugate bins): take the
       // lowest (slot, lane) key over the wave
