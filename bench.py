@@ -61,7 +61,7 @@ def measured_traffic(kernel, n_blocks, workload):
     source or another workload."""
     try:
         with open(TRAFFIC_FILE) as fh:
-            t = json.load(fh).get(kernel)
+            t = json.load(fh).get(f"{kernel}@{workload}")
     except (OSError, ValueError):
         return None
     if not t or t.get("kernel_sha") != kernel_source_hash() or t.get("blocks") != n_blocks \
