@@ -447,15 +447,16 @@ int32_t fse_warm_trace_stride(fse_batch_t batch, int32_t restricted_iters, int32
  * the Conclusion): the same iteration on an F x F x Ft grid, the window
  * rho^(distance) in pixel and frame units, B a lost volume. One workgroup
  * of 1024 threads per volume: R_w in registers (32 bins per thread), the
- * half of W with l <= 32 in LDS (132 KB), the transform as 2-D FFTs of the
- * frames followed by Ft-point DFTs through a scratch buffer in HBM.
+ * half of W with l <= 32 in LDS (132 KB), the transform as Ft-point DFTs
+ * per pixel followed by the 2-D FFTs of the Ft slices in LDS; nothing but
+ * the output is written to device memory.
  *
  * fse_batch3d_create validates h_volumes (fft = 64, fft_t = 8, area within
  * the transform, B inside the clip, 0 <= iters <= the plan's max_iters, no
  * two B overlapping; the plan must not have FSE_PLAN_MASKED_B,
  * FSE_PLAN_REAL or FSE_PLAN_FIXED), uploads
- * them, the 3-D window table and the scratch buffers (256 KB per resident
- * workgroup) to the current device. Synchronous. *bad_index (if not null)
+ * them and the 3-D window table to the current device. Synchronous.
+ * *bad_index (if not null)
  * receives the first offending volume or -1. */
 typedef struct fse_batch3d_s* fse_batch3d_t;
 fse_status_t fse_batch3d_create(fse_plan_t plan, const fse_volume_t* h_volumes, int32_t n_volumes,
