@@ -263,6 +263,22 @@ fse_status_t fse_batch_autotune(fse_batch_t batch, const uint8_t* d_image, const
                                 float* d_out, int64_t out_pitch, int32_t* d_status, int32_t reps, void* stream,
                                 char* report, size_t report_len);
 
+/* The autotuner with a decision cache: a text file of lines "key threads
+ * microseconds", where the key names the device (architecture name and
+ * compute-unit count) and the class (transform size, rectangular or
+ * mask-driven loss areas, block count and largest iteration count rounded
+ * up to powers of two). A class whose key the file holds, with a compiled
+ * variant that fits, is configured from it without timing (report line "F
+ * threads cached"); every other class is timed as by fse_batch_autotune
+ * and its decision appended to the file (created if absent; an unreadable
+ * or unwritable path acts as an empty cache). cache_path null: exactly
+ * fse_batch_autotune. Synchronous when it times; a fully cached call
+ * launches nothing. */
+fse_status_t fse_batch_autotune_cached(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail,
+                                       int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
+                                       int32_t reps, void* stream, char* report, size_t report_len,
+                                       const char* cache_path);
+
 /* Kernel timing, a profiling hook. fse_batch_set_timing(batch, max_records)
  * makes every later kernel launch of this batch (fse_extrapolate_batch,
  * fse_warm_extrapolate_batch; not the autotuner) record a HIP event on its

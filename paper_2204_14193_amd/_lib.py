@@ -50,6 +50,7 @@ SIGNATURES = {
     "fse_batch_launch_info": (I32, [P, I32, PI32, PI32, PI32, PI32]),
     "fse_batch_set_variant": (I32, [P, I32, I32]),
     "fse_batch_autotune": (I32, [P, P, P, I64, P, I64, P, I32, P, C.c_char_p, C.c_size_t]),
+    "fse_batch_autotune_cached": (I32, [P, P, P, I64, P, I64, P, I32, P, C.c_char_p, C.c_size_t, C.c_char_p]),
     "fse_batch_set_timing": (I32, [P, I32]),
     "fse_batch_kernel_times": (I32, [P, P, P, P, I32]),
     "fse_last_error": (C.c_char_p, []),

@@ -12,6 +12,7 @@
 #include <mutex>
 #include <new>
 #include <numeric>
+#include <string>
 #include <vector>
 
 #include "cnn_internal.h"
@@ -639,25 +640,93 @@ extern "C" fse_status_t fse_batch_set_variant(fse_batch_t batch, int32_t F, int3
   return fail(FSE_ERR_UNSUPPORTED, "no compiled kernel with this workgroup shape");
 }
 
-extern "C" fse_status_t fse_batch_autotune(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail,
-                                           int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
-                                           int32_t reps, void* stream, char* report, size_t report_len) {
+namespace {
+
+// Autotuner cache: one text line per decision, "key threads microseconds",
+// the last line of a key winning. The key names the device (architecture
+// and compute-unit count) and the class's shape: transform size, loss-area
+// kind, and the block count and largest iteration count rounded up to
+// powers of two.
+int pow2_at_least(int64_t x) {
+  int p = 0;
+  while (p < 40 && ((int64_t)1 << p) < x) ++p;
+  return p;
+}
+
+std::string tune_key(const hipDeviceProp_t& prop, const fse_batch_s* b, int ci) {
+  std::string arch(prop.gcnArchName);
+  for (char& ch : arch)
+    if (ch == ' ') ch = '_';
+  char buf[160];
+  snprintf(buf, sizeof buf, "/%dcu/F%d/%s/n2^%d/i2^%d", prop.multiProcessorCount, kSizes[ci],
+           (b->plan->flags & FSE_PLAN_MASKED_B) ? "masked" : "rect", pow2_at_least(b->cls[ci].count),
+           pow2_at_least(b->cls[ci].iters_cap));
+  return arch + buf;
+}
+
+int tune_lookup(const char* path, const std::string& key) {
+  FILE* f = path ? std::fopen(path, "r") : nullptr;
+  if (!f) return 0;
+  int threads = 0;
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    char k[400];
+    int t = 0;
+    float us = 0.f;
+    if (std::sscanf(line, "%399s %d %f", k, &t, &us) == 3 && key == k) threads = t;
+  }
+  std::fclose(f);
+  return threads;
+}
+
+void tune_store(const char* path, const std::string& key, int threads, float us) {
+  FILE* f = path ? std::fopen(path, "a") : nullptr;
+  if (!f) return;
+  std::fprintf(f, "%s %d %.3f\n", key.c_str(), threads, us);
+  std::fclose(f);
+}
+
+}  // namespace
+
+extern "C" fse_status_t fse_batch_autotune_cached(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail,
+                                                  int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
+                                                  int32_t reps, void* stream, char* report, size_t report_len,
+                                                  const char* cache_path) {
   if (!batch) return fail(FSE_ERR_INVALID_ARG, "null batch");
   if (reps < 1) return fail(FSE_ERR_INVALID_ARG, "reps must be >= 1");
   if (batch->plan->flags & (FSE_PLAN_REAL | FSE_PLAN_FIXED))
     return fail(FSE_ERR_UNSUPPORTED, "the rFSE and fixed-point kernels have one workgroup shape");
   if (report && report_len) report[0] = 0;
   size_t used = 0;
+  hipDeviceProp_t prop;
+  if (cache_path && hipGetDeviceProperties(&prop, batch->device) != hipSuccess)
+    return fail(FSE_ERR_HIP, "hipGetDeviceProperties failed");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-    return fail(FSE_ERR_HIP, "hipEventCreate failed");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   fse_status_t st = FSE_OK;
   for (int ci = 0; ci < 3 && st == FSE_OK; ++ci) {
     fse_batch_s::Cls& c = batch->cls[ci];
     if (c.count == 0) continue;
     const fse::Variant* vs[16];
     const int nv = std::min(fse::variants_for(kSizes[ci], vs, 16), 16);
+    std::string key;
+    if (cache_path) {
+      // a cached decision for this device and class shape: no timing
+      key = tune_key(prop, batch, ci);
+      const int cached = tune_lookup(cache_path, key);
+      bool hit = false;
+      for (int i = 0; i < nv && cached > 0 && !hit; ++i)
+        if (vs[i]->threads == cached && configure(batch, c, vs[i]) == FSE_OK) hit = true;
+      if (hit) {
+        if (report && used + 64 < report_len)
+          used += (size_t)snprintf(report + used, report_len - used, "%d %d cached\n", kSizes[ci], cached);
+        continue;
+      }
+    }
+    if (!e0 && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) {
+      st = fail(FSE_ERR_HIP, "hipEventCreate failed");
+      break;
+    }
     const fse::Variant* best = nullptr;
     float best_ms = 0.f;
     for (int i = 0; i < nv && st == FSE_OK; ++i) {
@@ -686,11 +755,19 @@ extern "C" fse_status_t fse_batch_autotune(fse_batch_t batch, const uint8_t* d_i
     if (st == FSE_OK) {
       if (!best) st = fail(FSE_ERR_UNSUPPORTED, "no variant fits");
       else st = configure(batch, c, best);
+      if (st == FSE_OK && cache_path) tune_store(cache_path, key, best->threads, 1000.f * best_ms);
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   return st;
+}
+
+extern "C" fse_status_t fse_batch_autotune(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail,
+                                           int64_t pitch, float* d_out, int64_t out_pitch, int32_t* d_status,
+                                           int32_t reps, void* stream, char* report, size_t report_len) {
+  return fse_batch_autotune_cached(batch, d_image, d_avail, pitch, d_out, out_pitch, d_status, reps, stream, report,
+                                   report_len, nullptr);
 }
 
 extern "C" fse_status_t fse_cnn_patches(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail,

@@ -4,6 +4,7 @@ Device memory and streams come from PyTorch; every step of the
 extrapolation runs in the library's HIP kernels.
 """
 import ctypes as C
+import os
 
 import numpy as np
 
@@ -150,21 +151,23 @@ class Batch:
     def set_variant(self, F, threads):
         _check(_lib.lib().fse_batch_set_variant(self._h, int(F), int(threads)), "fse_batch_set_variant")
 
-    def autotune(self, image, avail, out, status, reps=3, stream=None):
+    def autotune(self, image, avail, out, status, reps=3, stream=None, cache=None):
         """Time every compiled workgroup shape on these inputs and keep the
-        fastest per transform size; returns [(F, threads, us), ...]."""
+        fastest per transform size; returns [(F, threads, us), ...] (us None
+        for a decision taken from the cache file `cache`, if given)."""
         import torch
         self._check_tensors(image, avail, out, status)
         s = stream if stream is not None else torch.cuda.current_stream()
         buf = C.create_string_buffer(4096)
-        _check(_lib.lib().fse_batch_autotune(
+        _check(_lib.lib().fse_batch_autotune_cached(
             self._h, C.c_void_p(image.data_ptr()), C.c_void_p(avail.data_ptr()), image.stride(1),
             C.c_void_p(out.data_ptr()), out.stride(1), C.c_void_p(status.data_ptr()), int(reps),
-            C.c_void_p(s.cuda_stream), buf, len(buf)), "fse_batch_autotune")
+            C.c_void_p(s.cuda_stream), buf, len(buf), None if cache is None else os.fsencode(cache)),
+            "fse_batch_autotune_cached")
         rows = []
         for line in buf.value.decode().splitlines():
             f, t, us = line.split()
-            rows.append((int(f), int(t), float(us)))
+            rows.append((int(f), int(t), None if us == "cached" else float(us)))
         return rows
 
     def _check_tensors(self, image, avail, out, status):

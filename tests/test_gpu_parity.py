@@ -204,6 +204,58 @@ def test_autotune_picks_a_variant_and_keeps_results():
     assert np.array_equal(out.cpu().numpy(), ref[0])
 
 
+def test_autotune_cache(tmp_path):
+    """The tuner's decision cache: a first call times every shape of each
+    class and appends one line per class; a second batch of the same shape
+    takes the decisions from the file without timing and keeps results
+    bit-identical; a cached shape that is not compiled is ignored (timed
+    again)."""
+    import torch
+    import paper_2204_14193_amd as fse
+    wl = _ragged_workload()
+    _say("case autotune cache")
+    ref = _run_batch(wl)
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(wl.distorted).to(dev)
+    av = torch.from_numpy(wl.avail).to(dev)
+    cache = tmp_path / "tune.txt"
+    classes = sorted({int(f) for f in wl.blocks["fft"]})
+
+    def tuned():
+        plan = fse.Plan(wl.rho, wl.gamma, int(wl.blocks["iters"].max()))
+        batch = fse.Batch(plan, wl.blocks, *wl.frames.shape)
+        out = (img * (av != 0)).to(torch.float32)
+        status = torch.zeros(len(wl.blocks), dtype=torch.int32, device=dev)
+        rows = batch.autotune(img, av, out, status, reps=1, cache=str(cache))
+        chosen = {F: batch.launch_info(F)["threads"] for F in classes}
+        out.copy_((img * (av != 0)).to(torch.float32))
+        batch.run(img, av, out, status)
+        torch.cuda.synchronize()
+        res = out.cpu().numpy()
+        batch.close()
+        plan.close()
+        return rows, chosen, res
+
+    rows1, chosen1, out1 = tuned()
+    assert all(r[2] is not None for r in rows1) and {r[0] for r in rows1} == set(classes)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == len(classes)
+    assert all(line.split()[0].split("/")[2] in {f"F{F}" for F in classes} for line in lines), lines
+    rows2, chosen2, out2 = tuned()
+    assert sorted(rows2) == [(F, chosen1[F], None) for F in classes], rows2
+    assert chosen2 == chosen1
+    assert np.array_equal(out1, ref[0]) and np.array_equal(out2, ref[0])
+    assert len(cache.read_text().splitlines()) == len(classes)  # nothing timed, nothing appended
+    # a decision naming a shape that is not compiled: that class is timed again
+    key = lines[0].split()[0]
+    with open(cache, "a") as fh:
+        fh.write(f"{key} 96 1.0\n")
+    rows3, chosen3, _ = tuned()
+    F0 = int(key.split("/")[2][1:])
+    assert any(r[0] == F0 and r[2] is not None for r in rows3), rows3
+    assert all(r[2] is None for r in rows3 if r[0] != F0), rows3
+
+
 def _mixed_4k(n_frames=2):
     return workloads.mixed_4k(seeds=tuple(range(2, 2 + n_frames)))
 
