@@ -55,7 +55,8 @@ typedef enum {
   FSE_ERR_UNSUPPORTED = -2,  /* F not in {32,64,128}, area larger than F ... */
   FSE_ERR_OOM = -3,          /* device or host allocation failed             */
   FSE_ERR_HIP = -4,          /* a HIP runtime call failed                    */
-  FSE_ERR_OVERLAP = -5       /* two blocks' loss areas B overlap             */
+  FSE_ERR_OVERLAP = -5,      /* two blocks' loss areas B overlap             */
+  FSE_ERR_WORKSPACE = -6     /* caller's workspace too small or misplaced    */
 } fse_status_t;
 
 /* Per-block result codes written to d_status[i] for block i. */
@@ -211,8 +212,43 @@ fse_status_t fse_blocks_from_mask(const uint8_t* h_avail, int32_t n_frames, int3
 fse_status_t fse_batch_create(fse_plan_t plan, const fse_block_t* h_blocks, int32_t n_blocks,
                               int32_t n_frames, int32_t H, int32_t W, fse_batch_t* out_batch);
 
-/* Release a batch's device memory. Synchronises the device. Null is ignored. */
+/* Release a batch's device memory (none for a batch made by
+ * fse_batch_create_in: its workspace stays the caller's). Synchronises the
+ * device. Null is ignored. */
 void fse_batch_destroy(fse_batch_t batch);
+
+/* Flag of fse_batch_workspace_size and fse_batch_create_in: the workspace
+ * also holds the staging of the warm start's two-kernel form
+ * (fse_warm_extrapolate_batch, n_blocks x (16896 + 4096) bytes). */
+#define FSE_WS_WARM 1u
+
+/* Bytes of device workspace that fse_batch_create_in needs for n_blocks
+ * blocks under `plan`: the block descriptors and their schedule, the
+ * work-queue counters, a copy of the plan's window table of eq. (3) and its
+ * twiddles (and, for FSE_PLAN_FIXED, their integer forms), each array
+ * 256-byte aligned, plus the warm staging when ws_flags has FSE_WS_WARM.
+ * Host-only. FSE_ERR_INVALID_ARG for a null argument, n_blocks < 0 or an
+ * unknown flag; FSE_ERR_UNSUPPORTED for FSE_WS_WARM with a plan the warm
+ * start does not take. */
+fse_status_t fse_batch_workspace_size(fse_plan_t plan, int32_t n_blocks, uint32_t ws_flags, size_t* bytes);
+
+/* fse_batch_create with caller-owned device memory: every device array of
+ * the batch (those of fse_batch_workspace_size) lies in
+ * [d_workspace, d_workspace + ws_bytes), so neither this call, the launches
+ * nor fse_batch_destroy allocate or free device memory, and the plan's
+ * tables are not shared with other batches. d_workspace must be 256-byte
+ * aligned device memory of the current device, ws_bytes at least
+ * fse_batch_workspace_size(plan, n_blocks, ws_flags) and the whole range
+ * inside one allocation; it must stay allocated, and must not be written
+ * by anyone else, until fse_batch_destroy. Results are those of
+ * fse_batch_create's batch, bit for bit. Synchronous (uploads). Errors as
+ * fse_batch_create, plus FSE_ERR_INVALID_ARG for a null, misaligned or
+ * non-device workspace and FSE_ERR_WORKSPACE for one that is too small or
+ * runs past its allocation. A batch made without FSE_WS_WARM returns
+ * FSE_ERR_WORKSPACE from the warm-start calls that need the staging. */
+fse_status_t fse_batch_create_in(fse_plan_t plan, const fse_block_t* h_blocks, int32_t n_blocks,
+                                 int32_t n_frames, int32_t H, int32_t W, void* d_workspace, size_t ws_bytes,
+                                 uint32_t ws_flags, fse_batch_t* out_batch);
 
 /* Largest iteration count among the batch's blocks (the trace stride). */
 int32_t fse_batch_max_iters(fse_batch_t batch);
@@ -393,7 +429,9 @@ fse_status_t fse_cnn_topk(const float* d_logits, int32_t B, int32_t K, int16_t* 
  * restricted selections first. The staging buffer of the two-kernel form
  * (n_blocks x (16896 + 4096) bytes, room for any compiled kc) is allocated
  * by fse_warm_prepare, or by the first call here if that was not called,
- * and kept by the batch until fse_batch_destroy. After fse_warm_prepare
+ * and kept by the batch until fse_batch_destroy; a batch made by
+ * fse_batch_create_in with FSE_WS_WARM takes it from its workspace instead
+ * (without the flag: FSE_ERR_WORKSPACE). After fse_warm_prepare
  * with the same (kc, restricted_iters, fallback_iters) this call allocates
  * nothing and may be captured into a HIP graph; a call with other counts
  * reconfigures the batch (host state only), which a graph captured before

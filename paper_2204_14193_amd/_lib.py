@@ -45,6 +45,8 @@ SIGNATURES = {
     "fse_warm3d_extrapolate_batch": (I32, [P, P, P, I64, P, I64, P, P, P, P, I32, P]),
     "fse_batch_create": (I32, [P, P, I32, I32, I32, I32, C.POINTER(P)]),
     "fse_batch_destroy": (None, [P]),
+    "fse_batch_workspace_size": (I32, [P, I32, C.c_uint32, C.POINTER(C.c_size_t)]),
+    "fse_batch_create_in": (I32, [P, P, I32, I32, I32, I32, P, C.c_size_t, C.c_uint32, C.POINTER(P)]),
     "fse_batch_max_iters": (I32, [P]),
     "fse_extrapolate_batch": (I32, [P, P, P, I64, P, I64, P, P, P]),
     "fse_batch_launch_info": (I32, [P, I32, PI32, PI32, PI32, PI32]),

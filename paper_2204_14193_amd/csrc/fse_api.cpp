@@ -52,6 +52,17 @@ struct DeviceTables {
   float2* twid[3] = {nullptr, nullptr, nullptr};
 };
 
+// Candidate counts the warm start's staging is sized for: the largest
+// compiled one, so that a later change of kc never reallocates it.
+constexpr int kStageKcMax = 512;
+
+// Byte offsets of a batch's device arrays inside one buffer (a caller's
+// workspace), each 256-byte aligned.
+struct WsLayout {
+  size_t blocks = 0, orig = 0, queue = 0, wtab = 0, twid[3] = {0, 0, 0};
+  size_t wtab_q = 0, twid_q = 0, stage_r = 0, stage_w = 0, total = 0;
+};
+
 }  // namespace
 
 struct fse_plan_s {
@@ -98,6 +109,8 @@ struct fse_batch_s {
   size_t alt_lds = 0;
   int32_t* d_wtab_q = nullptr;             // fixed point: integer window table
   int2* d_twid_q = nullptr;                // fixed point: integer twiddles
+  bool in_workspace = false;               // device arrays lie in a caller's workspace (never freed here)
+  DeviceTables ws_tables;                  // the plan tables' copy in that workspace
 };
 
 extern "C" const char* fse_last_error(void) { return g_error; }
@@ -311,20 +324,109 @@ hipError_t timed(fse_batch_s* b, int kind, int fft, hipStream_t s, Go go) {
 
 void free_batch(fse_batch_s* b) {
   free_timing(b);
-  (void)hipFree(b->d_stage_w);
-  (void)hipFree(b->d_stage_r);
-  (void)hipFree(b->d_wtab_q);
-  (void)hipFree(b->d_twid_q);
-  (void)hipFree(b->d_blocks);
-  (void)hipFree(b->d_orig);
-  (void)hipFree(b->d_queue);
+  if (!b->in_workspace) {
+    (void)hipFree(b->d_stage_w);
+    (void)hipFree(b->d_stage_r);
+    (void)hipFree(b->d_wtab_q);
+    (void)hipFree(b->d_twid_q);
+    (void)hipFree(b->d_blocks);
+    (void)hipFree(b->d_orig);
+    (void)hipFree(b->d_queue);
+  }
   delete b;
 }
+
+bool valid_ws_flags(uint32_t ws_flags) { return (ws_flags & ~(uint32_t)FSE_WS_WARM) == 0; }
+
+WsLayout ws_layout(fse_plan_t plan, int32_t n_blocks, uint32_t ws_flags) {
+  WsLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return at;
+  };
+  const size_t n = (size_t)std::max(n_blocks, 0), nb = std::max<size_t>(n, 1);
+  L.blocks = take(nb * sizeof(fse_block_t));
+  L.orig = take(nb * sizeof(int32_t));
+  L.queue = take(3 * 32 * sizeof(int32_t));
+  L.wtab = take(plan->wtab.size() * sizeof(float));
+  for (int c = 0; c < 3; ++c) L.twid[c] = take(plan->twid[c].size() * sizeof(float2));
+  if (plan->flags & FSE_PLAN_FIXED) {
+    L.wtab_q = take((size_t)fse::kWinStride * fse::kWinStride * sizeof(int32_t));
+    L.twid_q = take(64 * sizeof(int2));
+  }
+  if (ws_flags & FSE_WS_WARM) {
+    L.stage_r = take(n * kStageKcMax * sizeof(float2));
+    L.stage_w = take(n * fse::kHalfRows * 64 * sizeof(float2));
+  }
+  L.total = off;
+  return L;
+}
+
+// Batch creation; ws null: the library allocates the batch's device
+// arrays, else they are carved from [ws, ws + ws_bytes) and the plan
+// tables are copied there.
+fse_status_t create_batch(fse_plan_t plan, const fse_block_t* h_blocks, int32_t n_blocks, int32_t n_frames,
+                          int32_t H, int32_t W, uint8_t* ws, size_t ws_bytes, uint32_t ws_flags,
+                          fse_batch_t* out_batch);
 
 }  // namespace
 
 extern "C" fse_status_t fse_batch_create(fse_plan_t plan, const fse_block_t* h_blocks, int32_t n_blocks,
                                          int32_t n_frames, int32_t H, int32_t W, fse_batch_t* out_batch) {
+  return create_batch(plan, h_blocks, n_blocks, n_frames, H, W, nullptr, 0, 0, out_batch);
+}
+
+extern "C" fse_status_t fse_batch_workspace_size(fse_plan_t plan, int32_t n_blocks, uint32_t ws_flags,
+                                                 size_t* bytes) {
+  if (!plan || !bytes) return fail(FSE_ERR_INVALID_ARG, "null argument");
+  *bytes = 0;
+  if (n_blocks < 0) return fail(FSE_ERR_INVALID_ARG, "negative block count");
+  if (!valid_ws_flags(ws_flags)) return fail(FSE_ERR_INVALID_ARG, "unknown workspace flag");
+  if ((ws_flags & FSE_WS_WARM) && (plan->flags & (FSE_PLAN_MASKED_B | FSE_PLAN_REAL | FSE_PLAN_FIXED)))
+    return fail(FSE_ERR_UNSUPPORTED, "the warm start needs a cFSE plan with rectangular loss areas");
+  *bytes = ws_layout(plan, n_blocks, ws_flags).total;
+  return FSE_OK;
+}
+
+extern "C" fse_status_t fse_batch_create_in(fse_plan_t plan, const fse_block_t* h_blocks, int32_t n_blocks,
+                                            int32_t n_frames, int32_t H, int32_t W, void* d_workspace,
+                                            size_t ws_bytes, uint32_t ws_flags, fse_batch_t* out_batch) {
+  if (!out_batch) return fail(FSE_ERR_INVALID_ARG, "null argument");
+  *out_batch = nullptr;
+  size_t need = 0;
+  fse_status_t st = fse_batch_workspace_size(plan, n_blocks, ws_flags, &need);
+  if (st != FSE_OK) return st;
+  if (!d_workspace) return fail(FSE_ERR_INVALID_ARG, "null workspace");
+  if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0)
+    return fail(FSE_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  if (ws_bytes < need) return fail(FSE_ERR_WORKSPACE, "workspace smaller than fse_batch_workspace_size");
+  // the whole range must lie in one device allocation of the current device
+  int dev = -1;
+  hipPointerAttribute_t attr;
+  hipDeviceptr_t base = nullptr;
+  size_t extent = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(FSE_ERR_HIP, "hipGetDevice failed");
+  if (hipPointerGetAttributes(&attr, d_workspace) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+      attr.device != dev) {
+    (void)hipGetLastError();
+    return fail(FSE_ERR_INVALID_ARG, "workspace is not device memory of the current device");
+  }
+  if (hipMemGetAddressRange(&base, &extent, d_workspace) != hipSuccess ||
+      static_cast<uint8_t*>(d_workspace) + need > static_cast<uint8_t*>(base) + extent) {
+    (void)hipGetLastError();
+    return fail(FSE_ERR_WORKSPACE, "workspace extends beyond its allocation");
+  }
+  return create_batch(plan, h_blocks, n_blocks, n_frames, H, W, static_cast<uint8_t*>(d_workspace), ws_bytes,
+                      ws_flags, out_batch);
+}
+
+namespace {
+fse_status_t create_batch(fse_plan_t plan, const fse_block_t* h_blocks, int32_t n_blocks, int32_t n_frames,
+                          int32_t H, int32_t W, uint8_t* ws, size_t ws_bytes, uint32_t ws_flags,
+                          fse_batch_t* out_batch) {
+  (void)ws_bytes;
   if (!out_batch) return fail(FSE_ERR_INVALID_ARG, "null argument");
   *out_batch = nullptr;
   fse_status_t st = fse_validate_blocks(plan, h_blocks, n_blocks, n_frames, H, W, nullptr);
@@ -400,17 +502,46 @@ extern "C" fse_status_t fse_batch_create(fse_plan_t plan, const fse_block_t* h_b
       return st;
     }
   }
-  st = upload_tables(plan, b->device, &b->tables);
-  if (st != FSE_OK) {
-    delete b;
-    return st;
-  }
-  const size_t nb = (size_t)std::max(n_blocks, 1);
-  if (hipMalloc(&b->d_blocks, nb * sizeof(fse_block_t)) != hipSuccess ||
-      hipMalloc(&b->d_orig, nb * sizeof(int32_t)) != hipSuccess ||
-      hipMalloc(&b->d_queue, 3 * 32 * sizeof(int32_t)) != hipSuccess) {
-    free_batch(b);
-    return fail(FSE_ERR_OOM, "hipMalloc failed (batch)");
+  const WsLayout L = ws_layout(plan, n_blocks, ws_flags);
+  if (ws) {
+    b->in_workspace = true;
+    b->d_blocks = reinterpret_cast<fse_block_t*>(ws + L.blocks);
+    b->d_orig = reinterpret_cast<int32_t*>(ws + L.orig);
+    b->d_queue = reinterpret_cast<int32_t*>(ws + L.queue);
+    b->ws_tables.wtab = reinterpret_cast<float*>(ws + L.wtab);
+    for (int c = 0; c < 3; ++c) b->ws_tables.twid[c] = reinterpret_cast<float2*>(ws + L.twid[c]);
+    b->tables = &b->ws_tables;
+    if (plan->flags & FSE_PLAN_FIXED) {
+      b->d_wtab_q = reinterpret_cast<int32_t*>(ws + L.wtab_q);
+      b->d_twid_q = reinterpret_cast<int2*>(ws + L.twid_q);
+    }
+    if (ws_flags & FSE_WS_WARM) {
+      b->d_stage_r = reinterpret_cast<float2*>(ws + L.stage_r);
+      b->d_stage_w = reinterpret_cast<float2*>(ws + L.stage_w);
+      b->stage_kc = kStageKcMax;
+    }
+    bool ok = hipMemcpy(b->ws_tables.wtab, plan->wtab.data(), plan->wtab.size() * sizeof(float),
+                        hipMemcpyHostToDevice) == hipSuccess;
+    for (int c = 0; c < 3 && ok; ++c)
+      ok = hipMemcpy(b->ws_tables.twid[c], plan->twid[c].data(), plan->twid[c].size() * sizeof(float2),
+                     hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+      free_batch(b);
+      return fail(FSE_ERR_HIP, "upload of the plan tables failed");
+    }
+  } else {
+    st = upload_tables(plan, b->device, &b->tables);
+    if (st != FSE_OK) {
+      delete b;
+      return st;
+    }
+    const size_t nb = (size_t)std::max(n_blocks, 1);
+    if (hipMalloc(&b->d_blocks, nb * sizeof(fse_block_t)) != hipSuccess ||
+        hipMalloc(&b->d_orig, nb * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&b->d_queue, 3 * 32 * sizeof(int32_t)) != hipSuccess) {
+      free_batch(b);
+      return fail(FSE_ERR_OOM, "hipMalloc failed (batch)");
+    }
   }
   if ((n_blocks > 0 &&
        (hipMemcpy(b->d_blocks, sorted.data(), n_blocks * sizeof(fse_block_t), hipMemcpyHostToDevice) != hipSuccess ||
@@ -434,8 +565,8 @@ extern "C" fse_status_t fse_batch_create(fse_plan_t plan, const fse_block_t* h_b
       const double th = 2.0 * M_PI * q / 64.0;
       tq[q] = make_int2((int)std::floor(std::cos(th) * 16384.0 + 0.5), (int)std::floor(-std::sin(th) * 16384.0 + 0.5));
     }
-    if (hipMalloc(&b->d_wtab_q, wq.size() * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc(&b->d_twid_q, tq.size() * sizeof(int2)) != hipSuccess) {
+    if (!ws && (hipMalloc(&b->d_wtab_q, wq.size() * sizeof(int32_t)) != hipSuccess ||
+                hipMalloc(&b->d_twid_q, tq.size() * sizeof(int2)) != hipSuccess)) {
       free_batch(b);
       return fail(FSE_ERR_OOM, "hipMalloc failed (fixed-point tables)");
     }
@@ -448,6 +579,7 @@ extern "C" fse_status_t fse_batch_create(fse_plan_t plan, const fse_block_t* h_b
   *out_batch = b;
   return FSE_OK;
 }
+}  // namespace
 
 extern "C" void fse_batch_destroy(fse_batch_t batch) {
   if (!batch) return;
@@ -801,10 +933,6 @@ extern "C" int32_t fse_warm_trace_stride(fse_batch_t batch, int32_t restricted_i
 
 namespace {
 
-// Candidate counts the staging is sized for: the largest compiled one, so
-// that a later change of kc never reallocates it.
-constexpr int kStageKcMax = 512;
-
 fse_status_t warm_check(fse_batch_t batch, const uint8_t* d_image, const uint8_t* d_avail, int64_t pitch,
                         float* d_out, int64_t out_pitch, int32_t* d_status, const int16_t* d_cand,
                         const int32_t* d_flags, int32_t restricted_iters, int32_t fallback_iters) {
@@ -868,6 +996,8 @@ fse_status_t warm_configure(fse_batch_t batch, int32_t kc, int32_t restricted_it
 // sized for kStageKcMax candidates; allocated once.
 fse_status_t warm_staging(fse_batch_t batch) {
   if (!batch->warm_split || (batch->d_stage_w && batch->d_stage_r)) return FSE_OK;
+  if (batch->in_workspace)
+    return fail(FSE_ERR_WORKSPACE, "the batch's workspace holds no warm-start staging (FSE_WS_WARM)");
   if (hipMalloc(&batch->d_stage_r, (size_t)batch->n * kStageKcMax * sizeof(float2)) != hipSuccess) {
     batch->d_stage_r = nullptr;
     return fail(FSE_ERR_OOM, "hipMalloc failed (warm staging)");

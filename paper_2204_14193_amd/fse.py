@@ -28,7 +28,8 @@ assert VOLUME_DTYPE.itemsize == C.sizeof(_lib.fse_volume_t) == 32
 assert TRACE_DTYPE.itemsize == C.sizeof(_lib.fse_trace_t) == 16
 
 _STATUS = {0: "FSE_OK", -1: "FSE_ERR_INVALID_ARG", -2: "FSE_ERR_UNSUPPORTED",
-           -3: "FSE_ERR_OOM", -4: "FSE_ERR_HIP", -5: "FSE_ERR_OVERLAP"}
+           -3: "FSE_ERR_OOM", -4: "FSE_ERR_HIP", -5: "FSE_ERR_OVERLAP",
+           -6: "FSE_ERR_WORKSPACE"}
 
 
 class FseError(RuntimeError):
@@ -50,6 +51,7 @@ def _blocks_array(blocks):
     return arr
 
 
+WS_WARM = 1  # FSE_WS_WARM: the workspace also holds the warm-start staging
 PLAN_MASKED_B = 1  # FSE_PLAN_MASKED_B of include/fse.h
 PLAN_REAL = 2      # FSE_PLAN_REAL: real-valued FSE (rFSE)
 PLAN_FIXED = 4     # FSE_PLAN_FIXED: fixed-point cFSE
@@ -94,6 +96,14 @@ class Plan:
                                             int(n_frames), int(H), int(W), C.byref(bad))
         return st, bad.value
 
+    def workspace_size(self, n_blocks, warm=False):
+        """Device bytes a Batch of n_blocks needs in a caller's workspace
+        (fse_batch_workspace_size; warm=True adds the warm-start staging)."""
+        n = C.c_size_t()
+        _check(_lib.lib().fse_batch_workspace_size(self._h, int(n_blocks), WS_WARM if warm else 0, C.byref(n)),
+               "fse_batch_workspace_size")
+        return n.value
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.lib().fse_plan_destroy(self._h)
@@ -109,12 +119,25 @@ class Plan:
 class Batch:
     """fse_batch_t: a validated, scheduled block list resident on the GPU."""
 
-    def __init__(self, plan, blocks, n_frames, H, W):
+    def __init__(self, plan, blocks, n_frames, H, W, workspace=None, warm=False):
+        """workspace: None (the library allocates the batch's device memory)
+        or a CUDA uint8 tensor of at least plan.workspace_size(len(blocks),
+        warm) bytes that holds it instead (fse_batch_create_in; the batch
+        keeps a reference)."""
         arr = _blocks_array(blocks)
         h = C.c_void_p()
-        _check(_lib.lib().fse_batch_create(plan.handle, arr.ctypes.data_as(C.c_void_p), len(arr),
-                                           int(n_frames), int(H), int(W), C.byref(h)),
-               "fse_batch_create")
+        if workspace is None:
+            _check(_lib.lib().fse_batch_create(plan.handle, arr.ctypes.data_as(C.c_void_p), len(arr),
+                                               int(n_frames), int(H), int(W), C.byref(h)),
+                   "fse_batch_create")
+        else:
+            if not workspace.is_cuda or not workspace.is_contiguous():
+                raise ValueError("workspace must be a contiguous CUDA tensor")
+            _check(_lib.lib().fse_batch_create_in(
+                plan.handle, arr.ctypes.data_as(C.c_void_p), len(arr), int(n_frames), int(H), int(W),
+                C.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),
+                WS_WARM if warm else 0, C.byref(h)), "fse_batch_create_in")
+        self._workspace = workspace
         self._h = h
         self.plan = plan
         self.n = len(arr)
@@ -204,6 +227,7 @@ class Batch:
         if getattr(self, "_h", None):
             _lib.lib().fse_batch_destroy(self._h)
             self._h = None
+            self._workspace = None
 
     def __del__(self):
         try:

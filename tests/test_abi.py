@@ -200,3 +200,38 @@ def test_real_plan_flags():
     assert L.fse_plan_create(C.byref(d), C.byref(h)) == -1
     d = _lib.fse_plan_desc_t(0.8, 0.5, 100, 32)
     assert L.fse_plan_create(C.byref(d), C.byref(h)) == -1
+
+
+def test_batch_workspace_size_and_host_rejections():
+    """fse_batch_workspace_size is host-only: 256-byte aligned arrays for the
+    descriptors (24 B), the schedule (4 B), the queue counters, the plan
+    tables, the fixed-point tables and the warm staging; fse_batch_create_in
+    rejects a null, misaligned or short workspace before any device call."""
+    import paper_2204_14193_amd as fse
+    from paper_2204_14193_amd import _lib
+    L = _lib.lib()
+    up = lambda b: (b + 255) // 256 * 256
+    plan = fse.Plan(0.8, 0.5, 500)
+    base0 = plan.workspace_size(0)
+    assert base0 == plan.workspace_size(1) and base0 % 256 == 0
+    for n in (1, 10, 11, 1000, 4097):
+        got = plan.workspace_size(n)
+        assert got - base0 == up(24 * n) - 256 + up(4 * n) - 256
+        assert plan.workspace_size(n, warm=True) - got == up(n * 512 * 8) + up(n * 33 * 64 * 8)
+    fixed = fse.Plan(0.8, 0.5, 500, fixed=True)
+    assert fixed.workspace_size(10) - plan.workspace_size(10) == 128 * 128 * 4 + 512
+    for bad_plan, n, flags, code in ((plan, -1, 0, -1), (plan, 1, 2, -1),
+                                     (fse.Plan(0.8, 0.5, 500, masked=True), 1, 1, -2),
+                                     (fixed, 1, 1, -2)):
+        nbytes = C.c_size_t(7)
+        assert L.fse_batch_workspace_size(bad_plan.handle, n, flags, C.byref(nbytes)) == code
+        assert nbytes.value == 0
+    assert L.fse_batch_workspace_size(None, 1, 0, C.byref(C.c_size_t())) == -1
+    assert L.fse_batch_workspace_size(plan.handle, 1, 0, None) == -1
+    blk = losses.blocks_to_array([losses.Block(0, 32, 32, 16, 16, 16, 64, 10)])
+    need = plan.workspace_size(1)
+    for ptr, size, code in ((None, need, -1), (0x100008, need, -1), (0x100000, need - 1, -6)):
+        h = C.c_void_p()
+        assert L.fse_batch_create_in(plan.handle, blk.ctypes.data_as(C.c_void_p), 1, 1, 128, 128,
+                                     C.c_void_p(ptr), size, 0, C.byref(h)) == code
+        assert not h.value
