@@ -19,6 +19,10 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -31,7 +35,23 @@ __device__ __forceinline__ f32x16 mfma(uint4 a, uint4 b, f32x16 c) {
                                                  0, 0, 0);
 }
 
+// 16 x 16 x 32 product: lane l supplies 8 K elements of row l%16 of A and
+// of column l%16 of B (the same K elements in both, group l/16); accumulator
+// i of lane l holds D[4*(l/16) + i][l%16].
+__device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                 0, 0, 0);
+}
+
 __device__ __forceinline__ int drow(int i, int lane) { return 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3); }
+
+// Workgroup barrier that orders LDS accesses only: global loads in flight
+// (weights requested ahead of their layer) stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 // Sum over the 64 lanes of a wave, the same value in every lane.
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
@@ -44,51 +64,97 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
   return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
+// Position of grid column gx within its row: a row holds its even columns
+// first, then its odd ones, so that the stride-2 taps of consecutive output
+// pixels are consecutive entries and a wave's tap reads are free of LDS
+// bank conflicts. Tap dx = 0, 1, 2 of output column x lies at x, x + (G+1)/2
+// and x + 1.
+template <int G>
+__device__ __forceinline__ constexpr int gpos(int gx) { return (gx & 1) ? (G + 1) / 2 + (gx >> 1) : gx >> 1; }
+template <int G>
+__device__ __forceinline__ constexpr int tap_col(int dx) { return dx == 0 ? 0 : dx == 1 ? (G + 1) / 2 : 1; }
+
 // ------------------------------------------------------------------ patches
-// Network input of block `b` (48x48 area) into `out` (one word per pixel:
-// the two BF16 channels; rows of 48 words, or rows of `grid` words from
-// (1, 1) on), by the 256 threads of a workgroup; `red` is 8 words of LDS.
-// Channel 0 = (s - mean over A)/64 on A, channel 1 = 1 on A.
-__device__ __forceinline__ void build_input(const uint8_t* img, const uint8_t* avail, int64_t pitch, int H, int W,
-                                            const fse_block_t& bd, uint32_t* out, uint32_t (*red)[4], int t,
-                                            int grid = 0) {
+// Network input of a block (its 48x48 area): one word per pixel, the two
+// BF16 channels, channel 0 = (s - mean over A)/64 on A, channel 1 = 1 on A
+// (0 elsewhere). Built by four waves in two halves, so that a pipelined
+// caller can put a barrier of its own between them: input_load (wave w of
+// the four reads area rows w, w + 4, ..., lane l < 48 column l; a row's
+// address is uniform, so a pixel costs its two byte loads) keeps the 12
+// pixel values and the mask of those in A, and writes the wave's integer
+// sums over A to red[.][w]; after a barrier, input_store forms the mean
+// (integer sums: exact in any order) and writes the rows.
+struct InputRows {
+  uint32_t pv[3];  // 12 pixel values, four per word
+  uint32_t in_a;   // bit r: row r's pixel lies in A
+};
+
+__device__ __forceinline__ InputRows input_load(const uint8_t* img, const uint8_t* avail, int64_t pitch, int H,
+                                                int W, const fse_block_t& bd, uint32_t (*red)[4], int wave,
+                                                int lane) {
+  constexpr int R = kIn / 4;  // rows per wave
   const int bo = bd.border;
   const int ya = bd.y0 - bo, xa = bd.x0 - bo;
-  const uint8_t* im = img + (int64_t)bd.frame * H * pitch;
-  const uint8_t* av = avail + (int64_t)bd.frame * H * pitch;
-  // pixel values and counts are integers, so their sums are exact in any order
+  const int c = min(lane, kIn - 1);
+  const int x = xa + c;
+  const bool col_in = lane < kIn && x >= 0 && x < W;
+  const bool col_b = c >= bo && c < bo + bd.bw;
+  const int xo = min(max(x, 0), W - 1);
+  const uint8_t* const im = img + (int64_t)bd.frame * H * pitch;
+  const uint8_t* const av = avail + (int64_t)bd.frame * H * pitch;
+  InputRows out = {{0u, 0u, 0u}, 0u};
   uint32_t sum = 0, cnt = 0;
-  uint32_t sv[9];
-  bool ia[9];
+  // two passes of six rows, each with all of its loads first (row base
+  // uniform, column offset per lane); a scheduling barrier keeps the second
+  // pass's loads behind the first pass's use, which bounds the registers
 #pragma unroll
-  for (int r = 0; r < 9; ++r) {
-    const int e = t + 256 * r;
-    const int m = e / kIn, c = e % kIn;
-    const int y = ya + m, xx = xa + c;
-    const bool inB = m >= bo && m < bo + bd.bh && c >= bo && c < bo + bd.bw;
-    const bool inside = !inB && y >= 0 && y < H && xx >= 0 && xx < W;
-    const int64_t p = (int64_t)min(max(y, 0), H - 1) * pitch + min(max(xx, 0), W - 1);
-    const uint32_t a = av[p], s = im[p];
-    ia[r] = inside && a != 0;
-    sv[r] = s;
-    sum += ia[r] ? s : 0u;
-    cnt += ia[r] ? 1u : 0u;
+  for (int r0 = 0; r0 < R; r0 += R / 2) {
+    uint32_t sv[R / 2], ab[R / 2];
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) {
+      const int64_t ro = (int64_t)min(max(ya + wave + 4 * (r0 + i), 0), H - 1) * pitch;
+      ab[i] = (av + ro)[(uint32_t)xo];
+      sv[i] = (im + ro)[(uint32_t)xo];
+    }
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) {
+      const int r = r0 + i;
+      const int m = wave + 4 * r;
+      const int y = ya + m;
+      const bool row_in = y >= 0 && y < H;
+      const bool row_b = m >= bo && m < bo + bd.bh;
+      const bool ia = col_in && row_in && !(row_b && col_b) && ab[i] != 0;
+      sum += ia ? sv[i] : 0u;
+      cnt += ia ? 1u : 0u;
+      out.in_a |= ia ? 1u << r : 0u;
+      out.pv[r >> 2] |= sv[i] << (8 * (r & 3));
+    }
+    __builtin_amdgcn_sched_barrier(0);
   }
   sum = wave_sum_u32(sum);
   cnt = wave_sum_u32(cnt);
-  if ((t & 63) == 0) {
-    red[0][t >> 6] = sum;
-    red[1][t >> 6] = cnt;
+  if (lane == 0) {
+    red[0][wave] = sum;
+    red[1][wave] = cnt;
   }
-  __syncthreads();
+  return out;
+}
+
+// Rows of 48 words, or (GRID) the guarded 49 x 49 grid from (1, 1) on.
+template <bool GRID>
+__device__ __forceinline__ void input_store(const InputRows& in, const uint32_t (*red)[4], uint32_t* out, int wave,
+                                            int lane) {
   const uint32_t S = red[0][0] + red[0][1] + red[0][2] + red[0][3];
   const uint32_t N = red[1][0] + red[1][1] + red[1][2] + red[1][3];
   const float mu = N > 0 ? (float)S / (float)N : 0.f;
+  if (lane < kIn) {
 #pragma unroll
-  for (int r = 0; r < 9; ++r) {
-    const int e = t + 256 * r;
-    const int o = grid ? (e / kIn + 1) * grid + e % kIn + 1 : e;  // dense rows, or the guarded grid
-    out[o] = ia[r] ? ((uint32_t)f2bf((sv[r] - mu) * (1.0f / 64.0f)) | (0x3f80u << 16)) : 0u;
+    for (int r = 0; r < kIn / 4; ++r) {
+      const int m = wave + 4 * r;
+      const uint32_t sv = (in.pv[r >> 2] >> (8 * (r & 3))) & 0xffu;
+      const int o = GRID ? (m + 1) * (kIn + 1) + gpos<kIn + 1>(lane + 1) : m * kIn + lane;
+      out[o] = ((in.in_a >> r) & 1u) ? ((uint32_t)f2bf((sv - mu) * (1.0f / 64.0f)) | (0x3f80u << 16)) : 0u;
+    }
   }
 }
 
@@ -98,19 +164,21 @@ __global__ __launch_bounds__(256) void k_patches(const uint8_t* img, const uint8
   __shared__ uint32_t red[2][4];
   const int b = blockIdx.x;
   if (b >= n) return;
-  build_input(img, avail, pitch, H, W, blocks[b], reinterpret_cast<uint32_t*>(x + (int64_t)orig[b] * kPatchElems),
-              red, threadIdx.x);
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const InputRows in = input_load(img, avail, pitch, H, W, blocks[b], red, wave, lane);
+  lds_barrier();
+  input_store<false>(in, red, reinterpret_cast<uint32_t*>(x + (int64_t)orig[b] * kPatchElems), wave, lane);
 }
 
 // ------------------------------------------------------------------ forward
 // Layouts in LDS. A layer's input sits on a (H+1) x (H+1) grid whose row 0
 // and column 0 are zero, the pixel (y, x) at (y+1, x+1): the taps of a 3x3
 // stride-2 convolution with padding 1 then never leave the grid, and every
-// A-operand read is a per-lane base plus a compile-time offset. The network
-// input (2 channels) is one 32-bit word per grid point; 32-channel
-// activations are four planes of 8 channels (16 bytes per grid point per
-// plane), so that the stride-2 reads of consecutive lanes fall 32 bytes
-// apart across the LDS banks.
+// activation-operand read is a per-lane base plus a compile-time offset.
+// Each grid row stores its even columns first, then its odd ones (gpos), so
+// consecutive output pixels read consecutive entries. The network input (2
+// channels) is one 32-bit word per grid point; 32-channel activations are
+// four planes of 8 channels (16 bytes per grid point per plane).
 template <int G>
 __device__ __forceinline__ constexpr int plane_elems() { return G * G * 8; }
 
@@ -125,96 +193,89 @@ __device__ __forceinline__ void zero_guard(uint16_t* buf, int t) {
   }
 }
 
-// Weights of one layer as MFMA A fragments: lane l holds output channel
-// l & 31 and depth values 16 ks + 8 (l >> 5) .. + 8 of step ks, and the
-// biases of the output channels its accumulators hold (8 g + 4 (l >> 5) +
-// 0..3 for g = 0..3), as BF16.
+// Weights of the first layer (2 input channels: depth 18, padded to 32) as
+// fragments of the 32 x 32 x 16 product: lane l holds output channel l & 31
+// and depth values 16 ks + 8 (l >> 5) .. + 8 of step ks. Depth 18, the first
+// padding slot, holds the channel's bias and the input side supplies a 1
+// there, so that the product adds the bias.
 struct LayerW {
-  uint4 w[18];
-  uint2 b[4];
+  uint4 w[2];
 };
 
-template <int CIN>
-__device__ __forceinline__ void load_layer(const uint16_t* w, const uint16_t* bias, LayerW& L, int lane) {
-  constexpr int K = 9 * CIN, KS = (K + 15) / 16;
+__device__ __forceinline__ void load_layer1(const uint16_t* w, const uint16_t* bias, LayerW& L, int lane) {
+  constexpr int K = 9 * 2;
   const int n = lane & 31, h = lane >> 5;
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) {
+  for (int ks = 0; ks < 2; ++ks) {
     const int k0 = ks * 16 + 8 * h;
-    if constexpr (CIN == kCh) {
-      L.w[ks] = *reinterpret_cast<const uint4*>(w + n * K + k0);
-    } else {
-      uint32_t b4[4];
+    uint32_t b4[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int k = k0 + 2 * q;
-        const uint32_t lo = k < K ? w[n * K + k] : 0u;
-        const uint32_t hi = k + 1 < K ? w[n * K + k + 1] : 0u;
-        b4[q] = lo | (hi << 16);
-      }
-      L.w[ks] = make_uint4(b4[0], b4[1], b4[2], b4[3]);
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + 2 * q;  // even: depth K is a low half
+      const uint32_t lo = k < K ? w[n * K + k] : k == K ? bias[n] : 0u;
+      const uint32_t hi = k + 1 < K ? w[n * K + k + 1] : 0u;
+      b4[q] = lo | (hi << 16);
     }
+    L.w[ks] = make_uint4(b4[0], b4[1], b4[2], b4[3]);
   }
-#pragma unroll
-  for (int g = 0; g < 4; ++g) L.b[g] = *reinterpret_cast<const uint2*>(bias + 8 * g + 4 * h);
 }
 
+// ReLU of two values, rounded to BF16 and packed (a in the low half): one
+// v_cvt_pk_bf16_f32, then a signed 16-bit maximum with 0 on both halves,
+// which maps every negative BF16 value (-0 included) to +0 and keeps the
+// others. Rounding and ReLU commute for ordered values; a NaN with the sign
+// bit clear stays NaN.
 __device__ __forceinline__ uint32_t relu_pack(float a, float b) {
-  return (uint32_t)f2bf(fmaxf(a, 0.f)) | ((uint32_t)f2bf(fmaxf(b, 0.f)) << 16);
+  const f32x2 v = {a, b};
+  const s16x2 h = __builtin_bit_cast(s16x2, __builtin_convertvector(v, bf16x2));
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(h, (s16x2){0, 0}));
 }
 
-// One 3x3 stride-2 convolution with bias and ReLU as an implicit GEMM:
-// D[channel][pixel] = W[channel][depth] X[depth][pixel], depth = (tap,
-// input channel), pixels in tiles of 32 (tile = wave, wave + 4, ... run two
-// at a time). Each lane of the result holds one pixel and 16 output
-// channels, 4 consecutive ones per 8-channel plane, stored as one 8-byte
-// write per plane. The output goes to a guarded grid (PAD) or, for the last
-// layer, to an unguarded 3x3 planar buffer.
-template <int CIN, int HIN, bool PAD>
-__device__ __forceinline__ void conv_layer(const uint16_t* in, uint16_t* out, const LayerW& L, int t) {
-  constexpr int HO = HIN / 2, P = HO * HO, K = 9 * CIN, KS = (K + 15) / 16;
+// The first layer, a 3x3 stride-2 convolution of the 2-channel input with
+// bias and ReLU as an implicit GEMM: D[channel][pixel] = W[channel][depth]
+// X[depth][pixel], depth = (tap, input channel), pixels in tiles of 32 (tile
+// = wave, wave + 4, ... run two at a time). Step 0 holds taps 0-3 (lanes
+// l < 32) and 4-7 (l >= 32), step 1 tap 8 and the bias slot (l < 32) and
+// zeros. Each lane of the result holds one pixel and 16 output channels, 4
+// consecutive ones per 8-channel plane, stored as one 8-byte write per
+// plane into the guarded 25 x 25 grid.
+__device__ __forceinline__ void conv_layer1(const uint16_t* in, uint16_t* out, const LayerW& L, int t) {
+  constexpr int HIN = kIn, HO = HIN / 2, P = HO * HO;
   constexpr int MT = (P + 31) / 32;
   constexpr int G = HIN + 1;            // input grid
-  constexpr int GO = HO + 1;            // output grid (PAD)
+  constexpr int GO = HO + 1;            // output grid
   const int lane = t & 63, wave = t >> 6;
   const int h = lane >> 5;              // which 8 of the 16 depth values of a step
-  // grid index of tap (0, 0) of the output pixel in column `lane & 31` of a
-  // tile (columns past the end repeat the last pixel; they are not stored)
+  const uint32_t* gw = reinterpret_cast<const uint32_t*>(in);
+  // word offsets of this lane's taps of step 0, relative to tap 0
+  int off[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int ta = q, tb = 4 + q;
+    const int oa = (ta / 3) * G + tap_col<G>(ta % 3), ob = (tb / 3) * G + tap_col<G>(tb % 3);
+    off[q] = h ? ob : oa;
+  }
+  constexpr int o8 = 2 * G + tap_col<G>(2);  // tap 8
+  const uint32_t keep = h ? 0u : ~0u;        // lanes l >= 32 read the zero word 0 for step 1
+  const uint32_t one = h ? 0u : 0x3f80u;     // BF16 1 against the bias slot
+  // word of tap 0 of the output pixel in column `lane & 31` of a tile
+  // (columns past the end repeat the last pixel; they are not stored)
   auto base_of = [&](int tile) {
     const int m = min(tile * 32 + (lane & 31), P - 1);
-    return 2 * (m / HO) * G + 2 * (m % HO);
+    return 2 * (m / HO) * G + m % HO;
   };
-  auto gather = [&](int base, int ks) -> uint4 {
-    if constexpr (CIN == kCh) {
-      // step ks: tap ks/2, input channels (ks & 1)*16 + 8h .. +8, i.e. plane (ks & 1)*2 + h
-      const int tap = ks >> 1;
-      const uint16_t* p = in + ((ks & 1) * 2 + h) * plane_elems<G>() + (base + (tap / 3) * G + tap % 3) * 8;
-      return *reinterpret_cast<const uint4*>(p);
-    } else {
-      // step ks, word q: tap 8*ks + 4h + q (both input channels), zero past tap 8
-      const uint32_t* gw = reinterpret_cast<const uint32_t*>(in);
-      uint32_t a4[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int t0 = 8 * ks + q, t1 = 8 * ks + 4 + q;  // the tap for h = 0 and h = 1
-        const int o0 = t0 < 9 ? (t0 / 3) * G + t0 % 3 : 0;
-        const int o1 = t1 < 9 ? (t1 / 3) * G + t1 % 3 : 0;
-        const uint32_t v = gw[base + (h ? o1 : o0)];
-        a4[q] = (h ? t1 < 9 : t0 < 9) ? v : 0u;
-      }
-      return make_uint4(a4[0], a4[1], a4[2], a4[3]);
-    }
+  auto gather0 = [&](int base) -> uint4 {
+    return make_uint4(gw[base + off[0]], gw[base + off[1]], gw[base + off[2]], gw[base + off[3]]);
   };
+  auto gather1 = [&](int base) -> uint4 { return make_uint4(gw[(base + o8) & keep], one, 0u, 0u); };
   auto store = [&](int tile, const f32x16& acc) {
     const int p = tile * 32 + (lane & 31);
     if (p >= P) return;
-    const int px = PAD ? (p / HO + 1) * GO + p % HO + 1 : p;
-    constexpr int PE = PAD ? plane_elems<GO>() : P * 8;
+    const int px = (p / HO + 1) * GO + gpos<GO>(p % HO + 1);
+    constexpr int PE = plane_elems<GO>();
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-      const uint2 bb = L.b[g];
-      const uint2 v = make_uint2(relu_pack(acc[4 * g] + bf2f(bb.x & 0xffff), acc[4 * g + 1] + bf2f(bb.x >> 16)),
-                                 relu_pack(acc[4 * g + 2] + bf2f(bb.y & 0xffff), acc[4 * g + 3] + bf2f(bb.y >> 16)));
+      const uint2 v = make_uint2(relu_pack(acc[4 * g], acc[4 * g + 1]), relu_pack(acc[4 * g + 2], acc[4 * g + 3]));
       *reinterpret_cast<uint2*>(out + g * PE + px * 8 + 4 * h) = v;
     }
   };
@@ -224,17 +285,88 @@ __device__ __forceinline__ void conv_layer(const uint16_t* in, uint16_t* out, co
     f32x16 acc = {}, acc2 = {};
     if (tile2 < MT) {
       const int b2 = base_of(tile2);
+      const uint4 a1 = gather0(b1), a2 = gather0(b2);
+      const uint4 c1 = gather1(b1), c2 = gather1(b2);
+      acc = mfma(L.w[0], a1, acc);
+      acc2 = mfma(L.w[0], a2, acc2);
+      acc = mfma(L.w[1], c1, acc);
+      acc2 = mfma(L.w[1], c2, acc2);
+      store(tile, acc);
+      store(tile2, acc2);
+    } else {
+      acc = mfma(L.w[0], gather0(b1), acc);
+      acc = mfma(L.w[1], gather1(b1), acc);
+      store(tile, acc);
+    }
+  }
+}
+
+// Weights of one 32-channel layer for the 16 x 16 x 32 product, half `hf`
+// of its output channels: lane l holds output channel 16 hf + l%16 and the
+// input channels 8 (l/16) .. + 8 of each of the 9 taps (one depth step per
+// tap), and the biases of the 4 channels its accumulators hold (16 hf +
+// 4 (l/16) + 0..3), widened to FP32 once.
+struct HalfW {
+  uint4 w[9];
+  float4 b;
+};
+
+__device__ __forceinline__ void load_half(const uint16_t* w, const uint16_t* bias, HalfW& L, int hf, int lane) {
+  const int n = 16 * hf + (lane & 15), g = lane >> 4;
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const uint4 a1 = gather(b1, ks), a2 = gather(b2, ks);
-        acc = mfma(L.w[ks], a1, acc);
-        acc2 = mfma(L.w[ks], a2, acc2);
+  for (int s = 0; s < 9; ++s) L.w[s] = *reinterpret_cast<const uint4*>(w + n * (9 * kCh) + s * kCh + 8 * g);
+  const uint2 bb = *reinterpret_cast<const uint2*>(bias + 16 * hf + 4 * g);
+  L.b = make_float4(bf2f(bb.x & 0xffff), bf2f(bb.x >> 16), bf2f(bb.y & 0xffff), bf2f(bb.y >> 16));
+}
+
+// A 3x3 stride-2 convolution of 32 input channels with bias and ReLU on the
+// 16 x 16 x 32 product: output tiles of 16 channels (half hf) x 16 pixels,
+// depth step s = tap s over the 32 input channels, so that lane l reads the
+// 16 bytes of plane l/16 at the tap's grid point of its pixel. The wave runs
+// tiles first, first + 2, ... (two at a time); the other wave of its half
+// takes the tiles in between. Output layout as conv_layer1, to a guarded
+// grid (PAD) or, for the last layer, an unguarded 3x3 planar buffer.
+template <int HIN, bool PAD>
+__device__ __forceinline__ void conv32(const uint16_t* in, uint16_t* out, const HalfW& L, int hf, int first, int t) {
+  constexpr int HO = HIN / 2, P = HO * HO, MT = (P + 15) / 16;
+  constexpr int G = HIN + 1, GO = HO + 1;
+  const int lane = t & 63, g = lane >> 4, col = lane & 15;
+  const uint16_t* const inp = in + g * plane_elems<G>();
+  // element offset of tap (0, 0) of the pixel in column `col` of a tile
+  // (columns past the end repeat the last pixel; they are not stored)
+  auto base_of = [&](int tile) {
+    const int m = min(tile * 16 + col, P - 1);
+    return (2 * (m / HO) * G + m % HO) * 8;
+  };
+  auto tap = [&](int base, int s) -> uint4 {
+    return *reinterpret_cast<const uint4*>(inp + base + ((s / 3) * G + tap_col<G>(s % 3)) * 8);
+  };
+  auto store = [&](int tile, const f32x4& acc) {
+    const int p = tile * 16 + col;
+    if (p >= P) return;
+    const int px = PAD ? (p / HO + 1) * GO + gpos<GO>(p % HO + 1) : p;
+    constexpr int PE = PAD ? plane_elems<GO>() : P * 8;
+    const int ch = 16 * hf + 4 * g;
+    const uint2 v = make_uint2(relu_pack(acc[0] + L.b.x, acc[1] + L.b.y), relu_pack(acc[2] + L.b.z, acc[3] + L.b.w));
+    *reinterpret_cast<uint2*>(out + (ch >> 3) * PE + px * 8 + (ch & 7)) = v;
+  };
+  for (int tile = first; tile < MT; tile += 4) {
+    const int tile2 = tile + 2;
+    const int b1 = base_of(tile);
+    f32x4 acc = {}, acc2 = {};
+    if (tile2 < MT) {
+      const int b2 = base_of(tile2);
+#pragma unroll
+      for (int s = 0; s < 9; ++s) {
+        const uint4 a1 = tap(b1, s), a2 = tap(b2, s);
+        acc = mfma16(L.w[s], a1, acc);
+        acc2 = mfma16(L.w[s], a2, acc2);
       }
       store(tile, acc);
       store(tile2, acc2);
     } else {
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) acc = mfma(L.w[ks], gather(b1, ks), acc);
+      for (int s = 0; s < 9; ++s) acc = mfma16(L.w[s], tap(b1, s), acc);
       store(tile, acc);
     }
   }
@@ -248,7 +380,7 @@ __device__ __forceinline__ void copy_act_nhwc(const uint16_t* src, uint16_t* dst
   for (int i = t; i < H * H * 4; i += 256) {
     const int px = i >> 2, g = i & 3;
     const int y = px / H, x = px % H;
-    reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[g * G * G + (y + 1) * G + x + 1];
+    reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[g * G * G + (y + 1) * G + gpos<G>(x + 1)];
   }
 }
 
@@ -263,42 +395,49 @@ constexpr int kYElems = 4 * 25 * 25 * 8;                             // layer-1 
 static_assert(kGridIn * kGridIn * 2 <= kXElems, "input grid fits region X");
 constexpr int kA4Off = 4 * 7 * 7 * 8;                                // layer-4 output after layer 3's grid
 
-// Number of 32-pixel tiles of the layer with input size HIN: the waves
-// below it run the layer and load its weights.
-constexpr int tiles_of(int hin) { return ((hin / 2) * (hin / 2) + 31) / 32; }
+// Every layer's weights: layer 1 for the 32 x 32 x 16 product, layers 2-4
+// for half (wave & 1) of their output channels. Layers 1 and 2 are loaded
+// before the input is built, layers 3 and 4 once layer 1 is done, so that
+// layer 2's products cover their latency.
+struct NetW {
+  LayerW L1;
+  HalfW L2, L3, L4;
+};
 
-// Weights of layers 1 and 2, loaded before the input is built so that
-// their latency overlaps it.
-__device__ __forceinline__ void load_first_layers(const uint16_t* prm, LayerW& L1, LayerW& L2, int t) {
-  const int lane = t & 63;
-  load_layer<2>(prm + kOffW[0], prm + kOffB[0], L1, lane);
-  load_layer<kCh>(prm + kOffW[1], prm + kOffB[1], L2, lane);
+__device__ __forceinline__ void load_weights(const uint16_t* prm, NetW& N, int t) {
+  const int lane = t & 63, hf = (t >> 6) & 1;
+  load_layer1(prm + kOffW[0], prm + kOffB[0], N.L1, lane);
+  load_half(prm + kOffW[1], prm + kOffB[1], N.L2, hf, lane);
 }
 
-// Each later layer's weights are requested before the barrier that ends
-// the previous layer. Returns the 3x3x32 features (planar: 8-channel plane
-// g of pixel px at 72 g + 8 px), complete in LDS for every thread.
-__device__ __forceinline__ const uint16_t* conv_stack(uint16_t* X, uint16_t* Y, const uint16_t* prm,
-                                                      const LayerW& L1, const LayerW& L2, uint16_t* dst, int t) {
-  const int lane = t & 63, wave = t >> 6;
+__device__ __forceinline__ void load_late_weights(const uint16_t* prm, NetW& N, int t) {
+  const int lane = t & 63, hf = (t >> 6) & 1;
+  load_half(prm + kOffW[2], prm + kOffB[2], N.L3, hf, lane);
+  load_half(prm + kOffW[3], prm + kOffB[3], N.L4, hf, lane);
+}
+
+// Returns the 3x3x32 features (planar: 8-channel plane g of pixel px at
+// 72 g + 8 px), complete in LDS for every thread. Waves 0 and 1 (one per
+// channel half) take the even pixel tiles of layers 2 and 4 and the odd
+// ones of layer 3, waves 2 and 3 the others: 7 and 6 tiles of 9 products.
+__device__ __forceinline__ const uint16_t* conv_stack(uint16_t* X, uint16_t* Y, const uint16_t* prm, NetW& N,
+                                                      uint16_t* dst, int t) {
+  const int wave = t >> 6, hf = wave & 1, q = wave >> 1;
   uint16_t* const a4 = Y + kA4Off;
-  conv_layer<2, 48, true>(X, Y, L1, t);
-  __syncthreads();
+  conv_layer1(X, Y, N.L1, t);
+  load_late_weights(prm, N, t);
+  lds_barrier();
   if (dst) copy_act_nhwc<24>(Y, dst + kActOff[0], t);
   zero_guard<13>(X, t);  // the input grid is no longer read
-  conv_layer<kCh, 24, true>(Y, X, L2, t);
-  LayerW L3;
-  if (wave < tiles_of(12)) load_layer<kCh>(prm + kOffW[2], prm + kOffB[2], L3, lane);
-  __syncthreads();
+  conv32<24, true>(Y, X, N.L2, hf, q, t);
+  lds_barrier();
   if (dst) copy_act_nhwc<12>(X, dst + kActOff[1], t);
   zero_guard<7>(Y, t);   // layer 1's grid is no longer read
-  conv_layer<kCh, 12, true>(X, Y, L3, t);
-  LayerW L4;
-  if (wave < tiles_of(6)) load_layer<kCh>(prm + kOffW[3], prm + kOffB[3], L4, lane);
-  __syncthreads();
+  conv32<12, true>(X, Y, N.L3, hf, 1 - q, t);
+  lds_barrier();
   if (dst) copy_act_nhwc<6>(Y, dst + kActOff[2], t);
-  conv_layer<kCh, 6, false>(Y, a4, L4, t);
-  __syncthreads();
+  conv32<6, false>(Y, a4, N.L4, hf, q, t);
+  lds_barrier();
   return a4;
 }
 
@@ -318,14 +457,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
   const int t = threadIdx.x;
   uint32_t* const grid = reinterpret_cast<uint32_t*>(X);
   const uint32_t* src = reinterpret_cast<const uint32_t*>(x + (int64_t)b * kPatchElems);
-  for (int e = t; e < kIn * kIn; e += 256) grid[(e / kIn + 1) * kGridIn + e % kIn + 1] = src[e];
-  LayerW L1, L2;
-  load_first_layers(prm, L1, L2, t);
+  for (int e = t; e < kIn * kIn; e += 256) grid[(e / kIn + 1) * kGridIn + gpos<kGridIn>(e % kIn + 1)] = src[e];
+  NetW N;
+  load_weights(prm, N, t);
   zero_input_guard(grid, t);
   zero_guard<25>(Y, t);
-  __syncthreads();
+  lds_barrier();
   uint16_t* const dst = acts ? acts + (int64_t)b * kActElems : nullptr;
-  const uint16_t* a4 = conv_stack(X, Y, prm, L1, L2, dst, t);
+  const uint16_t* a4 = conv_stack(X, Y, prm, N, dst, t);
   for (int i = t; i < kFeat; i += 256) {
     const int px = i / kCh, c = i % kCh;
     const uint16_t v = a4[(c >> 3) * (9 * 8) + px * 8 + (c & 7)];
@@ -334,33 +473,82 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
   }
 }
 
-// The same with the input of block b built in LDS straight from the frames;
-// the features go to row orig[b] of a matrix in fragment layout (see
-// k_head_frag).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_forward_blocks(const uint8_t* img, const uint8_t* avail, int64_t pitch,
-                                                        int H, int W, const fse_block_t* blocks,
-                                                        const int32_t* orig, int n, const uint16_t* prm,
-                                                        uint16_t* feats) {
-  __shared__ __align__(16) uint16_t X[kXElems];
-  __shared__ __align__(16) uint16_t Y[kYElems];
-  __shared__ uint32_t red[2][4];
-  const int b = blockIdx.x;
-  if (b >= n) return;
-  const int t = threadIdx.x;
-  uint32_t* const grid = reinterpret_cast<uint32_t*>(X);
-  LayerW L1, L2;
-  load_first_layers(prm, L1, L2, t);
-  build_input(img, avail, pitch, H, W, blocks[b], grid, red, t, kGridIn);
-  zero_input_guard(grid, t);
-  zero_guard<25>(Y, t);
-  __syncthreads();
-  const uint16_t* a4 = conv_stack(X, Y, prm, L1, L2, nullptr, t);
-  // features to row r = orig[b] of the fragment layout: 8 features (one
-  // 8-channel plane of one pixel) per 16-byte piece
+// The forward pass of the blocks of a batch, inputs built from the frames,
+// as a pipeline over the blocks a workgroup takes (b = blockIdx.x + k *
+// gridDim.x): waves 0-3 run layers 1 and 2 of block k while waves 4-7 run
+// layers 3 and 4 of block k - 1 and build the input of block k + 1, so that
+// the latency of the input loads and of the short chains of layers 3 and 4
+// overlaps the heavy layers and the two halves carry similar work. Every
+// stage has three workgroup barriers, executed by both halves: (A0) input
+// of block k written to X and the features of block k - 2 stored from A4,
+// (A) layer 1 of k (X -> Y) and layer 3 of k - 1 (Z -> V), (B) layer 2 of k
+// (Y -> Z), layer 4 of k - 1 (V -> A4) and the loads for block k + 1. The
+// features go to row orig[b] of a matrix in fragment layout (see
+// k_head_frag). 63 KB of LDS: two workgroups per CU.
+constexpr int kPipeY = 4 * 25 * 25 * 8;  // layer-1 output grid (BF16 elements)
+constexpr int kPipeZ = 4 * 13 * 13 * 8;  // layer-2 output grid
+constexpr int kPipeV = 4 * 7 * 7 * 8;    // layer-3 output grid
+constexpr int kPipeA4 = 4 * 9 * 8;       // layer-4 output (planar, unguarded)
+
+__device__ __forceinline__ void store_features(const uint16_t* a4, int r, uint16_t* feats, int t) {
+  // 8 features (one 8-channel plane of one pixel) per 16-byte piece
   if (t < kFeat / 8) {
-    const int r = orig[b], s16 = t >> 1, h = t & 1;
+    const int s16 = t >> 1, h = t & 1;
     const uint4 v = *reinterpret_cast<const uint4*>(a4 + (t & 3) * 72 + (t >> 2) * 8);
     reinterpret_cast<uint4*>(feats)[((int64_t)(r >> 5) * kSteps + s16) * 64 + h * 32 + (r & 31)] = v;
+  }
+}
+
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_forward_blocks(
+    const uint8_t* img, const uint8_t* avail, int64_t pitch, int H, int W, const fse_block_t* blocks,
+    const int32_t* orig, int n, const uint16_t* prm, uint16_t* feats) {
+  __shared__ __align__(16) uint32_t X[kGridIn * kGridIn];
+  __shared__ __align__(16) uint16_t Y[kPipeY];
+  __shared__ __align__(16) uint16_t Z[kPipeZ];
+  __shared__ __align__(16) uint16_t V[kPipeV];
+  __shared__ __align__(16) uint16_t A4[kPipeA4];
+  __shared__ uint32_t red[2][4];
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int g0 = blockIdx.x, gs = gridDim.x;
+  const int nloc = (n - g0 + gs - 1) / gs;  // blocks of this workgroup (>= 1: the grid is at most n)
+  zero_input_guard(X, t);
+  zero_guard<25>(Y, t);
+  zero_guard<13>(Z, t);
+  zero_guard<7>(V, t);
+  if (wave < 4) {
+    const int hf = wave & 1, q = wave >> 1;
+    LayerW L1;
+    HalfW L2;
+    load_layer1(prm + kOffW[0], prm + kOffB[0], L1, lane);
+    load_half(prm + kOffW[1], prm + kOffB[1], L2, hf, lane);
+    lds_barrier();
+    for (int k = 0; k <= nloc; ++k) {
+      const bool live = k < nloc;
+      lds_barrier();  // A0
+      if (live) conv_layer1(reinterpret_cast<const uint16_t*>(X), Y, L1, t);
+      lds_barrier();  // A
+      if (live) conv32<24, true>(Y, Z, L2, hf, q, t);
+      lds_barrier();  // B
+    }
+  } else {
+    const int w4 = wave - 4, hf = w4 & 1, q = w4 >> 1, t4 = t - 256;
+    HalfW L3, L4;
+    load_half(prm + kOffW[2], prm + kOffB[2], L3, hf, lane);
+    load_half(prm + kOffW[3], prm + kOffB[3], L4, hf, lane);
+    InputRows in = input_load(img, avail, pitch, H, W, blocks[g0], red, w4, lane);
+    lds_barrier();
+    for (int k = 0; k <= nloc; ++k) {
+      if (k < nloc) input_store<true>(in, red, X, w4, lane);
+      if (k >= 2) store_features(A4, orig[g0 + (k - 2) * gs], feats, t4);
+      lds_barrier();  // A0
+      if (k >= 1) conv32<12, true>(Z, V, L3, hf, 1 - q, t4);
+      lds_barrier();  // A
+      if (k >= 1) conv32<6, false>(V, A4, L4, hf, q, t4);
+      if (k + 1 < nloc) in = input_load(img, avail, pitch, H, W, blocks[g0 + (k + 1) * gs], red, w4, lane);
+      lds_barrier();  // B
+    }
+    store_features(A4, orig[g0 + (nloc - 1) * gs], feats, t4);
   }
 }
 
@@ -1026,7 +1214,19 @@ hipError_t forward_blocks(const uint8_t* img, const uint8_t* avail, int64_t pitc
                           const void* blocks, const int32_t* orig, int32_t n, const uint16_t* prm, uint16_t* feats,
                           hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_forward_blocks, dim3(n), dim3(256), 0, s, img, avail, pitch, H, W,
+  // two workgroups per CU, each taking every grid-th block
+  static int cus[64] = {0};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  if (cus[dev] == 0) {
+    int c = 0;
+    if ((e = hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    cus[dev] = c > 0 ? c : 1;
+  }
+  const int grid = std::min(n, 2 * cus[dev]);
+  hipLaunchKernelGGL(k_forward_blocks, dim3(grid), dim3(512), 0, s, img, avail, pitch, H, W,
                      reinterpret_cast<const fse_block_t*>(blocks), orig, n, prm, feats);
   return hipGetLastError();
 }
