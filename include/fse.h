@@ -518,6 +518,22 @@ fse_status_t fse_batch3d_create(fse_plan_t plan, const fse_volume_t* h_volumes, 
                                 int32_t* bad_index);
 void fse_batch3d_destroy(fse_batch3d_t batch);
 
+/* Bytes of device workspace fse_batch3d_create_in needs for n_volumes
+ * volumes: the volume descriptors, the 3-D window table of eq. (3) and the
+ * 64-point twiddles, each 256-byte aligned. Host-only. FSE_ERR_INVALID_ARG
+ * for a null argument or n_volumes < 0. */
+fse_status_t fse_batch3d_workspace_size(fse_plan_t plan, int32_t n_volumes, size_t* bytes);
+
+/* fse_batch3d_create with caller-owned device memory, under the conditions
+ * of fse_batch_create_in (256-byte aligned device memory of the current
+ * device, at least fse_batch3d_workspace_size bytes inside one allocation,
+ * kept and untouched until fse_batch3d_destroy, which frees nothing).
+ * Same results as fse_batch3d_create's batch; errors as fse_batch3d_create
+ * plus FSE_ERR_INVALID_ARG and FSE_ERR_WORKSPACE as fse_batch_create_in. */
+fse_status_t fse_batch3d_create_in(fse_plan_t plan, const fse_volume_t* h_volumes, int32_t n_volumes,
+                                   int32_t n_frames, int32_t H, int32_t W, void* d_workspace, size_t ws_bytes,
+                                   fse_batch3d_t* out_batch, int32_t* bad_index);
+
 /* Conceal every volume of the batch: frames and avail are uint8
  * [n_frames][H][pitch], d_out float32 [n_frames][H][out_pitch] (only the
  * voxels of each B are written), d_status int32 [n_volumes] (FSE_BLOCK_*),

@@ -41,6 +41,8 @@ SIGNATURES = {
     "fse_blocks_from_mask": (I32, [P, I32, I32, I32, I64, I32, I32, I32, I32, P, I32, PI32]),
     "fse_batch3d_create": (I32, [P, P, I32, I32, I32, I32, C.POINTER(P), PI32]),
     "fse_batch3d_destroy": (None, [P]),
+    "fse_batch3d_workspace_size": (I32, [P, I32, C.POINTER(C.c_size_t)]),
+    "fse_batch3d_create_in": (I32, [P, P, I32, I32, I32, I32, P, C.c_size_t, C.POINTER(P), PI32]),
     "fse_extrapolate3d_batch": (I32, [P, P, P, I64, P, I64, P, P, P]),
     "fse_warm3d_extrapolate_batch": (I32, [P, P, P, I64, P, I64, P, P, P, P, I32, P]),
     "fse_batch_create": (I32, [P, P, I32, I32, I32, I32, C.POINTER(P)]),

@@ -338,6 +338,32 @@ void free_batch(fse_batch_s* b) {
 
 bool valid_ws_flags(uint32_t ws_flags) { return (ws_flags & ~(uint32_t)FSE_WS_WARM) == 0; }
 
+// A caller's workspace: non-null, 256-byte aligned, at least `need` bytes,
+// and (checked last, the only device queries) device memory of the current
+// device with the whole range inside one allocation.
+fse_status_t check_workspace(void* d_workspace, size_t ws_bytes, size_t need) {
+  if (!d_workspace) return fail(FSE_ERR_INVALID_ARG, "null workspace");
+  if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0)
+    return fail(FSE_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  if (ws_bytes < need) return fail(FSE_ERR_WORKSPACE, "workspace smaller than the size query's result");
+  int dev = -1;
+  hipPointerAttribute_t attr;
+  hipDeviceptr_t base = nullptr;
+  size_t extent = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(FSE_ERR_HIP, "hipGetDevice failed");
+  if (hipPointerGetAttributes(&attr, d_workspace) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+      attr.device != dev) {
+    (void)hipGetLastError();
+    return fail(FSE_ERR_INVALID_ARG, "workspace is not device memory of the current device");
+  }
+  if (hipMemGetAddressRange(&base, &extent, d_workspace) != hipSuccess ||
+      static_cast<uint8_t*>(d_workspace) + need > static_cast<uint8_t*>(base) + extent) {
+    (void)hipGetLastError();
+    return fail(FSE_ERR_WORKSPACE, "workspace extends beyond its allocation");
+  }
+  return FSE_OK;
+}
+
 WsLayout ws_layout(fse_plan_t plan, int32_t n_blocks, uint32_t ws_flags) {
   WsLayout L;
   size_t off = 0;
@@ -398,26 +424,8 @@ extern "C" fse_status_t fse_batch_create_in(fse_plan_t plan, const fse_block_t* 
   size_t need = 0;
   fse_status_t st = fse_batch_workspace_size(plan, n_blocks, ws_flags, &need);
   if (st != FSE_OK) return st;
-  if (!d_workspace) return fail(FSE_ERR_INVALID_ARG, "null workspace");
-  if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0)
-    return fail(FSE_ERR_INVALID_ARG, "workspace not 256-byte aligned");
-  if (ws_bytes < need) return fail(FSE_ERR_WORKSPACE, "workspace smaller than fse_batch_workspace_size");
-  // the whole range must lie in one device allocation of the current device
-  int dev = -1;
-  hipPointerAttribute_t attr;
-  hipDeviceptr_t base = nullptr;
-  size_t extent = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return fail(FSE_ERR_HIP, "hipGetDevice failed");
-  if (hipPointerGetAttributes(&attr, d_workspace) != hipSuccess || attr.type != hipMemoryTypeDevice ||
-      attr.device != dev) {
-    (void)hipGetLastError();
-    return fail(FSE_ERR_INVALID_ARG, "workspace is not device memory of the current device");
-  }
-  if (hipMemGetAddressRange(&base, &extent, d_workspace) != hipSuccess ||
-      static_cast<uint8_t*>(d_workspace) + need > static_cast<uint8_t*>(base) + extent) {
-    (void)hipGetLastError();
-    return fail(FSE_ERR_WORKSPACE, "workspace extends beyond its allocation");
-  }
+  st = check_workspace(d_workspace, ws_bytes, need);
+  if (st != FSE_OK) return st;
   return create_batch(plan, h_blocks, n_blocks, n_frames, H, W, static_cast<uint8_t*>(d_workspace), ws_bytes,
                       ws_flags, out_batch);
 }
@@ -1148,13 +1156,37 @@ struct fse_batch3d_s {
   const DeviceTables* tables = nullptr;
   fse_volume_t* d_vols = nullptr;
   float* d_wtab3 = nullptr;
+  bool in_workspace = false;               // device arrays lie in a caller's workspace (never freed here)
+  DeviceTables ws_tables;                  // the F = 64 twiddles' copy in that workspace
 };
 
 namespace {
 void free_batch3d(fse_batch3d_s* b) {
-  (void)hipFree(b->d_vols);
-  (void)hipFree(b->d_wtab3);
+  if (!b->in_workspace) {
+    (void)hipFree(b->d_vols);
+    (void)hipFree(b->d_wtab3);
+  }
   delete b;
+}
+
+// Byte offsets of a 3-D batch's arrays in a caller's workspace (256-byte
+// aligned): volumes, the 3-D window table, the F = 64 twiddles.
+struct Ws3Layout {
+  size_t vols = 0, wtab3 = 0, twid = 0, total = 0;
+};
+Ws3Layout ws3_layout(fse_plan_t plan, int32_t n_volumes) {
+  Ws3Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return at;
+  };
+  L.vols = take((size_t)std::max(n_volumes, 1) * sizeof(fse_volume_t));
+  L.wtab3 = take((size_t)fse::kWinStrideT * fse::kWinStride * fse::kWinStride * sizeof(float));
+  L.twid = take(plan->twid[class_of(fse::kF3)].size() * sizeof(float2));
+  L.total = off;
+  return L;
 }
 
 fse_status_t validate_volumes(fse_plan_t plan, const fse_volume_t* v, int32_t n, int32_t n_frames, int32_t H,
@@ -1200,9 +1232,43 @@ fse_status_t validate_volumes(fse_plan_t plan, const fse_volume_t* v, int32_t n,
 }
 }  // namespace
 
+namespace {
+fse_status_t create_batch3d(fse_plan_t plan, const fse_volume_t* h_volumes, int32_t n_volumes, int32_t n_frames,
+                            int32_t H, int32_t W, uint8_t* ws, fse_batch3d_t* out_batch, int32_t* bad_index);
+}  // namespace
+
 extern "C" fse_status_t fse_batch3d_create(fse_plan_t plan, const fse_volume_t* h_volumes, int32_t n_volumes,
                                            int32_t n_frames, int32_t H, int32_t W, fse_batch3d_t* out_batch,
                                            int32_t* bad_index) {
+  return create_batch3d(plan, h_volumes, n_volumes, n_frames, H, W, nullptr, out_batch, bad_index);
+}
+
+extern "C" fse_status_t fse_batch3d_workspace_size(fse_plan_t plan, int32_t n_volumes, size_t* bytes) {
+  if (!plan || !bytes) return fail(FSE_ERR_INVALID_ARG, "null argument");
+  *bytes = 0;
+  if (n_volumes < 0) return fail(FSE_ERR_INVALID_ARG, "negative volume count");
+  *bytes = ws3_layout(plan, n_volumes).total;
+  return FSE_OK;
+}
+
+extern "C" fse_status_t fse_batch3d_create_in(fse_plan_t plan, const fse_volume_t* h_volumes, int32_t n_volumes,
+                                              int32_t n_frames, int32_t H, int32_t W, void* d_workspace,
+                                              size_t ws_bytes, fse_batch3d_t* out_batch, int32_t* bad_index) {
+  if (!out_batch) return fail(FSE_ERR_INVALID_ARG, "null argument");
+  *out_batch = nullptr;
+  if (bad_index) *bad_index = -1;
+  size_t need = 0;
+  fse_status_t st = fse_batch3d_workspace_size(plan, n_volumes, &need);
+  if (st != FSE_OK) return st;
+  st = check_workspace(d_workspace, ws_bytes, need);
+  if (st != FSE_OK) return st;
+  return create_batch3d(plan, h_volumes, n_volumes, n_frames, H, W, static_cast<uint8_t*>(d_workspace), out_batch,
+                        bad_index);
+}
+
+namespace {
+fse_status_t create_batch3d(fse_plan_t plan, const fse_volume_t* h_volumes, int32_t n_volumes, int32_t n_frames,
+                            int32_t H, int32_t W, uint8_t* ws, fse_batch3d_t* out_batch, int32_t* bad_index) {
   if (!out_batch) return fail(FSE_ERR_INVALID_ARG, "null argument");
   *out_batch = nullptr;
   fse_status_t st = validate_volumes(plan, h_volumes, n_volumes, n_frames, H, W, bad_index);
@@ -1231,10 +1297,25 @@ extern "C" fse_status_t fse_batch3d_create(fse_plan_t plan, const fse_volume_t* 
     return fail(FSE_ERR_UNSUPPORTED, "3-D kernel does not fit on a compute unit (iteration count too large)");
   }
   b->grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(n_volumes, (int64_t)per_cu * prop.multiProcessorCount));
-  st = upload_tables(plan, b->device, &b->tables);
-  if (st != FSE_OK) {
-    delete b;
-    return st;
+  if (ws) {
+    const Ws3Layout L = ws3_layout(plan, n_volumes);
+    const std::vector<float2>& tw = plan->twid[class_of(fse::kF3)];
+    b->in_workspace = true;
+    b->d_vols = reinterpret_cast<fse_volume_t*>(ws + L.vols);
+    b->d_wtab3 = reinterpret_cast<float*>(ws + L.wtab3);
+    b->ws_tables.twid[class_of(fse::kF3)] = reinterpret_cast<float2*>(ws + L.twid);
+    b->tables = &b->ws_tables;
+    if (hipMemcpy(b->ws_tables.twid[class_of(fse::kF3)], tw.data(), tw.size() * sizeof(float2),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      free_batch3d(b);
+      return fail(FSE_ERR_HIP, "upload of the twiddles failed");
+    }
+  } else {
+    st = upload_tables(plan, b->device, &b->tables);
+    if (st != FSE_OK) {
+      delete b;
+      return st;
+    }
   }
   // eq. (3) in 3-D: rho^(sqrt(a^2 + b^2 + c^2) / 2) for doubled offsets, FP64, rounded once
   const int S = fse::kWinStride, ST = fse::kWinStrideT;
@@ -1245,8 +1326,8 @@ extern "C" fse_status_t fse_batch3d_create(fse_plan_t plan, const fse_volume_t* 
         w3[((size_t)c * S + a) * S + d] =
             (float)std::pow((double)plan->rho, 0.5 * std::sqrt((double)a * a + (double)d * d + (double)c * c));
   const size_t nv = (size_t)std::max(n_volumes, 1);
-  if (hipMalloc(&b->d_vols, nv * sizeof(fse_volume_t)) != hipSuccess ||
-      hipMalloc(&b->d_wtab3, w3.size() * sizeof(float)) != hipSuccess) {
+  if (!ws && (hipMalloc(&b->d_vols, nv * sizeof(fse_volume_t)) != hipSuccess ||
+              hipMalloc(&b->d_wtab3, w3.size() * sizeof(float)) != hipSuccess)) {
     free_batch3d(b);
     return fail(FSE_ERR_OOM, "hipMalloc failed (3-D batch)");
   }
@@ -1259,6 +1340,7 @@ extern "C" fse_status_t fse_batch3d_create(fse_plan_t plan, const fse_volume_t* 
   *out_batch = b;
   return FSE_OK;
 }
+}  // namespace
 
 extern "C" void fse_batch3d_destroy(fse_batch3d_t batch) {
   if (!batch) return;

@@ -104,6 +104,14 @@ class Plan:
                "fse_batch_workspace_size")
         return n.value
 
+    def workspace3d_size(self, n_volumes):
+        """Device bytes a Batch3d of n_volumes needs in a caller's workspace
+        (fse_batch3d_workspace_size)."""
+        n = C.c_size_t()
+        _check(_lib.lib().fse_batch3d_workspace_size(self._h, int(n_volumes), C.byref(n)),
+               "fse_batch3d_workspace_size")
+        return n.value
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.lib().fse_plan_destroy(self._h)
@@ -240,15 +248,28 @@ class Batch3d:
     """fse_batch3d_t: validated lost volumes of a clip, resident on the GPU
     (3-D cFSE, 64 x 64 x 8 transform)."""
 
-    def __init__(self, plan, volumes, n_frames, H, W):
+    def __init__(self, plan, volumes, n_frames, H, W, workspace=None):
+        """workspace: None, or a CUDA uint8 tensor of at least
+        Plan.workspace3d_size(len(volumes)) bytes that holds the batch's
+        device memory (fse_batch3d_create_in; the batch keeps a reference)."""
         arr = np.ascontiguousarray(volumes)
         if arr.dtype != VOLUME_DTYPE:
             arr = arr.astype(VOLUME_DTYPE)
         h = C.c_void_p()
         bad = C.c_int32(-1)
-        st = _lib.lib().fse_batch3d_create(plan.handle, arr.ctypes.data_as(C.c_void_p), len(arr), int(n_frames),
-                                           int(H), int(W), C.byref(h), C.byref(bad))
-        _check(st, f"fse_batch3d_create (volume {bad.value})")
+        if workspace is None:
+            st = _lib.lib().fse_batch3d_create(plan.handle, arr.ctypes.data_as(C.c_void_p), len(arr), int(n_frames),
+                                               int(H), int(W), C.byref(h), C.byref(bad))
+            _check(st, f"fse_batch3d_create (volume {bad.value})")
+        else:
+            if not workspace.is_cuda or not workspace.is_contiguous():
+                raise ValueError("workspace must be a contiguous CUDA tensor")
+            st = _lib.lib().fse_batch3d_create_in(
+                plan.handle, arr.ctypes.data_as(C.c_void_p), len(arr), int(n_frames), int(H), int(W),
+                C.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(), C.byref(h),
+                C.byref(bad))
+            _check(st, f"fse_batch3d_create_in (volume {bad.value})")
+        self._workspace = workspace
         self._h = h
         self.plan = plan
         self.n = len(arr)
@@ -298,6 +319,7 @@ class Batch3d:
         if getattr(self, "_h", None):
             _lib.lib().fse_batch3d_destroy(self._h)
             self._h = None
+            self._workspace = None
 
     def __del__(self):
         try:

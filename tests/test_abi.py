@@ -235,3 +235,28 @@ def test_batch_workspace_size_and_host_rejections():
         assert L.fse_batch_create_in(plan.handle, blk.ctypes.data_as(C.c_void_p), 1, 1, 128, 128,
                                      C.c_void_p(ptr), size, 0, C.byref(h)) == code
         assert not h.value
+
+
+def test_batch3d_workspace_size_and_host_rejections():
+    """fse_batch3d_workspace_size: the volume descriptors (32 B each), the
+    16 x 128 x 128 FP32 window table and the 64 twiddles, 256-byte aligned;
+    fse_batch3d_create_in refuses a null, misaligned or short workspace
+    before any device call."""
+    import paper_2204_14193_amd as fse
+    from paper_2204_14193_amd import _lib
+    L = _lib.lib()
+    up = lambda b: (b + 255) // 256 * 256
+    plan = fse.Plan(0.8, 0.5, 300)
+    for n in (0, 1, 9, 3216):
+        assert plan.workspace3d_size(n) == up(32 * max(n, 1)) + 16 * 128 * 128 * 4 + 512
+    nbytes = C.c_size_t(7)
+    assert L.fse_batch3d_workspace_size(plan.handle, -1, C.byref(nbytes)) == -1 and nbytes.value == 0
+    assert L.fse_batch3d_workspace_size(None, 1, C.byref(nbytes)) == -1
+    vols = np.zeros(1, dtype=fse.VOLUME_DTYPE)
+    vols[0] = (2, 32, 32, 2, 16, 16, 16, 2, 64, 8, 0, 10)
+    need = plan.workspace3d_size(1)
+    for ptr, size, code in ((None, need, -1), (0x100008, need, -1), (0x100000, need - 1, -6)):
+        h, bad = C.c_void_p(), C.c_int32(5)
+        assert L.fse_batch3d_create_in(plan.handle, vols.ctypes.data_as(C.c_void_p), 1, 8, 128, 128,
+                                       C.c_void_p(ptr), size, C.byref(h), C.byref(bad)) == code
+        assert not h.value and bad.value == -1

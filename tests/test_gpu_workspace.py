@@ -1,7 +1,7 @@
-"""Batches in a caller's workspace (fse_batch_create_in): the same results,
-bit for bit, as batches whose device memory the library allocates, for the
-three transform sizes, the fixed-point plan and the warm start; the
-device-side rejections of a workspace.
+"""Batches in a caller's workspace (fse_batch_create_in, fse_batch3d_create_in):
+the same results, bit for bit, as batches whose device memory the library
+allocates, for the three transform sizes, the fixed-point plan, the warm
+start and 3-D volumes; the device-side rejections of a workspace.
 
 Each test prints the case it runs before touching the GPU.
 """
@@ -153,4 +153,37 @@ def test_workspace_device_rejections():
         assert st == code and not h.value, (st, L.fse_last_error())
     b = fse.Batch(plan, wl.blocks, *wl.frames.shape, workspace=dev_ws[256:])   # offset by 256: aligned
     b.close()
+    plan.close()
+
+
+def test_workspace_batch3d_matches_the_allocating_batch():
+    """A 3-D batch in a caller's workspace gives the allocating batch's
+    output and status, bit for bit, twice in a row on the same workspace."""
+    import torch
+    import paper_2204_14193_amd as fse
+    wl = workloads.clip_small()
+    n = len(wl.blocks)
+    _say(f"case workspace batch3d: {n} volumes")
+    dev = torch.device("cuda:0")
+    fr = torch.from_numpy(wl.distorted).to(dev)
+    av = torch.from_numpy(wl.avail).to(dev)
+    plan = fse.Plan(wl.rho, wl.gamma, int(wl.blocks["iters"].max()))
+
+    def run(b):
+        out = (fr * (av != 0)).to(torch.float32)
+        st = torch.full((n,), -1, dtype=torch.int32, device=dev)
+        b.run(fr, av, out, st)
+        torch.cuda.synchronize()
+        return out.cpu().numpy(), st.cpu().numpy()
+
+    ref = fse.Batch3d(plan, wl.blocks, *wl.frames.shape)
+    o1, s1 = run(ref)
+    ref.close()
+    ws = torch.full((plan.workspace3d_size(n) + 512,), 0x5A, dtype=torch.uint8, device=dev)
+    for rep in range(2):
+        b = fse.Batch3d(plan, wl.blocks, *wl.frames.shape, workspace=ws)
+        o2, s2 = run(b)
+        b.close()
+        assert (s1 == 0).all() and np.array_equal(s1, s2), rep
+        assert np.array_equal(o1, o2), rep
     plan.close()
