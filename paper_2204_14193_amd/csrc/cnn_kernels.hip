@@ -678,11 +678,20 @@ __global__ __launch_bounds__(256) void k_permute_head(const uint16_t* w, uint4* 
 // ceil(M / 32) row blocks). Workgroup tile 128 x 128, each wave 64 x 64
 // (2 x 2 MFMA tiles of 32 x 32); the same arithmetic per element as
 // k_gemm_nt (one MFMA chain over the depth in steps of 16, then the bias).
+// Workgroups are handed to the eight XCDs in turn, so the tiles are ordered
+// for that: XCD x takes the x-th contiguous eighth of the tiles (row tile
+// major), and its L2 holds that slice of F and all of W (about 2.9 MB for
+// 6432 rows) instead of all of both.
 __global__ __launch_bounds__(256) void k_head_frag(const uint4* F, const uint4* Wf, const uint16_t* bias,
                                                    float* C, int M) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int rb0 = blockIdx.x * 4 + (wave & 1) * 2;   // row blocks rb0, rb0 + 1
-  const int cb0 = blockIdx.y * 4 + (wave >> 1) * 2;  // column blocks
+  constexpr int kColTiles = kBins / 128;
+  const int tiles = ((M + 127) >> 7) * kColTiles;
+  const int per_xcd = (tiles + 7) >> 3;
+  const int tile = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  if (tile >= tiles) return;
+  const int rb0 = (tile / kColTiles) * 4 + (wave & 1) * 2;   // row blocks rb0, rb0 + 1
+  const int cb0 = (tile % kColTiles) * 4 + (wave >> 1) * 2;  // column blocks
   const int nrb = (M + 31) >> 5;
   if (rb0 >= nrb) return;
   const int rb1 = min(rb0 + 1, nrb - 1);             // a block past the end repeats the last (never stored)
@@ -1240,7 +1249,8 @@ hipError_t permute_head(const uint16_t* w, uint16_t* frag, hipStream_t s) {
 hipError_t head_frag(const uint16_t* feats_frag, const uint16_t* w_frag, const uint16_t* bias, float* logits, int32_t M,
                      hipStream_t s) {
   if (M <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_head_frag, dim3((M + 127) / 128, kBins / 128), dim3(256), 0, s,
+  const int tiles = (M + 127) / 128 * (kBins / 128);
+  hipLaunchKernelGGL(k_head_frag, dim3(8 * ((tiles + 7) / 8)), dim3(256), 0, s,
                      reinterpret_cast<const uint4*>(feats_frag), reinterpret_cast<const uint4*>(w_frag), bias, logits,
                      M);
   return hipGetLastError();
