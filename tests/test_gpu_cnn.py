@@ -116,15 +116,21 @@ def test_forward_matches_oracle():
     net.close()
 
 
-def test_forward_from_frames_equals_patches_then_forward():
+@pytest.mark.parametrize("case", ["256", "1080p-300"])
+def test_forward_from_frames_equals_patches_then_forward(case):
     """fse_cnn_forward_blocks builds the inputs in LDS; its logits are the
-    bits of fse_cnn_patches followed by fse_cnn_forward (a batch with frame
-    edges, in a non-trivial block order)."""
+    bits of fse_cnn_patches followed by fse_cnn_forward: a batch with frame
+    edges in a non-trivial block order, and 300 blocks of a 1080p frame
+    (ragged row tiles of the head product, spread over the XCDs)."""
     import torch
     import paper_2204_14193_amd as fse
     from paper_2204_14193_amd import warm
-    _say("case forward from frames")
-    wl = workloads.subset(workloads.isolated_256(iters=30), np.arange(64)[::-1].copy())
+    _say(f"case forward from frames {case}")
+    if case == "256":
+        wl = workloads.subset(workloads.isolated_256(iters=30), np.arange(64)[::-1].copy())
+    else:
+        full = workloads.random_1080p_16x16(seeds=(100,), iters=0)
+        wl = workloads.subset(full, np.arange(0, len(full.blocks), 2)[:300])
     dev = torch.device("cuda:0")
     img = torch.from_numpy(wl.distorted).to(dev)
     av = torch.from_numpy(wl.avail).to(dev)
