@@ -684,7 +684,7 @@ __global__ __launch_bounds__(256) void k_permute_head(const uint16_t* w, uint4* 
 // 6432 rows) instead of all of both.
 __global__ __launch_bounds__(256) void k_head_frag(const uint4* F, const uint4* Wf, const uint16_t* bias,
                                                    float* C, int M) {
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
   constexpr int kColTiles = kBins / 128;
   const int tiles = ((M + 127) >> 7) * kColTiles;
   const int per_xcd = (tiles + 7) >> 3;
@@ -695,14 +695,15 @@ __global__ __launch_bounds__(256) void k_head_frag(const uint4* F, const uint4* 
   const int nrb = (M + 31) >> 5;
   if (rb0 >= nrb) return;
   const int rb1 = min(rb0 + 1, nrb - 1);             // a block past the end repeats the last (never stored)
-  const uint4* pa0 = F + (int64_t)rb0 * kSteps * 64 + lane;
-  const uint4* pa1 = F + (int64_t)rb1 * kSteps * 64 + lane;
-  const uint4* pb0 = Wf + (int64_t)cb0 * kSteps * 64 + lane;
+  // uniform fragment bases, one lane offset for all four operands
+  const uint4* pa0 = F + (int64_t)rb0 * kSteps * 64;
+  const uint4* pa1 = F + (int64_t)rb1 * kSteps * 64;
+  const uint4* pb0 = Wf + (int64_t)cb0 * kSteps * 64;
   const uint4* pb1 = pb0 + kSteps * 64;
   f32x16 acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};
   uint4 a0[2], b0[2], a1[2], b1[2];
   auto load = [&](uint4 (&av)[2], uint4 (&bv)[2], int st) {
-    const int o = min(st, kSteps - 1) * 64;
+    const int o = min(st, kSteps - 1) * 64 + lane;
     av[0] = pa0[o];
     av[1] = pa1[o];
     bv[0] = pb0[o];
