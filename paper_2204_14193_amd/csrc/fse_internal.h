@@ -141,11 +141,10 @@ const Variant* power_variant_for(int F);
 // block of the class, grid = class size): null if kc is not compiled.
 const void* restricted_kernel(int kc);
 
-// Dynamic LDS bytes of the restricted kernel for ir restricted iterations,
-// and its threads per workgroup.
-// Dynamic LDS of the restricted kernel for kc candidates; `lists` = room
-// for the per-block coefficient list, needed only by blocks with more than
-// kRestrictedInloopPixels pixels in B.
+// Dynamic LDS bytes of the restricted kernel for kc candidates and ir
+// restricted iterations (W and the twiddles are static: 17 KB); `lists` =
+// room for the per-block coefficient list, needed only by blocks with more
+// than kRestrictedInloopPixels pixels in B. Then its threads per workgroup.
 size_t restricted_lds_bytes(int kc, int ir, bool lists);
 constexpr int kRestrictedInloopPixels = 256;
 int restricted_threads(int kc);

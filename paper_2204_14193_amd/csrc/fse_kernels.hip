@@ -882,10 +882,13 @@ __global__ __launch_bounds__(64 * NWB) void fse_restricted(ClassArgs a) {
   constexpr int F = 64, NT = 64 * NWB, CPL = KC / NT;
   static_assert(NWB == 1 || NWB == 2, "one or two waves per block");
   static_assert(KC % NT == 0 && CPL >= 1 && CPL <= 16, "candidate count must be a multiple of the thread count");
+  // W and the twiddles at fixed LDS addresses, so that every address into
+  // them is an offset the compiler knows; the dynamic part holds the
+  // cross-wave slots (two waves) and the coefficient list (large B only)
+  __shared__ __align__(16) float2 Wh[kHalfRows * F];  // W rows 0..F/2
+  __shared__ __align__(16) float2 tw[F];              // F twiddles
   extern __shared__ __align__(16) unsigned char smem[];
-  float2* const Wh = reinterpret_cast<float2*>(smem);  // kHalfRows x F
-  float2* const tw = Wh + kHalfRows * F;                // F twiddles
-  int4* const xch = reinterpret_cast<int4*>(tw + F);   // 2 x NWB cross-wave argmax slots (two waves)
+  int4* const xch = reinterpret_cast<int4*>(smem);    // 2 x NWB cross-wave argmax slots (two waves)
   float2* const cl_c = reinterpret_cast<float2*>(xch + (NWB == 2 ? 4 : 0));  // ir coefficients
   int* const cl_idx = reinterpret_cast<int*>(cl_c + a.ir);
   const int t = threadIdx.x, lane = t & 63;
@@ -2062,8 +2065,7 @@ const void* restricted_kernel(int kc) {
 int restricted_threads(int kc) { return 64 * restricted_waves(kc); }
 
 size_t restricted_lds_bytes(int kc, int ir, bool lists) {
-  return (size_t)kHalfRows * 64 * 8 + 64 * 8 + (restricted_waves(kc) == 2 ? 4 * 16 : 0) +
-         (lists ? (size_t)ir * 12 : 0);
+  return (restricted_waves(kc) == 2 ? 4 * 16 : 0) + (lists ? (size_t)ir * 12 : 0);
 }
 
 hipError_t launch_restricted(int kc, const ClassArgs& a, size_t lds, hipStream_t s) {
