@@ -1091,12 +1091,12 @@ __global__ __launch_bounds__(256) void k_topk(const float* logits, int B, int K,
     bk[t] = sv;
   }
   __syncthreads();
+  const float p = (float)K * (1.0f / kBins);
+  const int r = (K + 8) / 16;                                        // expected rank of T in the sample
+  const int mg = (int)(3.0f * sqrtf(256.0f * p * (1.0f - p))) + 2;   // margin
+  const int r_hi = r - mg, r_lo = r + mg;
+  uint32_t sv[4];  // the sorted sample, kept by wave 0 for the bracket search
   if (wave == 0) {
-    const float p = (float)K * (1.0f / kBins);
-    const int r = (K + 8) / 16;                                        // expected rank of T in the sample
-    const int mg = (int)(3.0f * sqrtf(256.0f * p * (1.0f - p))) + 2;   // margin
-    const int r_hi = r - mg, r_lo = r + mg;
-    uint32_t sv[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) sv[j] = bk[4 * lane + j];
     wave_sort256_desc(sv, lane);
@@ -1151,12 +1151,67 @@ __global__ __launch_bounds__(256) void k_topk(const float* logits, int B, int K,
         uint32_t r[kBracketRegs];
 #pragma unroll
         for (int i = 0; i < kBracketRegs; ++i) r[i] = (uint32_t)(lane + 64 * i) < m ? bk[lane + 64 * i] : 0u;
-        for (int bit = top; bit >= 0; --bit) {
-          const uint32_t c = v | (1u << bit);
+        auto count_ge = [&](uint32_t c) {
           uint32_t n = 0;
 #pragma unroll
           for (int i = 0; i < kBracketRegs; ++i) n += r[i] >= c ? 1u : 0u;
-          if (wave_sum_u32(n) >= need) v = c;
+          return wave_sum_u32(n);
+        };
+        // The sorted sample keys inside the bracket split it into pieces of
+        // about 16 keys: a binary search over them (index e0 - 1 stands for
+        // "above every key", e1 + 1 for t_lo) finds the piece [lo_k, hi_k]
+        // that holds T, and how many bracket keys lie above it.
+        const int e0 = max(r_hi, 1) - 1, e1 = min(r_lo, 256) - 1;
+        int elo = e0 - 1, ehi = e1 + 1;  // count(elo) < need <= count(ehi)
+        uint32_t above = 0;              // bracket keys at or above the key of elo
+        while (ehi - elo > 1) {
+          const int mid = (elo + ehi) >> 1;
+          const uint32_t n = count_ge(wave_elem256(sv, mid));
+          if (n >= need) {
+            ehi = mid;
+          } else {
+            elo = mid;
+            above = n;
+          }
+        }
+        const uint32_t lo_k = ehi == e1 + 1 ? t_lo : wave_elem256(sv, ehi);
+        const uint32_t hi_k = elo == e0 - 1 ? t_hi : wave_elem256(sv, elo) - 1u;
+        uint64_t msk[kBracketRegs];
+        uint32_t sub = 0;
+#pragma unroll
+        for (int i = 0; i < kBracketRegs; ++i) {
+          msk[i] = __ballot((uint32_t)(lane + 64 * i) < m && r[i] >= lo_k && r[i] <= hi_k);
+          sub += (uint32_t)__builtin_popcountll(msk[i]);
+        }
+        if (sub <= 128) {
+          // the piece in two registers, then a bisection with two ballots per step
+          uint32_t* const piece = bk + 64 * kBracketRegs;  // past the bracket keys
+          uint32_t at = 0;
+#pragma unroll
+          for (int i = 0; i < kBracketRegs; ++i) {
+            if ((msk[i] >> lane) & 1ull)
+              piece[at + __builtin_amdgcn_mbcnt_hi((uint32_t)(msk[i] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)msk[i], 0u))] = r[i];
+            at += (uint32_t)__builtin_popcountll(msk[i]);
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+          const uint32_t x0 = (uint32_t)lane < sub ? piece[lane] : 0u;  // 0 pads, as above
+          const uint32_t x1 = (uint32_t)lane + 64u < sub ? piece[lane + 64] : 0u;
+          const uint32_t need2 = need - above;
+          const uint32_t d2 = lo_k ^ hi_k;
+          const int top2 = d2 ? 31 - __builtin_clz(d2) : -1;
+          v = top2 >= 31 ? 0u : (lo_k >> (top2 + 1)) << (top2 + 1);
+          for (int bit = top2; bit >= 0; --bit) {
+            const uint32_t c = v | (1u << bit);
+            if ((uint32_t)(__builtin_popcountll(__ballot(x0 >= c)) + __builtin_popcountll(__ballot(x1 >= c))) >= need2)
+              v = c;
+          }
+        } else {
+          for (int bit = top; bit >= 0; --bit) {
+            const uint32_t c = v | (1u << bit);
+            if (count_ge(c) >= need) v = c;
+          }
         }
       } else {
         for (int bit = top; bit >= 0; --bit) {
