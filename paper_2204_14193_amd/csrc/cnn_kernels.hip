@@ -1005,9 +1005,21 @@ __device__ __forceinline__ uint32_t threshold_by_bisection(const uint32_t (&key)
   return T;
 }
 
+// The value of lane (this lane xor ld): DPP moves for ld = 1, 2 (quad
+// permutes) and 8 (row rotation), a swizzle for 4 and 16, a permute for 32.
+__device__ __forceinline__ uint32_t xor_lanes(uint32_t x, int ld) {
+  switch (ld) {
+    case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xb1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
+    case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4e, 0xf, 0xf, false);   // quad_perm [2,3,0,1]
+    case 8: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xf, 0xf, false);  // row_ror:8
+    case 4: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x101f);               // xor 4 in 32 lanes
+    case 16: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401f);              // xor 16 in 32 lanes
+    default: return (uint32_t)__shfl_xor((int)x, ld);
+  }
+}
+
 // Sort the 256 values v[j] of lane l (element 4 l + j) of a wave into
-// descending order (bitonic network; partners in other lanes via lane
-// shuffles).
+// descending order (bitonic network; partners in other lanes by xor_lanes).
 __device__ __forceinline__ void wave_sort256_desc(uint32_t (&v)[4], int lane) {
 #pragma unroll
   for (int k = 2; k <= 256; k <<= 1) {
@@ -1020,7 +1032,7 @@ __device__ __forceinline__ void wave_sort256_desc(uint32_t (&v)[4], int lane) {
         for (int j = 0; j < 4; ++j) {
           const int e = 4 * lane + j;
           const bool desc = (e & k) == 0;      // this block of the merge sorts descending
-          const uint32_t o = (uint32_t)__shfl_xor((int)v[j], ld);
+          const uint32_t o = xor_lanes(v[j], ld);
           // the lower index keeps the larger value in a descending block
           const bool keep_max = lower == desc;
           v[j] = keep_max ? max(v[j], o) : min(v[j], o);
