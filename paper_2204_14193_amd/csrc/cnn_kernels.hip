@@ -1082,17 +1082,15 @@ __global__ __launch_bounds__(256) void k_topk(const float* logits, int B, int K,
   if (b >= B) return;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   uint32_t key[16];
-  uint32_t nan = 0;
+  uint64_t nan_lanes = 0;  // lanes holding a NaN (one unordered compare per pair of values)
   const float4* src = reinterpret_cast<const float4*>(logits + (int64_t)b * kBins + 16 * t);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const float4 v = src[q];
+    nan_lanes |= __ballot(__builtin_isunordered(v.x, v.y)) | __ballot(__builtin_isunordered(v.z, v.w));
     const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      nan |= (vv[r] != vv[r]) ? 1u : 0u;
-      key[4 * q + r] = order_key(vv[r]);
-    }
+    for (int r = 0; r < 4; ++r) key[4 * q + r] = order_key(vv[r]);
   }
   // 1. sample key: bin 16 t + ((t ^ (t >> 4)) & 15)
   {
@@ -1128,13 +1126,14 @@ __global__ __launch_bounds__(256) void k_topk(const float* logits, int B, int K,
     n_gt += key[j] > t_hi;
     n_ge += key[j] >= t_lo;
   }
-  n_gt = wave_sum_u32(n_gt);
-  n_ge = wave_sum_u32(n_ge);
-  nan = wave_sum_u32(nan);
+  // this thread's keys in the bracket: keys at or above t_lo less those above
+  // t_hi (t_lo <= t_hi; the clamp keeps it exact, 0, were they ever crossed)
+  const uint32_t inb = n_ge > n_gt ? n_ge - n_gt : 0u;
+  const uint32_t w_gt = wave_sum_u32(n_gt), w_ge = wave_sum_u32(n_ge);
   if (lane == 0) {
-    red[0][wave] = n_gt;
-    red[1][wave] = n_ge;
-    red[2][wave] = nan;
+    red[0][wave] = w_gt;
+    red[1][wave] = w_ge;
+    red[2][wave] = nan_lanes != 0 ? 1u : 0u;
   }
   __syncthreads();
   const uint32_t c_gt = red[0][0] + red[0][1] + red[0][2] + red[0][3];
@@ -1143,9 +1142,6 @@ __global__ __launch_bounds__(256) void k_topk(const float* logits, int B, int K,
   int par = 0;
   uint32_t T;
   if (c_gt < (uint32_t)K && (uint32_t)K <= c_ge) {
-    uint32_t inb = 0;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) inb += key[j] >= t_lo && key[j] <= t_hi;
     uint32_t m = 0;
     uint32_t pos = block_exscan(inb, slots, par, m);  // m = c_ge - c_gt
 #pragma unroll
