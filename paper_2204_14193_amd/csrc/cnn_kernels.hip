@@ -1252,16 +1252,26 @@ __global__ __launch_bounds__(256) void k_topk(const float* logits, int B, int K,
   const uint32_t eq_take = min(eq_before + eq, remaining) - taken_before;
   // selected before this thread: all greater keys, plus the ties taken
   uint32_t pos = gt_before + taken_before;
-  uint32_t eq_seen = 0;
-  int16_t* out = cand + (int64_t)b * K;
+  char* const out = reinterpret_cast<char*>(cand + (int64_t)b * K);  // int16 entries at byte offsets 2 pos
+  if ((tot & 0xffffu) == remaining) {
+    // every tie at T is taken (the usual case): the keys at or above T
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    bool take = key[j] > T;
-    if (key[j] == T) {
-      take = eq_seen < eq_take;
-      ++eq_seen;
+    for (int j = 0; j < 16; ++j) {
+      if (key[j] >= T && pos < (uint32_t)K) *reinterpret_cast<int16_t*>(out + 2 * pos) = (int16_t)(16 * t + j);
+      pos += key[j] >= T ? 1u : 0u;
     }
-    if (take && pos < (uint32_t)K) out[pos++] = (int16_t)(16 * t + j);
+  } else {
+    uint32_t eq_seen = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      bool take = key[j] > T;
+      if (key[j] == T) {
+        take = eq_seen < eq_take;
+        ++eq_seen;
+      }
+      if (take && pos < (uint32_t)K) *reinterpret_cast<int16_t*>(out + 2 * pos) = (int16_t)(16 * t + j);
+      pos += take ? 1u : 0u;
+    }
   }
   if (t == 0) flags[b] = any_nan ? 1 : 0;
 }
